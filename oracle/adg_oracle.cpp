@@ -1,0 +1,954 @@
+// Plain, slow FP64 CPU oracle for one ADER-DG step of 2D compressible
+// Navier-Stokes with gravity, and for the total-variation refinement
+// indicator.  TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the
+// CPU-baseline leg of the benchmark may load it; the product path never does.
+//
+// It shares no code with the GPU library: its own quadrature, its own
+// matrices, its own mesh/face search, its own physics.  Every routine follows
+// the paper (Krenz, Rannabauer, Bader, arXiv:1905.05524) or, where the paper
+// delegates the scheme to cited works, the reading of the method stated next
+// to it.  Loops are written in the order of the definitions, with no blocking
+// or fusion.  Compiled with -O2 -ffp-contract=off and no fast-math.
+//
+// Scalar type is a template parameter so that the same code runs on doubles
+// and on forward-mode dual numbers (used for exact directional derivatives of
+// a multi-step rollout, the reference for the hand-written adjoint).
+//
+// Conventions
+//   reference element [0,1]^2, Gauss-Legendre (GL) nodes xi_0..xi_N, n=N+1
+//   Q[cell][var][jz][ix], var = (rho, rho*u, rho*w, rho*E)
+//   node coordinates x = x0 + h*xi_ix, z = z0 + h*xi_jz
+//   face f: 0 = -x side, 1 = +x side, 2 = -z side, 3 = +z side
+//   face data FD[cell][f][0=Qbar,1=Fbar][var][k] (k: tangential node)
+//   fluxes at faces are always the flux in the +axis direction
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+#include <utility>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+// ---------------------------------------------------------------- dual numbers
+struct Dual {
+  double v, d;
+  Dual() : v(0), d(0) {}
+  Dual(double a) : v(a), d(0) {}
+  Dual(double a, double b) : v(a), d(b) {}
+};
+inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(Dual a, Dual b) {
+  return Dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v));
+}
+inline Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
+inline Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
+inline Dual sqrt(Dual a) { double s = std::sqrt(a.v); return Dual(s, a.d / (2.0 * s)); }
+inline Dual fabs(Dual a) { return a.v > 0 ? a : (a.v < 0 ? -a : Dual(0.0, 0.0)); }
+inline Dual pow(Dual a, double e) {
+  double p = std::pow(a.v, e);
+  return Dual(p, e * std::pow(a.v, e - 1.0) * a.d);
+}
+inline double val(double a) { return a; }
+inline double val(Dual a) { return a.v; }
+using std::sqrt; using std::fabs; using std::pow;
+
+// -------------------------------------------------------------------- params
+// Flat parameter vector (indices shared with the Python wrapper of this file).
+enum {
+  P_N = 0, P_PICARD, P_GAMMA, P_PR, P_R, P_CP, P_MU, P_G, P_P0, P_THETA,
+  P_GRAVITY, P_MMS, P_MMS_AMP, P_MMS_U, P_MMS_W, P_MMS_KX, P_MMS_KZ, P_MMS_P,
+  P_CFL, P_COUNT
+};
+
+struct Params {
+  int N, n, iters;
+  double gamma, Pr, R, cp, mu, g, p0, theta_bg;
+  bool gravity, mms;
+  double mms_amp, mms_u, mms_w, mms_kx, mms_kz, mms_p;
+  double cfl;
+  double kappa;
+};
+
+Params read_params(const double* p) {
+  Params P;
+  P.N = (int)p[P_N]; P.n = P.N + 1;
+  P.iters = (int)p[P_PICARD]; if (P.iters <= 0) P.iters = P.N + 1;
+  P.gamma = p[P_GAMMA]; P.Pr = p[P_PR]; P.R = p[P_R]; P.cp = p[P_CP];
+  P.mu = p[P_MU]; P.g = p[P_G]; P.p0 = p[P_P0]; P.theta_bg = p[P_THETA];
+  P.gravity = p[P_GRAVITY] != 0.0; P.mms = p[P_MMS] != 0.0;
+  P.mms_amp = p[P_MMS_AMP]; P.mms_u = p[P_MMS_U]; P.mms_w = p[P_MMS_W];
+  P.mms_kx = p[P_MMS_KX]; P.mms_kz = p[P_MMS_KZ]; P.mms_p = p[P_MMS_P];
+  P.cfl = p[P_CFL];
+  // heat conductivity kappa = mu*cp/Pr (paper, eq. heat-conduction-coeff)
+  P.kappa = P.mu * P.cp / P.Pr;
+  return P;
+}
+
+// --------------------------------------------------------------------- basis
+// Gauss-Legendre nodes and weights on [0,1], Newton on the Legendre
+// polynomial P_n in long double, then the Lagrange nodal basis on them.
+struct Basis {
+  int n;
+  std::vector<double> xi, w, D, e0, e1, P;  // D[i*n+j] = phi_j'(xi_i)
+};
+
+void legendre(int n, long double x, long double& pn, long double& dpn) {
+  long double p0 = 1.0L, p1 = x;
+  if (n == 0) { pn = 1.0L; dpn = 0.0L; return; }
+  for (int k = 2; k <= n; ++k) {
+    long double pk = ((2.0L * k - 1.0L) * x * p1 - (k - 1.0L) * p0) / k;
+    p0 = p1; p1 = pk;
+  }
+  pn = p1;
+  dpn = n * (x * p1 - p0) / (x * x - 1.0L);
+}
+
+long double lagrange(const std::vector<long double>& X, int j, long double x) {
+  long double r = 1.0L;
+  for (int m = 0; m < (int)X.size(); ++m)
+    if (m != j) r *= (x - X[m]) / (X[j] - X[m]);
+  return r;
+}
+
+Basis make_basis(int N) {
+  Basis B; int n = N + 1; B.n = n;
+  const long double PI = 3.141592653589793238462643383279502884L;
+  std::vector<long double> X(n), W(n);
+  for (int k = 0; k < n; ++k) {
+    // k-th root of P_n on [-1,1] in decreasing order, mapped increasing below
+    long double x = std::cos(PI * (k + 0.75L) / (n + 0.5L));
+    for (int it = 0; it < 100; ++it) {
+      long double pn, dpn; legendre(n, x, pn, dpn);
+      long double dx = pn / dpn; x -= dx;
+      if (std::fabs(dx) < 1e-30L) break;
+    }
+    long double pn, dpn; legendre(n, x, pn, dpn);
+    long double wk = 2.0L / ((1.0L - x * x) * dpn * dpn);
+    X[n - 1 - k] = (x + 1.0L) / 2.0L;
+    W[n - 1 - k] = wk / 2.0L;
+  }
+  B.xi.resize(n); B.w.resize(n);
+  for (int k = 0; k < n; ++k) { B.xi[k] = (double)X[k]; B.w[k] = (double)W[k]; }
+  // derivative matrix D_ij = phi_j'(xi_i), from the product form of phi_j
+  B.D.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      long double s = 0.0L;
+      for (int m = 0; m < n; ++m) {
+        if (m == j) continue;
+        long double term = 1.0L / (X[j] - X[m]);
+        for (int l = 0; l < n; ++l)
+          if (l != j && l != m) term *= (X[i] - X[l]) / (X[j] - X[l]);
+        s += term;
+      }
+      B.D[i * n + j] = (double)s;
+    }
+  B.e0.resize(n); B.e1.resize(n);
+  for (int j = 0; j < n; ++j) {
+    B.e0[j] = (double)lagrange(X, j, 0.0L);
+    B.e1[j] = (double)lagrange(X, j, 1.0L);
+  }
+  // Space-time predictor matrices: the weak form of d/dtau on [0,1] with the
+  // upwind value at tau=0 gives K1 q = e0 Q^n + dt W R, where
+  //   K1_ab = phi_a(1) phi_b(1) - w_b phi_a'(tau_b).
+  // Because K1 * 1 = e0, q = Q^n + dt K1^{-1} W R; P = K1^{-1} W.
+  std::vector<long double> K(n * n), Pm(n * n);
+  std::vector<long double> E0(n), E1(n), DD(n * n);
+  for (int j = 0; j < n; ++j) { E0[j] = lagrange(X, j, 0.0L); E1[j] = lagrange(X, j, 1.0L); }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      long double s = 0.0L;
+      for (int m = 0; m < n; ++m) {
+        if (m == j) continue;
+        long double term = 1.0L / (X[j] - X[m]);
+        for (int l = 0; l < n; ++l)
+          if (l != j && l != m) term *= (X[i] - X[l]) / (X[j] - X[l]);
+        s += term;
+      }
+      DD[i * n + j] = s;
+    }
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b)
+      K[a * n + b] = E1[a] * E1[b] - W[b] * DD[b * n + a];
+  // Solve K * Pm = diag(W) by Gauss-Jordan with partial pivoting.
+  std::vector<long double> A(K), Rhs(n * n, 0.0L);
+  for (int a = 0; a < n; ++a) Rhs[a * n + a] = W[a];
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(A[r * n + col]) > std::fabs(A[piv * n + col])) piv = r;
+    if (piv != col)
+      for (int c = 0; c < n; ++c) {
+        std::swap(A[piv * n + c], A[col * n + c]);
+        std::swap(Rhs[piv * n + c], Rhs[col * n + c]);
+      }
+    long double d = A[col * n + col];
+    for (int c = 0; c < n; ++c) { A[col * n + c] /= d; Rhs[col * n + c] /= d; }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      long double f = A[r * n + col];
+      if (f == 0.0L) continue;
+      for (int c = 0; c < n; ++c) {
+        A[r * n + c] -= f * A[col * n + c];
+        Rhs[r * n + c] -= f * Rhs[col * n + c];
+      }
+    }
+  }
+  B.P.resize(n * n);
+  for (int k = 0; k < n * n; ++k) B.P[k] = (double)Rhs[k];
+  return B;
+}
+
+// Lagrange basis of B evaluated at an arbitrary point (long double product).
+double phi_at(const Basis& B, int j, double x) {
+  std::vector<long double> X(B.xi.begin(), B.xi.end());
+  return (double)lagrange(X, j, (long double)x);
+}
+
+// ---------------------------------------------------------------- background
+// Hydrostatic background of constant potential temperature theta_bg
+// (paper eq. hydrostatic-balance, potential temperature definition):
+//   Exner pi(z) = 1 - g z / (cp theta), p = p0 pi^(cp/R), T = theta pi,
+//   rho = p / (R T).   d p/dz = -g rho holds exactly.
+void background(const Params& P, double z, double& rho_b, double& p_b) {
+  if (!P.gravity) { rho_b = 0.0; p_b = 0.0; return; }
+  double pi = 1.0 - P.g * z / (P.cp * P.theta_bg);
+  p_b = P.p0 * std::pow(pi, P.cp / P.R);
+  rho_b = p_b / (P.R * P.theta_bg * pi);
+}
+
+// Manufactured energy source for the advected density wave
+//   rho = 1 + A sin(kx X) sin(kz Z), X = x - u t, Z = z - w t, v = (u, w), p const:
+// the Euler part is solved exactly, the heat flux -kappa grad T with
+// T = p/(R rho) leaves S_E = -kappa Lap T.
+double mms_source_E(const Params& P, double x, double z, double t) {
+  double X = x - P.mms_u * t, Z = z - P.mms_w * t;
+  double sx = std::sin(P.mms_kx * X), cx = std::cos(P.mms_kx * X);
+  double sz = std::sin(P.mms_kz * Z), cz = std::cos(P.mms_kz * Z);
+  double rho = 1.0 + P.mms_amp * sx * sz;
+  double rx = P.mms_amp * P.mms_kx * cx * sz;
+  double rz = P.mms_amp * P.mms_kz * sx * cz;
+  double lap = -(P.mms_kx * P.mms_kx + P.mms_kz * P.mms_kz) * P.mms_amp * sx * sz;
+  double lapT = (P.mms_p / P.R) * (-lap / (rho * rho) + 2.0 * (rx * rx + rz * rz) / (rho * rho * rho));
+  return -P.kappa * lapT;
+}
+
+// ----------------------------------------------------------- pointwise physics
+// Flux F = F^h(Q) + F^v(Q, grad Q) in x and z and source S at one point
+// (paper eq. equation-set, eos, temperature, stress-tensor,
+// heat-conduction-coeff, momentum-equation-split), 2D.
+// Readings: the EOS geopotential term is rho*g*z; the momentum flux uses the
+// perturbation pressure p - p_bar(z) and the source -g (rho - rho_bar(z));
+// the energy flux uses the full pressure; gradients of primitive variables
+// come from the gradients of the conserved variables by the chain rule.
+template <class T>
+void pointwise(const Params& P, const T q[4], const T gx[4], const T gz[4],
+               double x, double z, double t, double rho_b, double p_b,
+               T Fx[4], T Fz[4], T S[4]) {
+  const double gm1 = P.gamma - 1.0;
+  T rho = q[0], mx = q[1], mz = q[2], E = q[3];
+  T u = mx / rho, w = mz / rho;
+  T geo = P.gravity ? rho * (P.g * z) : T(0.0);
+  T p = gm1 * (E - 0.5 * (mx * u + mz * w) - geo);
+  T pm = P.gravity ? p - p_b : p;     // pressure in the momentum flux
+  T Tm = p / (rho * P.R);             // temperature, p = rho R T
+  // primitive gradients
+  T dux = (gx[1] - u * gx[0]) / rho, duz = (gz[1] - u * gz[0]) / rho;
+  T dwx = (gx[2] - w * gx[0]) / rho, dwz = (gz[2] - w * gz[0]) / rho;
+  T v2 = u * u + w * w;
+  T dpx = gm1 * (gx[3] - 0.5 * v2 * gx[0] - rho * (u * dux + w * dwx));
+  T dpz = gm1 * (gz[3] - 0.5 * v2 * gz[0] - rho * (u * duz + w * dwz));
+  if (P.gravity) {
+    dpx = dpx - gm1 * (P.g * z) * gx[0];
+    dpz = dpz - gm1 * ((P.g * z) * gz[0] + rho * P.g);
+  }
+  T dTx = (dpx - P.R * Tm * gx[0]) / (rho * P.R);
+  T dTz = (dpz - P.R * Tm * gz[0]) / (rho * P.R);
+  // stress tensor sigma = mu (2/3 div v I - (grad v + grad v^T))
+  T div = dux + dwz;
+  T sxx = P.mu * ((2.0 / 3.0) * div - 2.0 * dux);
+  T szz = P.mu * ((2.0 / 3.0) * div - 2.0 * dwz);
+  T sxz = -P.mu * (duz + dwx);
+  Fx[0] = mx;
+  Fx[1] = mx * u + pm + sxx;
+  Fx[2] = mz * u + sxz;
+  Fx[3] = u * (E + p) + (u * sxx + w * sxz) - P.kappa * dTx;
+  Fz[0] = mz;
+  Fz[1] = mx * w + sxz;
+  Fz[2] = mz * w + pm + szz;
+  Fz[3] = w * (E + p) + (u * sxz + w * szz) - P.kappa * dTz;
+  S[0] = T(0.0); S[1] = T(0.0);
+  S[2] = P.gravity ? -P.g * (rho - rho_b) : T(0.0);
+  S[3] = P.mms ? T(mms_source_E(P, x, z, t)) : T(0.0);
+}
+
+// pressure and eigenvalue bounds at a state (used by the face flux and dt)
+template <class T>
+T pressure(const Params& P, const T q[4], double z) {
+  T geo = P.gravity ? q[0] * (P.g * z) : T(0.0);
+  return (P.gamma - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / q[0] - geo);
+}
+// viscous eigenvalue bound lambda_v = max(4 mu / (3 rho), gamma mu / (Pr rho))
+template <class T>
+T lambda_visc(const Params& P, const T& rho) {
+  T a = (4.0 * P.mu / 3.0) / rho, b = (P.gamma * P.mu / P.Pr) / rho;
+  return val(a) >= val(b) ? a : b;
+}
+
+// ---------------------------------------------------------------------- mesh
+// Cells are leaves (level, i, j) of a 3-way refined coarse grid nx x nz; the
+// oracle finds face neighbours through a dense map at the finest level.
+struct Cell { int level, i, j; double x0, z0, h; };
+enum { BC_PERIODIC = 0, BC_WALL = 1 };
+
+struct Neighbor {
+  // kind: 0 conforming, 1 wall, 2 this cell is fine (nb coarse, sub-face k),
+  //       3 this cell is coarse (nb[0..2] fine, in sub-face order)
+  int kind; int nb[3]; int k;
+};
+
+struct Mesh {
+  int nx, nz, L, bc[4];
+  double x0, z0, Lx, Lz;
+  std::vector<Cell> cells;
+  std::vector<Neighbor> nbr;  // [cell*4 + face]
+  bool ok = true;
+};
+
+int ipow3(int e) { int r = 1; while (e-- > 0) r *= 3; return r; }
+
+Mesh build_mesh(const int* mi, const double* md, const int* lev, const int* ci, const int* cj) {
+  Mesh M;
+  M.nx = mi[0]; M.nz = mi[1]; M.L = mi[2];
+  for (int s = 0; s < 4; ++s) M.bc[s] = mi[3 + s];
+  int C = mi[7];
+  M.x0 = md[0]; M.z0 = md[1]; M.Lx = md[2]; M.Lz = md[3];
+  double hc = M.Lx / M.nx;
+  M.cells.resize(C);
+  for (int c = 0; c < C; ++c) {
+    Cell& k = M.cells[c];
+    if (lev) { k.level = lev[c]; k.i = ci[c]; k.j = cj[c]; }
+    else { k.level = 0; k.i = c % M.nx; k.j = c / M.nx; }
+    k.h = hc / ipow3(k.level);
+    k.x0 = M.x0 + k.i * k.h; k.z0 = M.z0 + k.j * k.h;
+  }
+  int F = ipow3(M.L), NXf = M.nx * F, NZf = M.nz * F;
+  std::vector<int> owner((size_t)NXf * NZf, -1);
+  for (int c = 0; c < C; ++c) {
+    const Cell& k = M.cells[c]; int sz = ipow3(M.L - k.level);
+    for (int a = 0; a < sz; ++a)
+      for (int b = 0; b < sz; ++b) {
+        int X = k.i * sz + a, Z = k.j * sz + b;
+        if (X < 0 || X >= NXf || Z < 0 || Z >= NZf || owner[(size_t)Z * NXf + X] != -1) { M.ok = false; continue; }
+        owner[(size_t)Z * NXf + X] = c;
+      }
+  }
+  for (size_t q = 0; q < owner.size(); ++q) if (owner[q] < 0) M.ok = false;
+  if (!M.ok) return M;
+  M.nbr.resize((size_t)C * 4);
+  for (int c = 0; c < C; ++c) {
+    const Cell& k = M.cells[c]; int sz = ipow3(M.L - k.level);
+    for (int f = 0; f < 4; ++f) {
+      Neighbor& nb = M.nbr[c * 4 + f];
+      nb.kind = 1; nb.k = 0; nb.nb[0] = nb.nb[1] = nb.nb[2] = -1;
+      // fine-unit cells just outside face f
+      std::vector<int> outs;
+      bool outside = false;
+      for (int t = 0; t < sz; ++t) {
+        int X, Z;
+        if (f == 0) { X = k.i * sz - 1; Z = k.j * sz + t; }
+        else if (f == 1) { X = (k.i + 1) * sz; Z = k.j * sz + t; }
+        else if (f == 2) { X = k.i * sz + t; Z = k.j * sz - 1; }
+        else { X = k.i * sz + t; Z = (k.j + 1) * sz; }
+        if (X < 0 || X >= NXf || Z < 0 || Z >= NZf) {
+          if (M.bc[f] != BC_PERIODIC) { outside = true; break; }
+          X = (X + NXf) % NXf; Z = (Z + NZf) % NZf;
+        }
+        int o = owner[(size_t)Z * NXf + X];
+        if (outs.empty() || outs.back() != o) outs.push_back(o);
+      }
+      if (outside) { nb.kind = 1; continue; }
+      if (outs.size() == 1) {
+        const Cell& o = M.cells[outs[0]];
+        if (o.level == k.level) { nb.kind = 0; nb.nb[0] = outs[0]; }
+        else if (o.level == k.level - 1) {
+          nb.kind = 2; nb.nb[0] = outs[0];
+          // sub-face index along the tangential direction
+          int tk = (f < 2) ? k.j : k.i, to = (f < 2) ? o.j : o.i;
+          nb.k = tk - 3 * to;
+          if (nb.k < 0 || nb.k > 2) M.ok = false;
+        } else M.ok = false;
+      } else if (outs.size() == 3) {
+        nb.kind = 3;
+        for (int s = 0; s < 3; ++s) {
+          nb.nb[s] = outs[s];
+          if (M.cells[outs[s]].level != k.level + 1) M.ok = false;
+        }
+      } else M.ok = false;
+    }
+  }
+  return M;
+}
+
+// ------------------------------------------------------------------ predictor
+// Element-local space-time predictor (ADER-DG, Dumbser et al. 2008), read as:
+// initial guess q^0 = Q^n at every time node; a fixed number of Picard sweeps
+//   q^{k+1}[a] = Q^n + dt sum_b P_ab R(q^k)[b],
+//   R = S - (1/h)(D_x F_x + D_z F_z)   (strong form, no face terms);
+// then F, S on the last iterate and their GL time averages.
+template <class T>
+struct CellPred {
+  std::vector<T> Qbar, Fbx, Fbz, Sbar;   // [4][n][n] each, time averages
+};
+
+template <class T>
+void residual_slice(const Params& P, const Basis& B, const Cell& c, const T* q /*[4][n][n]*/,
+                    double t, T* Fx, T* Fz, T* S, T* R /*nullable*/) {
+  const int n = P.n;
+  std::vector<T> gx(4 * n * n), gz(4 * n * n);
+  for (int v = 0; v < 4; ++v)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        T sx = 0.0, sz = 0.0;
+        for (int m = 0; m < n; ++m) {
+          sx += B.D[i * n + m] * q[(v * n + j) * n + m];
+          sz += B.D[j * n + m] * q[(v * n + m) * n + i];
+        }
+        gx[(v * n + j) * n + i] = sx / c.h;
+        gz[(v * n + j) * n + i] = sz / c.h;
+      }
+  for (int j = 0; j < n; ++j) {
+    double z = c.z0 + c.h * B.xi[j];
+    double rb, pb; background(P, z, rb, pb);
+    for (int i = 0; i < n; ++i) {
+      double x = c.x0 + c.h * B.xi[i];
+      T qq[4], a[4], b[4], fx[4], fz[4], s[4];
+      for (int v = 0; v < 4; ++v) {
+        int id = (v * n + j) * n + i;
+        qq[v] = q[id]; a[v] = gx[id]; b[v] = gz[id];
+      }
+      pointwise(P, qq, a, b, x, z, t, rb, pb, fx, fz, s);
+      for (int v = 0; v < 4; ++v) {
+        int id = (v * n + j) * n + i;
+        Fx[id] = fx[v]; Fz[id] = fz[v]; S[id] = s[v];
+      }
+    }
+  }
+  if (!R) return;
+  for (int v = 0; v < 4; ++v)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        T dx = 0.0, dz = 0.0;
+        for (int m = 0; m < n; ++m) {
+          dx += B.D[i * n + m] * Fx[(v * n + j) * n + m];
+          dz += B.D[j * n + m] * Fz[(v * n + m) * n + i];
+        }
+        int id = (v * n + j) * n + i;
+        R[id] = S[id] - (dx + dz) / c.h;
+      }
+}
+
+template <class T>
+void predictor_cell(const Params& P, const Basis& B, const Cell& c, const T* Qn,
+                    double tn, double dt, CellPred<T>& out) {
+  const int n = P.n, sl = 4 * n * n;
+  std::vector<T> q((size_t)n * sl), qn((size_t)n * sl), R((size_t)n * sl);
+  std::vector<T> Fx(sl), Fz(sl), S(sl);
+  for (int a = 0; a < n; ++a)
+    for (int k = 0; k < sl; ++k) q[(size_t)a * sl + k] = Qn[k];
+  for (int it = 0; it < P.iters; ++it) {
+    for (int b = 0; b < n; ++b)
+      residual_slice(P, B, c, &q[(size_t)b * sl], tn + B.xi[b] * dt, Fx.data(), Fz.data(), S.data(),
+                     &R[(size_t)b * sl]);
+    for (int a = 0; a < n; ++a)
+      for (int k = 0; k < sl; ++k) {
+        T acc = 0.0;
+        for (int b = 0; b < n; ++b) acc += B.P[a * n + b] * R[(size_t)b * sl + k];
+        qn[(size_t)a * sl + k] = Qn[k] + dt * acc;
+      }
+    std::swap(q, qn);
+  }
+  out.Qbar.assign(sl, T(0.0)); out.Fbx.assign(sl, T(0.0));
+  out.Fbz.assign(sl, T(0.0)); out.Sbar.assign(sl, T(0.0));
+  for (int a = 0; a < n; ++a) {
+    residual_slice(P, B, c, &q[(size_t)a * sl], tn + B.xi[a] * dt, Fx.data(), Fz.data(), S.data(),
+                   (T*)nullptr);
+    for (int k = 0; k < sl; ++k) {
+      out.Qbar[k] += B.w[a] * q[(size_t)a * sl + k];
+      out.Fbx[k] += B.w[a] * Fx[k];
+      out.Fbz[k] += B.w[a] * Fz[k];
+      out.Sbar[k] += B.w[a] * S[k];
+    }
+  }
+}
+
+// Volume integral of the time-averaged flux plus the averaged source (the
+// weak-form corrector without its face terms), GL collocation mass matrix:
+//   Q*_ji = Q^n_ji + dt[(1/h)((1/w_i) sum_m w_m D_mi Fx_jm + (1/w_j) sum_m w_m D_mj Fz_mi) + S_ji]
+template <class T>
+void volume_update(const Params& P, const Basis& B, const Cell& c, const T* Qn, const CellPred<T>& pr,
+                   double dt, T* Qs) {
+  const int n = P.n;
+  for (int v = 0; v < 4; ++v)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        T ax = 0.0, az = 0.0;
+        for (int m = 0; m < n; ++m) {
+          ax += B.w[m] * B.D[m * n + i] * pr.Fbx[(v * n + j) * n + m];
+          az += B.w[m] * B.D[m * n + j] * pr.Fbz[(v * n + m) * n + i];
+        }
+        int id = (v * n + j) * n + i;
+        Qs[id] = Qn[id] + dt * ((ax / B.w[i] + az / B.w[j]) / c.h + pr.Sbar[id]);
+      }
+}
+
+// Face data: the time-averaged state and normal flux (flux along the face's
+// axis, +axis direction) extrapolated to face f by the basis values at 0 or 1.
+template <class T>
+void face_data(const Params& P, const Basis& B, const CellPred<T>& pr, T* FD /*[4][2][4][n]*/) {
+  const int n = P.n;
+  for (int f = 0; f < 4; ++f)
+    for (int v = 0; v < 4; ++v)
+      for (int k = 0; k < n; ++k) {
+        const std::vector<double>& e = (f == 0 || f == 2) ? B.e0 : B.e1;
+        T sq = 0.0, sf = 0.0;
+        for (int m = 0; m < n; ++m) {
+          int id = (f < 2) ? (v * n + k) * n + m : (v * n + m) * n + k;
+          sq += e[m] * pr.Qbar[id];
+          sf += e[m] * ((f < 2) ? pr.Fbx[id] : pr.Fbz[id]);
+        }
+        FD[((f * 2 + 0) * 4 + v) * n + k] = sq;
+        FD[((f * 2 + 1) * 4 + v) * n + k] = sf;
+      }
+}
+
+// ---------------------------------------------------------------- face flux
+// Rusanov-type flux with a viscous penalty (Gassner et al. 2008, used in
+// ADER-DG by Dumbser 2010 / Fambri 2017), read as
+//   G = 1/2 (Fn_L + Fn_R) - 1/2 s (Q_R - Q_L),
+//   s = max_nodes(|v_d| + c) + 2 eta max_nodes(lambda_v), eta = (2N+1)/(h sqrt(pi/2)),
+// maxima over the face nodes of both sides; L is the lower-coordinate side.
+template <class T>
+void rusanov(const Params& P, int d, double h, const double* zf /*[n]*/, const T* QL, const T* FL,
+             const T* QR, const T* FR, T* G /*[4][n]*/) {
+  const int n = P.n;
+  const double PI = 3.14159265358979323846;
+  T lam = 0.0, lv = 0.0; bool first = true;
+  for (int side = 0; side < 2; ++side) {
+    const T* Q = side ? QR : QL;
+    for (int k = 0; k < n; ++k) {
+      T q[4] = {Q[0 * n + k], Q[1 * n + k], Q[2 * n + k], Q[3 * n + k]};
+      T p = pressure(P, q, zf[k]);
+      T c = sqrt(P.gamma * p / q[0]);
+      T vn = q[1 + d] / q[0];
+      T l = fabs(vn) + c;
+      T lvk = lambda_visc(P, q[0]);
+      if (first || val(l) > val(lam)) lam = l;
+      if (first || val(lvk) > val(lv)) lv = lvk;
+      first = false;
+    }
+  }
+  double eta = (2.0 * P.N + 1.0) / (h * std::sqrt(PI / 2.0));
+  T s = lam + 2.0 * eta * lv;
+  for (int v = 0; v < 4; ++v)
+    for (int k = 0; k < n; ++k)
+      G[v * n + k] = 0.5 * (FL[v * n + k] + FR[v * n + k]) - 0.5 * s * (QR[v * n + k] - QL[v * n + k]);
+}
+
+// Ghost data at a no-slip wall (paper: background density and energy at the
+// boundary, background heat flux imposed): velocity mirrored, density and
+// pressure from the background (from the interior state without gravity),
+// mass flux mirrored, momentum flux copied, energy flux 2 q_bg - F.
+template <class T>
+void wall_ghost(const Params& P, int d, const double* zf, const T* Qi, const T* Fi, T* Qg, T* Fg) {
+  const int n = P.n;
+  for (int k = 0; k < n; ++k) {
+    T q[4] = {Qi[0 * n + k], Qi[1 * n + k], Qi[2 * n + k], Qi[3 * n + k]};
+    T u = q[1] / q[0], w = q[2] / q[0];
+    T rb, pb;
+    if (P.gravity) { double r, p; background(P, zf[k], r, p); rb = r; pb = p; }
+    else { rb = q[0]; pb = pressure(P, q, zf[k]); }
+    T geo = P.gravity ? rb * (P.g * zf[k]) : T(0.0);
+    Qg[0 * n + k] = rb;
+    Qg[1 * n + k] = -(rb * u);
+    Qg[2 * n + k] = -(rb * w);
+    Qg[3 * n + k] = pb / (P.gamma - 1.0) + 0.5 * rb * (u * u + w * w) + geo;
+    double qbg = (P.gravity && d == 1) ? P.kappa * P.g / P.cp : 0.0;
+    Fg[0 * n + k] = -Fi[0 * n + k];
+    Fg[1 * n + k] = Fi[1 * n + k];
+    Fg[2 * n + k] = Fi[2 * n + k];
+    Fg[3 * n + k] = 2.0 * qbg - Fi[3 * n + k];
+  }
+}
+
+// z coordinates of the nodes of face f of cell c (fine sub-face: own nodes)
+void face_z(const Basis& B, const Cell& c, int f, double* zf) {
+  for (int k = 0; k < B.n; ++k) {
+    if (f < 2) zf[k] = c.z0 + c.h * B.xi[k];
+    else zf[k] = c.z0 + (f == 3 ? c.h : 0.0);
+  }
+}
+
+// Numerical flux on face f of cell c, at c's own face nodes.
+template <class T>
+void face_flux(const Params& P, const Basis& B, const Mesh& M, int c, int f,
+               const std::vector<T>& FD /*[C][4][2][4][n]*/, T* G /*[4][n]*/) {
+  const int n = P.n, fs = 2 * 4 * n;   // per-face stride
+  const int d = f / 2;
+  const bool lower = (f == 0 || f == 2);   // face on the lower side: c is the R side
+  const Cell& cc = M.cells[c];
+  const Neighbor& nb = M.nbr[c * 4 + f];
+  const int opp = f ^ 1;
+  const T* Qm = &FD[((size_t)c * 4 + f) * fs];
+  const T* Fm = Qm + 4 * n;
+  double zf[16]; face_z(B, cc, f, zf);
+  std::vector<T> Qo(4 * n), Fo(4 * n);
+  if (nb.kind == 0) {
+    const T* Qx = &FD[((size_t)nb.nb[0] * 4 + opp) * fs];
+    for (int k = 0; k < 4 * n; ++k) { Qo[k] = Qx[k]; Fo[k] = Qx[4 * n + k]; }
+  } else if (nb.kind == 1) {
+    wall_ghost(P, d, zf, Qm, Fm, Qo.data(), Fo.data());
+  } else if (nb.kind == 2) {
+    // coarse neighbour: prolong its face polynomial to sub-face k
+    const T* Qx = &FD[((size_t)nb.nb[0] * 4 + opp) * fs];
+    for (int v = 0; v < 4; ++v)
+      for (int q = 0; q < n; ++q) {
+        T sq = 0.0, sf = 0.0;
+        for (int m = 0; m < n; ++m) {
+          double ph = phi_at(B, m, (nb.k + B.xi[q]) / 3.0);
+          sq += ph * Qx[v * n + m]; sf += ph * Qx[4 * n + v * n + m];
+        }
+        Qo[v * n + q] = sq; Fo[v * n + q] = sf;
+      }
+  } else {
+    // coarse cell: three fine sub-faces; prolong own data, solve, restrict
+    std::vector<T> Gc(4 * n, T(0.0));
+    for (int s = 0; s < 3; ++s) {
+      const int fc = nb.nb[s];
+      const Cell& fcell = M.cells[fc];
+      const T* Qx = &FD[((size_t)fc * 4 + opp) * fs];
+      std::vector<T> Qp(4 * n), Fp(4 * n), Gk(4 * n);
+      for (int v = 0; v < 4; ++v)
+        for (int q = 0; q < n; ++q) {
+          T sq = 0.0, sf = 0.0;
+          for (int m = 0; m < n; ++m) {
+            double ph = phi_at(B, m, (s + B.xi[q]) / 3.0);
+            sq += ph * Qm[v * n + m]; sf += ph * Fm[v * n + m];
+          }
+          Qp[v * n + q] = sq; Fp[v * n + q] = sf;
+        }
+      double zs[16]; face_z(B, fcell, opp, zs);
+      if (lower) rusanov(P, d, fcell.h, zs, Qx, Qx + 4 * n, Qp.data(), Fp.data(), Gk.data());
+      else rusanov(P, d, fcell.h, zs, Qp.data(), Fp.data(), Qx, Qx + 4 * n, Gk.data());
+      // L2 restriction to the coarse face: G_C[m] = (1/w_m) sum_q (w_q/3) phi_m((s+xi_q)/3) G_s[q]
+      for (int v = 0; v < 4; ++v)
+        for (int m = 0; m < n; ++m) {
+          T acc = 0.0;
+          for (int q = 0; q < n; ++q)
+            acc += (B.w[q] / 3.0) * phi_at(B, m, (s + B.xi[q]) / 3.0) * Gk[v * n + q];
+          Gc[v * n + m] += acc / B.w[m];
+        }
+    }
+    for (int k = 0; k < 4 * n; ++k) G[k] = Gc[k];
+    return;
+  }
+  if (lower) rusanov(P, d, cc.h, zf, Qo.data(), Fo.data(), Qm, Fm, G);
+  else rusanov(P, d, cc.h, zf, Qm, Fm, Qo.data(), Fo.data(), G);
+}
+
+// Surface part of the corrector (GL collocation mass matrix):
+//   Q^{n+1}_ji = Q*_ji - (dt/h)[(e1_i G1_j - e0_i G0_j)/w_i + (e1_j G3_i - e0_j G2_i)/w_j]
+template <class T>
+void lift(const Params& P, const Basis& B, const Cell& c, double dt, const T* G /*[4][4][n]*/, T* Q) {
+  const int n = P.n;
+  for (int v = 0; v < 4; ++v)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        T sx = (B.e1[i] * G[(1 * 4 + v) * n + j] - B.e0[i] * G[(0 * 4 + v) * n + j]) / B.w[i];
+        T sz = (B.e1[j] * G[(3 * 4 + v) * n + i] - B.e0[j] * G[(2 * 4 + v) * n + i]) / B.w[j];
+        Q[(v * n + j) * n + i] = Q[(v * n + j) * n + i] - (dt / c.h) * (sx + sz);
+      }
+}
+
+// One full step: predictor on every cell, face fluxes, corrector.
+template <class T>
+void step(const Params& P, const Basis& B, const Mesh& M, const T* Q, double t, double dt, T* Qout,
+          T* Qstar_out, T* FD_out) {
+  const int C = (int)M.cells.size(), n = P.n, sl = 4 * n * n, fsz = 4 * 2 * 4 * n;
+  std::vector<T> Qs((size_t)C * sl), FD((size_t)C * fsz);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int c = 0; c < C; ++c) {
+    CellPred<T> pr;
+    predictor_cell(P, B, M.cells[c], Q + (size_t)c * sl, t, dt, pr);
+    volume_update(P, B, M.cells[c], Q + (size_t)c * sl, pr, dt, &Qs[(size_t)c * sl]);
+    face_data(P, B, pr, &FD[(size_t)c * fsz]);
+  }
+  if (Qstar_out) for (size_t k = 0; k < Qs.size(); ++k) Qstar_out[k] = Qs[k];
+  if (FD_out) for (size_t k = 0; k < FD.size(); ++k) FD_out[k] = FD[k];
+  if (!Qout) return;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int c = 0; c < C; ++c) {
+    std::vector<T> G(4 * 4 * n);
+    for (int f = 0; f < 4; ++f) face_flux(P, B, M, c, f, FD, &G[(size_t)f * 4 * n]);
+    for (int k = 0; k < sl; ++k) Qout[(size_t)c * sl + k] = Qs[(size_t)c * sl + k];
+    lift(P, B, M.cells[c], dt, G.data(), Qout + (size_t)c * sl);
+  }
+}
+
+// ---------------------------------------------------------------------- CFL
+// dt = cfl * min_cells h / (d (2N+1) (lambda + 2 lambda_v (2N+1)/h)), d = 2,
+// lambda = max over nodes of max(|u|,|w|) + c, lambda_v as in the face flux.
+double compute_dt(const Params& P, const Basis& B, const Mesh& M, const double* Q) {
+  const int n = P.n, sl = 4 * n * n;
+  double dt = 1e300;
+  for (size_t c = 0; c < M.cells.size(); ++c) {
+    const Cell& cc = M.cells[c];
+    double lam = 0.0, lv = 0.0;
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        double q[4];
+        for (int v = 0; v < 4; ++v) q[v] = Q[c * sl + (v * n + j) * n + i];
+        double z = cc.z0 + cc.h * B.xi[j];
+        double p = pressure(P, q, z);
+        double cs = std::sqrt(P.gamma * p / q[0]);
+        double l = std::max(std::fabs(q[1] / q[0]), std::fabs(q[2] / q[0])) + cs;
+        lam = std::max(lam, l);
+        lv = std::max(lv, lambda_visc(P, q[0]));
+      }
+    double o = 2.0 * P.N + 1.0;
+    double dtc = P.cfl * cc.h / (2.0 * o * (lam + 2.0 * lv * o / cc.h));
+    dt = std::min(dt, dtc);
+  }
+  return dt;
+}
+
+// ------------------------------------------------------------- TV indicator
+// Potential temperature theta = T (p0/p)^(R/cp) (paper, stratified flows).
+template <class T>
+T theta_of(const Params& P, const T q[4], double z) {
+  T p = pressure(P, q, z);
+  T Tm = p / (q[0] * P.R);
+  return Tm * pow(P.p0 / p, P.R / P.cp);
+}
+
+// TV of f over a cell (paper eq. tv): integral of the l1 norm of grad f,
+// by GL quadrature on the collocated nodes, derivatives by D on the cell:
+//   TV = h sum_ji w_i w_j (|sum_m D_im f_jm| + |sum_m D_jm f_mi|)
+template <class T>
+T cell_tv(const Params& P, const Basis& B, const Cell& c, const T* Qc, int var) {
+  const int n = P.n;
+  std::vector<T> f(n * n);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      T q[4];
+      for (int v = 0; v < 4; ++v) q[v] = Qc[(v * n + j) * n + i];
+      f[j * n + i] = (var == 0) ? theta_of(P, q, c.z0 + c.h * B.xi[j]) : q[0];
+    }
+  T tv = 0.0;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      T dx = 0.0, dz = 0.0;
+      for (int m = 0; m < n; ++m) {
+        dx += B.D[i * n + m] * f[j * n + m];
+        dz += B.D[j * n + m] * f[m * n + i];
+      }
+      tv += B.w[i] * B.w[j] * (fabs(dx) + fabs(dz));
+    }
+  return c.h * tv;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+int oracle_set_threads(int nt) {
+#ifdef _OPENMP
+  if (nt > 0) omp_set_num_threads(nt);
+  return omp_get_max_threads();
+#else
+  (void)nt; return 1;
+#endif
+}
+
+int oracle_param_count(void) { return P_COUNT; }
+
+int oracle_basis(int N, double* xi, double* w, double* D, double* e0, double* e1, double* P) {
+  if (N < 0 || N > 15) return -1;
+  Basis B = make_basis(N);
+  int n = N + 1;
+  for (int k = 0; k < n; ++k) { xi[k] = B.xi[k]; w[k] = B.w[k]; e0[k] = B.e0[k]; e1[k] = B.e1[k]; }
+  for (int k = 0; k < n * n; ++k) { D[k] = B.D[k]; P[k] = B.P[k]; }
+  return 0;
+}
+
+int oracle_lagrange(int N, int j, double x, double* out) {
+  Basis B = make_basis(N);
+  *out = phi_at(B, j, x);
+  return 0;
+}
+
+int oracle_background(const double* prm, double z, double* rho_b, double* p_b) {
+  Params P = read_params(prm);
+  background(P, z, *rho_b, *p_b);
+  return 0;
+}
+
+int oracle_pointwise(const double* prm, const double* q, const double* gx, const double* gz,
+                     double x, double z, double t, double* Fx, double* Fz, double* S) {
+  Params P = read_params(prm);
+  double rb, pb; background(P, z, rb, pb);
+  pointwise(P, q, gx, gz, x, z, t, rb, pb, Fx, Fz, S);
+  return 0;
+}
+
+int oracle_mesh_check(const int* mi, const double* md, const int* lev, const int* ci, const int* cj,
+                      int* kinds /*[C][4] or NULL*/) {
+  Mesh M = build_mesh(mi, md, lev, ci, cj);
+  if (!M.ok) return -1;
+  if (kinds)
+    for (size_t k = 0; k < M.nbr.size(); ++k) kinds[k] = M.nbr[k].kind;
+  return 0;
+}
+
+// Predictor outputs: Q* [C][4][n][n] and face data [C][4][2][4][n].
+int oracle_predictor(const double* prm, const int* mi, const double* md, const int* lev, const int* ci,
+                     const int* cj, const double* Q, double t, double dt, double* Qstar, double* FD) {
+  Params P = read_params(prm);
+  Basis B = make_basis(P.N);
+  Mesh M = build_mesh(mi, md, lev, ci, cj);
+  if (!M.ok) return -1;
+  step<double>(P, B, M, Q, t, dt, nullptr, Qstar, FD);
+  return 0;
+}
+
+int oracle_step(const double* prm, const int* mi, const double* md, const int* lev, const int* ci,
+                const int* cj, const double* Q, double t, double dt, double* Qout) {
+  Params P = read_params(prm);
+  Basis B = make_basis(P.N);
+  Mesh M = build_mesh(mi, md, lev, ci, cj);
+  if (!M.ok) return -1;
+  step<double>(P, B, M, Q, t, dt, Qout, nullptr, nullptr);
+  return 0;
+}
+
+// nsteps steps in place; dt fixed if dt > 0 else recomputed by the CFL rule
+// before every step.  t is advanced.
+int oracle_run(const double* prm, const int* mi, const double* md, const int* lev, const int* ci,
+               const int* cj, double* Q, double* t, double dt, int nsteps) {
+  Params P = read_params(prm);
+  Basis B = make_basis(P.N);
+  Mesh M = build_mesh(mi, md, lev, ci, cj);
+  if (!M.ok) return -1;
+  size_t tot = M.cells.size() * 4 * P.n * P.n;
+  std::vector<double> Qn(tot);
+  for (int s = 0; s < nsteps; ++s) {
+    double h = dt > 0 ? dt : compute_dt(P, B, M, Q);
+    step<double>(P, B, M, Q, *t, h, Qn.data(), nullptr, nullptr);
+    std::memcpy(Q, Qn.data(), tot * sizeof(double));
+    *t += h;
+  }
+  return 0;
+}
+
+int oracle_dt(const double* prm, const int* mi, const double* md, const int* lev, const int* ci,
+              const int* cj, const double* Q, double* dt) {
+  Params P = read_params(prm);
+  Basis B = make_basis(P.N);
+  Mesh M = build_mesh(mi, md, lev, ci, cj);
+  if (!M.ok) return -1;
+  *dt = compute_dt(P, B, M, Q);
+  return 0;
+}
+
+// TV per cell, mean/std over cells merged pairwise with the update formulas of
+// Chan, Golub & LeVeque (paper, refinement criterion), and flags
+//   +1 refine if TV >= mu + Tr sigma, -1 coarsen if TV < mu + Tc sigma, else 0;
+// sigma == 0 keeps every cell.  stats = (count, mean, population sigma).
+int oracle_tv(const double* prm, const int* mi, const double* md, const int* lev, const int* ci,
+              const int* cj, const double* Q, int var, double Tr, double Tc, double* tv,
+              int8_t* flags, double* stats) {
+  Params P = read_params(prm);
+  Basis B = make_basis(P.N);
+  Mesh M = build_mesh(mi, md, lev, ci, cj);
+  if (!M.ok) return -1;
+  const int C = (int)M.cells.size(), sl = 4 * P.n * P.n;
+  for (int c = 0; c < C; ++c) tv[c] = cell_tv(P, B, M.cells[c], Q + (size_t)c * sl, var);
+  // Chan et al. pairwise merge: singletons (1, x, 0) merged bottom-up in a
+  // balanced binary tree over the cell order.
+  std::vector<double> cn(C), mu(C), m2(C);
+  for (int c = 0; c < C; ++c) { cn[c] = 1.0; mu[c] = tv[c]; m2[c] = 0.0; }
+  for (int width = 1; width < C; width *= 2)
+    for (int a = 0; a + width < C; a += 2 * width) {
+      int b = a + width;
+      double n = cn[a] + cn[b], delta = mu[b] - mu[a];
+      double m = mu[a] + delta * cn[b] / n;
+      double M2 = m2[a] + m2[b] + delta * delta * cn[a] * cn[b] / n;
+      cn[a] = n; mu[a] = m; m2[a] = M2;
+    }
+  double mean = C ? mu[0] : 0.0, sigma = C ? std::sqrt(m2[0] / cn[0]) : 0.0;
+  stats[0] = C; stats[1] = mean; stats[2] = sigma;
+  for (int c = 0; c < C; ++c) {
+    if (sigma == 0.0) { flags[c] = 0; continue; }
+    if (tv[c] >= mean + Tr * sigma) flags[c] = 1;
+    else if (tv[c] < mean + Tc * sigma) flags[c] = -1;
+    else flags[c] = 0;
+  }
+  return 0;
+}
+
+// Initial conditions by nodal interpolation.
+// kind 0: hydrostatic background of constant potential temperature perturbed
+//   by bubbles; bubbles[b] = (shape, A, a, s, xc, zc), shape 0 = cosine
+//   theta' = A/2 (1 + cos(pi r / a)) for r <= a, shape 1 = A for r <= a and
+//   A exp(-(r-a)^2/s^2) beyond; theta' of several bubbles add; the pressure
+//   stays the background one, rho = p/(R T), T = theta * Exner, at rest.
+// kind 1: the advected density wave of the manufactured solution at time t0.
+int oracle_ic(const double* prm, const int* mi, const double* md, const int* lev, const int* ci,
+              const int* cj, int kind, int nb, const double* bubbles, double t0, double* Q) {
+  Params P = read_params(prm);
+  Basis B = make_basis(P.N);
+  Mesh M = build_mesh(mi, md, lev, ci, cj);
+  if (!M.ok) return -1;
+  const int n = P.n, sl = 4 * n * n;
+  const double PI = 3.14159265358979323846;
+  for (size_t c = 0; c < M.cells.size(); ++c) {
+    const Cell& cc = M.cells[c];
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        double x = cc.x0 + cc.h * B.xi[i], z = cc.z0 + cc.h * B.xi[j];
+        double q[4];
+        if (kind == 1) {
+          double X = x - P.mms_u * t0, Z = z - P.mms_w * t0;
+          double rho = 1.0 + P.mms_amp * std::sin(P.mms_kx * X) * std::sin(P.mms_kz * Z);
+          q[0] = rho; q[1] = rho * P.mms_u; q[2] = rho * P.mms_w;
+          q[3] = P.mms_p / (P.gamma - 1.0) + 0.5 * rho * (P.mms_u * P.mms_u + P.mms_w * P.mms_w);
+        } else {
+          double th = 0.0;
+          for (int b = 0; b < nb; ++b) {
+            const double* bb = bubbles + 6 * b;
+            double r = std::sqrt((x - bb[4]) * (x - bb[4]) + (z - bb[5]) * (z - bb[5]));
+            if ((int)bb[0] == 0) { if (r <= bb[2]) th += 0.5 * bb[1] * (1.0 + std::cos(PI * r / bb[2])); }
+            else th += (r <= bb[2]) ? bb[1] : bb[1] * std::exp(-(r - bb[2]) * (r - bb[2]) / (bb[3] * bb[3]));
+          }
+          double pi = 1.0 - P.g * z / (P.cp * P.theta_bg);
+          double pb = P.p0 * std::pow(pi, P.cp / P.R);
+          double T = (P.theta_bg + th) * pi;
+          double rho = pb / (P.R * T);
+          q[0] = rho; q[1] = 0.0; q[2] = 0.0;
+          q[3] = pb / (P.gamma - 1.0) + rho * P.g * z;
+        }
+        for (int v = 0; v < 4; ++v) Q[c * sl + (v * n + j) * n + i] = q[v];
+      }
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,217 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (``adg_oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  The product path
+(``paper_1905_05524_amd``) never imports it and has no CPU fallback.
+
+Inputs are described by plain dicts from ``paper_1905_05524_amd.inputs``
+(physical constants, mesh description, bubble list); this module turns them
+into the oracle's own flat arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "adg_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# indices of the flat parameter vector (same order as the enum in the source)
+P_NAMES = ["N", "picard_iters", "gamma", "Pr", "R", "cp", "mu", "g", "p0", "theta_bg",
+           "gravity", "mms", "mms_amp", "mms_u", "mms_w", "mms_kx", "mms_kz", "mms_p", "cfl"]
+
+BC_PERIODIC, BC_WALL = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (-O2, no FP contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-shared", "-fPIC", "-o", _LIB, _SRC]
+        subprocess.run(cmd, check=True)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        i8p = ctypes.POINTER(ctypes.c_int8)
+        for name in ["oracle_basis"]:
+            getattr(L, name).argtypes = [ctypes.c_int, dp, dp, dp, dp, dp, dp]
+        L.oracle_lagrange.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp]
+        L.oracle_background.argtypes = [dp, ctypes.c_double, dp, dp]
+        L.oracle_pointwise.argtypes = [dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, dp, dp, dp]
+        mesh = [ip, dp, ip, ip, ip]
+        L.oracle_mesh_check.argtypes = mesh + [ip]
+        L.oracle_predictor.argtypes = [dp] + mesh + [dp, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.oracle_step.argtypes = [dp] + mesh + [dp, ctypes.c_double, ctypes.c_double, dp]
+        L.oracle_run.argtypes = [dp] + mesh + [dp, dp, ctypes.c_double, ctypes.c_int]
+        L.oracle_dt.argtypes = [dp] + mesh + [dp, dp]
+        L.oracle_tv.argtypes = [dp] + mesh + [dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                              dp, i8p, dp]
+        L.oracle_ic.argtypes = [dp] + mesh + [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, dp]
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def set_threads(nt: int) -> int:
+    return lib().oracle_set_threads(int(nt))
+
+
+# --------------------------------------------------------------------- inputs
+def params(phys: dict) -> np.ndarray:
+    p = np.zeros(len(P_NAMES), dtype=np.float64)
+    for k, name in enumerate(P_NAMES):
+        v = phys.get(name, 0.0)
+        p[k] = float(v)
+    return p
+
+
+class _Mesh:
+    """The oracle's own flat mesh arrays built from a mesh dict."""
+
+    def __init__(self, mesh: dict):
+        leaves = mesh.get("leaves")
+        self.C = len(leaves) if leaves is not None else mesh["nx"] * mesh["nz"]
+        bc = mesh.get("bc", [BC_WALL] * 4)
+        self.mi = np.array([mesh["nx"], mesh["nz"], mesh.get("max_level", 0), bc[0], bc[1], bc[2],
+                            bc[3], self.C], dtype=np.int32)
+        self.md = np.array([mesh.get("x0", 0.0), mesh.get("z0", 0.0), mesh["Lx"], mesh["Lz"]],
+                           dtype=np.float64)
+        if leaves is not None:
+            lv = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 3))
+            self.lev = np.ascontiguousarray(lv[:, 0])
+            self.ci = np.ascontiguousarray(lv[:, 1])
+            self.cj = np.ascontiguousarray(lv[:, 2])
+            self.args = (_ip(self.mi), _dp(self.md), _ip(self.lev), _ip(self.ci), _ip(self.cj))
+        else:
+            self.args = (_ip(self.mi), _dp(self.md), None, None, None)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed (rc={rc})")
+
+
+# ------------------------------------------------------------------ functions
+def basis(N: int):
+    n = N + 1
+    xi, w, e0, e1 = (np.zeros(n) for _ in range(4))
+    D, P = np.zeros((n, n)), np.zeros((n, n))
+    _check(lib().oracle_basis(N, _dp(xi), _dp(w), _dp(D), _dp(e0), _dp(e1), _dp(P)), "basis")
+    return dict(xi=xi, w=w, D=D, e0=e0, e1=e1, P=P)
+
+
+def lagrange(N: int, j: int, x: float) -> float:
+    out = np.zeros(1)
+    lib().oracle_lagrange(N, j, float(x), _dp(out))
+    return float(out[0])
+
+
+def background(phys: dict, z: float):
+    p = params(phys)
+    r, pb = np.zeros(1), np.zeros(1)
+    lib().oracle_background(_dp(p), float(z), _dp(r), _dp(pb))
+    return float(r[0]), float(pb[0])
+
+
+def pointwise(phys: dict, q, gx, gz, x, z, t=0.0):
+    p = params(phys)
+    q, gx, gz = (np.ascontiguousarray(a, dtype=np.float64) for a in (q, gx, gz))
+    Fx, Fz, S = np.zeros(4), np.zeros(4), np.zeros(4)
+    lib().oracle_pointwise(_dp(p), _dp(q), _dp(gx), _dp(gz), float(x), float(z), float(t),
+                           _dp(Fx), _dp(Fz), _dp(S))
+    return Fx, Fz, S
+
+
+def mesh_kinds(mesh: dict):
+    m = _Mesh(mesh)
+    kinds = np.zeros((m.C, 4), dtype=np.int32)
+    _check(lib().oracle_mesh_check(*m.args, _ip(kinds)), "mesh")
+    return kinds
+
+
+def predictor(phys: dict, mesh: dict, Q: np.ndarray, t: float, dt: float):
+    """Returns (Q*, face data): Q* [C,4,n,n], face data [C,4 faces,2,4,n]."""
+    p, m = params(phys), _Mesh(mesh)
+    n = int(phys["N"]) + 1
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    Qs = np.zeros((m.C, 4, n, n))
+    FD = np.zeros((m.C, 4, 2, 4, n))
+    _check(lib().oracle_predictor(_dp(p), *m.args, _dp(Q), float(t), float(dt), _dp(Qs), _dp(FD)),
+           "predictor")
+    return Qs, FD
+
+
+def step(phys: dict, mesh: dict, Q: np.ndarray, t: float, dt: float) -> np.ndarray:
+    p, m = params(phys), _Mesh(mesh)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    out = np.zeros_like(Q)
+    _check(lib().oracle_step(_dp(p), *m.args, _dp(Q), float(t), float(dt), _dp(out)), "step")
+    return out
+
+
+def run(phys: dict, mesh: dict, Q: np.ndarray, t: float, nsteps: int, dt: float = 0.0):
+    """nsteps steps; dt > 0 fixed, else the CFL rule before each step.
+    Returns (Q, t)."""
+    p, m = params(phys), _Mesh(mesh)
+    Q = np.array(Q, dtype=np.float64, copy=True, order="C")
+    tt = np.array([t], dtype=np.float64)
+    _check(lib().oracle_run(_dp(p), *m.args, _dp(Q), _dp(tt), float(dt), int(nsteps)), "run")
+    return Q, float(tt[0])
+
+
+def dt(phys: dict, mesh: dict, Q: np.ndarray) -> float:
+    p, m = params(phys), _Mesh(mesh)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    out = np.zeros(1)
+    _check(lib().oracle_dt(_dp(p), *m.args, _dp(Q), _dp(out)), "dt")
+    return float(out[0])
+
+
+VAR_THETA, VAR_RHO = 0, 1
+
+
+def tv(phys: dict, mesh: dict, Q: np.ndarray, var: int, Tr: float, Tc: float):
+    """Returns (tv [C], flags [C] int8, stats (count, mean, sigma))."""
+    p, m = params(phys), _Mesh(mesh)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    tvv = np.zeros(m.C)
+    fl = np.zeros(m.C, dtype=np.int8)
+    st = np.zeros(3)
+    _check(lib().oracle_tv(_dp(p), *m.args, _dp(Q), int(var), float(Tr), float(Tc), _dp(tvv),
+                           fl.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), _dp(st)), "tv")
+    return tvv, fl, st
+
+
+def ic(phys: dict, mesh: dict, kind: str = "bubbles", bubbles=(), t0: float = 0.0) -> np.ndarray:
+    """Initial state by nodal interpolation; kind 'bubbles' or 'mms'."""
+    p, m = params(phys), _Mesh(mesh)
+    n = int(phys["N"]) + 1
+    Q = np.zeros((m.C, 4, n, n))
+    bb = np.ascontiguousarray(np.asarray(bubbles, dtype=np.float64).reshape(-1, 6))
+    k = 1 if kind == "mms" else 0
+    _check(lib().oracle_ic(_dp(p), *m.args, k, bb.shape[0], _dp(bb), float(t0), _dp(Q)), "ic")
+    return Q

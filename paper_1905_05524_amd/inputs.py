@@ -1,0 +1,128 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke check.
+
+This module holds workload descriptions and random draws only: physical
+constants, mesh sizes, bubble lists, scenario draws and random perturbations.
+It contains none of the method's arithmetic (no equation of state, no flux, no
+quadrature); each side (GPU library, oracle) builds its states from these
+descriptions with its own code.
+
+Workloads follow the paper's scenarios (Krenz, Rannabauer, Bader 2019):
+  * ``mms_small``   periodic unit square 9x9, N=2, advected density wave with
+                    its manufactured heat-flux source (CFD constants gamma=1.4,
+                    Pr=0.7, c_v=1 of the convergence section)
+  * ``bubble81``    2D cosine warm bubble (stratified-flow section) on 81x81
+                    cells of 12.35 m, N=6, no-slip walls
+  * ``amr27``       the same box on 27x27 coarse cells with one 3-way
+                    refinement level and a second, cold Gaussian bubble
+  * ``bubble27``    81x81's box on 27x27 cells (adjoint workload)
+  * ``batch64``     64 random bubble scenarios (grids 9..81, N in 3..6)
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+BC_PERIODIC, BC_WALL = 0, 1
+SHAPE_COSINE, SHAPE_PLATEAU_GAUSS = 0, 1
+
+# physical constants --------------------------------------------------------
+# CFD scenarios: gamma = 1.4, Pr = 0.7, c_v = 1 -> R = c_p - c_v = 0.4
+CFD = dict(gamma=1.4, Pr=0.7, R=0.4, cp=1.4, p0=1.0, theta_bg=1.0, g=0.0, gravity=0)
+# atmosphere: gamma, Pr and p0 of the stratified-flow section; g, R, c_p and
+# the background potential temperature of the bubble workloads
+ATMO = dict(gamma=1.4, Pr=0.71, R=287.0, cp=1005.0, p0=1.0e5, theta_bg=300.0, g=9.81, gravity=1)
+
+
+def mms_small(N: int = 2, nx: int = 9, mu: float = 0.01):
+    phys = dict(CFD, N=N, picard_iters=0, mu=mu, mms=1, mms_amp=0.1, mms_u=0.5, mms_w=0.5,
+                mms_kx=2.0 * math.pi, mms_kz=2.0 * math.pi, mms_p=1.0, cfl=0.5)
+    mesh = dict(nx=nx, nz=nx, max_level=0, x0=0.0, z0=0.0, Lx=1.0, Lz=1.0, bc=[BC_PERIODIC] * 4)
+    return dict(name=f"mms{nx}x{nx}_N{N}", phys=phys, mesh=mesh, ic="mms", bubbles=[], steps=10)
+
+
+def cosine_bubble(A=0.5, a=250.0, xc=500.0, zc=350.0):
+    return (SHAPE_COSINE, A, a, 0.0, xc, zc)
+
+
+def cold_bubble(A=-0.15, a=0.0, s=50.0, xc=560.0, zc=640.0):
+    return (SHAPE_PLATEAU_GAUSS, A, a, s, xc, zc)
+
+
+def bubble(nx: int = 81, N: int = 6, mu: float = 1e-3, bubbles=None, steps: int = 100):
+    phys = dict(ATMO, N=N, picard_iters=0, mu=mu, mms=0, cfl=0.5)
+    mesh = dict(nx=nx, nz=nx, max_level=0, x0=0.0, z0=0.0, Lx=1000.0, Lz=1000.0,
+                bc=[BC_WALL] * 4)
+    bl = [cosine_bubble()] if bubbles is None else list(bubbles)
+    return dict(name=f"bubble{nx}x{nx}_N{N}", phys=phys, mesh=mesh, ic="bubbles", bubbles=bl,
+                steps=steps)
+
+
+def bubble81():
+    return bubble(81, 6)
+
+
+def bubble27():
+    return bubble(27, 6, steps=50)
+
+
+def amr27():
+    w = bubble(27, 6, bubbles=[cosine_bubble(), cold_bubble()], steps=200)
+    w["mesh"]["max_level"] = 1
+    w["name"] = "amr27x27_L1_N6"
+    return w
+
+
+def uniform_leaves(nx: int, nz: int, level: int = 0):
+    """Leaf list (level, i, j) of a uniform grid in cell order c = j*nx + i."""
+    return [(level, i, j) for j in range(nz) for i in range(nx)]
+
+
+def batch_scenarios(count: int = 64, seed: int = 190505524):
+    """Random bubble scenarios: k x k grid on the 1000 m box, k in 9..81,
+    N in {3,4,5,6}, cosine bubble centre in [300,700]x[250,450] m, amplitude
+    in [0.2,1.0] K; everything else as the 81x81 bubble."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(count):
+        k = int(rng.integers(9, 82))
+        N = int(rng.integers(3, 7))
+        xc = float(rng.uniform(300.0, 700.0))
+        zc = float(rng.uniform(250.0, 450.0))
+        A = float(rng.uniform(0.2, 1.0))
+        w = bubble(k, N, bubbles=[cosine_bubble(A=A, xc=xc, zc=zc)])
+        w["name"] = f"scen{s}_{k}x{k}_N{N}"
+        out.append(w)
+    return out
+
+
+def fd_directions(count: int, size: int, seed: int = 4):
+    """Unit-norm Gaussian directions for finite-difference checks."""
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((count, size))
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+def random_state_cfd(C: int, N: int, seed: int):
+    """Random conserved state in CFD units with a safely positive pressure:
+    rho in [0.8,1.2], momenta in [-0.3,0.3], energy in [2.2,2.8]."""
+    rng = np.random.default_rng(seed)
+    n = N + 1
+    Q = np.empty((C, 4, n, n))
+    Q[:, 0] = 1.0 + 0.2 * rng.uniform(-1, 1, (C, n, n))
+    Q[:, 1] = 0.3 * rng.uniform(-1, 1, (C, n, n))
+    Q[:, 2] = 0.3 * rng.uniform(-1, 1, (C, n, n))
+    Q[:, 3] = 2.5 + 0.3 * rng.uniform(-1, 1, (C, n, n))
+    return Q
+
+
+def perturb(Q: np.ndarray, seed: int, rel: float = 1e-3, vel: float = 0.5):
+    """Seeded noise on a given state: relative noise `rel` on density and
+    energy, momentum noise of `vel` times the local density."""
+    rng = np.random.default_rng(seed)
+    P = np.array(Q, dtype=np.float64, copy=True)
+    P[:, 0] *= 1.0 + rel * rng.uniform(-1, 1, P[:, 0].shape)
+    P[:, 3] *= 1.0 + rel * rng.uniform(-1, 1, P[:, 3].shape)
+    P[:, 1] += vel * Q[:, 0] * rng.uniform(-1, 1, P[:, 1].shape)
+    P[:, 2] += vel * Q[:, 0] * rng.uniform(-1, 1, P[:, 2].shape)
+    return P
