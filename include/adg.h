@@ -1,0 +1,172 @@
+/*
+ * adg.h -- C ABI of the MI355X (gfx950) ADER-DG library for 2D compressible
+ * Navier-Stokes with gravity and the total-variation refinement indicator.
+ *
+ * Method: Krenz, Rannabauer, Bader, "A High-Order Discontinuous Galerkin
+ * Solver with Dynamic Adaptive Mesh Refinement to Simulate Cloud Formation
+ * Processes" (arXiv:1905.05524).  Equation set: Section 2 (eqs.
+ * equation-set, eos, temperature, stress-tensor, heat-conduction-coeff,
+ * hydrostatic-balance, momentum-equation-split).  Scheme: Section 3 (ADER-DG
+ * predictor/corrector with a Rusanov-type viscous flux).  Indicator: Section 3
+ * (eqs. tv, refinement-criterion, chebychev).
+ *
+ * Conventions shared by every call
+ *   - FP64 throughout.  Node sets are Gauss-Legendre (GL) points on [0,1].
+ *   - State Q is device memory, cell-major: Q[cell][var][jz][ix], var =
+ *     (rho, rho*u, rho*w, rho*E), n = N+1 nodes per direction; node (jz, ix)
+ *     of a cell with lower-left corner (x0, z0) and size h sits at
+ *     (x0 + h*xi_ix, z0 + h*xi_jz).  Energy includes the geopotential rho*g*z.
+ *   - Cell order: for a uniform grid, c = j*nx + i; otherwise the order of
+ *     the leaf list given to adg_init_mesh.
+ *   - clock: device double[4] = (t, dt, next-dt accumulator, step count).
+ *     Time and time step live on the device so that a step needs no host
+ *     scalar; the caller may write t and dt before a step.
+ *   - Ownership: every device buffer passed in (Q, workspace, clock, tv,
+ *     flags, stats, adjoint buffers) belongs to the caller and is never freed
+ *     by the library.  A handle owns only its metadata and constant tables
+ *     (allocated in adg_init_mesh, freed in adg_destroy).
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = default
+ *     stream).  Enqueuing calls are asynchronous and capturable in a HIP
+ *     graph, except adg_regrid and adg_check_health, which synchronise.
+ *   - Errors: every call returns an adg status; parameter and launch errors
+ *     are reported immediately, with a message from adg_last_error().  Device
+ *     state errors (non-finite values, rho <= 0, p <= 0) are reported by
+ *     adg_check_health.  Handles are not thread-safe.
+ */
+#ifndef ADG_H
+#define ADG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ADG_OK = 0,
+  ADG_EINVAL = -1,       /* bad argument or inconsistent parameters          */
+  ADG_ENOMEM = -2,       /* handle-owned allocation failed                    */
+  ADG_EHIP = -3,         /* HIP runtime or launch error                       */
+  ADG_ESTATE = -4,       /* no state bound, or unhealthy state on the device  */
+  ADG_EUNSUPPORTED = -5  /* valid request that this build does not support    */
+};
+
+enum { ADG_BC_PERIODIC = 0, ADG_BC_WALL = 1 };
+enum { ADG_VAR_THETA = 0, ADG_VAR_RHO = 1 };
+enum { ADG_SHAPE_COSINE = 0, ADG_SHAPE_PLATEAU_GAUSS = 1 };
+
+/* Physical and numerical parameters.
+ *   order N in 1..7 (n = N+1 <= 8 GL nodes per direction);
+ *   picard_iters: number of predictor sweeps, 0 -> N+1;
+ *   gamma, Pr, R, cp, mu: ideal gas and viscosity, kappa = mu*cp/Pr
+ *     (eq. heat-conduction-coeff);
+ *   gravity != 0: geopotential rho*g*z in the EOS, momentum flux with the
+ *     perturbation pressure p - p_bar(z), source -g (rho - rho_bar(z)) in the
+ *     vertical momentum (eq. momentum-equation-split); the background is the
+ *     hydrostatic atmosphere of constant potential temperature theta_bg
+ *     (eq. hydrostatic-balance) with reference pressure p0;
+ *   mms != 0: adds the energy source of the manufactured advected density
+ *     wave rho = 1 + mms_amp sin(mms_kx (x - mms_u t)) sin(mms_kz (z - mms_w t)),
+ *     velocity (mms_u, mms_w), pressure mms_p (for convergence checks);
+ *   cfl: Courant number of the time-step rule;
+ *   fixed_dt != 0: keep clock[1] unchanged (no CFL update after a step). */
+typedef struct {
+  int order;
+  int picard_iters;
+  double gamma, Pr, R, cp, mu, g, p0, theta_bg;
+  int gravity;
+  int mms;
+  double mms_amp, mms_u, mms_w, mms_kx, mms_kz, mms_p;
+  double cfl;
+  int fixed_dt;
+} adg_params;
+
+/* Mesh: a coarse grid of nx x nz square cells on [x0,x0+Lx] x [z0,z0+Lz]
+ * (Lx/nx == Lz/nz) refined by 3-way splits per level and dimension (paper,
+ * Sections 3 and 4.3) up to max_level.  bc[4] = (west, east, south, north).
+ * leaf_level/leaf_i/leaf_j (host arrays of n_leaves entries; all NULL for the
+ * uniform coarse grid) list the leaves; leaf (l, i, j) has size
+ * h = Lx/(nx 3^l) and corner (x0 + i h, z0 + j h).  Neighbouring leaves may
+ * differ by at most one level. */
+typedef struct {
+  double x0, z0, Lx, Lz;
+  int nx, nz;
+  int max_level;
+  int bc[4];
+  int n_leaves;
+  const int32_t* leaf_level;
+  const int32_t* leaf_i;
+  const int32_t* leaf_j;
+} adg_mesh_desc;
+
+typedef struct adg_mesh adg_mesh;
+
+/* Create a handle: validates parameters, builds the GL basis and the face
+ * tables, uploads constant tables.  EINVAL on bad parameters or an invalid
+ * leaf list.  *out is set only on success. */
+int adg_init_mesh(const adg_params* prm, const adg_mesh_desc* mesh, adg_mesh** out);
+int adg_destroy(adg_mesh* m);
+
+/* Number of cells, nodes per direction, and the size in bytes of the
+ * workspace the caller must provide to adg_set_state. */
+int adg_mesh_info(const adg_mesh* m, int* n_cells, int* n_nodes);
+int adg_workspace_bytes(const adg_mesh* m, size_t* bytes);
+
+/* Bind caller-owned device buffers: Q [C][4][n][n] (updated in place by each
+ * step), workspace (adg_workspace_bytes, 256-byte aligned), clock double[4]. */
+int adg_set_state(adg_mesh* m, double* Q, void* workspace, double* clock);
+
+/* Initial state by nodal interpolation (paper, Section 4.2: hydrostatic
+ * background of constant potential temperature, perturbed in theta at fixed
+ * pressure; cosine bubble eq. cos-pertubation read with cos(pi r / a);
+ * bubbles of eq. bubbles-pertubation).  bubbles: host array [n_bubbles][6] =
+ * (shape, A, a, s, xc, zc); perturbations add.  kind 0 = bubbles, 1 = the
+ * manufactured wave at time t0.  Writes the bound Q. */
+int adg_init_state(adg_mesh* m, int kind, int n_bubbles, const double* bubbles, double t0,
+                   void* stream);
+
+/* Time step by the CFL rule from the bound Q:
+ *   dt = cfl * min_cells h / (2 (2N+1) (lambda + 2 lambda_v (2N+1)/h)),
+ * lambda = max(|u|,|w|) + c, lambda_v = max(4 mu/(3 rho), gamma mu/(Pr rho));
+ * writes clock[1]. */
+int adg_compute_dt(adg_mesh* m, void* stream);
+
+/* Space-time predictor (ADER-DG, Section 3): Picard sweeps on the GL
+ * space-time nodes of every cell, then the time-averaged state and flux, the
+ * volume-plus-source update Q* and the face data, into the workspace. */
+int adg_predictor(adg_mesh* m, void* stream);
+
+/* Corrector: viscous Rusanov flux on every face from the face data (walls:
+ * background-state ghosts with the background heat flux, Section 4.2), the
+ * surface update Q = Q* - lifting, the next CFL time step (unless fixed_dt),
+ * then t += dt and step count += 1 in clock. */
+int adg_corrector(adg_mesh* m, void* stream);
+
+/* One full step: adg_predictor + adg_corrector. */
+int adg_step(adg_mesh* m, void* stream);
+
+/* TV indicator (eq. tv) of theta (ADG_VAR_THETA) or rho per cell, the
+ * population mean/std of TV over all cells merged with the pairwise updates of
+ * Chan, Golub and LeVeque, and the flags of eq. refinement-criterion:
+ * +1 refine if TV >= mu + T_refine sigma, -1 coarsen if TV < mu + T_coarsen
+ * sigma, else 0 (sigma == 0 keeps all).  tv: device double[C], flags: device
+ * int8[C], stats: device double[3] = (count, mean, sigma). */
+int adg_tv_indicator(adg_mesh* m, int var, double T_refine, double T_coarsen, double* tv,
+                     int8_t* flags, double* stats, void* stream);
+
+/* Synchronises the stream, then checks the bound state: ESTATE if any value
+ * is non-finite or any node has rho <= 0 or p <= 0. */
+int adg_check_health(adg_mesh* m, void* stream);
+
+/* Message of the last failing call on this thread. */
+const char* adg_last_error(void);
+
+/* Read back the handle's GL nodes/weights and matrices (n, n, n*n, n*n):
+ * D[i*n+j] = phi_j'(xi_i), P = K1^{-1} W of the time predictor. */
+int adg_basis(const adg_mesh* m, double* xi, double* w, double* D, double* P);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADG_H */

@@ -1,0 +1,232 @@
+"""Thin ctypes binding of ``libadg.so`` (C ABI in ``include/adg.h``).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch provides device memory and streams.  If the library is
+missing, loading fails loudly; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libadg.so")
+
+ADG_OK, ADG_EINVAL, ADG_ENOMEM, ADG_EHIP, ADG_ESTATE, ADG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+ADG_BC_PERIODIC, ADG_BC_WALL = 0, 1
+ADG_VAR_THETA, ADG_VAR_RHO = 0, 1
+
+EXPORTED = [
+    "adg_init_mesh", "adg_destroy", "adg_mesh_info", "adg_workspace_bytes", "adg_set_state",
+    "adg_init_state", "adg_compute_dt", "adg_predictor", "adg_corrector", "adg_step",
+    "adg_tv_indicator", "adg_check_health", "adg_last_error", "adg_basis",
+]
+
+
+class AdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"adg error {code}: {msg}")
+        self.code = code
+
+
+class adg_params(ctypes.Structure):
+    _fields_ = [
+        ("order", ctypes.c_int), ("picard_iters", ctypes.c_int),
+        ("gamma", ctypes.c_double), ("Pr", ctypes.c_double), ("R", ctypes.c_double),
+        ("cp", ctypes.c_double), ("mu", ctypes.c_double), ("g", ctypes.c_double),
+        ("p0", ctypes.c_double), ("theta_bg", ctypes.c_double),
+        ("gravity", ctypes.c_int), ("mms", ctypes.c_int),
+        ("mms_amp", ctypes.c_double), ("mms_u", ctypes.c_double), ("mms_w", ctypes.c_double),
+        ("mms_kx", ctypes.c_double), ("mms_kz", ctypes.c_double), ("mms_p", ctypes.c_double),
+        ("cfl", ctypes.c_double), ("fixed_dt", ctypes.c_int),
+    ]
+
+
+class adg_mesh_desc(ctypes.Structure):
+    _fields_ = [
+        ("x0", ctypes.c_double), ("z0", ctypes.c_double), ("Lx", ctypes.c_double),
+        ("Lz", ctypes.c_double), ("nx", ctypes.c_int), ("nz", ctypes.c_int),
+        ("max_level", ctypes.c_int), ("bc", ctypes.c_int * 4), ("n_leaves", ctypes.c_int),
+        ("leaf_level", ctypes.POINTER(ctypes.c_int32)), ("leaf_i", ctypes.POINTER(ctypes.c_int32)),
+        ("leaf_j", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libadg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1905_05524_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+        L.adg_init_mesh.argtypes = [ctypes.POINTER(adg_params), ctypes.POINTER(adg_mesh_desc),
+                                    ctypes.POINTER(vp)]
+        L.adg_destroy.argtypes = [vp]
+        L.adg_mesh_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.adg_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.adg_set_state.argtypes = [vp, vp, vp, vp]
+        L.adg_init_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, vp]
+        for name in ("adg_compute_dt", "adg_predictor", "adg_corrector", "adg_step", "adg_check_health"):
+            getattr(L, name).argtypes = [vp, vp]
+        L.adg_tv_indicator.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp]
+        L.adg_last_error.restype = ctypes.c_char_p
+        L.adg_basis.argtypes = [vp, dp, dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != ADG_OK:
+        raise AdgError(rc, lib().adg_last_error().decode())
+
+
+def make_params(phys: dict, fixed_dt: bool = False) -> adg_params:
+    p = adg_params()
+    p.order = int(phys["N"])
+    p.picard_iters = int(phys.get("picard_iters", 0))
+    for k in ("gamma", "Pr", "R", "cp", "mu", "g", "p0", "theta_bg", "mms_amp", "mms_u", "mms_w",
+              "mms_kx", "mms_kz", "mms_p", "cfl"):
+        setattr(p, k, float(phys.get(k, 0.0)))
+    p.gravity = int(phys.get("gravity", 0))
+    p.mms = int(phys.get("mms", 0))
+    p.fixed_dt = 1 if fixed_dt else 0
+    return p
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Mesh:
+    """Handle of one mesh + parameters; owns nothing on the device beyond the
+    library's constant tables.  State buffers are torch tensors owned here."""
+
+    def __init__(self, phys: dict, mesh: dict, fixed_dt: bool = False, device="cuda"):
+        import torch
+        self.phys, self.mesh_desc = dict(phys), dict(mesh)
+        self._p = make_params(phys, fixed_dt)
+        d = adg_mesh_desc()
+        d.x0, d.z0 = float(mesh.get("x0", 0.0)), float(mesh.get("z0", 0.0))
+        d.Lx, d.Lz = float(mesh["Lx"]), float(mesh["Lz"])
+        d.nx, d.nz = int(mesh["nx"]), int(mesh["nz"])
+        d.max_level = int(mesh.get("max_level", 0))
+        for k, b in enumerate(mesh.get("bc", [ADG_BC_WALL] * 4)):
+            d.bc[k] = int(b)
+        leaves = mesh.get("leaves")
+        self._keep = []
+        if leaves is not None:
+            lv = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 3))
+            cols = [np.ascontiguousarray(lv[:, k]) for k in range(3)]
+            self._keep = cols
+            d.n_leaves = lv.shape[0]
+            d.leaf_level, d.leaf_i, d.leaf_j = (c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) for c in cols)
+        self._d = d
+        h = ctypes.c_void_p()
+        _check(lib().adg_init_mesh(ctypes.byref(self._p), ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
+        nc, nn = ctypes.c_int(), ctypes.c_int()
+        _check(lib().adg_mesh_info(h, ctypes.byref(nc), ctypes.byref(nn)))
+        self.C, self.n = nc.value, nn.value
+        wb = ctypes.c_size_t()
+        _check(lib().adg_workspace_bytes(h, ctypes.byref(wb)))
+        self.ws_bytes = wb.value
+        self.device = torch.device(device)
+        self.Q = torch.zeros((self.C, 4, self.n, self.n), dtype=torch.float64, device=self.device)
+        # 256-byte aligned workspace (torch allocations are at least 512-aligned)
+        self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)
+        self.clock = torch.zeros(4, dtype=torch.float64, device=self.device)
+        self.bind()
+
+    def bind(self):
+        _check(lib().adg_set_state(self.h, ctypes.c_void_p(self.Q.data_ptr()),
+                                   ctypes.c_void_p(self.ws.data_ptr()),
+                                   ctypes.c_void_p(self.clock.data_ptr())))
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().adg_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    # -- calls with the C names --------------------------------------------
+    def init_state(self, kind="bubbles", bubbles=(), t0=0.0, stream=None):
+        bb = np.ascontiguousarray(np.asarray(bubbles, dtype=np.float64).reshape(-1, 6))
+        k = 1 if kind == "mms" else 0
+        _check(lib().adg_init_state(self.h, k, bb.shape[0],
+                                    bb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(t0),
+                                    _stream_ptr(stream)))
+
+    def set_state(self, Q, t=None, dt=None):
+        """Copy a state (numpy or tensor [C,4,n,n]) into the bound buffer."""
+        import torch
+        self.Q.copy_(torch.as_tensor(np.asarray(Q) if not torch.is_tensor(Q) else Q, dtype=torch.float64))
+        if t is not None:
+            self.clock[0] = float(t)
+        if dt is not None:
+            self.clock[1] = float(dt)
+
+    def compute_dt(self, stream=None):
+        _check(lib().adg_compute_dt(self.h, _stream_ptr(stream)))
+
+    def predictor(self, stream=None):
+        _check(lib().adg_predictor(self.h, _stream_ptr(stream)))
+
+    def corrector(self, stream=None):
+        _check(lib().adg_corrector(self.h, _stream_ptr(stream)))
+
+    def step(self, stream=None):
+        _check(lib().adg_step(self.h, _stream_ptr(stream)))
+
+    def tv_indicator(self, var, T_refine, T_coarsen, tv, flags, stats, stream=None):
+        _check(lib().adg_tv_indicator(self.h, int(var), float(T_refine), float(T_coarsen),
+                                      ctypes.c_void_p(tv.data_ptr()), ctypes.c_void_p(flags.data_ptr()),
+                                      ctypes.c_void_p(stats.data_ptr()), _stream_ptr(stream)))
+
+    def check_health(self, stream=None):
+        _check(lib().adg_check_health(self.h, _stream_ptr(stream)))
+
+    def basis(self):
+        n = self.n
+        xi, w, D, P = np.zeros(n), np.zeros(n), np.zeros((n, n)), np.zeros((n, n))
+        dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        _check(lib().adg_basis(self.h, dp(xi), dp(w), dp(D), dp(P)))
+        return dict(xi=xi, w=w, D=D, P=P)
+
+    # -- views of the workspace (predictor outputs) --------------------------
+    def qstar(self):
+        nn = self.n * self.n
+        return self.ws[:self.C * 4 * nn * 8].view(torch_float64()).view(self.C, 4, self.n, self.n)
+
+    def face_data(self):
+        import torch
+        n = self.n
+        off = _align256(self.C * 4 * n * n * 8)
+        return self.ws[off:off + self.C * 32 * n * 8].view(torch.float64).view(self.C, 4, 2, 4, n)
+
+    @property
+    def t(self):
+        return float(self.clock[0].item())
+
+    @property
+    def dt(self):
+        return float(self.clock[1].item())
+
+
+def _align256(x):
+    return (x + 255) & ~255
+
+
+def torch_float64():
+    import torch
+    return torch.float64

@@ -1,0 +1,165 @@
+// Internal definitions of the gfx950 ADER-DG library: constant tables,
+// physics parameters in kernel-argument form, the mesh handle, and the
+// pointwise physics as device functions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "adg.h"
+
+namespace adg {
+
+constexpr int kMaxN = 8;          // nodes per direction supported (order 7)
+constexpr int kWave = 64;         // CDNA wavefront size
+
+// Basis tables for n nodes, passed by value as a kernel argument so that every
+// entry read with a compile-time index becomes a scalar (SGPR) operand.
+template <int n>
+struct Tab {
+  double D[n][n];    // D[i][m] = phi_m'(xi_i)
+  double P[n][n];    // time predictor matrix K1^{-1} W
+  double Dw[n][n];   // volume term: Dw[i][m] = w_m D[m][i] / w_i
+  double w[n];
+  double e0[n], e1[n];
+};
+
+// Lane-indexed tables in global memory (one per handle):
+//   xi[n], w[n], L0[n] = e0/w, L1[n] = e1/w, Pk[3][n][n] (sub-face k
+//   prolongation phi_m((k+xi_q)/3) at [k][q][m]), Rk[3][n][n] (restriction
+//   (w_q/3) phi_m((k+xi_q)/3)/w_m at [k][m][q]).
+struct GTab {
+  static constexpr int XI = 0, W = 1, L0 = 2, L1 = 3;
+  static __host__ __device__ inline int off(int which, int n) { return which * n; }
+  static __host__ __device__ inline int pk(int n) { return 4 * n; }
+  static __host__ __device__ inline int rk(int n) { return 4 * n + 3 * n * n; }
+  static __host__ __device__ inline int size(int n) { return 4 * n + 6 * n * n; }
+};
+
+struct Phys {
+  double gamma, gm1, R, iR, cp, Pr, mu, kappa, g, p0, theta;
+  double cp_over_R, R_over_cp, ex_coef;   // ex_coef = g/(cp theta)
+  double lv_coef;                         // lambda_v = lv_coef / rho
+  double mms_amp, mms_u, mms_w, mms_kx, mms_kz, mms_p;
+  double cfl;
+  int gravity, mms, fixed_dt, N;
+};
+
+enum FaceKind { kConforming = 0, kWall = 1, kFineSide = 2, kCoarseSide = 3 };
+
+}  // namespace adg
+
+struct adg_mesh {
+  adg_params prm;
+  adg::Phys ph;
+  int N = 0, n = 0, iters = 0, C = 0;
+  adg_mesh_desc desc{};
+  std::vector<int> lev, ci, cj;
+  std::vector<double> geom_h;         // [C][4] = x0, z0, h, 0
+  std::vector<int> nbr_h;             // [C][4 faces][4]
+  // host copies of the basis
+  std::vector<double> xi, w, D, P, Dw, e0, e1, gtab_h;
+  // device (handle-owned)
+  double* d_geom = nullptr;
+  int* d_nbr = nullptr;
+  double* d_gtab = nullptr;
+  // bound (caller-owned)
+  double* Q = nullptr;
+  void* ws = nullptr;
+  double* clock = nullptr;
+  // workspace partition (bytes offsets)
+  size_t off_qs = 0, off_fd = 0, off_health = 0, ws_bytes = 0;
+};
+
+namespace adg {
+
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int check_launch(const char* what);
+
+// ---------------------------------------------------------------- physics
+// Hydrostatic background of constant potential temperature:
+// Exner pi = 1 - g z/(cp theta), p = p0 pi^(cp/R), rho = p/(R theta pi).
+__device__ inline void background(const Phys& ph, double z, double& rb, double& pb) {
+  if (!ph.gravity) { rb = 0.0; pb = 0.0; return; }
+  double pi = 1.0 - ph.ex_coef * z;
+  pb = ph.p0 * pow(pi, ph.cp_over_R);
+  rb = pb / (ph.R * ph.theta * pi);
+}
+
+__device__ inline double pressure(const Phys& ph, double rho, double mx, double mz, double E, double z) {
+  double geo = ph.gravity ? rho * (ph.g * z) : 0.0;
+  return ph.gm1 * (E - 0.5 * (mx * mx + mz * mz) / rho - geo);
+}
+
+// Energy source of the manufactured advected density wave (T = p/(R rho),
+// S_E = -kappa Lap T).
+__device__ inline double mms_source(const Phys& ph, double x, double z, double t) {
+  double X = x - ph.mms_u * t, Z = z - ph.mms_w * t;
+  double sx, cx, sz, cz;
+  sincos(ph.mms_kx * X, &sx, &cx);
+  sincos(ph.mms_kz * Z, &sz, &cz);
+  double rho = 1.0 + ph.mms_amp * sx * sz;
+  double rx = ph.mms_amp * ph.mms_kx * cx * sz;
+  double rz = ph.mms_amp * ph.mms_kz * sx * cz;
+  double lap = -(ph.mms_kx * ph.mms_kx + ph.mms_kz * ph.mms_kz) * ph.mms_amp * sx * sz;
+  double ir = 1.0 / rho;
+  double lapT = ph.mms_p * ph.iR * (-lap * ir * ir + 2.0 * (rx * rx + rz * rz) * ir * ir * ir);
+  return -ph.kappa * lapT;
+}
+
+// Flux (hyperbolic + viscous) in x and z and the gravity source of the
+// vertical momentum at one node (eqs. equation-set, eos, temperature,
+// stress-tensor, heat-conduction-coeff, momentum-equation-split).  q: conserved state; gx, gz: its physical gradients;
+// rb, pb: background density and pressure at the node height z.
+__device__ inline void flux_source(const Phys& ph, const double q[4], const double gx[4],
+                                   const double gz[4], double z, double rb, double pb,
+                                   double Fx[4], double Fz[4], double& Sw) {
+  const double rho = q[0], mx = q[1], mz = q[2], E = q[3];
+  const double ir = 1.0 / rho;
+  const double u = mx * ir, w = mz * ir;
+  const double gzz = ph.gravity ? ph.g * z : 0.0;
+  const double p = ph.gm1 * (E - 0.5 * (mx * u + mz * w) - rho * gzz);
+  const double pm = ph.gravity ? p - pb : p;
+  const double T = p * ir * ph.iR;
+  const double dux = (gx[1] - u * gx[0]) * ir, duz = (gz[1] - u * gz[0]) * ir;
+  const double dwx = (gx[2] - w * gx[0]) * ir, dwz = (gz[2] - w * gz[0]) * ir;
+  const double hv2 = 0.5 * (u * u + w * w) + gzz;
+  double dpx = ph.gm1 * (gx[3] - hv2 * gx[0] - rho * (u * dux + w * dwx));
+  double dpz = ph.gm1 * (gz[3] - hv2 * gz[0] - rho * (u * duz + w * dwz));
+  if (ph.gravity) dpz -= ph.gm1 * rho * ph.g;
+  const double dTx = (dpx - ph.R * T * gx[0]) * ir * ph.iR;
+  const double dTz = (dpz - ph.R * T * gz[0]) * ir * ph.iR;
+  const double div = dux + dwz;
+  const double sxx = ph.mu * ((2.0 / 3.0) * div - 2.0 * dux);
+  const double szz = ph.mu * ((2.0 / 3.0) * div - 2.0 * dwz);
+  const double sxz = -ph.mu * (duz + dwx);
+  const double H = E + p;
+  Fx[0] = mx;
+  Fx[1] = mx * u + pm + sxx;
+  Fx[2] = mz * u + sxz;
+  Fx[3] = u * H + u * sxx + w * sxz - ph.kappa * dTx;
+  Fz[0] = mz;
+  Fz[1] = mx * w + sxz;
+  Fz[2] = mz * w + pm + szz;
+  Fz[3] = w * H + u * sxz + w * szz - ph.kappa * dTz;
+  Sw = ph.gravity ? -ph.g * (rho - rb) : 0.0;
+}
+
+// max over the 64 lanes of a wavefront (butterfly, fixed order)
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+}  // namespace adg

@@ -1,0 +1,214 @@
+// Auxiliary kernels for gfx950: initial state, total-variation indicator with
+// Chan-merged statistics and refinement flags, state health check.
+#include "adg_internal.h"
+
+namespace adg {
+
+// --------------------------------------------------------- initial state
+// One thread per node.  kind 0: hydrostatic background of constant potential
+// temperature perturbed in theta at fixed pressure (rho from p = rho R T,
+// T = theta * Exner, at rest); kind 1: the manufactured density wave at t0.
+__global__ void k_init_state(Phys ph, int n, int C, const double* geom, const double* gtab, int kind,
+                             int nbub, const double* bub, double t0, double* Q) {
+  const int nn = n * n;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long long)C * nn) return;
+  const int c = (int)(gid / nn), node = (int)(gid % nn);
+  const int jz = node / n, ix = node % n;
+  const double h = geom[4 * c + 2];
+  const double x = geom[4 * c + 0] + h * gtab[GTab::XI * n + ix];
+  const double z = geom[4 * c + 1] + h * gtab[GTab::XI * n + jz];
+  double q[4];
+  if (kind == 1) {
+    const double rho = 1.0 + ph.mms_amp * sin(ph.mms_kx * (x - ph.mms_u * t0)) * sin(ph.mms_kz * (z - ph.mms_w * t0));
+    q[0] = rho; q[1] = rho * ph.mms_u; q[2] = rho * ph.mms_w;
+    q[3] = ph.mms_p / ph.gm1 + 0.5 * rho * (ph.mms_u * ph.mms_u + ph.mms_w * ph.mms_w);
+  } else {
+    double dth = 0.0;
+    for (int b = 0; b < nbub; ++b) {
+      const double* bb = bub + 6 * b;
+      const double dx = x - bb[4], dz = z - bb[5];
+      const double r = sqrt(dx * dx + dz * dz);
+      if ((int)bb[0] == ADG_SHAPE_COSINE) {
+        if (r <= bb[2]) dth += 0.5 * bb[1] * (1.0 + cos(M_PI * r / bb[2]));
+      } else {
+        const double e = (r - bb[2]) / bb[3];
+        dth += (r <= bb[2]) ? bb[1] : bb[1] * exp(-e * e);
+      }
+    }
+    const double pi = 1.0 - ph.ex_coef * z;
+    const double pb = ph.p0 * pow(pi, ph.cp_over_R);
+    const double T = (ph.theta + dth) * pi;
+    const double rho = pb / (ph.R * T);
+    q[0] = rho; q[1] = 0.0; q[2] = 0.0;
+    q[3] = pb / ph.gm1 + rho * ph.g * z;
+  }
+  for (int v = 0; v < 4; ++v) Q[(size_t)c * 4 * nn + v * nn + node] = q[v];
+}
+
+// ------------------------------------------------------------- TV per cell
+// TV = h sum_ji w_i w_j (|sum_m D_im f_jm| + |sum_m D_jm f_mi|), f = theta or
+// rho at the nodes.  One wavefront per cell; lanes < 2n run the line jobs.
+template <int n>
+__global__ __launch_bounds__(kWave) void k_tv(Tab<n> T, Phys ph, const double* Q, const double* geom,
+                                                const double* gtab, int var, double* tv) {
+  constexpr int nn = n * n;
+  __shared__ double sfv[nn];
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
+  const double z0 = geom[4 * c + 1], h = geom[4 * c + 2];
+  if (lane < nn) {
+    const int jz = lane / n;
+    const double* Qc = Q + (size_t)c * 4 * nn;
+    const double rho = Qc[lane];
+    double f = rho;
+    if (var == ADG_VAR_THETA) {
+      const double z = z0 + h * gtab[GTab::XI * n + jz];
+      const double p = pressure(ph, rho, Qc[nn + lane], Qc[2 * nn + lane], Qc[3 * nn + lane], z);
+      const double Tm = p / (rho * ph.R);
+      f = Tm * pow(ph.p0 / p, ph.R_over_cp);
+    }
+    sfv[lane] = f;
+  }
+  __syncthreads();
+  double part = 0.0;
+  if (lane < 2 * n) {
+    const int dir = lane / n, line = lane % n;
+    const int base = dir == 0 ? line * n : line, stride = dir == 0 ? 1 : n;
+    double in[n];
+#pragma unroll
+    for (int m = 0; m < n; ++m) in[m] = sfv[base + m * stride];
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < n; ++m) s = fma(T.D[i][m], in[m], s);
+      part = fma(T.w[i], fabs(s), part);
+    }
+    part *= gtab[GTab::W * n + line];
+  }
+  part = wave_sum(part);
+  if (lane == 0) tv[c] = h * part;
+}
+
+// ---------------------------------------------------- statistics and flags
+// Single workgroup: each thread folds a contiguous chunk of cells with the
+// one-element updates of Chan, Golub & LeVeque (count, mean, M2); partials are
+// then merged pairwise in a fixed tree.  Deterministic for a given C.
+// stats = (count, mean, population sigma); flags as in the refinement rule.
+constexpr int kStatThreads = 1024;
+
+__device__ inline void chan_merge(double& na, double& ma, double& qa, double nb, double mb, double qb) {
+  const double nt = na + nb;
+  if (nb == 0.0) return;
+  if (na == 0.0) { na = nb; ma = mb; qa = qb; return; }
+  const double d = mb - ma;
+  ma = ma + d * nb / nt;
+  qa = qa + qb + d * d * na * nb / nt;
+  na = nt;
+}
+
+__global__ __launch_bounds__(kStatThreads) void k_stats_flags(const double* tv, int C, double Tr, double Tc,
+                                                                 int8_t* flags, double* stats) {
+  __shared__ double sn[kStatThreads], sm[kStatThreads], sq[kStatThreads];
+  const int t = threadIdx.x;
+  const int chunk = (C + kStatThreads - 1) / kStatThreads;
+  const int lo = t * chunk, hi = min(C, lo + chunk);
+  double na = 0.0, ma = 0.0, qa = 0.0;
+  for (int c = lo; c < hi; ++c) chan_merge(na, ma, qa, 1.0, tv[c], 0.0);
+  sn[t] = na; sm[t] = ma; sq[t] = qa;
+  __syncthreads();
+  for (int w = 1; w < kStatThreads; w *= 2) {
+    if ((t % (2 * w)) == 0 && t + w < kStatThreads) {
+      double a = sn[t], b = sm[t], q = sq[t];
+      chan_merge(a, b, q, sn[t + w], sm[t + w], sq[t + w]);
+      sn[t] = a; sm[t] = b; sq[t] = q;
+    }
+    __syncthreads();
+  }
+  const double cnt = sn[0], mean = sm[0];
+  const double sigma = cnt > 0.0 ? sqrt(sq[0] / cnt) : 0.0;
+  if (t == 0) { stats[0] = cnt; stats[1] = mean; stats[2] = sigma; }
+  const double thr_r = mean + Tr * sigma, thr_c = mean + Tc * sigma;
+  for (int c = t; c < C; c += kStatThreads) {
+    int8_t f = 0;
+    if (sigma != 0.0) {
+      const double v = tv[c];
+      if (v >= thr_r) f = 1;
+      else if (v < thr_c) f = -1;
+    }
+    flags[c] = f;
+  }
+}
+
+// ------------------------------------------------------------------ health
+__global__ void k_health(Phys ph, int n, int C, const double* Q, const double* geom, const double* gtab,
+                         int* flag) {
+  const int nn = n * n;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long long)C * nn) return;
+  const int c = (int)(gid / nn), node = (int)(gid % nn);
+  const double* Qc = Q + (size_t)c * 4 * nn;
+  const double rho = Qc[node], mx = Qc[nn + node], mz = Qc[2 * nn + node], E = Qc[3 * nn + node];
+  const double z = geom[4 * c + 1] + geom[4 * c + 2] * gtab[GTab::XI * n + node / n];
+  bool bad = !(isfinite(rho) && isfinite(mx) && isfinite(mz) && isfinite(E)) || !(rho > 0.0);
+  if (!bad) bad = !(pressure(ph, rho, mx, mz, E, z) > 0.0);
+  if (bad) atomicOr(flag, 1);
+}
+
+// --------------------------------------------------------------- launchers
+int launch_init_state(adg_mesh* m, int kind, int nbub, const double* d_bub, double t0, hipStream_t s) {
+  const long long tot = (long long)m->C * m->n * m->n;
+  const int bs = 256;
+  const long long nb = (tot + bs - 1) / bs;
+  hipLaunchKernelGGL(k_init_state, dim3((unsigned)nb), dim3(bs), 0, s, m->ph, m->n, m->C, m->d_geom,
+                     m->d_gtab, kind, nbub, d_bub, t0, m->Q);
+  return check_launch("init_state");
+}
+
+template <int n>
+static Tab<n> tab_of(const adg_mesh* m) {
+  Tab<n> T;
+  for (int i = 0; i < n; ++i) {
+    T.w[i] = m->w[i]; T.e0[i] = m->e0[i]; T.e1[i] = m->e1[i];
+    for (int j = 0; j < n; ++j) {
+      T.D[i][j] = m->D[i * n + j]; T.P[i][j] = m->P[i * n + j]; T.Dw[i][j] = m->Dw[i * n + j];
+    }
+  }
+  return T;
+}
+
+template <int n>
+static int launch_tv_n(adg_mesh* m, int var, double* tv, hipStream_t s) {
+  hipLaunchKernelGGL(k_tv<n>, dim3(m->C), dim3(kWave), 0, s, tab_of<n>(m), m->ph, m->Q, m->d_geom,
+                     m->d_gtab, var, tv);
+  return check_launch("tv");
+}
+
+int launch_tv(adg_mesh* m, int var, double Tr, double Tc, double* tv, int8_t* flags, double* stats,
+              hipStream_t s) {
+  int rc;
+  switch (m->n) {
+    case 2: rc = launch_tv_n<2>(m, var, tv, s); break;
+    case 3: rc = launch_tv_n<3>(m, var, tv, s); break;
+    case 4: rc = launch_tv_n<4>(m, var, tv, s); break;
+    case 5: rc = launch_tv_n<5>(m, var, tv, s); break;
+    case 6: rc = launch_tv_n<6>(m, var, tv, s); break;
+    case 7: rc = launch_tv_n<7>(m, var, tv, s); break;
+    case 8: rc = launch_tv_n<8>(m, var, tv, s); break;
+    default: return fail(ADG_EUNSUPPORTED, "order not supported");
+  }
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_stats_flags, dim3(1), dim3(kStatThreads), 0, s, tv, m->C, Tr, Tc, flags, stats);
+  return check_launch("stats_flags");
+}
+
+int launch_health(adg_mesh* m, int* flag, hipStream_t s) {
+  const long long tot = (long long)m->C * m->n * m->n;
+  const int bs = 256;
+  hipLaunchKernelGGL(k_health, dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, s, m->ph, m->n, m->C, m->Q,
+                     m->d_geom, m->d_gtab, flag);
+  return check_launch("health");
+}
+
+}  // namespace adg

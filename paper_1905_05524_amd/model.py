@@ -1,0 +1,60 @@
+"""Algorithmic flop and byte counts of the kernels, per cell and step.
+
+Counts follow the implemented arithmetic (FMA = 2 flops, a division = 1),
+with n = N+1 nodes per direction and I Picard sweeps:
+
+predictor, per sweep and time slice (n*n spatial nodes, 4 variables):
+    gradients   2 dirs * 4 vars * n^2 outputs * n MACs      = 16 n^3
+    pointwise   flux + source (FLUX_FLOPS) + gradient scaling (8)
+    divergence  16 n^3, residual assembly 10 per node
+    time solve  4 vars * n targets * n^2 nodes MACs         = 8 n^3
+  per sweep: n * (40 n^3 + (FLUX_FLOPS + 18) n^2) + 8 n^3 (q = Q + dt acc)
+  final pass: n * (16 n^3 + (FLUX_FLOPS + 8 + 28) n^2)  (28: averages)
+  epilogue:   16 n^3 (volume contraction) + 64 n^2 (face values) + 16 n^2
+corrector: per face node 2 eigen bounds (~14 each) + flux (4 * 4), plus the
+  lifting (4 vars * 8 per node) -> small; it is bound by memory traffic.
+
+Bytes (8-byte words, each read or written once):
+  predictor: read Q (4 n^2), write Q* (4 n^2), write face data (32 n)
+  corrector: read Q* (4 n^2), own and neighbour face data (64 n), write Q (4 n^2)
+"""
+
+FLUX_FLOPS = 99   # counted operation by operation in the flux/source function
+
+
+def predictor_flops(N: int, iters: int = 0) -> int:
+    n = N + 1
+    I = iters or n
+    c = FLUX_FLOPS
+    sweep = n * (40 * n ** 3 + (c + 18) * n ** 2) + 8 * n ** 3
+    final = n * (16 * n ** 3 + (c + 36) * n ** 2)
+    epi = 16 * n ** 3 + 80 * n ** 2
+    return I * sweep + final + epi
+
+
+def corrector_flops(N: int) -> int:
+    n = N + 1
+    return 4 * n * (2 * 2 * 14 + 16 + 4) + 4 * n * n * 8
+
+
+def step_flops(N: int, iters: int = 0) -> int:
+    return predictor_flops(N, iters) + corrector_flops(N)
+
+
+def predictor_bytes(N: int) -> int:
+    n = N + 1
+    return 8 * (8 * n * n + 32 * n)
+
+
+def corrector_bytes(N: int) -> int:
+    n = N + 1
+    return 8 * (8 * n * n + 64 * n)
+
+
+def tv_bytes(N: int) -> int:
+    n = N + 1
+    return 8 * (4 * n * n + 1)
+
+
+def dofs(cells: int, N: int) -> int:
+    return cells * (N + 1) ** 2 * 4

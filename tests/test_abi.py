@@ -1,0 +1,68 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function the
+header declares, and rejects invalid parameters before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1905_05524_amd import adg
+from paper_1905_05524_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "adg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(adg_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = adg.lib()
+    names = header_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(adg.EXPORTED)
+
+
+def _init(phys, mesh):
+    p = adg.make_params(phys)
+    d = adg.adg_mesh_desc()
+    d.x0, d.z0, d.Lx, d.Lz = 0.0, 0.0, float(mesh["Lx"]), float(mesh["Lz"])
+    d.nx, d.nz, d.max_level = mesh["nx"], mesh["nz"], mesh.get("max_level", 0)
+    for k, b in enumerate(mesh["bc"]):
+        d.bc[k] = b
+    h = ctypes.c_void_p()
+    rc = adg.lib().adg_init_mesh(ctypes.byref(p), ctypes.byref(d), ctypes.byref(h))
+    return rc, adg.lib().adg_last_error().decode()
+
+
+@pytest.mark.parametrize("change,msg", [
+    (dict(N=0), "order"), (dict(N=8), "order"), (dict(gamma=1.0), "gas"), (dict(cfl=0.0), "cfl"),
+    (dict(mu=-1.0), "gas"), (dict(picard_iters=-2), "picard"),
+])
+def test_invalid_params_rejected(change, msg):
+    w = I.bubble81()
+    phys = dict(w["phys"], **change)
+    rc, err = _init(phys, w["mesh"])
+    assert rc == adg.ADG_EINVAL and msg in err
+
+
+@pytest.mark.parametrize("change,msg", [
+    (dict(nx=0), "domain"), (dict(Lz=500.0), "square"), (dict(bc=[0, 1, 1, 1]), "pairs"),
+    (dict(bc=[1, 1, 7, 1]), "bc"), (dict(max_level=1), "max_level"),
+])
+def test_invalid_mesh_rejected(change, msg):
+    w = I.bubble81()
+    mesh = dict(w["mesh"], **change)
+    rc, err = _init(w["phys"], mesh)
+    assert rc == adg.ADG_EINVAL and msg in err
+
+
+def test_null_arguments_rejected():
+    L = adg.lib()
+    assert L.adg_step(None, None) == adg.ADG_EINVAL
+    assert L.adg_destroy(None) == adg.ADG_EINVAL
+    assert L.adg_set_state(None, None, None, None) == adg.ADG_EINVAL
