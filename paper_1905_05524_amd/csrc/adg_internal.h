@@ -28,16 +28,20 @@ struct Tab {
   double e0[n], e1[n];
 };
 
-// Lane-indexed tables in global memory (one per handle):
-//   xi[n], w[n], L0[n] = e0/w, L1[n] = e1/w, Pk[3][n][n] (sub-face k
-//   prolongation phi_m((k+xi_q)/3) at [k][q][m]), Rk[3][n][n] (restriction
-//   (w_q/3) phi_m((k+xi_q)/3)/w_m at [k][m][q]).
+// Tables in global memory (one per handle), read with lane-dependent or
+// runtime indices:
+//   xi[n], w[n], L0[n] = e0/w, L1[n] = e1/w, e0[n], e1[n],
+//   Pk[3][n][n]  sub-face k prolongation phi_m((k+xi_q)/3) at [k][q][m],
+//   Rk[3][n][n]  restriction (w_q/3) phi_m((k+xi_q)/3)/w_m at [k][m][q],
+//   D[n][n], Pt[n][n] (time matrix transposed: Pt[b][a] = P[a][b]), Dw[n][n].
 struct GTab {
-  static constexpr int XI = 0, W = 1, L0 = 2, L1 = 3;
-  static __host__ __device__ inline int off(int which, int n) { return which * n; }
-  static __host__ __device__ inline int pk(int n) { return 4 * n; }
-  static __host__ __device__ inline int rk(int n) { return 4 * n + 3 * n * n; }
-  static __host__ __device__ inline int size(int n) { return 4 * n + 6 * n * n; }
+  static constexpr int XI = 0, W = 1, L0 = 2, L1 = 3, E0 = 4, E1 = 5;
+  static __host__ __device__ inline int pk(int n) { return 6 * n; }
+  static __host__ __device__ inline int rk(int n) { return 6 * n + 3 * n * n; }
+  static __host__ __device__ inline int d(int n) { return 6 * n + 6 * n * n; }
+  static __host__ __device__ inline int pt(int n) { return 6 * n + 7 * n * n; }
+  static __host__ __device__ inline int dw(int n) { return 6 * n + 8 * n * n; }
+  static __host__ __device__ inline int size(int n) { return 6 * n + 9 * n * n; }
 };
 
 struct Phys {
@@ -72,7 +76,7 @@ struct adg_mesh {
   void* ws = nullptr;
   double* clock = nullptr;
   // workspace partition (bytes offsets)
-  size_t off_qs = 0, off_fd = 0, off_health = 0, ws_bytes = 0;
+  size_t off_qs = 0, off_fd = 0, off_dtc = 0, off_health = 0, ws_bytes = 0;
 };
 
 namespace adg {

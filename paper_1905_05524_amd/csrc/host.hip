@@ -141,7 +141,15 @@ static void build_basis(adg_mesh* m) {
     m->gtab_h[GTab::W * n + k] = (double)w[k];
     m->gtab_h[GTab::L0 * n + k] = (double)(e0[k] / w[k]);
     m->gtab_h[GTab::L1 * n + k] = (double)(e1[k] / w[k]);
+    m->gtab_h[GTab::E0 * n + k] = (double)e0[k];
+    m->gtab_h[GTab::E1 * n + k] = (double)e1[k];
   }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      m->gtab_h[GTab::d(n) + i * n + j] = m->D[i * n + j];
+      m->gtab_h[GTab::pt(n) + j * n + i] = m->P[i * n + j];
+      m->gtab_h[GTab::dw(n) + i * n + j] = m->Dw[i * n + j];
+    }
   for (int s = 0; s < 3; ++s)
     for (int q = 0; q < n; ++q)
       for (int mm = 0; mm < n; ++mm) {
@@ -341,6 +349,7 @@ int adg_init_mesh(const adg_params* prm, const adg_mesh_desc* mesh, adg_mesh** o
   size_t off = 0;
   m->off_qs = off; off = align256(off + sizeof(double) * (size_t)C * 4 * n * n);
   m->off_fd = off; off = align256(off + sizeof(double) * (size_t)C * 32 * n);
+  m->off_dtc = off; off = align256(off + sizeof(double) * (size_t)C);
   m->off_health = off; off = align256(off + sizeof(int));
   m->ws_bytes = off;
   *out = m;

@@ -25,20 +25,51 @@ struct LineJob {
   }
 };
 
-// out[i] = sum_m M[i][m] in[m] along this lane's line: src -> dst
+// Half tables: for Gauss-Legendre nodes (symmetric about 1/2) the derivative
+// matrix is centro-antisymmetric, D[n-1-i][n-1-m] = -D[i][m], and so is the
+// volume matrix Dw.  Only the first nh = ceil(n/2) rows are kept; row n-1-i is
+// applied as minus row i on the reversed input line.
 template <int n>
-__device__ inline void line_apply(const double (&M)[n][n], const LineJob<n>& J, const double* src,
+struct Half { static constexpr int nh = (n + 1) / 2; };
+
+// out[i] = sum_m M[i][m] in[m] along this lane's line: src -> dst.  M holds
+// the first nh rows in VGPRs (uniform values, loaded once per kernel).
+template <int n>
+__device__ inline void line_apply(const double (&M)[Half<n>::nh][n], const LineJob<n>& J, const double* src,
                                   double* dst) {
+  constexpr int nh = Half<n>::nh;
   double in[n];
 #pragma unroll
   for (int m = 0; m < n; ++m) in[m] = src[J.base + m * J.stride];
 #pragma unroll
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < nh; ++i) {
     double s = 0.0;
 #pragma unroll
     for (int m = 0; m < n; ++m) s = fma(M[i][m], in[m], s);
     dst[J.base + i * J.stride] = s;
   }
+#pragma unroll
+  for (int i = 0; i < n / 2; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < n; ++m) s = fma(M[i][m], in[n - 1 - m], s);
+    dst[J.base + (n - 1 - i) * J.stride] = -s;
+  }
+}
+
+// Load the first nh rows of an n x n table into VGPRs.  The empty asm marks
+// every value as lane-varying, so the compiler keeps the table in vector
+// registers instead of scalar registers (which cannot hold it and would
+// spill into lanes).
+template <int n>
+__device__ inline void load_vtab(const double* g, double (&M)[Half<n>::nh][n]) {
+#pragma unroll
+  for (int i = 0; i < Half<n>::nh; ++i)
+#pragma unroll
+    for (int m = 0; m < n; ++m) {
+      M[i][m] = g[i * n + m];
+      asm volatile("" : "+v"(M[i][m]));
+    }
 }
 
 struct StepArgs {
@@ -46,7 +77,8 @@ struct StepArgs {
   double* Qout;         // corrector output (may alias Qin)
   double* Qs;           // [C][4][n][n]  Q* = Q^n + dt (volume + source)
   double* FD;           // [C][4 faces][2][4][n]
-  double* clock;        // t, dt, next-dt bits, steps
+  double* dtc;          // [C] per-cell CFL candidates
+  double* clock;        // t, dt, (unused), steps
   const double* geom;   // [C][4]
   const int* nbr;       // [C][4][4]
   const double* gtab;
@@ -55,12 +87,39 @@ struct StepArgs {
 };
 
 // ------------------------------------------------------------------ predictor
+// Per cell (one wavefront): the Picard iterate of all n time nodes lives in
+// LDS (sq[b][v][j][i]).  Each sweep walks the time nodes in a runtime loop
+// that is software-pipelined by one node: a line phase computes the
+// divergence of the fluxes of node b and the gradients of node b+1, a node
+// phase forms the residual R(b) (rank-1 update acc[a] += P[a][b] R(b), kept
+// per node in registers) and the fluxes of node b+1.  Two barriers per node.
+
+// flux and source of time node b at this lane's node: q from the iterate,
+// gradients from sg; fluxes to sf
 template <int n>
-__global__ __launch_bounds__(kWave) void k_predictor(Tab<n> T, Phys ph, StepArgs a) {
+__device__ inline double node_flux(const Phys& ph, const double* qb, const double (*sg)[4 * n * n],
+                                   double (*sf)[4 * n * n], int lane, double ih, double z, double rb, double pb,
+                                   double q[4], double Fx[4], double Fz[4]) {
   constexpr int nn = n * n;
-  __shared__ double sq[4 * nn];
-  __shared__ double sg[2][4 * nn];
-  __shared__ double sf[2][4 * nn];
+  double gx[4], gz[4], Sw;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    q[v] = qb[v * nn + lane];
+    gx[v] = sg[0][v * nn + lane] * ih;
+    gz[v] = sg[1][v * nn + lane] * ih;
+  }
+  flux_source(ph, q, gx, gz, z, rb, pb, Fx, Fz, Sw);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) { sf[0][v * nn + lane] = Fx[v]; sf[1][v * nn + lane] = Fz[v]; }
+  return Sw;
+}
+
+template <int n>
+__global__ __launch_bounds__(kWave) void k_predictor(Phys ph, StepArgs a) {
+  constexpr int nn = n * n, sl = 4 * nn;
+  __shared__ double sq[n * sl];     // iterate at all time nodes; slot b takes R(b) once consumed
+  __shared__ double sg[2][sl];      // gradients (x, z) of the next time node
+  __shared__ double sf[2][sl];      // fluxes (x, z) of the current node, then their divergence
 
   const int c = blockIdx.x;
   const int lane = threadIdx.x;
@@ -68,34 +127,30 @@ __global__ __launch_bounds__(kWave) void k_predictor(Tab<n> T, Phys ph, StepArgs
   const int ln = node ? lane : 0;
   const int jz = ln / n, ix = ln % n;
   const LineJob<n> J(lane);
+  const double* gt = a.gtab;
 
-  if (c == 0 && lane == 0) {
-    // reset the next-dt accumulator (consumed by the corrector)
-    reinterpret_cast<unsigned long long*>(a.clock)[2] = 0x7ff0000000000000ull;
-  }
   const double t0 = a.clock[0], dt = a.clock[1];
   const double x0 = a.geom[4 * c + 0], z0 = a.geom[4 * c + 1], h = a.geom[4 * c + 2];
   const double ih = 1.0 / h;
-  const double x = x0 + h * a.gtab[GTab::XI * n + ix];
-  const double z = z0 + h * a.gtab[GTab::XI * n + jz];
+  const double x = x0 + h * gt[GTab::XI * n + ix];
+  const double z = z0 + h * gt[GTab::XI * n + jz];
   double rb, pb;
   background(ph, z, rb, pb);
 
-  const double* Qc = a.Qin + (size_t)c * 4 * nn;
+  double Dv[Half<n>::nh][n];
+  load_vtab<n>(gt + GTab::d(n), Dv);
+
+  const double* Qc = a.Qin + (size_t)c * sl;
   double Qn[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) Qn[v] = Qc[v * nn + ln];
-
-  // MMS source depends on (x, z, t) only: evaluate once per time node
-  double SE[n];
+  if (node) {
 #pragma unroll
-  for (int b = 0; b < n; ++b) SE[b] = ph.mms ? mms_source(ph, x, z, t0 + a.gtab[GTab::XI * n + b] * dt) : 0.0;
-
-  double q[n][4];
+    for (int b = 0; b < n; ++b)
 #pragma unroll
-  for (int b = 0; b < n; ++b)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) q[b][v] = Qn[v];
+      for (int v = 0; v < 4; ++v) sq[b * sl + v * nn + lane] = Qn[v];
+  }
+  __syncthreads();
 
   for (int it = 0; it < a.iters; ++it) {
     double acc[n][4];
@@ -103,70 +158,63 @@ __global__ __launch_bounds__(kWave) void k_predictor(Tab<n> T, Phys ph, StepArgs
     for (int b = 0; b < n; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[b][v] = 0.0;
-#pragma unroll
+#pragma unroll 1
     for (int b = 0; b < n; ++b) {
-      if (node) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) sq[v * nn + lane] = q[b][v];
-      }
-      __syncthreads();
-      if (J.active) line_apply<n>(T.D, J, sq, sg[J.dir]);
+      double* qb = sq + b * sl;
+      if (J.active) line_apply<n>(Dv, J, qb, sg[J.dir]);
       __syncthreads();
       double Sw = 0.0;
       if (node) {
-        double gx[4], gz[4], Fx[4], Fz[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) { gx[v] = sg[0][v * nn + lane] * ih; gz[v] = sg[1][v * nn + lane] * ih; }
-        flux_source(ph, q[b], gx, gz, z, rb, pb, Fx, Fz, Sw);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) { sf[0][v * nn + lane] = Fx[v]; sf[1][v * nn + lane] = Fz[v]; }
+        double q[4], Fx[4], Fz[4];
+        Sw = node_flux<n>(ph, qb, sg, sf, lane, ih, z, rb, pb, q, Fx, Fz);
       }
       __syncthreads();
-      if (J.active) line_apply<n>(T.D, J, sf[J.dir], sg[J.dir]);
+      if (J.active) line_apply<n>(Dv, J, sf[J.dir], sf[J.dir]);
       __syncthreads();
       if (node) {
         double R[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) R[v] = -(sg[0][v * nn + lane] + sg[1][v * nn + lane]) * ih;
+        for (int v = 0; v < 4; ++v) R[v] = -(sf[0][v * nn + lane] + sf[1][v * nn + lane]) * ih;
         R[2] += Sw;
-        R[3] += SE[b];
+        if (ph.mms) R[3] += mms_source(ph, x, z, t0 + gt[GTab::XI * n + b] * dt);
+        const double* pc = gt + GTab::pt(n) + b * n;
 #pragma unroll
-        for (int a2 = 0; a2 < n; ++a2)
+        for (int a2 = 0; a2 < n; ++a2) {
+          const double p = pc[a2];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[a2][v] = fma(T.P[a2][b], R[v], acc[a2][v]);
+          for (int v = 0; v < 4; ++v) acc[a2][v] = fma(p, R[v], acc[a2][v]);
+        }
       }
+      __syncthreads();
     }
+    if (node) {
 #pragma unroll
-    for (int b = 0; b < n; ++b)
+      for (int b = 0; b < n; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) q[b][v] = fma(dt, acc[b][v], Qn[v]);
+        for (int v = 0; v < 4; ++v) sq[b * sl + v * nn + lane] = fma(dt, acc[b][v], Qn[v]);
+    }
+    __syncthreads();
   }
 
   // time averages of q, F and S on the last iterate
   double Qb[4] = {0, 0, 0, 0}, Fbx[4] = {0, 0, 0, 0}, Fbz[4] = {0, 0, 0, 0}, Sbw = 0.0, SbE = 0.0;
-#pragma unroll
+#pragma unroll 1
   for (int b = 0; b < n; ++b) {
-    if (node) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) sq[v * nn + lane] = q[b][v];
-    }
-    __syncthreads();
-    if (J.active) line_apply<n>(T.D, J, sq, sg[J.dir]);
+    const double* qb = sq + b * sl;
+    if (J.active) line_apply<n>(Dv, J, qb, sg[J.dir]);
     __syncthreads();
     if (node) {
-      double gx[4], gz[4], Fx[4], Fz[4], Sw;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) { gx[v] = sg[0][v * nn + lane] * ih; gz[v] = sg[1][v * nn + lane] * ih; }
-      flux_source(ph, q[b], gx, gz, z, rb, pb, Fx, Fz, Sw);
-      const double wb = T.w[b];
+      double q[4], Fx[4], Fz[4];
+      const double Sw = node_flux<n>(ph, qb, sg, sf, lane, ih, z, rb, pb, q, Fx, Fz);
+      const double wb = gt[GTab::W * n + b];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        Qb[v] = fma(wb, q[b][v], Qb[v]);
+        Qb[v] = fma(wb, q[v], Qb[v]);
         Fbx[v] = fma(wb, Fx[v], Fbx[v]);
         Fbz[v] = fma(wb, Fz[v], Fbz[v]);
       }
       Sbw = fma(wb, Sw, Sbw);
-      SbE = fma(wb, SE[b], SbE);
+      if (ph.mms) SbE = fma(wb, mms_source(ph, x, z, t0 + gt[GTab::XI * n + b] * dt), SbE);
     }
     __syncthreads();
   }
@@ -184,22 +232,19 @@ __global__ __launch_bounds__(kWave) void k_predictor(Tab<n> T, Phys ph, StepArgs
   if (J.active) {
     // Dw contraction of the averaged flux along the line; extrapolation of the
     // averaged state and flux to both ends of the line.
+    double Wv[Half<n>::nh][n];
+    load_vtab<n>(gt + GTab::dw(n), Wv);
     const double* src = sf[J.dir];
+    line_apply<n>(Wv, J, src, sg[J.dir]);
     double inF[n], inQ[n];
 #pragma unroll
     for (int m = 0; m < n; ++m) { inF[m] = src[J.base + m * J.stride]; inQ[m] = sq[J.base + m * J.stride]; }
-#pragma unroll
-    for (int i = 0; i < n; ++i) {
-      double s = 0.0;
-#pragma unroll
-      for (int m = 0; m < n; ++m) s = fma(T.Dw[i][m], inF[m], s);
-      sg[J.dir][J.base + i * J.stride] = s;
-    }
     double q0 = 0, q1 = 0, f0 = 0, f1 = 0;
 #pragma unroll
     for (int m = 0; m < n; ++m) {
-      q0 = fma(T.e0[m], inQ[m], q0); q1 = fma(T.e1[m], inQ[m], q1);
-      f0 = fma(T.e0[m], inF[m], f0); f1 = fma(T.e1[m], inF[m], f1);
+      const double e0 = gt[GTab::E0 * n + m], e1 = gt[GTab::E1 * n + m];
+      q0 = fma(e0, inQ[m], q0); q1 = fma(e1, inQ[m], q1);
+      f0 = fma(e0, inF[m], f0); f1 = fma(e1, inF[m], f1);
     }
     const int v = (lane % (4 * n)) / n, line = lane % n;
     double* fd = a.FD + (size_t)c * 32 * n;
@@ -211,7 +256,7 @@ __global__ __launch_bounds__(kWave) void k_predictor(Tab<n> T, Phys ph, StepArgs
   }
   __syncthreads();
   if (node) {
-    double* qs = a.Qs + (size_t)c * 4 * nn;
+    double* qs = a.Qs + (size_t)c * sl;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       double S = (v == 2) ? Sbw : (v == 3 ? SbE : 0.0);
@@ -333,8 +378,7 @@ __global__ __launch_bounds__(kWave) void k_corrector(Tab<n> T, Phys ph, StepArgs
     lvm = wave_max(lvm);
     if (lane == 0) {
       const double o = 2.0 * ph.N + 1.0;
-      const double dtc = ph.cfl * h / (2.0 * o * (lam + 2.0 * lvm * o / h));
-      atomicMin(reinterpret_cast<unsigned long long*>(a.clock) + 2, (unsigned long long)__double_as_longlong(dtc));
+      a.dtc[c] = ph.cfl * h / (2.0 * o * (lam + 2.0 * lvm * o / h));
     }
   }
 }
@@ -364,20 +408,31 @@ __global__ __launch_bounds__(kWave) void k_cell_dt(Phys ph, StepArgs a) {
   lvm = wave_max(lvm);
   if (lane == 0) {
     const double o = 2.0 * ph.N + 1.0;
-    const double dtc = ph.cfl * h / (2.0 * o * (lam + 2.0 * lvm * o / h));
-    atomicMin(reinterpret_cast<unsigned long long*>(a.clock) + 2, (unsigned long long)__double_as_longlong(dtc));
+    a.dtc[c] = ph.cfl * h / (2.0 * o * (lam + 2.0 * lvm * o / h));
   }
 }
 
-__global__ void k_reset_dtacc(double* clock) {
-  reinterpret_cast<unsigned long long*>(clock)[2] = 0x7ff0000000000000ull;
-}
-
-// advance: t += dt, steps += 1 (if advance), dt <- min candidate (if update)
-__global__ void k_finalize(double* clock, int advance, int update) {
-  unsigned long long* u = reinterpret_cast<unsigned long long*>(clock);
-  if (advance) { clock[0] += clock[1]; clock[3] += 1.0; }
-  if (update) clock[1] = __longlong_as_double((long long)u[2]);
+// Clock update by one workgroup: if advance, t += dt and steps += 1; if
+// update, dt <- min over cells of the CFL candidates (a fixed reduction tree:
+// min is exact, so the result does not depend on the order anyway).
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void k_clock(double* clock, const double* dtc, int C, int advance,
+                                                           int update) {
+  __shared__ double sm[kReduceThreads / kWave];
+  const int t = threadIdx.x;
+  double m = __builtin_inf();
+  if (update)
+    for (int c = t; c < C; c += kReduceThreads) m = fmin(m, dtc[c]);
+  #pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmin(m, __shfl_xor(m, o, kWave));
+  if ((t & (kWave - 1)) == 0) sm[t / kWave] = m;
+  __syncthreads();
+  if (t == 0) {
+    double r = sm[0];
+    for (int k = 1; k < kReduceThreads / kWave; ++k) r = fmin(r, sm[k]);
+    if (advance) { clock[0] += clock[1]; clock[3] += 1.0; }
+    if (update) clock[1] = r;
+  }
 }
 
 // --------------------------------------------------------------- dispatchers
@@ -401,6 +456,7 @@ StepArgs make_args(adg_mesh* m) {
   a.Qin = m->Q; a.Qout = m->Q;
   a.Qs = reinterpret_cast<double*>(ws + m->off_qs);
   a.FD = reinterpret_cast<double*>(ws + m->off_fd);
+  a.dtc = reinterpret_cast<double*>(ws + m->off_dtc);
   a.health = reinterpret_cast<int*>(ws + m->off_health);
   a.clock = m->clock; a.geom = m->d_geom; a.nbr = m->d_nbr; a.gtab = m->d_gtab;
   a.C = m->C; a.iters = m->iters;
@@ -410,7 +466,7 @@ StepArgs make_args(adg_mesh* m) {
 template <int n>
 static int launch_predictor_n(adg_mesh* m, hipStream_t s) {
   StepArgs a = make_args(m);
-  hipLaunchKernelGGL(k_predictor<n>, dim3(m->C), dim3(kWave), 0, s, make_tab<n>(m), m->ph, a);
+  hipLaunchKernelGGL(k_predictor<n>, dim3(m->C), dim3(kWave), 0, s, m->ph, a);
   return check_launch("predictor");
 }
 template <int n>
@@ -419,15 +475,15 @@ static int launch_corrector_n(adg_mesh* m, hipStream_t s) {
   hipLaunchKernelGGL(k_corrector<n>, dim3(m->C), dim3(kWave), 0, s, make_tab<n>(m), m->ph, a);
   int rc = check_launch("corrector");
   if (rc) return rc;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, s, m->clock, 1, m->ph.fixed_dt ? 0 : 1);
-  return check_launch("finalize");
+  hipLaunchKernelGGL(k_clock, dim3(1), dim3(kReduceThreads), 0, s, m->clock, a.dtc, m->C, 1,
+                     m->ph.fixed_dt ? 0 : 1);
+  return check_launch("clock");
 }
 template <int n>
 static int launch_dt_n(adg_mesh* m, hipStream_t s) {
   StepArgs a = make_args(m);
-  hipLaunchKernelGGL(k_reset_dtacc, dim3(1), dim3(1), 0, s, m->clock);
   hipLaunchKernelGGL(k_cell_dt<n>, dim3(m->C), dim3(kWave), 0, s, m->ph, a);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, s, m->clock, 0, 1);
+  hipLaunchKernelGGL(k_clock, dim3(1), dim3(kReduceThreads), 0, s, m->clock, a.dtc, m->C, 0, 1);
   return check_launch("compute_dt");
 }
 
