@@ -18,7 +18,7 @@
  *     (x0 + h*xi_ix, z0 + h*xi_jz).  Energy includes the geopotential rho*g*z.
  *   - Cell order: for a uniform grid, c = j*nx + i; otherwise the order of
  *     the leaf list given to adg_init_mesh.
- *   - clock: device double[4] = (t, dt, next-dt accumulator, step count).
+ *   - clock: device double[4] = (t, dt, unused, step count).
  *     Time and time step live on the device so that a step needs no host
  *     scalar; the caller may write t and dt before a step.
  *   - Ownership: every device buffer passed in (Q, workspace, clock, tv,
@@ -165,6 +165,52 @@ const char* adg_last_error(void);
 /* Read back the handle's GL nodes/weights and matrices (n, n, n*n, n*n):
  * D[i*n+j] = phi_j'(xi_i), P = K1^{-1} W of the time predictor. */
 int adg_basis(const adg_mesh* m, double* xi, double* w, double* D, double* P);
+
+/* Launch shape of the predictor and corrector: cells per wavefront (1, 2 or
+ * 4, with cells_per_wave * n^2 <= 64) and wavefronts per workgroup (1, 2 or
+ * 4).  Results do not depend on the shape.  Default 1, 1. */
+int adg_set_launch(adg_mesh* m, int cells_per_wave, int waves_per_block);
+
+/* Time every launch shape on the bound state (reps predictor + corrector
+ * pairs each; the corrector writes into the workspace so Q and clock are left
+ * unchanged), keep the fastest and return it.  Synchronises the stream. */
+int adg_autotune(adg_mesh* m, int reps, void* stream, int* cells_per_wave, int* waves_per_block);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent scenarios (own mesh, own order, own clock) stepped
+ * together.  All scenarios share the physical parameters; orders may differ.
+ * Scenarios are grouped by order; each group is one concatenated cell array.
+ * One step forks one stream per order group (predictor, corrector), joins,
+ * and updates every scenario's clock (t, dt, steps) with its own CFL step.
+ * The state is one device array: scenario s occupies
+ * [q_offset, q_offset + n_cells*4*n*n) with the single-mesh layout; clocks
+ * is device double[n_scen][4]. */
+typedef struct adg_batch adg_batch;
+
+/* prm and mesh: host arrays of n_scen entries.  EINVAL if parameters other
+ * than the order differ between scenarios or a mesh is invalid. */
+int adg_batch_create(const adg_params* prm, const adg_mesh_desc* mesh, int n_scen, adg_batch** out);
+int adg_batch_destroy(adg_batch* b);
+int adg_batch_info(const adg_batch* b, int* n_groups, int* total_cells, size_t* q_doubles, size_t* ws_bytes);
+int adg_batch_scenario(const adg_batch* b, int s, size_t* q_offset, int* n_cells, int* n_nodes);
+/* Bind caller-owned device buffers (Q of q_doubles, workspace of ws_bytes,
+ * clocks [n_scen][4]); drops a captured graph. */
+int adg_batch_set_state(adg_batch* b, double* Q, void* workspace, double* clocks);
+/* As adg_init_state, for scenario s (synchronises). */
+int adg_batch_init_state(adg_batch* b, int s, int kind, int n_bubbles, const double* bubbles, double t0,
+                         void* stream);
+/* CFL time step of every scenario (writes clocks[s][1]). */
+int adg_batch_compute_dt(adg_batch* b, void* stream);
+/* One step of every scenario, launched eagerly. */
+int adg_batch_step(adg_batch* b, void* stream);
+/* One step of every scenario as one HIP graph launch: the first call on a
+ * stream captures the step (fork/join over the group streams) and
+ * instantiates it; later calls replay it.  stream must not be NULL. */
+int adg_batch_step_graph(adg_batch* b, void* stream);
+/* Autotune the launch shape of every order group (outputs: host arrays of
+ * n_groups entries, may be NULL).  Drops a captured graph.  Synchronises. */
+int adg_batch_autotune(adg_batch* b, int reps, void* stream, int* cells_per_wave, int* waves_per_block);
+int adg_batch_set_launch(adg_batch* b, int group, int cells_per_wave, int waves_per_block);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,10 @@ ADG_VAR_THETA, ADG_VAR_RHO = 0, 1
 EXPORTED = [
     "adg_init_mesh", "adg_destroy", "adg_mesh_info", "adg_workspace_bytes", "adg_set_state",
     "adg_init_state", "adg_compute_dt", "adg_predictor", "adg_corrector", "adg_step",
-    "adg_tv_indicator", "adg_check_health", "adg_last_error", "adg_basis",
+    "adg_tv_indicator", "adg_check_health", "adg_last_error", "adg_basis", "adg_set_launch",
+    "adg_autotune", "adg_batch_create", "adg_batch_destroy", "adg_batch_info", "adg_batch_scenario",
+    "adg_batch_set_state", "adg_batch_init_state", "adg_batch_compute_dt", "adg_batch_step",
+    "adg_batch_step_graph", "adg_batch_autotune", "adg_batch_set_launch",
 ]
 
 
@@ -77,6 +80,20 @@ def lib():
         L.adg_tv_indicator.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp]
         L.adg_last_error.restype = ctypes.c_char_p
         L.adg_basis.argtypes = [vp, dp, dp, dp, dp]
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.adg_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+        L.adg_autotune.argtypes = [vp, ctypes.c_int, vp, ip, ip]
+        L.adg_batch_create.argtypes = [ctypes.POINTER(adg_params), ctypes.POINTER(adg_mesh_desc), ctypes.c_int,
+                                       ctypes.POINTER(vp)]
+        L.adg_batch_destroy.argtypes = [vp]
+        L.adg_batch_info.argtypes = [vp, ip, ip, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+        L.adg_batch_scenario.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t), ip, ip]
+        L.adg_batch_set_state.argtypes = [vp, vp, vp, vp]
+        L.adg_batch_init_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, vp]
+        for name in ("adg_batch_compute_dt", "adg_batch_step", "adg_batch_step_graph"):
+            getattr(L, name).argtypes = [vp, vp]
+        L.adg_batch_autotune.argtypes = [vp, ctypes.c_int, vp, ip, ip]
+        L.adg_batch_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -106,6 +123,26 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def make_mesh_desc(mesh: dict, keep: list) -> adg_mesh_desc:
+    """Fill an adg_mesh_desc; leaf arrays are appended to `keep` (they must
+    outlive the call that reads them)."""
+    d = adg_mesh_desc()
+    d.x0, d.z0 = float(mesh.get("x0", 0.0)), float(mesh.get("z0", 0.0))
+    d.Lx, d.Lz = float(mesh["Lx"]), float(mesh["Lz"])
+    d.nx, d.nz = int(mesh["nx"]), int(mesh["nz"])
+    d.max_level = int(mesh.get("max_level", 0))
+    for k, b in enumerate(mesh.get("bc", [ADG_BC_WALL] * 4)):
+        d.bc[k] = int(b)
+    leaves = mesh.get("leaves")
+    if leaves is not None:
+        lv = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 3))
+        cols = [np.ascontiguousarray(lv[:, k]) for k in range(3)]
+        keep.extend(cols)
+        d.n_leaves = lv.shape[0]
+        d.leaf_level, d.leaf_i, d.leaf_j = (c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) for c in cols)
+    return d
+
+
 class Mesh:
     """Handle of one mesh + parameters; owns nothing on the device beyond the
     library's constant tables.  State buffers are torch tensors owned here."""
@@ -114,21 +151,8 @@ class Mesh:
         import torch
         self.phys, self.mesh_desc = dict(phys), dict(mesh)
         self._p = make_params(phys, fixed_dt)
-        d = adg_mesh_desc()
-        d.x0, d.z0 = float(mesh.get("x0", 0.0)), float(mesh.get("z0", 0.0))
-        d.Lx, d.Lz = float(mesh["Lx"]), float(mesh["Lz"])
-        d.nx, d.nz = int(mesh["nx"]), int(mesh["nz"])
-        d.max_level = int(mesh.get("max_level", 0))
-        for k, b in enumerate(mesh.get("bc", [ADG_BC_WALL] * 4)):
-            d.bc[k] = int(b)
-        leaves = mesh.get("leaves")
         self._keep = []
-        if leaves is not None:
-            lv = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 3))
-            cols = [np.ascontiguousarray(lv[:, k]) for k in range(3)]
-            self._keep = cols
-            d.n_leaves = lv.shape[0]
-            d.leaf_level, d.leaf_i, d.leaf_j = (c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) for c in cols)
+        d = make_mesh_desc(mesh, self._keep)
         self._d = d
         h = ctypes.c_void_p()
         _check(lib().adg_init_mesh(ctypes.byref(self._p), ctypes.byref(d), ctypes.byref(h)))
@@ -196,6 +220,14 @@ class Mesh:
     def check_health(self, stream=None):
         _check(lib().adg_check_health(self.h, _stream_ptr(stream)))
 
+    def set_launch(self, cells_per_wave: int, waves_per_block: int):
+        _check(lib().adg_set_launch(self.h, int(cells_per_wave), int(waves_per_block)))
+
+    def autotune(self, reps: int = 5, stream=None):
+        c, w = ctypes.c_int(), ctypes.c_int()
+        _check(lib().adg_autotune(self.h, int(reps), _stream_ptr(stream), ctypes.byref(c), ctypes.byref(w)))
+        return c.value, w.value
+
     def basis(self):
         n = self.n
         xi, w, D, P = np.zeros(n), np.zeros(n), np.zeros((n, n)), np.zeros((n, n))
@@ -221,6 +253,78 @@ class Mesh:
     @property
     def dt(self):
         return float(self.clock[1].item())
+
+
+class Batch:
+    """Many independent scenarios stepped together (scenarios grouped by
+    order; one device state array, one clock per scenario)."""
+
+    def __init__(self, workloads: list, fixed_dt: bool = False, device="cuda"):
+        import torch
+        S = len(workloads)
+        self.workloads = workloads
+        P = (adg_params * S)()
+        D = (adg_mesh_desc * S)()
+        self._keep = []
+        for s, w in enumerate(workloads):
+            P[s] = make_params(w["phys"], fixed_dt)
+            D[s] = make_mesh_desc(w["mesh"], self._keep)
+        h = ctypes.c_void_p()
+        _check(lib().adg_batch_create(P, D, S, ctypes.byref(h)))
+        self.h = h
+        self.S = S
+        ng, tc = ctypes.c_int(), ctypes.c_int()
+        qd, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().adg_batch_info(h, ctypes.byref(ng), ctypes.byref(tc), ctypes.byref(qd), ctypes.byref(wb)))
+        self.n_groups, self.C_total, self.q_doubles, self.ws_bytes = ng.value, tc.value, qd.value, wb.value
+        self.device = torch.device(device)
+        self.Q = torch.zeros(max(self.q_doubles, 1), dtype=torch.float64, device=self.device)
+        self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)
+        self.clock = torch.zeros((S, 4), dtype=torch.float64, device=self.device)
+        self.scen = []
+        for s in range(S):
+            off, nc, nn = ctypes.c_size_t(), ctypes.c_int(), ctypes.c_int()
+            _check(lib().adg_batch_scenario(h, s, ctypes.byref(off), ctypes.byref(nc), ctypes.byref(nn)))
+            self.scen.append((off.value, nc.value, nn.value))
+        _check(lib().adg_batch_set_state(h, ctypes.c_void_p(self.Q.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+                                         ctypes.c_void_p(self.clock.data_ptr())))
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().adg_batch_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def state(self, s):
+        """View of scenario s's state [C][4][n][n]."""
+        off, C, n = self.scen[s]
+        return self.Q[off:off + C * 4 * n * n].view(C, 4, n, n)
+
+    def init_state(self, s, kind="bubbles", bubbles=(), t0=0.0, stream=None):
+        bb = np.ascontiguousarray(np.asarray(bubbles, dtype=np.float64).reshape(-1, 6))
+        _check(lib().adg_batch_init_state(self.h, int(s), 1 if kind == "mms" else 0, bb.shape[0],
+                                          bb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(t0),
+                                          _stream_ptr(stream)))
+
+    def compute_dt(self, stream=None):
+        _check(lib().adg_batch_compute_dt(self.h, _stream_ptr(stream)))
+
+    def step(self, stream=None):
+        _check(lib().adg_batch_step(self.h, _stream_ptr(stream)))
+
+    def step_graph(self, stream):
+        _check(lib().adg_batch_step_graph(self.h, _stream_ptr(stream)))
+
+    def autotune(self, reps: int = 5, stream=None):
+        G = self.n_groups
+        c, w = (ctypes.c_int * G)(), (ctypes.c_int * G)()
+        _check(lib().adg_batch_autotune(self.h, int(reps), _stream_ptr(stream), c, w))
+        return list(c), list(w)
+
+    def set_launch(self, group: int, cells_per_wave: int, waves_per_block: int):
+        _check(lib().adg_batch_set_launch(self.h, int(group), int(cells_per_wave), int(waves_per_block)))
 
 
 def _align256(x):

@@ -55,27 +55,53 @@ struct Phys {
 
 enum FaceKind { kConforming = 0, kWall = 1, kFineSide = 2, kCoarseSide = 3 };
 
+// Everything a kernel launch needs for one set of cells of one order: the
+// cells of one mesh, or of all scenarios of one order in a batch.
+struct Group {
+  int n = 0, N = 0, iters = 0, C = 0;
+  Phys ph{};
+  // handle-owned device tables
+  double* d_geom = nullptr;   // [C][4] x0, z0, h, 0
+  int* d_nbr = nullptr;       // [C][4 faces][4] kind, a, b, c (cell indices local to the group)
+  double* d_gtab = nullptr;   // GTab layout
+  int* d_scen = nullptr;      // [C] scenario index into clock (NULL: all 0)
+  // caller-owned buffers bound by set_state
+  double* Q = nullptr;        // [C][4][n][n]
+  double* Qs = nullptr;       // [C][4][n][n]
+  double* FD = nullptr;       // [C][4][2][4][n]
+  double* dtc = nullptr;      // [C]
+  double* clock = nullptr;    // [S][4]
+  // launch shape: cells per wavefront, wavefronts per workgroup
+  int cpw = 1, wpb = 1;
+};
+
+// Host copies of the basis of one order.
+struct HostBasis {
+  int n = 0;
+  std::vector<double> xi, w, D, P, Dw, e0, e1, gtab;
+};
+
+// Host mesh: leaves, geometry and face table.
+struct HostMesh {
+  int C = 0;
+  std::vector<int> lev, ci, cj;
+  std::vector<double> geom;   // [C][4]
+  std::vector<int> nbr;       // [C][16]
+};
+
 }  // namespace adg
 
 struct adg_mesh {
   adg_params prm;
-  adg::Phys ph;
-  int N = 0, n = 0, iters = 0, C = 0;
   adg_mesh_desc desc{};
-  std::vector<int> lev, ci, cj;
-  std::vector<double> geom_h;         // [C][4] = x0, z0, h, 0
-  std::vector<int> nbr_h;             // [C][4 faces][4]
-  // host copies of the basis
-  std::vector<double> xi, w, D, P, Dw, e0, e1, gtab_h;
-  // device (handle-owned)
-  double* d_geom = nullptr;
-  int* d_nbr = nullptr;
-  double* d_gtab = nullptr;
+  adg::HostBasis basis;
+  adg::HostMesh hm;
+  adg::Group g;
   // bound (caller-owned)
   double* Q = nullptr;
   void* ws = nullptr;
   double* clock = nullptr;
-  // workspace partition (bytes offsets)
+  // workspace partition (byte offsets)
   size_t off_qs = 0, off_fd = 0, off_dtc = 0, off_health = 0, ws_bytes = 0;
 };
 

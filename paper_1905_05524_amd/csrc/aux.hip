@@ -10,6 +10,7 @@ namespace adg {
 // T = theta * Exner, at rest); kind 1: the manufactured density wave at t0.
 __global__ void k_init_state(Phys ph, int n, int C, const double* geom, const double* gtab, int kind,
                              int nbub, const double* bub, double t0, double* Q) {
+  // geom and Q point at the first cell of the range
   const int nn = n * n;
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (long long)C * nn) return;
@@ -157,57 +158,60 @@ __global__ void k_health(Phys ph, int n, int C, const double* Q, const double* g
 }
 
 // --------------------------------------------------------------- launchers
-int launch_init_state(adg_mesh* m, int kind, int nbub, const double* d_bub, double t0, hipStream_t s) {
-  const long long tot = (long long)m->C * m->n * m->n;
+int launch_init_state(const Group& g, int c0, int count, int kind, int nbub, const double* d_bub, double t0,
+                      hipStream_t s) {
+  const long long tot = (long long)count * g.n * g.n;
+  if (tot == 0) return ADG_OK;
   const int bs = 256;
   const long long nb = (tot + bs - 1) / bs;
-  hipLaunchKernelGGL(k_init_state, dim3((unsigned)nb), dim3(bs), 0, s, m->ph, m->n, m->C, m->d_geom,
-                     m->d_gtab, kind, nbub, d_bub, t0, m->Q);
+  hipLaunchKernelGGL(k_init_state, dim3((unsigned)nb), dim3(bs), 0, s, g.ph, g.n, count, g.d_geom + 4 * (size_t)c0,
+                     g.d_gtab, kind, nbub, d_bub, t0, g.Q + (size_t)c0 * 4 * g.n * g.n);
   return check_launch("init_state");
 }
 
 template <int n>
-static Tab<n> tab_of(const adg_mesh* m) {
+static Tab<n> tab_of(const HostBasis& B) {
   Tab<n> T;
   for (int i = 0; i < n; ++i) {
-    T.w[i] = m->w[i]; T.e0[i] = m->e0[i]; T.e1[i] = m->e1[i];
+    T.w[i] = B.w[i]; T.e0[i] = B.e0[i]; T.e1[i] = B.e1[i];
     for (int j = 0; j < n; ++j) {
-      T.D[i][j] = m->D[i * n + j]; T.P[i][j] = m->P[i * n + j]; T.Dw[i][j] = m->Dw[i * n + j];
+      T.D[i][j] = B.D[i * n + j]; T.P[i][j] = B.P[i * n + j]; T.Dw[i][j] = B.Dw[i * n + j];
     }
   }
   return T;
 }
 
 template <int n>
-static int launch_tv_n(adg_mesh* m, int var, double* tv, hipStream_t s) {
-  hipLaunchKernelGGL(k_tv<n>, dim3(m->C), dim3(kWave), 0, s, tab_of<n>(m), m->ph, m->Q, m->d_geom,
-                     m->d_gtab, var, tv);
+static int launch_tv_n(const Group& g, const HostBasis& B, int var, double* tv, hipStream_t s) {
+  hipLaunchKernelGGL(k_tv<n>, dim3(g.C), dim3(kWave), 0, s, tab_of<n>(B), g.ph, g.Q, g.d_geom, g.d_gtab, var, tv);
   return check_launch("tv");
 }
 
-int launch_tv(adg_mesh* m, int var, double Tr, double Tc, double* tv, int8_t* flags, double* stats,
-              hipStream_t s) {
+int launch_tv(const Group& g, const HostBasis& B, int var, double Tr, double Tc, double* tv, int8_t* flags,
+              double* stats, hipStream_t s) {
   int rc;
-  switch (m->n) {
-    case 2: rc = launch_tv_n<2>(m, var, tv, s); break;
-    case 3: rc = launch_tv_n<3>(m, var, tv, s); break;
-    case 4: rc = launch_tv_n<4>(m, var, tv, s); break;
-    case 5: rc = launch_tv_n<5>(m, var, tv, s); break;
-    case 6: rc = launch_tv_n<6>(m, var, tv, s); break;
-    case 7: rc = launch_tv_n<7>(m, var, tv, s); break;
-    case 8: rc = launch_tv_n<8>(m, var, tv, s); break;
+  if (g.C == 0) return fail(ADG_EINVAL, "empty mesh");
+  switch (g.n) {
+    case 2: rc = launch_tv_n<2>(g, B, var, tv, s); break;
+    case 3: rc = launch_tv_n<3>(g, B, var, tv, s); break;
+    case 4: rc = launch_tv_n<4>(g, B, var, tv, s); break;
+    case 5: rc = launch_tv_n<5>(g, B, var, tv, s); break;
+    case 6: rc = launch_tv_n<6>(g, B, var, tv, s); break;
+    case 7: rc = launch_tv_n<7>(g, B, var, tv, s); break;
+    case 8: rc = launch_tv_n<8>(g, B, var, tv, s); break;
     default: return fail(ADG_EUNSUPPORTED, "order not supported");
   }
   if (rc) return rc;
-  hipLaunchKernelGGL(k_stats_flags, dim3(1), dim3(kStatThreads), 0, s, tv, m->C, Tr, Tc, flags, stats);
+  hipLaunchKernelGGL(k_stats_flags, dim3(1), dim3(kStatThreads), 0, s, tv, g.C, Tr, Tc, flags, stats);
   return check_launch("stats_flags");
 }
 
-int launch_health(adg_mesh* m, int* flag, hipStream_t s) {
-  const long long tot = (long long)m->C * m->n * m->n;
+int launch_health(const Group& g, int* flag, hipStream_t s) {
+  const long long tot = (long long)g.C * g.n * g.n;
+  if (tot == 0) return ADG_OK;
   const int bs = 256;
-  hipLaunchKernelGGL(k_health, dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, s, m->ph, m->n, m->C, m->Q,
-                     m->d_geom, m->d_gtab, flag);
+  hipLaunchKernelGGL(k_health, dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, s, g.ph, g.n, g.C, g.Q,
+                     g.d_geom, g.d_gtab, flag);
   return check_launch("health");
 }
 

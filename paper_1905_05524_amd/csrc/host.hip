@@ -9,13 +9,17 @@
 
 namespace adg {
 
-int launch_predictor(adg_mesh* m, hipStream_t s);
-int launch_corrector(adg_mesh* m, hipStream_t s);
-int launch_dt(adg_mesh* m, hipStream_t s);
-int launch_init_state(adg_mesh* m, int kind, int nbub, const double* d_bub, double t0, hipStream_t s);
-int launch_tv(adg_mesh* m, int var, double Tr, double Tc, double* tv, int8_t* flags, double* stats,
-              hipStream_t s);
-int launch_health(adg_mesh* m, int* flag, hipStream_t s);
+int launch_predictor(const Group& g, hipStream_t s);
+int launch_corrector(const Group& g, hipStream_t s);
+int launch_cell_dt(const Group& g, hipStream_t s);
+int launch_clock(double* clock, const double* dtc, const int* beg, const int* end, int nscen, int C, int advance,
+                 int update, hipStream_t s);
+int max_cpw(int n);
+int launch_init_state(const Group& g, int c0, int count, int kind, int nbub, const double* d_bub, double t0,
+                      hipStream_t s);
+int launch_tv(const Group& g, const HostBasis& B, int var, double Tr, double Tc, double* tv, int8_t* flags,
+              double* stats, hipStream_t s);
+int launch_health(const Group& g, int* flag, hipStream_t s);
 
 static thread_local std::string g_err;
 
@@ -76,8 +80,8 @@ static long double bary_phi(const std::vector<long double>& x, const std::vector
   return num / den;
 }
 
-static void build_basis(adg_mesh* m) {
-  const int n = m->n;
+static void build_basis(int n, HostBasis& B) {
+  B.n = n;
   std::vector<long double> x, w;
   gauss_legendre(n, x, w);
   std::vector<long double> lam(n, 1.0L);
@@ -123,39 +127,39 @@ static void build_basis(adg_mesh* m) {
     }
     for (int r = 0; r < n; ++r) X[r * n + col] = y[r];
   }
-  m->xi.resize(n); m->w.resize(n); m->e0.resize(n); m->e1.resize(n);
-  m->D.resize(n * n); m->P.resize(n * n); m->Dw.resize(n * n);
+  B.xi.resize(n); B.w.resize(n); B.e0.resize(n); B.e1.resize(n);
+  B.D.resize(n * n); B.P.resize(n * n); B.Dw.resize(n * n);
   for (int k = 0; k < n; ++k) {
-    m->xi[k] = (double)x[k]; m->w[k] = (double)w[k];
-    m->e0[k] = (double)e0[k]; m->e1[k] = (double)e1[k];
+    B.xi[k] = (double)x[k]; B.w[k] = (double)w[k];
+    B.e0[k] = (double)e0[k]; B.e1[k] = (double)e1[k];
   }
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {
-      m->D[i * n + j] = (double)D[i * n + j];
-      m->P[i * n + j] = (double)X[i * n + j];
-      m->Dw[i * n + j] = (double)(w[j] * D[j * n + i] / w[i]);
+      B.D[i * n + j] = (double)D[i * n + j];
+      B.P[i * n + j] = (double)X[i * n + j];
+      B.Dw[i * n + j] = (double)(w[j] * D[j * n + i] / w[i]);
     }
-  m->gtab_h.assign(GTab::size(n), 0.0);
+  B.gtab.assign(GTab::size(n), 0.0);
   for (int k = 0; k < n; ++k) {
-    m->gtab_h[GTab::XI * n + k] = (double)x[k];
-    m->gtab_h[GTab::W * n + k] = (double)w[k];
-    m->gtab_h[GTab::L0 * n + k] = (double)(e0[k] / w[k]);
-    m->gtab_h[GTab::L1 * n + k] = (double)(e1[k] / w[k]);
-    m->gtab_h[GTab::E0 * n + k] = (double)e0[k];
-    m->gtab_h[GTab::E1 * n + k] = (double)e1[k];
+    B.gtab[GTab::XI * n + k] = (double)x[k];
+    B.gtab[GTab::W * n + k] = (double)w[k];
+    B.gtab[GTab::L0 * n + k] = (double)(e0[k] / w[k]);
+    B.gtab[GTab::L1 * n + k] = (double)(e1[k] / w[k]);
+    B.gtab[GTab::E0 * n + k] = (double)e0[k];
+    B.gtab[GTab::E1 * n + k] = (double)e1[k];
   }
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {
-      m->gtab_h[GTab::d(n) + i * n + j] = m->D[i * n + j];
-      m->gtab_h[GTab::pt(n) + j * n + i] = m->P[i * n + j];
-      m->gtab_h[GTab::dw(n) + i * n + j] = m->Dw[i * n + j];
+      B.gtab[GTab::d(n) + i * n + j] = B.D[i * n + j];
+      B.gtab[GTab::pt(n) + j * n + i] = B.P[i * n + j];
+      B.gtab[GTab::dw(n) + i * n + j] = B.Dw[i * n + j];
     }
   for (int s = 0; s < 3; ++s)
     for (int q = 0; q < n; ++q)
       for (int mm = 0; mm < n; ++mm) {
         long double ph = bary_phi(x, lam, mm, (s + x[q]) / 3.0L);
-        m->gtab_h[GTab::pk(n) + (s * n + q) * n + mm] = (double)ph;
-        m->gtab_h[GTab::rk(n) + (s * n + mm) * n + q] = (double)((w[q] / 3.0L) * ph / w[mm]);
+        B.gtab[GTab::pk(n) + (s * n + q) * n + mm] = (double)ph;
+        B.gtab[GTab::rk(n) + (s * n + mm) * n + q] = (double)((w[q] / 3.0L) * ph / w[mm]);
       }
 }
 
@@ -163,19 +167,18 @@ static void build_basis(adg_mesh* m) {
 static long long key3(int l, int i, int j) { return ((long long)l << 52) ^ ((long long)i << 26) ^ (long long)j; }
 static int pow3(int e) { int r = 1; while (e-- > 0) r *= 3; return r; }
 
-static int build_mesh(adg_mesh* m) {
-  const adg_mesh_desc& d = m->desc;
+static int build_mesh(const adg_mesh_desc& d, HostMesh& H) {
   const bool uniform = d.leaf_level == nullptr;
   const int C = uniform ? d.nx * d.nz : d.n_leaves;
-  m->C = C;
-  m->lev.resize(C); m->ci.resize(C); m->cj.resize(C);
+  H.C = C;
+  H.lev.resize(C); H.ci.resize(C); H.cj.resize(C);
   for (int c = 0; c < C; ++c) {
-    if (uniform) { m->lev[c] = 0; m->ci[c] = c % d.nx; m->cj[c] = c / d.nx; }
-    else { m->lev[c] = d.leaf_level[c]; m->ci[c] = d.leaf_i[c]; m->cj[c] = d.leaf_j[c]; }
-    const int l = m->lev[c];
+    if (uniform) { H.lev[c] = 0; H.ci[c] = c % d.nx; H.cj[c] = c / d.nx; }
+    else { H.lev[c] = d.leaf_level[c]; H.ci[c] = d.leaf_i[c]; H.cj[c] = d.leaf_j[c]; }
+    const int l = H.lev[c];
     if (l < 0 || l > d.max_level) return fail(ADG_EINVAL, "leaf level out of range");
     const int s = pow3(l);
-    if (m->ci[c] < 0 || m->ci[c] >= d.nx * s || m->cj[c] < 0 || m->cj[c] >= d.nz * s)
+    if (H.ci[c] < 0 || H.ci[c] >= d.nx * s || H.cj[c] < 0 || H.cj[c] >= d.nz * s)
       return fail(ADG_EINVAL, "leaf index out of range");
   }
   std::unordered_map<long long, int> idx;
@@ -183,36 +186,36 @@ static int build_mesh(adg_mesh* m) {
   long long area = 0;
   const int L = d.max_level;
   for (int c = 0; c < C; ++c) {
-    if (!idx.emplace(key3(m->lev[c], m->ci[c], m->cj[c]), c).second) return fail(ADG_EINVAL, "duplicate leaf");
-    const long long s = pow3(L - m->lev[c]);
+    if (!idx.emplace(key3(H.lev[c], H.ci[c], H.cj[c]), c).second) return fail(ADG_EINVAL, "duplicate leaf");
+    const long long s = pow3(L - H.lev[c]);
     area += s * s;
   }
   const long long full = (long long)d.nx * pow3(L) * (long long)d.nz * pow3(L);
   if (area != full) return fail(ADG_EINVAL, "leaves do not tile the domain");
   for (int c = 0; c < C; ++c) {   // no leaf may have an ancestor among the leaves
-    int l = m->lev[c], i = m->ci[c], j = m->cj[c];
+    int l = H.lev[c], i = H.ci[c], j = H.cj[c];
     while (l > 0) {
       l -= 1; i /= 3; j /= 3;
       if (idx.count(key3(l, i, j))) return fail(ADG_EINVAL, "leaf overlaps an ancestor");
     }
   }
   const double hc = d.Lx / d.nx;
-  m->geom_h.assign((size_t)C * 4, 0.0);
-  m->nbr_h.assign((size_t)C * 16, -1);
+  H.geom.assign((size_t)C * 4, 0.0);
+  H.nbr.assign((size_t)C * 16, -1);
   for (int c = 0; c < C; ++c) {
-    const int l = m->lev[c];
+    const int l = H.lev[c];
     const double h = hc / pow3(l);
-    m->geom_h[4 * c + 0] = d.x0 + m->ci[c] * h;
-    m->geom_h[4 * c + 1] = d.z0 + m->cj[c] * h;
-    m->geom_h[4 * c + 2] = h;
+    H.geom[4 * c + 0] = d.x0 + H.ci[c] * h;
+    H.geom[4 * c + 1] = d.z0 + H.cj[c] * h;
+    H.geom[4 * c + 2] = h;
   }
   const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
   for (int c = 0; c < C; ++c) {
-    const int l = m->lev[c];
+    const int l = H.lev[c];
     const int NX = d.nx * pow3(l), NZ = d.nz * pow3(l);
     for (int f = 0; f < 4; ++f) {
-      int* nb = &m->nbr_h[(size_t)c * 16 + f * 4];
-      int i = m->ci[c] + di[f], j = m->cj[c] + dj[f];
+      int* nb = &H.nbr[(size_t)c * 16 + f * 4];
+      int i = H.ci[c] + di[f], j = H.cj[c] + dj[f];
       if (i < 0 || i >= NX || j < 0 || j >= NZ) {
         if (d.bc[f] == ADG_BC_WALL) { nb[0] = kWall; continue; }
         i = (i + NX) % NX; j = (j + NZ) % NZ;
@@ -223,7 +226,7 @@ static int build_mesh(adg_mesh* m) {
         auto pc = idx.find(key3(l - 1, i / 3, j / 3));
         if (pc != idx.end()) {
           nb[0] = kFineSide; nb[1] = pc->second;
-          nb[2] = (f < 2) ? (m->cj[c] % 3) : (m->ci[c] % 3);
+          nb[2] = (f < 2) ? (H.cj[c] % 3) : (H.ci[c] % 3);
           continue;
         }
       }
@@ -248,8 +251,8 @@ static int build_mesh(adg_mesh* m) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static int validate(const adg_params* p, const adg_mesh_desc* d) {
-  if (!p || !d) return fail(ADG_EINVAL, "null params or mesh");
+static int validate_params(const adg_params* p) {
+  if (!p) return fail(ADG_EINVAL, "null params");
   if (p->order < 1 || p->order > kMaxN - 1) return fail(ADG_EINVAL, "order must be in 1..7");
   if (p->picard_iters < 0) return fail(ADG_EINVAL, "picard_iters < 0");
   if (!(p->gamma > 1.0) || !(p->R > 0.0) || !(p->cp > 0.0) || !(p->Pr > 0.0) || !(p->mu >= 0.0))
@@ -257,6 +260,11 @@ static int validate(const adg_params* p, const adg_mesh_desc* d) {
   if (p->gravity && (!(p->theta_bg > 0.0) || !(p->p0 > 0.0) || !(p->g >= 0.0)))
     return fail(ADG_EINVAL, "invalid background atmosphere");
   if (!(p->cfl > 0.0)) return fail(ADG_EINVAL, "cfl must be > 0");
+  return ADG_OK;
+}
+
+static int validate_mesh(const adg_mesh_desc* d) {
+  if (!d) return fail(ADG_EINVAL, "null mesh");
   if (d->nx < 1 || d->nz < 1 || !(d->Lx > 0.0) || !(d->Lz > 0.0)) return fail(ADG_EINVAL, "invalid domain");
   if (std::fabs(d->Lx / d->nx - d->Lz / d->nz) > 1e-12 * (d->Lx / d->nx))
     return fail(ADG_EINVAL, "cells must be square (Lx/nx == Lz/nz)");
@@ -276,9 +284,8 @@ static int validate(const adg_params* p, const adg_mesh_desc* d) {
   return ADG_OK;
 }
 
-static void set_phys(adg_mesh* m) {
-  const adg_params& p = m->prm;
-  Phys& ph = m->ph;
+static Phys make_phys(const adg_params& p) {
+  Phys ph{};
   ph.gamma = p.gamma; ph.gm1 = p.gamma - 1.0; ph.R = p.R; ph.iR = 1.0 / p.R; ph.cp = p.cp; ph.Pr = p.Pr;
   ph.mu = p.mu; ph.kappa = p.mu * p.cp / p.Pr; ph.g = p.g; ph.p0 = p.p0; ph.theta = p.theta_bg;
   ph.cp_over_R = p.cp / p.R; ph.R_over_cp = p.R / p.cp;
@@ -288,13 +295,37 @@ static void set_phys(adg_mesh* m) {
   ph.mms_kx = p.mms_kx; ph.mms_kz = p.mms_kz; ph.mms_p = p.mms_p;
   ph.cfl = p.cfl; ph.gravity = p.gravity ? 1 : 0; ph.mms = p.mms ? 1 : 0; ph.fixed_dt = p.fixed_dt ? 1 : 0;
   ph.N = p.order;
+  return ph;
 }
 
-static void free_dev(adg_mesh* m) {
-  if (m->d_geom) (void)hipFree(m->d_geom);
-  if (m->d_nbr) (void)hipFree(m->d_nbr);
-  if (m->d_gtab) (void)hipFree(m->d_gtab);
-  m->d_geom = nullptr; m->d_nbr = nullptr; m->d_gtab = nullptr;
+static void free_group(Group& g) {
+  if (g.d_geom) (void)hipFree(g.d_geom);
+  if (g.d_nbr) (void)hipFree(g.d_nbr);
+  if (g.d_gtab) (void)hipFree(g.d_gtab);
+  if (g.d_scen) (void)hipFree(g.d_scen);
+  g.d_geom = nullptr; g.d_nbr = nullptr; g.d_gtab = nullptr; g.d_scen = nullptr;
+}
+
+// Allocate and upload a group's tables.
+static int upload_group(Group& g, const std::vector<double>& geom, const std::vector<int>& nbr,
+                        const std::vector<double>& gtab, const std::vector<int>* scen) {
+  const size_t C = (size_t)g.C;
+  hipError_t e = hipSuccess;
+  if (C) {
+    e = hipMalloc(&g.d_geom, sizeof(double) * 4 * C);
+    if (e == hipSuccess) e = hipMalloc(&g.d_nbr, sizeof(int) * 16 * C);
+    if (e == hipSuccess && scen) e = hipMalloc(&g.d_scen, sizeof(int) * C);
+  }
+  if (e == hipSuccess) e = hipMalloc(&g.d_gtab, sizeof(double) * gtab.size());
+  if (e != hipSuccess) { free_group(g); return fail(ADG_ENOMEM, "device allocation failed"); }
+  if (C) {
+    e = hipMemcpy(g.d_geom, geom.data(), sizeof(double) * 4 * C, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(g.d_nbr, nbr.data(), sizeof(int) * 16 * C, hipMemcpyHostToDevice);
+    if (e == hipSuccess && scen) e = hipMemcpy(g.d_scen, scen->data(), sizeof(int) * C, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipMemcpy(g.d_gtab, gtab.data(), sizeof(double) * gtab.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { free_group(g); return fail(ADG_EHIP, "upload failed"); }
+  return ADG_OK;
 }
 
 static int need_state(adg_mesh* m) {
@@ -303,53 +334,113 @@ static int need_state(adg_mesh* m) {
   return ADG_OK;
 }
 
+static int check_bubbles(int kind, int gravity, int n_bubbles, const double* bubbles) {
+  if (kind != 0 && kind != 1) return fail(ADG_EINVAL, "kind must be 0 (bubbles) or 1 (manufactured)");
+  if (kind == 0 && !gravity) return fail(ADG_EINVAL, "bubble states need gravity (background)");
+  if (n_bubbles < 0 || n_bubbles > 16 || (n_bubbles > 0 && !bubbles)) return fail(ADG_EINVAL, "bad bubble list");
+  for (int b = 0; b < n_bubbles; ++b) {
+    const double* bb = bubbles + 6 * b;
+    if (bb[0] != ADG_SHAPE_COSINE && bb[0] != ADG_SHAPE_PLATEAU_GAUSS) return fail(ADG_EINVAL, "bad bubble shape");
+    if (bb[0] == ADG_SHAPE_COSINE && !(bb[2] > 0.0)) return fail(ADG_EINVAL, "cosine bubble radius must be > 0");
+    if (bb[0] == ADG_SHAPE_PLATEAU_GAUSS && !(bb[3] > 0.0)) return fail(ADG_EINVAL, "decay s must be > 0");
+  }
+  return ADG_OK;
+}
+
+// init_state on cells [c0, c0+count) of a group (synchronous: the bubble list
+// travels through a temporary device copy).
+static int init_state_range(const Group& g, int c0, int count, int kind, int n_bubbles, const double* bubbles,
+                            double t0, hipStream_t s) {
+  double* d_bub = nullptr;
+  if (n_bubbles > 0) {
+    if (hipMalloc(&d_bub, sizeof(double) * 6 * n_bubbles) != hipSuccess) return fail(ADG_ENOMEM, "alloc");
+    if (hipMemcpy(d_bub, bubbles, sizeof(double) * 6 * n_bubbles, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(d_bub);
+      return fail(ADG_EHIP, "upload bubbles");
+    }
+  }
+  int rc = launch_init_state(g, c0, count, kind, n_bubbles, d_bub, t0, s);
+  if (d_bub) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(d_bub);
+  }
+  return rc;
+}
+
+// Time pred + corr (corrector writing into Q*, so the state is untouched) for
+// every launch shape and keep the fastest.
+static int autotune_group(Group& g, hipStream_t s, int reps, float* best_ms) {
+  if (g.C == 0) return ADG_OK;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(ADG_EHIP, "event");
+  const int cpws[3] = {1, 2, 4}, wpbs[3] = {1, 2, 4};
+  int bc = g.cpw, bw = g.wpb;
+  float best = 1e30f;
+  double* Qsave = g.Q;
+  for (int ci = 0; ci < 3; ++ci) {
+    if (cpws[ci] > max_cpw(g.n)) continue;
+    for (int wi = 0; wi < 3; ++wi) {
+      Group t = g;
+      t.cpw = cpws[ci]; t.wpb = wpbs[wi];
+      Group tc = t;
+      tc.Q = t.Qs;   // corrector reads Q*, writes in place: state untouched
+      (void)Qsave;
+      int rc = launch_predictor(t, s);   // warm-up
+      if (!rc) rc = launch_corrector(tc, s);
+      if (rc) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return rc; }
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps; ++r) {
+        launch_predictor(t, s);
+        launch_corrector(tc, s);
+      }
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) { best = ms; bc = t.cpw; bw = t.wpb; }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g.cpw = bc; g.wpb = bw;
+  if (best_ms) *best_ms = best / reps;
+  return check_launch("autotune");
+}
+
 }  // namespace adg
 
 using namespace adg;
 
+// ================================================================ single mesh
 extern "C" {
 
 const char* adg_last_error(void) { return g_err.c_str(); }
 
 int adg_init_mesh(const adg_params* prm, const adg_mesh_desc* mesh, adg_mesh** out) {
   if (!out) return fail(ADG_EINVAL, "null out");
-  int rc = validate(prm, mesh);
+  int rc = validate_params(prm);
+  if (!rc) rc = validate_mesh(mesh);
   if (rc) return rc;
   adg_mesh* m = new (std::nothrow) adg_mesh();
   if (!m) return fail(ADG_ENOMEM, "out of host memory");
   m->prm = *prm;
+  rc = build_mesh(*mesh, m->hm);
   m->desc = *mesh;
-  m->desc.leaf_level = m->desc.leaf_i = m->desc.leaf_j = nullptr;
-  m->N = prm->order; m->n = prm->order + 1;
-  m->iters = prm->picard_iters > 0 ? prm->picard_iters : prm->order + 1;
-  set_phys(m);
-  // build the mesh from the caller's leaf arrays (not retained)
-  adg_mesh_desc d = *mesh;
-  m->desc = d;
-  rc = build_mesh(m);
-  m->desc.leaf_level = m->desc.leaf_i = m->desc.leaf_j = nullptr;
+  m->desc.leaf_level = m->desc.leaf_i = m->desc.leaf_j = nullptr;   // not retained
   if (rc) { delete m; return rc; }
-  for (size_t k = 0; k < m->nbr_h.size(); k += 4)
-    if (m->nbr_h[k] == kFineSide || m->nbr_h[k] == kCoarseSide) {
-      delete m;
-      return fail(ADG_EUNSUPPORTED, "non-conforming faces are not supported by this build");
-    }
-  build_basis(m);
-  const int C = m->C, n = m->n;
-  hipError_t e = hipMalloc(&m->d_geom, sizeof(double) * 4 * C);
-  if (e == hipSuccess) e = hipMalloc(&m->d_nbr, sizeof(int) * 16 * C);
-  if (e == hipSuccess) e = hipMalloc(&m->d_gtab, sizeof(double) * m->gtab_h.size());
-  if (e != hipSuccess) { free_dev(m); delete m; return fail(ADG_ENOMEM, "device allocation failed"); }
-  e = hipMemcpy(m->d_geom, m->geom_h.data(), sizeof(double) * 4 * C, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(m->d_nbr, m->nbr_h.data(), sizeof(int) * 16 * C, hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(m->d_gtab, m->gtab_h.data(), sizeof(double) * m->gtab_h.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) { free_dev(m); delete m; return fail(ADG_EHIP, "upload failed"); }
-  // workspace: Q* [C][4][n][n], face data [C][4][2][4][n], health flag
+  const int n = prm->order + 1;
+  build_basis(n, m->basis);
+  Group& g = m->g;
+  g.n = n; g.N = prm->order; g.iters = prm->picard_iters > 0 ? prm->picard_iters : n;
+  g.C = m->hm.C; g.ph = make_phys(*prm);
+  rc = upload_group(g, m->hm.geom, m->hm.nbr, m->basis.gtab, nullptr);
+  if (rc) { delete m; return rc; }
+  // workspace: Q* [C][4][n][n], face data [C][4][2][4][n], CFL candidates, health flag
+  const size_t C = (size_t)g.C;
   size_t off = 0;
-  m->off_qs = off; off = align256(off + sizeof(double) * (size_t)C * 4 * n * n);
-  m->off_fd = off; off = align256(off + sizeof(double) * (size_t)C * 32 * n);
-  m->off_dtc = off; off = align256(off + sizeof(double) * (size_t)C);
+  m->off_qs = off; off = align256(off + sizeof(double) * C * 4 * n * n);
+  m->off_fd = off; off = align256(off + sizeof(double) * C * 32 * n);
+  m->off_dtc = off; off = align256(off + sizeof(double) * C);
   m->off_health = off; off = align256(off + sizeof(int));
   m->ws_bytes = off;
   *out = m;
@@ -358,15 +449,15 @@ int adg_init_mesh(const adg_params* prm, const adg_mesh_desc* mesh, adg_mesh** o
 
 int adg_destroy(adg_mesh* m) {
   if (!m) return fail(ADG_EINVAL, "null handle");
-  free_dev(m);
+  free_group(m->g);
   delete m;
   return ADG_OK;
 }
 
 int adg_mesh_info(const adg_mesh* m, int* n_cells, int* n_nodes) {
   if (!m) return fail(ADG_EINVAL, "null handle");
-  if (n_cells) *n_cells = m->C;
-  if (n_nodes) *n_nodes = m->n;
+  if (n_cells) *n_cells = m->g.C;
+  if (n_nodes) *n_nodes = m->g.n;
   return ADG_OK;
 }
 
@@ -382,62 +473,50 @@ int adg_set_state(adg_mesh* m, double* Q, void* workspace, double* clock) {
   if (((uintptr_t)workspace & 255) != 0) return fail(ADG_EINVAL, "workspace must be 256-byte aligned");
   if (((uintptr_t)Q & 7) != 0 || ((uintptr_t)clock & 7) != 0) return fail(ADG_EINVAL, "misaligned buffer");
   m->Q = Q; m->ws = workspace; m->clock = clock;
+  char* ws = static_cast<char*>(workspace);
+  m->g.Q = Q;
+  m->g.Qs = reinterpret_cast<double*>(ws + m->off_qs);
+  m->g.FD = reinterpret_cast<double*>(ws + m->off_fd);
+  m->g.dtc = reinterpret_cast<double*>(ws + m->off_dtc);
+  m->g.clock = clock;
   return ADG_OK;
 }
 
 int adg_init_state(adg_mesh* m, int kind, int n_bubbles, const double* bubbles, double t0, void* stream) {
   int rc = need_state(m);
+  if (!rc) rc = check_bubbles(kind, m->prm.gravity, n_bubbles, bubbles);
   if (rc) return rc;
-  if (kind != 0 && kind != 1) return fail(ADG_EINVAL, "kind must be 0 (bubbles) or 1 (manufactured)");
-  if (kind == 0 && !m->prm.gravity) return fail(ADG_EINVAL, "bubble states need gravity (background)");
-  if (n_bubbles < 0 || n_bubbles > 16 || (n_bubbles > 0 && !bubbles)) return fail(ADG_EINVAL, "bad bubble list");
-  for (int b = 0; b < n_bubbles; ++b) {
-    const double* bb = bubbles + 6 * b;
-    if (bb[0] != ADG_SHAPE_COSINE && bb[0] != ADG_SHAPE_PLATEAU_GAUSS) return fail(ADG_EINVAL, "bad bubble shape");
-    if (bb[0] == ADG_SHAPE_COSINE && !(bb[2] > 0.0)) return fail(ADG_EINVAL, "cosine bubble radius must be > 0");
-    if (bb[0] == ADG_SHAPE_PLATEAU_GAUSS && !(bb[3] > 0.0)) return fail(ADG_EINVAL, "decay s must be > 0");
-  }
-  // the bubble list travels through a small device copy owned by the call's stream order
-  double* d_bub = nullptr;
-  if (n_bubbles > 0) {
-    if (hipMalloc(&d_bub, sizeof(double) * 6 * n_bubbles) != hipSuccess) return fail(ADG_ENOMEM, "alloc");
-    if (hipMemcpy(d_bub, bubbles, sizeof(double) * 6 * n_bubbles, hipMemcpyHostToDevice) != hipSuccess) {
-      (void)hipFree(d_bub);
-      return fail(ADG_EHIP, "upload bubbles");
-    }
-  }
-  rc = launch_init_state(m, kind, n_bubbles, d_bub, t0, (hipStream_t)stream);
-  if (d_bub) {
-    (void)hipStreamSynchronize((hipStream_t)stream);
-    (void)hipFree(d_bub);
-  }
-  return rc;
+  return init_state_range(m->g, 0, m->g.C, kind, n_bubbles, bubbles, t0, (hipStream_t)stream);
 }
 
 int adg_compute_dt(adg_mesh* m, void* stream) {
   int rc = need_state(m);
   if (rc) return rc;
-  return launch_dt(m, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  rc = launch_cell_dt(m->g, s);
+  if (rc) return rc;
+  return launch_clock(m->clock, m->g.dtc, nullptr, nullptr, 1, m->g.C, 0, 1, s);
 }
 
 int adg_predictor(adg_mesh* m, void* stream) {
   int rc = need_state(m);
   if (rc) return rc;
-  return launch_predictor(m, (hipStream_t)stream);
+  return launch_predictor(m->g, (hipStream_t)stream);
 }
 
 int adg_corrector(adg_mesh* m, void* stream) {
   int rc = need_state(m);
   if (rc) return rc;
-  return launch_corrector(m, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  rc = launch_corrector(m->g, s);
+  if (rc) return rc;
+  return launch_clock(m->clock, m->g.dtc, nullptr, nullptr, 1, m->g.C, 1, m->g.ph.fixed_dt ? 0 : 1, s);
 }
 
 int adg_step(adg_mesh* m, void* stream) {
-  int rc = need_state(m);
+  int rc = adg_predictor(m, stream);
   if (rc) return rc;
-  rc = launch_predictor(m, (hipStream_t)stream);
-  if (rc) return rc;
-  return launch_corrector(m, (hipStream_t)stream);
+  return adg_corrector(m, stream);
 }
 
 int adg_tv_indicator(adg_mesh* m, int var, double T_refine, double T_coarsen, double* tv, int8_t* flags,
@@ -448,7 +527,7 @@ int adg_tv_indicator(adg_mesh* m, int var, double T_refine, double T_coarsen, do
   if (var == ADG_VAR_THETA && !(m->prm.p0 > 0.0)) return fail(ADG_EINVAL, "theta needs p0 > 0");
   if (!tv || !flags || !stats) return fail(ADG_EINVAL, "null output");
   if (!(T_refine > T_coarsen)) return fail(ADG_EINVAL, "T_refine must exceed T_coarsen");
-  return launch_tv(m, var, T_refine, T_coarsen, tv, flags, stats, (hipStream_t)stream);
+  return launch_tv(m->g, m->basis, var, T_refine, T_coarsen, tv, flags, stats, (hipStream_t)stream);
 }
 
 int adg_check_health(adg_mesh* m, void* stream) {
@@ -457,7 +536,7 @@ int adg_check_health(adg_mesh* m, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   int* flag = reinterpret_cast<int*>(static_cast<char*>(m->ws) + m->off_health);
   if (hipMemsetAsync(flag, 0, sizeof(int), s) != hipSuccess) return fail(ADG_EHIP, "memset");
-  rc = launch_health(m, flag, s);
+  rc = launch_health(m->g, flag, s);
   if (rc) return rc;
   int h = 0;
   if (hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return fail(ADG_EHIP, "copy");
@@ -468,11 +547,344 @@ int adg_check_health(adg_mesh* m, void* stream) {
 
 int adg_basis(const adg_mesh* m, double* xi, double* w, double* D, double* P) {
   if (!m) return fail(ADG_EINVAL, "null handle");
-  const int n = m->n;
-  if (xi) std::memcpy(xi, m->xi.data(), sizeof(double) * n);
-  if (w) std::memcpy(w, m->w.data(), sizeof(double) * n);
-  if (D) std::memcpy(D, m->D.data(), sizeof(double) * n * n);
-  if (P) std::memcpy(P, m->P.data(), sizeof(double) * n * n);
+  const int n = m->g.n;
+  if (xi) std::memcpy(xi, m->basis.xi.data(), sizeof(double) * n);
+  if (w) std::memcpy(w, m->basis.w.data(), sizeof(double) * n);
+  if (D) std::memcpy(D, m->basis.D.data(), sizeof(double) * n * n);
+  if (P) std::memcpy(P, m->basis.P.data(), sizeof(double) * n * n);
+  return ADG_OK;
+}
+
+int adg_set_launch(adg_mesh* m, int cells_per_wave, int waves_per_block) {
+  if (!m) return fail(ADG_EINVAL, "null handle");
+  if ((cells_per_wave != 1 && cells_per_wave != 2 && cells_per_wave != 4) || cells_per_wave > max_cpw(m->g.n))
+    return fail(ADG_EINVAL, "cells_per_wave must be 1, 2 or 4 with cells_per_wave * n^2 <= 64");
+  if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+    return fail(ADG_EINVAL, "waves_per_block must be 1, 2 or 4");
+  m->g.cpw = cells_per_wave; m->g.wpb = waves_per_block;
+  return ADG_OK;
+}
+
+int adg_autotune(adg_mesh* m, int reps, void* stream, int* cells_per_wave, int* waves_per_block) {
+  int rc = need_state(m);
+  if (rc) return rc;
+  if (reps < 1) return fail(ADG_EINVAL, "reps < 1");
+  rc = autotune_group(m->g, (hipStream_t)stream, reps, nullptr);
+  if (rc) return rc;
+  if (cells_per_wave) *cells_per_wave = m->g.cpw;
+  if (waves_per_block) *waves_per_block = m->g.wpb;
+  return ADG_OK;
+}
+
+}  // extern "C"
+
+// ===================================================================== batch
+struct adg_batch {
+  int S = 0;
+  adg_params prm0;                       // physical parameters shared by all scenarios
+  std::vector<adg::Group> groups;        // one per distinct order
+  std::vector<adg::HostBasis> bases;
+  std::vector<int> scen_group, scen_c0, scen_C, scen_n;   // scenario -> group, first cell, cells, nodes
+  std::vector<int> group_c0;             // first global cell of each group
+  std::vector<size_t> group_q0;          // first double of each group's state
+  size_t q_doubles = 0, ws_bytes = 0;
+  std::vector<size_t> off_qs, off_fd;    // per group, bytes into the workspace
+  size_t off_dtc = 0;
+  int* d_beg = nullptr;                  // [S] global first cell
+  int* d_end = nullptr;                  // [S] global end cell
+  int C_total = 0;
+  // bound
+  double* Q = nullptr;
+  void* ws = nullptr;
+  double* clock = nullptr;
+  double* dtc = nullptr;
+  // concurrency and graph
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;        // [0] fork, [1+g] join
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipStream_t graph_stream = nullptr;
+};
+
+namespace adg {
+
+static void batch_free(adg_batch* b) {
+  for (auto& g : b->groups) free_group(g);
+  if (b->d_beg) (void)hipFree(b->d_beg);
+  if (b->d_end) (void)hipFree(b->d_end);
+  for (auto s : b->streams) (void)hipStreamDestroy(s);
+  for (auto e : b->events) (void)hipEventDestroy(e);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->streams.clear(); b->events.clear();
+  b->exec = nullptr; b->graph = nullptr;
+}
+
+static int batch_need_state(adg_batch* b) {
+  if (!b) return fail(ADG_EINVAL, "null batch");
+  if (!b->Q || !b->ws || !b->clock) return fail(ADG_ESTATE, "no state bound (adg_batch_set_state)");
+  return ADG_OK;
+}
+
+// one step of every scenario: fork one stream per order group (predictor,
+// corrector), join, then one clock update for all scenarios
+static int batch_enqueue_step(adg_batch* b, hipStream_t s) {
+  const int G = (int)b->groups.size();
+  if (hipEventRecord(b->events[0], s) != hipSuccess) return fail(ADG_EHIP, "event record");
+  for (int g = 0; g < G; ++g) {
+    hipStream_t gs = b->streams[g];
+    if (hipStreamWaitEvent(gs, b->events[0], 0) != hipSuccess) return fail(ADG_EHIP, "stream wait");
+    int rc = launch_predictor(b->groups[g], gs);
+    if (!rc) rc = launch_corrector(b->groups[g], gs);
+    if (rc) return rc;
+    if (hipEventRecord(b->events[1 + g], gs) != hipSuccess) return fail(ADG_EHIP, "event record");
+    if (hipStreamWaitEvent(s, b->events[1 + g], 0) != hipSuccess) return fail(ADG_EHIP, "stream wait");
+  }
+  return launch_clock(b->clock, b->dtc, b->d_beg, b->d_end, b->S, b->C_total, 1, b->prm0.fixed_dt ? 0 : 1, s);
+}
+
+}  // namespace adg
+
+extern "C" {
+
+int adg_batch_create(const adg_params* prm, const adg_mesh_desc* mesh, int n_scen, adg_batch** out) {
+  if (!out || !prm || !mesh) return fail(ADG_EINVAL, "null argument");
+  if (n_scen < 1 || n_scen > 4096) return fail(ADG_EINVAL, "n_scen must be in 1..4096");
+  for (int s = 0; s < n_scen; ++s) {
+    int rc = validate_params(&prm[s]);
+    if (!rc) rc = validate_mesh(&mesh[s]);
+    if (rc) return fail(rc, "scenario " + std::to_string(s) + ": " + g_err);
+    const adg_params& a = prm[0], &c = prm[s];
+    if (a.gamma != c.gamma || a.Pr != c.Pr || a.R != c.R || a.cp != c.cp || a.mu != c.mu || a.g != c.g ||
+        a.p0 != c.p0 || a.theta_bg != c.theta_bg || a.gravity != c.gravity || a.mms != c.mms || a.cfl != c.cfl ||
+        a.fixed_dt != c.fixed_dt || a.picard_iters != c.picard_iters)
+      return fail(ADG_EINVAL, "scenarios of a batch must share all parameters except the order");
+  }
+  adg_batch* b = new (std::nothrow) adg_batch();
+  if (!b) return fail(ADG_ENOMEM, "out of host memory");
+  b->S = n_scen;
+  b->prm0 = prm[0];
+  std::vector<HostMesh> hms(n_scen);
+  for (int s = 0; s < n_scen; ++s) {
+    int rc = build_mesh(mesh[s], hms[s]);
+    if (rc) { delete b; return fail(rc, "scenario " + std::to_string(s) + ": " + g_err); }
+  }
+  // group by order (ascending)
+  std::vector<int> orders;
+  for (int s = 0; s < n_scen; ++s) orders.push_back(prm[s].order);
+  std::sort(orders.begin(), orders.end());
+  orders.erase(std::unique(orders.begin(), orders.end()), orders.end());
+  const int G = (int)orders.size();
+  b->groups.resize(G); b->bases.resize(G);
+  b->scen_group.resize(n_scen); b->scen_c0.resize(n_scen); b->scen_C.resize(n_scen); b->scen_n.resize(n_scen);
+  b->group_c0.resize(G); b->group_q0.resize(G); b->off_qs.resize(G); b->off_fd.resize(G);
+  std::vector<int> beg(n_scen), end(n_scen);
+  int cglob = 0;
+  size_t q0 = 0;
+  for (int gi = 0; gi < G; ++gi) {
+    const int N = orders[gi], n = N + 1;
+    build_basis(n, b->bases[gi]);
+    std::vector<double> geom;
+    std::vector<int> nbr, scen;
+    int C = 0;
+    for (int s = 0; s < n_scen; ++s) {
+      if (prm[s].order != N) continue;
+      const HostMesh& H = hms[s];
+      b->scen_group[s] = gi; b->scen_c0[s] = C; b->scen_C[s] = H.C; b->scen_n[s] = n;
+      beg[s] = cglob + C; end[s] = cglob + C + H.C;
+      geom.insert(geom.end(), H.geom.begin(), H.geom.end());
+      for (int k = 0; k < H.C * 16; ++k) {
+        const int f = (k % 16) / 4, slot = k % 4;
+        (void)f;
+        int v = H.nbr[k];
+        const int kind = H.nbr[k - slot];
+        // cell references are local to the scenario: shift into the group
+        if (slot > 0 && v >= 0) {
+          const bool is_cell = (kind == kConforming && slot == 1) || (kind == kFineSide && slot == 1) ||
+                               (kind == kCoarseSide);
+          if (is_cell) v += C;
+        }
+        nbr.push_back(v);
+      }
+      for (int c = 0; c < H.C; ++c) scen.push_back(s);
+      C += H.C;
+    }
+    Group& g = b->groups[gi];
+    g.n = n; g.N = N; g.iters = prm[0].picard_iters > 0 ? prm[0].picard_iters : n; g.C = C;
+    adg_params pg = prm[0];
+    pg.order = N;
+    g.ph = make_phys(pg);
+    g.cpw = max_cpw(n); g.wpb = 1;
+    int rc = upload_group(g, geom, nbr, b->bases[gi].gtab, &scen);
+    if (rc) { batch_free(b); delete b; return rc; }
+    b->group_c0[gi] = cglob;
+    b->group_q0[gi] = q0;
+    q0 += (size_t)C * 4 * n * n;
+    cglob += C;
+  }
+  b->C_total = cglob;
+  b->q_doubles = q0;
+  size_t off = 0;
+  for (int gi = 0; gi < G; ++gi) {
+    const size_t C = b->groups[gi].C, n = b->groups[gi].n;
+    b->off_qs[gi] = off; off = align256(off + sizeof(double) * C * 4 * n * n);
+    b->off_fd[gi] = off; off = align256(off + sizeof(double) * C * 32 * n);
+  }
+  b->off_dtc = off; off = align256(off + sizeof(double) * (size_t)cglob);
+  b->ws_bytes = off;
+  if (hipMalloc(&b->d_beg, sizeof(int) * n_scen) != hipSuccess ||
+      hipMalloc(&b->d_end, sizeof(int) * n_scen) != hipSuccess ||
+      hipMemcpy(b->d_beg, beg.data(), sizeof(int) * n_scen, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_end, end.data(), sizeof(int) * n_scen, hipMemcpyHostToDevice) != hipSuccess) {
+    batch_free(b); delete b;
+    return fail(ADG_ENOMEM, "device allocation failed");
+  }
+  b->streams.resize(G, nullptr);
+  b->events.resize(G + 1, nullptr);
+  for (int gi = 0; gi < G; ++gi)
+    if (hipStreamCreateWithFlags(&b->streams[gi], hipStreamNonBlocking) != hipSuccess) {
+      batch_free(b); delete b;
+      return fail(ADG_EHIP, "stream creation failed");
+    }
+  for (int k = 0; k <= G; ++k)
+    if (hipEventCreateWithFlags(&b->events[k], hipEventDisableTiming) != hipSuccess) {
+      batch_free(b); delete b;
+      return fail(ADG_EHIP, "event creation failed");
+    }
+  *out = b;
+  return ADG_OK;
+}
+
+int adg_batch_destroy(adg_batch* b) {
+  if (!b) return fail(ADG_EINVAL, "null batch");
+  batch_free(b);
+  delete b;
+  return ADG_OK;
+}
+
+int adg_batch_info(const adg_batch* b, int* n_groups, int* total_cells, size_t* q_doubles, size_t* ws_bytes) {
+  if (!b) return fail(ADG_EINVAL, "null batch");
+  if (n_groups) *n_groups = (int)b->groups.size();
+  if (total_cells) *total_cells = b->C_total;
+  if (q_doubles) *q_doubles = b->q_doubles;
+  if (ws_bytes) *ws_bytes = b->ws_bytes;
+  return ADG_OK;
+}
+
+int adg_batch_scenario(const adg_batch* b, int s, size_t* q_offset, int* n_cells, int* n_nodes) {
+  if (!b) return fail(ADG_EINVAL, "null batch");
+  if (s < 0 || s >= b->S) return fail(ADG_EINVAL, "scenario out of range");
+  const int gi = b->scen_group[s], n = b->scen_n[s];
+  if (q_offset) *q_offset = b->group_q0[gi] + (size_t)b->scen_c0[s] * 4 * n * n;
+  if (n_cells) *n_cells = b->scen_C[s];
+  if (n_nodes) *n_nodes = n;
+  return ADG_OK;
+}
+
+int adg_batch_set_state(adg_batch* b, double* Q, void* workspace, double* clocks) {
+  if (!b) return fail(ADG_EINVAL, "null batch");
+  if (!Q || !workspace || !clocks) return fail(ADG_EINVAL, "null buffer");
+  if (((uintptr_t)workspace & 255) != 0) return fail(ADG_EINVAL, "workspace must be 256-byte aligned");
+  if (((uintptr_t)Q & 7) != 0 || ((uintptr_t)clocks & 7) != 0) return fail(ADG_EINVAL, "misaligned buffer");
+  b->Q = Q; b->ws = workspace; b->clock = clocks;
+  char* ws = static_cast<char*>(workspace);
+  b->dtc = reinterpret_cast<double*>(ws + b->off_dtc);
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    Group& g = b->groups[gi];
+    g.Q = Q + b->group_q0[gi];
+    g.Qs = reinterpret_cast<double*>(ws + b->off_qs[gi]);
+    g.FD = reinterpret_cast<double*>(ws + b->off_fd[gi]);
+    g.dtc = b->dtc + b->group_c0[gi];
+    g.clock = clocks;
+  }
+  // a captured graph holds the old pointers
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  return ADG_OK;
+}
+
+int adg_batch_init_state(adg_batch* b, int s, int kind, int n_bubbles, const double* bubbles, double t0,
+                         void* stream) {
+  int rc = batch_need_state(b);
+  if (rc) return rc;
+  if (s < 0 || s >= b->S) return fail(ADG_EINVAL, "scenario out of range");
+  rc = check_bubbles(kind, b->prm0.gravity, n_bubbles, bubbles);
+  if (rc) return rc;
+  return init_state_range(b->groups[b->scen_group[s]], b->scen_c0[s], b->scen_C[s], kind, n_bubbles, bubbles, t0,
+                          (hipStream_t)stream);
+}
+
+int adg_batch_compute_dt(adg_batch* b, void* stream) {
+  int rc = batch_need_state(b);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  for (auto& g : b->groups) {
+    rc = launch_cell_dt(g, s);
+    if (rc) return rc;
+  }
+  return launch_clock(b->clock, b->dtc, b->d_beg, b->d_end, b->S, b->C_total, 0, 1, s);
+}
+
+int adg_batch_step(adg_batch* b, void* stream) {
+  int rc = batch_need_state(b);
+  if (rc) return rc;
+  return batch_enqueue_step(b, (hipStream_t)stream);
+}
+
+int adg_batch_step_graph(adg_batch* b, void* stream) {
+  int rc = batch_need_state(b);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (!s) return fail(ADG_EINVAL, "graph steps need a non-default stream");
+  if (b->exec && b->graph_stream != s) {
+    (void)hipGraphExecDestroy(b->exec); b->exec = nullptr;
+    (void)hipGraphDestroy(b->graph); b->graph = nullptr;
+  }
+  if (!b->exec) {
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return fail(ADG_EHIP, "begin capture failed");
+    rc = batch_enqueue_step(b, s);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+    if (e != hipSuccess || !graph) return fail(ADG_EHIP, "end capture failed");
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return fail(ADG_EHIP, "graph instantiation failed");
+    }
+    b->graph = graph; b->exec = exec; b->graph_stream = s;
+  }
+  if (hipGraphLaunch(b->exec, s) != hipSuccess) return fail(ADG_EHIP, "graph launch failed");
+  return ADG_OK;
+}
+
+int adg_batch_autotune(adg_batch* b, int reps, void* stream, int* cells_per_wave, int* waves_per_block) {
+  int rc = batch_need_state(b);
+  if (rc) return rc;
+  if (reps < 1) return fail(ADG_EINVAL, "reps < 1");
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    rc = autotune_group(b->groups[gi], (hipStream_t)stream, reps, nullptr);
+    if (rc) return rc;
+    if (cells_per_wave) cells_per_wave[gi] = b->groups[gi].cpw;
+    if (waves_per_block) waves_per_block[gi] = b->groups[gi].wpb;
+  }
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  return ADG_OK;
+}
+
+int adg_batch_set_launch(adg_batch* b, int group, int cells_per_wave, int waves_per_block) {
+  if (!b) return fail(ADG_EINVAL, "null batch");
+  if (group < 0 || group >= (int)b->groups.size()) return fail(ADG_EINVAL, "group out of range");
+  Group& g = b->groups[group];
+  if ((cells_per_wave != 1 && cells_per_wave != 2 && cells_per_wave != 4) || cells_per_wave > max_cpw(g.n))
+    return fail(ADG_EINVAL, "cells_per_wave must be 1, 2 or 4 with cells_per_wave * n^2 <= 64");
+  if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+    return fail(ADG_EINVAL, "waves_per_block must be 1, 2 or 4");
+  g.cpw = cells_per_wave; g.wpb = waves_per_block;
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   return ADG_OK;
 }
 

@@ -1,25 +1,53 @@
 // ADER-DG step kernels for gfx950: space-time predictor, corrector with the
-// viscous Rusanov face flux, CFL time step.
+// viscous Rusanov face flux (conforming, wall and 1:3 non-conforming faces),
+// CFL time step.
 //
-// Work decomposition: one 64-lane wavefront per cell (n*n <= 64 spatial
-// nodes).  Lane l < n*n owns spatial node (j, i) = (l / n, l % n) and keeps
-// the whole time history of its node in registers; tensor-product
+// Work decomposition.  A wavefront (64 lanes) owns CPW cells (CPW * n*n <=
+// 64); a workgroup holds WPB independent wavefronts, each with its own LDS
+// region, synchronised at wavefront level only.  In a cell, lane (slot, l)
+// with l < n*n owns spatial node (j, i) = (l / n, l % n); tensor-product
 // contractions along x and z run as "line jobs" (one lane per (direction,
-// variable, line), 8n jobs) through LDS slices of the current time level.
+// variable, line), 8n jobs per cell) on LDS slices of one time level.
+// CPW and WPB are template parameters picked per order by the autotuner.
 #include "adg_internal.h"
 
 namespace adg {
 
+// wavefront-scope barrier for LDS hand-offs between lanes of one wavefront:
+// LDS operations of a wavefront execute in order, so a compiler fence and a
+// wave barrier are enough.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int n>
+struct Half { static constexpr int nh = (n + 1) / 2; };
+
+template <int n, int CPW>
+struct Lay {
+  static constexpr int nn = n * n, sl = 4 * nn;
+  static constexpr int jobs = 8 * n * CPW;                 // line jobs per wavefront
+  static constexpr int rounds = (jobs + kWave - 1) / kWave;
+  static constexpr int pred_cell = (n + 4) * sl;           // predictor LDS doubles per cell
+  static constexpr int corr_cell = 16 * n + 24 * n + 48 * n;  // sG, sL/sV, sGs
+};
+
+// Line job of one lane in one round: direction, base offset and stride in a
+// [4][n][n] slice, cell slot.
 template <int n>
 struct LineJob {
-  int dir, base, stride;
+  int dir, base, stride, slot, v, line;
   bool active;
-  __device__ LineJob(int lane) {
+  __device__ LineJob(int job, int cpw) {
     constexpr int nn = n * n;
-    active = lane < 8 * n;
-    dir = lane / (4 * n);
-    int v = (lane % (4 * n)) / n;
-    int line = lane % n;
+    slot = job / (8 * n);
+    active = slot < cpw;
+    const int jj = job % (8 * n);
+    dir = jj / (4 * n);
+    v = (jj % (4 * n)) / n;
+    line = jj % n;
     base = v * nn + (dir == 0 ? line * n : line);
     stride = dir == 0 ? 1 : n;
   }
@@ -30,30 +58,25 @@ struct LineJob {
 // volume matrix Dw.  Only the first nh = ceil(n/2) rows are kept; row n-1-i is
 // applied as minus row i on the reversed input line.
 template <int n>
-struct Half { static constexpr int nh = (n + 1) / 2; };
-
-// out[i] = sum_m M[i][m] in[m] along this lane's line: src -> dst.  M holds
-// the first nh rows in VGPRs (uniform values, loaded once per kernel).
-template <int n>
-__device__ inline void line_apply(const double (&M)[Half<n>::nh][n], const LineJob<n>& J, const double* src,
+__device__ inline void line_apply(const double (&M)[Half<n>::nh][n], int base, int stride, const double* src,
                                   double* dst) {
   constexpr int nh = Half<n>::nh;
   double in[n];
 #pragma unroll
-  for (int m = 0; m < n; ++m) in[m] = src[J.base + m * J.stride];
+  for (int m = 0; m < n; ++m) in[m] = src[base + m * stride];
 #pragma unroll
   for (int i = 0; i < nh; ++i) {
     double s = 0.0;
 #pragma unroll
     for (int m = 0; m < n; ++m) s = fma(M[i][m], in[m], s);
-    dst[J.base + i * J.stride] = s;
+    dst[base + i * stride] = s;
   }
 #pragma unroll
   for (int i = 0; i < n / 2; ++i) {
     double s = 0.0;
 #pragma unroll
     for (int m = 0; m < n; ++m) s = fma(M[i][m], in[n - 1 - m], s);
-    dst[J.base + (n - 1 - i) * J.stride] = -s;
+    dst[base + (n - 1 - i) * stride] = -s;
   }
 }
 
@@ -78,59 +101,64 @@ struct StepArgs {
   double* Qs;           // [C][4][n][n]  Q* = Q^n + dt (volume + source)
   double* FD;           // [C][4 faces][2][4][n]
   double* dtc;          // [C] per-cell CFL candidates
-  double* clock;        // t, dt, (unused), steps
+  double* clock;        // [S][4]: t, dt, (unused), steps
+  const int* scen;      // [C] scenario of each cell (NULL: scenario 0)
   const double* geom;   // [C][4]
   const int* nbr;       // [C][4][4]
   const double* gtab;
   int C, iters;
-  int* health;
 };
 
 // ------------------------------------------------------------------ predictor
-// Per cell (one wavefront): the Picard iterate of all n time nodes lives in
-// LDS (sq[b][v][j][i]).  Each sweep walks the time nodes in a runtime loop
-// that is software-pipelined by one node: a line phase computes the
-// divergence of the fluxes of node b and the gradients of node b+1, a node
-// phase forms the residual R(b) (rank-1 update acc[a] += P[a][b] R(b), kept
-// per node in registers) and the fluxes of node b+1.  Two barriers per node.
-
-// flux and source of time node b at this lane's node: q from the iterate,
-// gradients from sg; fluxes to sf
+// flux and source of one time node at this lane's node: q from the iterate
+// slice qb, gradients from sg; fluxes to sf
 template <int n>
-__device__ inline double node_flux(const Phys& ph, const double* qb, const double (*sg)[4 * n * n],
-                                   double (*sf)[4 * n * n], int lane, double ih, double z, double rb, double pb,
-                                   double q[4], double Fx[4], double Fz[4]) {
-  constexpr int nn = n * n;
+__device__ inline double node_flux(const Phys& ph, const double* qb, const double* sg, double* sf, int l,
+                                   double ih, double z, double rb, double pb, double q[4], double Fx[4],
+                                   double Fz[4]) {
+  constexpr int nn = n * n, sl = 4 * nn;
   double gx[4], gz[4], Sw;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    q[v] = qb[v * nn + lane];
-    gx[v] = sg[0][v * nn + lane] * ih;
-    gz[v] = sg[1][v * nn + lane] * ih;
+    q[v] = qb[v * nn + l];
+    gx[v] = sg[v * nn + l] * ih;
+    gz[v] = sg[sl + v * nn + l] * ih;
   }
   flux_source(ph, q, gx, gz, z, rb, pb, Fx, Fz, Sw);
 #pragma unroll
-  for (int v = 0; v < 4; ++v) { sf[0][v * nn + lane] = Fx[v]; sf[1][v * nn + lane] = Fz[v]; }
+  for (int v = 0; v < 4; ++v) { sf[v * nn + l] = Fx[v]; sf[sl + v * nn + l] = Fz[v]; }
   return Sw;
 }
 
-template <int n>
-__global__ __launch_bounds__(kWave) void k_predictor(Phys ph, StepArgs a) {
-  constexpr int nn = n * n, sl = 4 * nn;
-  __shared__ double sq[n * sl];     // iterate at all time nodes; slot b takes R(b) once consumed
-  __shared__ double sg[2][sl];      // gradients (x, z) of the next time node
-  __shared__ double sf[2][sl];      // fluxes (x, z) of the current node, then their divergence
+// Per cell: the Picard iterate of all n time nodes lives in LDS
+// (sq[b][v][j][i]); each sweep walks the time nodes b in a runtime loop:
+// gradients by line jobs, flux and source per node, divergence by line jobs
+// (in place), and the rank-1 update acc[a] += P[a][b] R(b) held per node in
+// registers.  Then time averages, the volume term and the face data.
+template <int n, int CPW, int WPB>
+__global__ __launch_bounds__(kWave * WPB) void k_predictor(Phys ph, StepArgs a) {
+  using L = Lay<n, CPW>;
+  constexpr int nn = L::nn, sl = L::sl;
+  extern __shared__ double lds[];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  double* wl = lds + (size_t)wave * CPW * L::pred_cell;
+  const int cell0 = (blockIdx.x * WPB + wave) * CPW;
 
-  const int c = blockIdx.x;
-  const int lane = threadIdx.x;
-  const bool node = lane < nn;
-  const int ln = node ? lane : 0;
-  const int jz = ln / n, ix = ln % n;
-  const LineJob<n> J(lane);
+  // node role
+  const int slot = lane / nn, l = lane % nn;
+  const bool node = slot < CPW;
+  const int c = cell0 + (node ? slot : 0);
+  const bool valid = node && c < a.C;
+  const int cc = valid ? c : 0;
+  double* sq = wl + (node ? slot : 0) * L::pred_cell;
+  double* sg = sq + n * sl;
+  double* sf = sg + 2 * sl;
+  const int jz = l / n, ix = l % n;
   const double* gt = a.gtab;
 
-  const double t0 = a.clock[0], dt = a.clock[1];
-  const double x0 = a.geom[4 * c + 0], z0 = a.geom[4 * c + 1], h = a.geom[4 * c + 2];
+  const int s = a.scen ? a.scen[cc] : 0;
+  const double t0 = a.clock[4 * s + 0], dt = a.clock[4 * s + 1];
+  const double x0 = a.geom[4 * cc + 0], z0 = a.geom[4 * cc + 1], h = a.geom[4 * cc + 2];
   const double ih = 1.0 / h;
   const double x = x0 + h * gt[GTab::XI * n + ix];
   const double z = z0 + h * gt[GTab::XI * n + jz];
@@ -140,17 +168,34 @@ __global__ __launch_bounds__(kWave) void k_predictor(Phys ph, StepArgs a) {
   double Dv[Half<n>::nh][n];
   load_vtab<n>(gt + GTab::d(n), Dv);
 
-  const double* Qc = a.Qin + (size_t)c * sl;
   double Qn[4];
+  {
+    const double* Qc = a.Qin + (size_t)cc * sl;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) Qn[v] = Qc[v * nn + ln];
+    for (int v = 0; v < 4; ++v) Qn[v] = valid ? Qc[v * nn + l] : (v == 0 || v == 3 ? 1.0 : 0.0);
+  }
   if (node) {
 #pragma unroll
     for (int b = 0; b < n; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) sq[b * sl + v * nn + lane] = Qn[v];
+      for (int v = 0; v < 4; ++v) sq[b * sl + v * nn + l] = Qn[v];
   }
-  __syncthreads();
+  wave_sync();
+
+  // line-job roles (rounds of 64 jobs)
+  const LineJob<n> J0(lane, CPW), J1(lane + kWave, CPW);
+  double* jl0 = wl + (J0.active ? J0.slot : 0) * L::pred_cell;
+  double* jl1 = wl + (J1.active ? J1.slot : 0) * L::pred_cell;
+  // src/dst are offsets in a cell's region; direction d adds d * (dir stride)
+  auto lines = [&](int src_off, int dst_off, int src_dir_stride, int dst_dir_stride) {
+    if (J0.active)
+      line_apply<n>(Dv, J0.base, J0.stride, jl0 + src_off + J0.dir * src_dir_stride,
+                    jl0 + dst_off + J0.dir * dst_dir_stride);
+    if (L::rounds > 1 && J1.active)
+      line_apply<n>(Dv, J1.base, J1.stride, jl1 + src_off + J1.dir * src_dir_stride,
+                    jl1 + dst_off + J1.dir * dst_dir_stride);
+  };
+  constexpr int OFF_G = n * sl, OFF_F = (n + 2) * sl;
 
   for (int it = 0; it < a.iters; ++it) {
     double acc[n][4];
@@ -160,21 +205,20 @@ __global__ __launch_bounds__(kWave) void k_predictor(Phys ph, StepArgs a) {
       for (int v = 0; v < 4; ++v) acc[b][v] = 0.0;
 #pragma unroll 1
     for (int b = 0; b < n; ++b) {
-      double* qb = sq + b * sl;
-      if (J.active) line_apply<n>(Dv, J, qb, sg[J.dir]);
-      __syncthreads();
+      lines(b * sl, OFF_G, 0, sl);           // gradients of time node b
+      wave_sync();
       double Sw = 0.0;
       if (node) {
         double q[4], Fx[4], Fz[4];
-        Sw = node_flux<n>(ph, qb, sg, sf, lane, ih, z, rb, pb, q, Fx, Fz);
+        Sw = node_flux<n>(ph, sq + b * sl, sg, sf, l, ih, z, rb, pb, q, Fx, Fz);
       }
-      __syncthreads();
-      if (J.active) line_apply<n>(Dv, J, sf[J.dir], sf[J.dir]);
-      __syncthreads();
+      wave_sync();
+      lines(OFF_F, OFF_F, sl, sl);           // divergence parts, in place
+      wave_sync();
       if (node) {
         double R[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) R[v] = -(sf[0][v * nn + lane] + sf[1][v * nn + lane]) * ih;
+        for (int v = 0; v < 4; ++v) R[v] = -(sf[v * nn + l] + sf[sl + v * nn + l]) * ih;
         R[2] += Sw;
         if (ph.mms) R[3] += mms_source(ph, x, z, t0 + gt[GTab::XI * n + b] * dt);
         const double* pc = gt + GTab::pt(n) + b * n;
@@ -185,27 +229,26 @@ __global__ __launch_bounds__(kWave) void k_predictor(Phys ph, StepArgs a) {
           for (int v = 0; v < 4; ++v) acc[a2][v] = fma(p, R[v], acc[a2][v]);
         }
       }
-      __syncthreads();
+      wave_sync();
     }
     if (node) {
 #pragma unroll
       for (int b = 0; b < n; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) sq[b * sl + v * nn + lane] = fma(dt, acc[b][v], Qn[v]);
+        for (int v = 0; v < 4; ++v) sq[b * sl + v * nn + l] = fma(dt, acc[b][v], Qn[v]);
     }
-    __syncthreads();
+    wave_sync();
   }
 
   // time averages of q, F and S on the last iterate
   double Qb[4] = {0, 0, 0, 0}, Fbx[4] = {0, 0, 0, 0}, Fbz[4] = {0, 0, 0, 0}, Sbw = 0.0, SbE = 0.0;
 #pragma unroll 1
   for (int b = 0; b < n; ++b) {
-    const double* qb = sq + b * sl;
-    if (J.active) line_apply<n>(Dv, J, qb, sg[J.dir]);
-    __syncthreads();
+    lines(b * sl, OFF_G, 0, sl);
+    wave_sync();
     if (node) {
       double q[4], Fx[4], Fz[4];
-      const double Sw = node_flux<n>(ph, qb, sg, sf, lane, ih, z, rb, pb, q, Fx, Fz);
+      const double Sw = node_flux<n>(ph, sq + b * sl, sg, sf, l, ih, z, rb, pb, q, Fx, Fz);
       const double wb = gt[GTab::W * n + b];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -216,51 +259,54 @@ __global__ __launch_bounds__(kWave) void k_predictor(Phys ph, StepArgs a) {
       Sbw = fma(wb, Sw, Sbw);
       if (ph.mms) SbE = fma(wb, mms_source(ph, x, z, t0 + gt[GTab::XI * n + b] * dt), SbE);
     }
-    __syncthreads();
+    wave_sync();
   }
 
-  // volume term and face data
+  // volume term and face data: averaged state to slot 0, averaged fluxes to sf
   if (node) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      sq[v * nn + lane] = Qb[v];
-      sf[0][v * nn + lane] = Fbx[v];
-      sf[1][v * nn + lane] = Fbz[v];
+      sq[v * nn + l] = Qb[v];
+      sf[v * nn + l] = Fbx[v];
+      sf[sl + v * nn + l] = Fbz[v];
     }
   }
-  __syncthreads();
-  if (J.active) {
-    // Dw contraction of the averaged flux along the line; extrapolation of the
-    // averaged state and flux to both ends of the line.
+  wave_sync();
+  {
     double Wv[Half<n>::nh][n];
     load_vtab<n>(gt + GTab::dw(n), Wv);
-    const double* src = sf[J.dir];
-    line_apply<n>(Wv, J, src, sg[J.dir]);
-    double inF[n], inQ[n];
 #pragma unroll
-    for (int m = 0; m < n; ++m) { inF[m] = src[J.base + m * J.stride]; inQ[m] = sq[J.base + m * J.stride]; }
-    double q0 = 0, q1 = 0, f0 = 0, f1 = 0;
+    for (int r = 0; r < L::rounds; ++r) {
+      const LineJob<n>& J = r == 0 ? J0 : J1;
+      double* jl = r == 0 ? jl0 : jl1;
+      if (!J.active) continue;
+      const int cj = cell0 + J.slot;
+      const double* src = jl + OFF_F + J.dir * sl;
+      line_apply<n>(Wv, J.base, J.stride, src, jl + OFF_G + J.dir * sl);
+      if (cj >= a.C) continue;
+      double q0 = 0, q1 = 0, f0 = 0, f1 = 0;
 #pragma unroll
-    for (int m = 0; m < n; ++m) {
-      const double e0 = gt[GTab::E0 * n + m], e1 = gt[GTab::E1 * n + m];
-      q0 = fma(e0, inQ[m], q0); q1 = fma(e1, inQ[m], q1);
-      f0 = fma(e0, inF[m], f0); f1 = fma(e1, inF[m], f1);
+      for (int m = 0; m < n; ++m) {
+        const double e0 = gt[GTab::E0 * n + m], e1 = gt[GTab::E1 * n + m];
+        const double iq = jl[J.base + m * J.stride], iF = src[J.base + m * J.stride];
+        q0 = fma(e0, iq, q0); q1 = fma(e1, iq, q1);
+        f0 = fma(e0, iF, f0); f1 = fma(e1, iF, f1);
+      }
+      double* fd = a.FD + (size_t)cj * 32 * n;
+      const int fl = 2 * J.dir, fu = 2 * J.dir + 1;
+      fd[((fl * 2 + 0) * 4 + J.v) * n + J.line] = q0;
+      fd[((fl * 2 + 1) * 4 + J.v) * n + J.line] = f0;
+      fd[((fu * 2 + 0) * 4 + J.v) * n + J.line] = q1;
+      fd[((fu * 2 + 1) * 4 + J.v) * n + J.line] = f1;
     }
-    const int v = (lane % (4 * n)) / n, line = lane % n;
-    double* fd = a.FD + (size_t)c * 32 * n;
-    const int fl = 2 * J.dir, fu = 2 * J.dir + 1;
-    fd[((fl * 2 + 0) * 4 + v) * n + line] = q0;
-    fd[((fl * 2 + 1) * 4 + v) * n + line] = f0;
-    fd[((fu * 2 + 0) * 4 + v) * n + line] = q1;
-    fd[((fu * 2 + 1) * 4 + v) * n + line] = f1;
   }
-  __syncthreads();
-  if (node) {
+  wave_sync();
+  if (valid) {
     double* qs = a.Qs + (size_t)c * sl;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      double S = (v == 2) ? Sbw : (v == 3 ? SbE : 0.0);
-      qs[v * nn + lane] = Qn[v] + dt * ((sg[0][v * nn + lane] + sg[1][v * nn + lane]) * ih + S);
+      const double S = (v == 2) ? Sbw : (v == 3 ? SbE : 0.0);
+      qs[v * nn + l] = Qn[v] + dt * ((sg[v * nn + l] + sg[sl + v * nn + l]) * ih + S);
     }
   }
 }
@@ -295,90 +341,192 @@ __device__ inline void eig(const Phys& ph, int d, const double q[4], double zf, 
   lv = ph.lv_coef * ir;
 }
 
+// face data of cell cf, face f, node k: averaged state and normal flux
 template <int n>
-__global__ __launch_bounds__(kWave) void k_corrector(Tab<n> T, Phys ph, StepArgs a) {
-  constexpr int nn = n * n;
-  __shared__ double sG[4][4][n];
-  __shared__ double sL[4][n], sV[4][n];
-  const int c = blockIdx.x;
-  const int lane = threadIdx.x;
-  const double dt = a.clock[1];
-  const double x0 = a.geom[4 * c + 0], z0 = a.geom[4 * c + 1], h = a.geom[4 * c + 2];
-  (void)x0;
-  const bool fl = lane < 4 * n;
-  const int f = fl ? lane / n : 0, k = lane % n;
+__device__ inline void load_face(const double* FD, int cf, int f, int k, double Q[4], double F[4]) {
+  const double* fd = FD + (size_t)cf * 32 * n + f * 8 * n;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) { Q[v] = fd[v * n + k]; F[v] = fd[4 * n + v * n + k]; }
+}
+
+// face polynomial of cell cf, face f, evaluated at node q of sub-face s
+template <int n>
+__device__ inline void prolong_face(const double* FD, const double* gt, int cf, int f, int s, int q, double Q[4],
+                                    double F[4]) {
+  const double* fd = FD + (size_t)cf * 32 * n + f * 8 * n;
+  const double* P = gt + GTab::pk(n) + (s * n + q) * n;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) { Q[v] = 0.0; F[v] = 0.0; }
+#pragma unroll
+  for (int m = 0; m < n; ++m) {
+    const double p = P[m];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { Q[v] = fma(p, fd[v * n + m], Q[v]); F[v] = fma(p, fd[4 * n + v * n + m], F[v]); }
+  }
+}
+
+__device__ inline void rusanov_flux(double s, const double QL[4], const double FL[4], const double QR[4],
+                                    const double FR[4], double G[4]) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) G[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * s * (QR[v] - QL[v]);
+}
+
+// Per cell: lanes (slot, f, k) handle face f at node k.  The Rusanov speed s
+// is one value per (sub-)face: max over the face nodes of both sides of the
+// normal eigenvalue bound, plus the viscous penalty 2 eta max lambda_v with
+// eta = (2N+1)/(h sqrt(pi/2)), h the (finer) cell size at the face.
+// Conforming: the neighbour's face data; wall: ghost data; fine side of a
+// 1:3 face: the coarse neighbour's face polynomial at this sub-face; coarse
+// side: the three sub-face fluxes restricted by L2 projection.  Both sides of
+// a face evaluate the identical expressions, so the fluxes agree bitwise.
+template <int n, int CPW, int WPB>
+__global__ __launch_bounds__(kWave * WPB) void k_corrector(Phys ph, StepArgs a) {
+  using L = Lay<n, CPW>;
+  constexpr int nn = L::nn, sl = L::sl;
+  extern __shared__ double lds[];
+  __shared__ double slam[WPB][2][kWave];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  double* wl = lds + (size_t)wave * CPW * L::corr_cell;
+  const int cell0 = (blockIdx.x * WPB + wave) * CPW;
+  const double* gt = a.gtab;
+  const double eta0 = (2.0 * ph.N + 1.0) / 1.2533141373155002512;   // (2N+1)/sqrt(pi/2)
+
+  // face role
+  const int fslot = lane / (4 * n);
+  const int f = (lane % (4 * n)) / n, k = lane % n;
+  const int fc = cell0 + fslot;
+  const bool fl = fslot < CPW && fc < a.C;
+  double* fw = wl + (fslot < CPW ? fslot : 0) * L::corr_cell;
+  double* sG = fw;                 // [4 faces][4 vars][n]
+  double* sL = fw + 16 * n;        // [4][3][n]
+  double* sV = sL + 12 * n;        // [4][3][n]
+  double* sGs = sV + 12 * n;       // [4][3][4][n]
   const int d = f >> 1;
   const bool lower = (f & 1) == 0;   // face on the lower side: this cell is R
+  int kind = kWall, nb1 = 0, nb2 = 0, nb3 = 0;
+  double hf = 1.0, z0f = 0.0;
   double Qm[4], Fm[4], Qo[4], Fo[4];
-  double zf = 0.0;
   if (fl) {
-    const double* fd = a.FD + (size_t)c * 32 * n + f * 8 * n;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) { Qm[v] = fd[v * n + k]; Fm[v] = fd[4 * n + v * n + k]; }
-    zf = (d == 0) ? z0 + h * a.gtab[GTab::XI * n + k] : z0 + ((f & 1) ? h : 0.0);
-    const int* nb = a.nbr + (size_t)c * 16 + f * 4;
-    const int kind = nb[0];
-    if (kind == kConforming) {
-      const double* fo = a.FD + (size_t)nb[1] * 32 * n + (f ^ 1) * 8 * n;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) { Qo[v] = fo[v * n + k]; Fo[v] = fo[4 * n + v * n + k]; }
+    const int* nb = a.nbr + (size_t)fc * 16 + f * 4;
+    kind = nb[0]; nb1 = nb[1]; nb2 = nb[2]; nb3 = nb[3];
+    hf = a.geom[4 * fc + 2]; z0f = a.geom[4 * fc + 1];
+    if (kind != kCoarseSide) {
+      const double zf = (d == 0) ? z0f + hf * gt[GTab::XI * n + k] : z0f + ((f & 1) ? hf : 0.0);
+      load_face<n>(a.FD, fc, f, k, Qm, Fm);
+      if (kind == kConforming) load_face<n>(a.FD, nb1, f ^ 1, k, Qo, Fo);
+      else if (kind == kFineSide) prolong_face<n>(a.FD, gt, nb1, f ^ 1, nb2, k, Qo, Fo);
+      else wall_ghost(ph, d, zf, Qm, Fm, Qo, Fo);
+      double l1, v1, l2, v2;
+      eig(ph, d, Qm, zf, l1, v1);
+      eig(ph, d, Qo, zf, l2, v2);
+      sL[(f * 3) * n + k] = fmax(l1, l2);
+      sV[(f * 3) * n + k] = fmax(v1, v2);
     } else {
-      wall_ghost(ph, d, zf, Qm, Fm, Qo, Fo);
+      for (int s = 0; s < 3; ++s) {
+        const int fine = s == 0 ? nb1 : (s == 1 ? nb2 : nb3);
+        const double zf = (d == 0) ? z0f + hf * (s + gt[GTab::XI * n + k]) / 3.0 : z0f + ((f & 1) ? hf : 0.0);
+        double Qp[4], Fp[4], Qx[4], Fx[4];
+        prolong_face<n>(a.FD, gt, fc, f, s, k, Qp, Fp);
+        load_face<n>(a.FD, fine, f ^ 1, k, Qx, Fx);
+        double l1, v1, l2, v2;
+        eig(ph, d, Qp, zf, l1, v1);
+        eig(ph, d, Qx, zf, l2, v2);
+        sL[(f * 3 + s) * n + k] = fmax(l1, l2);
+        sV[(f * 3 + s) * n + k] = fmax(v1, v2);
+      }
     }
-    double l1, v1, l2, v2;
-    eig(ph, d, Qm, zf, l1, v1);
-    eig(ph, d, Qo, zf, l2, v2);
-    sL[f][k] = fmax(l1, l2);
-    sV[f][k] = fmax(v1, v2);
   }
-  __syncthreads();
+  wave_sync();
   if (fl) {
-    double lam = sL[f][0], lv = sV[f][0];
+    if (kind != kCoarseSide) {
+      double lam = sL[(f * 3) * n], lv = sV[(f * 3) * n];
 #pragma unroll
-    for (int m = 1; m < n; ++m) { lam = fmax(lam, sL[f][m]); lv = fmax(lv, sV[f][m]); }
-    const double eta = (2.0 * ph.N + 1.0) / (h * 1.2533141373155002512);  // h sqrt(pi/2)
-    const double s = lam + 2.0 * eta * lv;
-    const double* QL = lower ? Qo : Qm;
-    const double* FL = lower ? Fo : Fm;
-    const double* QR = lower ? Qm : Qo;
-    const double* FR = lower ? Fm : Fo;
+      for (int m = 1; m < n; ++m) { lam = fmax(lam, sL[(f * 3) * n + m]); lv = fmax(lv, sV[(f * 3) * n + m]); }
+      const double s = lam + 2.0 * (eta0 / hf) * lv;
+      double G[4];
+      if (lower) rusanov_flux(s, Qo, Fo, Qm, Fm, G);
+      else rusanov_flux(s, Qm, Fm, Qo, Fo, G);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) sG[f][v][k] = 0.5 * (FL[v] + FR[v]) - 0.5 * s * (QR[v] - QL[v]);
+      for (int v = 0; v < 4; ++v) sG[(f * 4 + v) * n + k] = G[v];
+    } else {
+      const double hfine = hf / 3.0;
+      for (int s = 0; s < 3; ++s) {
+        const int fine = s == 0 ? nb1 : (s == 1 ? nb2 : nb3);
+        double lam = sL[(f * 3 + s) * n], lv = sV[(f * 3 + s) * n];
+        for (int m = 1; m < n; ++m) { lam = fmax(lam, sL[(f * 3 + s) * n + m]); lv = fmax(lv, sV[(f * 3 + s) * n + m]); }
+        const double sp = lam + 2.0 * (eta0 / hfine) * lv;
+        double Qp[4], Fp[4], Qx[4], Fx[4], G[4];
+        prolong_face<n>(a.FD, gt, fc, f, s, k, Qp, Fp);
+        load_face<n>(a.FD, fine, f ^ 1, k, Qx, Fx);
+        if (lower) rusanov_flux(sp, Qx, Fx, Qp, Fp, G);
+        else rusanov_flux(sp, Qp, Fp, Qx, Fx, G);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sGs[((f * 3 + s) * 4 + v) * n + k] = G[v];
+      }
+    }
   }
-  __syncthreads();
-  const bool node = lane < nn;
-  const int ln = node ? lane : 0;
-  const int jz = ln / n, ix = ln % n;
-  double lam = 0.0, lvm = 0.0;
-  if (node) {
-    const double L0i = a.gtab[GTab::L0 * n + ix], L1i = a.gtab[GTab::L1 * n + ix];
-    const double L0j = a.gtab[GTab::L0 * n + jz], L1j = a.gtab[GTab::L1 * n + jz];
-    const double* qs = a.Qs + (size_t)c * 4 * nn;
-    double* qo = a.Qout + (size_t)c * 4 * nn;
-    const double sc = dt / h;
+  wave_sync();
+  if (fl && kind == kCoarseSide) {
+    // L2 restriction to the coarse face node m = k
+    const double* Rk = gt + GTab::rk(n);
+    double G[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+      for (int q = 0; q < n; ++q) {
+        const double r = Rk[(s * n + k) * n + q];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) G[v] = fma(r, sGs[((f * 3 + s) * 4 + v) * n + q], G[v]);
+      }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sG[(f * 4 + v) * n + k] = G[v];
+  }
+  wave_sync();
+
+  // node role: lifting and the next CFL candidate
+  const int slot = lane / nn, l = lane % nn;
+  const int c = cell0 + slot;
+  const bool valid = slot < CPW && c < a.C;
+  const double* sGc = wl + (slot < CPW ? slot : 0) * L::corr_cell;
+  double lam_n = 0.0, lv_n = 0.0;
+  if (valid) {
+    const int jz = l / n, ix = l % n;
+    const int sc = a.scen ? a.scen[c] : 0;
+    const double dt = a.clock[4 * sc + 1];
+    const double z0 = a.geom[4 * c + 1], h = a.geom[4 * c + 2];
+    const double L0i = gt[GTab::L0 * n + ix], L1i = gt[GTab::L1 * n + ix];
+    const double L0j = gt[GTab::L0 * n + jz], L1j = gt[GTab::L1 * n + jz];
+    const double* qs = a.Qs + (size_t)c * sl;
+    double* qo = a.Qout + (size_t)c * sl;
+    const double scl = dt / h;
     double q[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const double sx = L1i * sG[1][v][jz] - L0i * sG[0][v][jz];
-      const double sz = L1j * sG[3][v][ix] - L0j * sG[2][v][ix];
-      q[v] = qs[v * nn + lane] - sc * (sx + sz);
-      qo[v * nn + lane] = q[v];
+      const double sx = L1i * sGc[(1 * 4 + v) * n + jz] - L0i * sGc[(0 * 4 + v) * n + jz];
+      const double sz = L1j * sGc[(3 * 4 + v) * n + ix] - L0j * sGc[(2 * 4 + v) * n + ix];
+      q[v] = qs[v * nn + l] - scl * (sx + sz);
+      qo[v * nn + l] = q[v];
     }
     if (!ph.fixed_dt) {
-      const double z = z0 + h * a.gtab[GTab::XI * n + jz];
+      const double zz = z0 + h * gt[GTab::XI * n + jz];
       double l0, lv0, l1, lv1;
-      eig(ph, 0, q, z, l0, lv0);
-      eig(ph, 1, q, z, l1, lv1);
-      lam = fmax(l0, l1);
-      lvm = lv0;
+      eig(ph, 0, q, zz, l0, lv0);
+      eig(ph, 1, q, zz, l1, lv1);
+      lam_n = fmax(l0, l1);
+      lv_n = lv0;
     }
   }
   if (!ph.fixed_dt) {
-    lam = wave_max(lam);
-    lvm = wave_max(lvm);
-    if (lane == 0) {
+    // maxima of lambda and lambda_v over the nodes of each cell slot (a
+    // contiguous lane range), then the CFL rule on the cell maxima
+    slam[wave][0][lane] = lam_n;
+    slam[wave][1][lane] = lv_n;
+    wave_sync();
+    if (valid && l == 0) {
+      double lm = lam_n, vm = lv_n;
+      for (int j = 1; j < nn; ++j) { lm = fmax(lm, slam[wave][0][lane + j]); vm = fmax(vm, slam[wave][1][lane + j]); }
+      const double h = a.geom[4 * c + 2];
       const double o = 2.0 * ph.N + 1.0;
-      a.dtc[c] = ph.cfl * h / (2.0 * o * (lam + 2.0 * lvm * o / h));
+      a.dtc[c] = ph.cfl * h / (2.0 * o * (lm + 2.0 * vm * o / h));
     }
   }
 }
@@ -412,95 +560,125 @@ __global__ __launch_bounds__(kWave) void k_cell_dt(Phys ph, StepArgs a) {
   }
 }
 
-// Clock update by one workgroup: if advance, t += dt and steps += 1; if
-// update, dt <- min over cells of the CFL candidates (a fixed reduction tree:
-// min is exact, so the result does not depend on the order anyway).
-constexpr int kReduceThreads = 1024;
-__global__ __launch_bounds__(kReduceThreads) void k_clock(double* clock, const double* dtc, int C, int advance,
-                                                           int update) {
+// Clock update, one workgroup per scenario: if advance, t += dt and
+// steps += 1; if update, dt <- min of the CFL candidates of the scenario's
+// cells [beg[s], end[s]) (min is exact, so the result is order independent).
+constexpr int kReduceThreads = 256;
+__global__ __launch_bounds__(kReduceThreads) void k_clock(double* clock, const double* dtc, const int* beg,
+                                                           const int* end, int C, int advance, int update) {
   __shared__ double sm[kReduceThreads / kWave];
-  const int t = threadIdx.x;
+  const int s = blockIdx.x, t = threadIdx.x;
+  const int b0 = beg ? beg[s] : 0, b1 = end ? end[s] : C;
   double m = __builtin_inf();
   if (update)
-    for (int c = t; c < C; c += kReduceThreads) m = fmin(m, dtc[c]);
-  #pragma unroll
+    for (int c = b0 + t; c < b1; c += kReduceThreads) m = fmin(m, dtc[c]);
+#pragma unroll
   for (int o = 32; o >= 1; o >>= 1) m = fmin(m, __shfl_xor(m, o, kWave));
   if ((t & (kWave - 1)) == 0) sm[t / kWave] = m;
   __syncthreads();
   if (t == 0) {
     double r = sm[0];
     for (int k = 1; k < kReduceThreads / kWave; ++k) r = fmin(r, sm[k]);
-    if (advance) { clock[0] += clock[1]; clock[3] += 1.0; }
-    if (update) clock[1] = r;
+    if (advance) { clock[4 * s + 0] += clock[4 * s + 1]; clock[4 * s + 3] += 1.0; }
+    if (update) clock[4 * s + 1] = r;
   }
 }
 
 // --------------------------------------------------------------- dispatchers
-template <int n>
-static Tab<n> make_tab(const adg_mesh* m) {
-  Tab<n> T;
-  for (int i = 0; i < n; ++i) {
-    T.w[i] = m->w[i]; T.e0[i] = m->e0[i]; T.e1[i] = m->e1[i];
-    for (int j = 0; j < n; ++j) {
-      T.D[i][j] = m->D[i * n + j];
-      T.P[i][j] = m->P[i * n + j];
-      T.Dw[i][j] = m->Dw[i * n + j];
-    }
-  }
-  return T;
-}
-
-StepArgs make_args(adg_mesh* m) {
+StepArgs make_args(const Group& g) {
   StepArgs a;
-  char* ws = static_cast<char*>(m->ws);
-  a.Qin = m->Q; a.Qout = m->Q;
-  a.Qs = reinterpret_cast<double*>(ws + m->off_qs);
-  a.FD = reinterpret_cast<double*>(ws + m->off_fd);
-  a.dtc = reinterpret_cast<double*>(ws + m->off_dtc);
-  a.health = reinterpret_cast<int*>(ws + m->off_health);
-  a.clock = m->clock; a.geom = m->d_geom; a.nbr = m->d_nbr; a.gtab = m->d_gtab;
-  a.C = m->C; a.iters = m->iters;
+  a.Qin = g.Q; a.Qout = g.Q; a.Qs = g.Qs; a.FD = g.FD; a.dtc = g.dtc;
+  a.clock = g.clock; a.scen = g.d_scen; a.geom = g.d_geom; a.nbr = g.d_nbr; a.gtab = g.d_gtab;
+  a.C = g.C; a.iters = g.iters;
   return a;
 }
 
-template <int n>
-static int launch_predictor_n(adg_mesh* m, hipStream_t s) {
-  StepArgs a = make_args(m);
-  hipLaunchKernelGGL(k_predictor<n>, dim3(m->C), dim3(kWave), 0, s, m->ph, a);
+template <int n, int CPW, int WPB>
+static int launch_pred_t(const Group& g, hipStream_t s) {
+  using L = Lay<n, CPW>;
+  const size_t lds = sizeof(double) * (size_t)WPB * CPW * L::pred_cell;
+  const int per_block = CPW * WPB;
+  const int blocks = (g.C + per_block - 1) / per_block;
+  if (blocks == 0) return ADG_OK;
+  hipLaunchKernelGGL((k_predictor<n, CPW, WPB>), dim3(blocks), dim3(kWave * WPB), lds, s, g.ph, make_args(g));
   return check_launch("predictor");
 }
-template <int n>
-static int launch_corrector_n(adg_mesh* m, hipStream_t s) {
-  StepArgs a = make_args(m);
-  hipLaunchKernelGGL(k_corrector<n>, dim3(m->C), dim3(kWave), 0, s, make_tab<n>(m), m->ph, a);
-  int rc = check_launch("corrector");
-  if (rc) return rc;
-  hipLaunchKernelGGL(k_clock, dim3(1), dim3(kReduceThreads), 0, s, m->clock, a.dtc, m->C, 1,
-                     m->ph.fixed_dt ? 0 : 1);
-  return check_launch("clock");
-}
-template <int n>
-static int launch_dt_n(adg_mesh* m, hipStream_t s) {
-  StepArgs a = make_args(m);
-  hipLaunchKernelGGL(k_cell_dt<n>, dim3(m->C), dim3(kWave), 0, s, m->ph, a);
-  hipLaunchKernelGGL(k_clock, dim3(1), dim3(kReduceThreads), 0, s, m->clock, a.dtc, m->C, 0, 1);
-  return check_launch("compute_dt");
+template <int n, int CPW, int WPB>
+static int launch_corr_t(const Group& g, hipStream_t s) {
+  using L = Lay<n, CPW>;
+  const size_t lds = sizeof(double) * (size_t)WPB * CPW * L::corr_cell;
+  const int per_block = CPW * WPB;
+  const int blocks = (g.C + per_block - 1) / per_block;
+  if (blocks == 0) return ADG_OK;
+  hipLaunchKernelGGL((k_corrector<n, CPW, WPB>), dim3(blocks), dim3(kWave * WPB), lds, s, g.ph, make_args(g));
+  return check_launch("corrector");
 }
 
-#define ADG_DISPATCH(fn, m, s)                         \
-  switch ((m)->n) {                                    \
-    case 2: return fn<2>(m, s);                        \
-    case 3: return fn<3>(m, s);                        \
-    case 4: return fn<4>(m, s);                        \
-    case 5: return fn<5>(m, s);                        \
-    case 6: return fn<6>(m, s);                        \
-    case 7: return fn<7>(m, s);                        \
-    case 8: return fn<8>(m, s);                        \
+template <int n, int CPW>
+static int pred_w(const Group& g, hipStream_t s) {
+  switch (g.wpb) {
+    case 1: return launch_pred_t<n, CPW, 1>(g, s);
+    case 2: return launch_pred_t<n, CPW, 2>(g, s);
+    case 4: return launch_pred_t<n, CPW, 4>(g, s);
+    default: return fail(ADG_EINVAL, "waves per block must be 1, 2 or 4");
+  }
+}
+template <int n, int CPW>
+static int corr_w(const Group& g, hipStream_t s) {
+  switch (g.wpb) {
+    case 1: return launch_corr_t<n, CPW, 1>(g, s);
+    case 2: return launch_corr_t<n, CPW, 2>(g, s);
+    case 4: return launch_corr_t<n, CPW, 4>(g, s);
+    default: return fail(ADG_EINVAL, "waves per block must be 1, 2 or 4");
+  }
+}
+// cells per wavefront: 1, 2 or 4 (while CPW * n^2 <= 64)
+template <int n>
+static int pred_n(const Group& g, hipStream_t s) {
+  constexpr int nn = n * n;
+  if (g.cpw == 1) return pred_w<n, 1>(g, s);
+  if constexpr (2 * nn <= kWave) { if (g.cpw == 2) return pred_w<n, 2>(g, s); }
+  if constexpr (4 * nn <= kWave) { if (g.cpw == 4) return pred_w<n, 4>(g, s); }
+  return fail(ADG_EINVAL, "cells per wavefront not supported for this order");
+}
+template <int n>
+static int corr_n(const Group& g, hipStream_t s) {
+  constexpr int nn = n * n;
+  if (g.cpw == 1) return corr_w<n, 1>(g, s);
+  if constexpr (2 * nn <= kWave) { if (g.cpw == 2) return corr_w<n, 2>(g, s); }
+  if constexpr (4 * nn <= kWave) { if (g.cpw == 4) return corr_w<n, 4>(g, s); }
+  return fail(ADG_EINVAL, "cells per wavefront not supported for this order");
+}
+template <int n>
+static int dt_n(const Group& g, hipStream_t s) {
+  if (g.C == 0) return ADG_OK;
+  hipLaunchKernelGGL(k_cell_dt<n>, dim3(g.C), dim3(kWave), 0, s, g.ph, make_args(g));
+  return check_launch("cell_dt");
+}
+
+#define ADG_DISPATCH_N(fn, g, s)                                   \
+  switch ((g).n) {                                                 \
+    case 2: return fn<2>(g, s);                                    \
+    case 3: return fn<3>(g, s);                                    \
+    case 4: return fn<4>(g, s);                                    \
+    case 5: return fn<5>(g, s);                                    \
+    case 6: return fn<6>(g, s);                                    \
+    case 7: return fn<7>(g, s);                                    \
+    case 8: return fn<8>(g, s);                                    \
     default: return fail(ADG_EUNSUPPORTED, "order not supported"); \
   }
 
-int launch_predictor(adg_mesh* m, hipStream_t s) { ADG_DISPATCH(launch_predictor_n, m, s); }
-int launch_corrector(adg_mesh* m, hipStream_t s) { ADG_DISPATCH(launch_corrector_n, m, s); }
-int launch_dt(adg_mesh* m, hipStream_t s) { ADG_DISPATCH(launch_dt_n, m, s); }
+int launch_predictor(const Group& g, hipStream_t s) { ADG_DISPATCH_N(pred_n, g, s); }
+int launch_corrector(const Group& g, hipStream_t s) { ADG_DISPATCH_N(corr_n, g, s); }
+int launch_cell_dt(const Group& g, hipStream_t s) { ADG_DISPATCH_N(dt_n, g, s); }
+
+int launch_clock(double* clock, const double* dtc, const int* beg, const int* end, int nscen, int C, int advance,
+                 int update, hipStream_t s) {
+  if (nscen <= 0) return ADG_OK;
+  hipLaunchKernelGGL(k_clock, dim3(nscen), dim3(kReduceThreads), 0, s, clock, dtc, beg, end, C, advance, update);
+  return check_launch("clock");
+}
+
+int max_cpw(int n) { return (4 * n * n <= kWave) ? 4 : ((2 * n * n <= kWave) ? 2 : 1); }
 
 }  // namespace adg

@@ -126,3 +126,15 @@ def perturb(Q: np.ndarray, seed: int, rel: float = 1e-3, vel: float = 0.5):
     P[:, 1] += vel * Q[:, 0] * rng.uniform(-1, 1, P[:, 1].shape)
     P[:, 2] += vel * Q[:, 0] * rng.uniform(-1, 1, P[:, 2].shape)
     return P
+
+
+def refined_leaves(nx: int, nz: int, refine):
+    """Leaf list (level, i, j) of an nx x nz coarse grid where the coarse
+    cells in `refine` (iterable of (i, j)) are split into 3x3 children.
+    Coarse cells come first in row-major order, then children family by
+    family."""
+    rs = set(tuple(r) for r in refine)
+    out = [(0, i, j) for j in range(nz) for i in range(nx) if (i, j) not in rs]
+    for (i, j) in sorted(rs, key=lambda t: (t[1], t[0])):
+        out += [(1, 3 * i + a, 3 * j + b) for b in range(3) for a in range(3)]
+    return out

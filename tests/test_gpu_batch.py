@@ -1,0 +1,201 @@
+"""GPU tests of the launch shapes, the multi-scenario batch (eager and HIP
+graph) and adaptive meshes with 1:3 non-conforming faces, all through the C
+ABI.  Launch shapes and batching must not change results: they are compared
+bitwise with the single-mesh default shape; adaptive meshes are compared with
+the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_1905_05524_amd import adg
+from paper_1905_05524_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+def relerr(a, b):
+    a = np.asarray(a).reshape(a.shape[0], 4, -1)
+    b = np.asarray(b).reshape(b.shape[0], 4, -1)
+    mx = [np.max(np.abs(b[:, v])) for v in range(4)]
+    ac = math.sqrt(mx[0] * mx[3])
+    sc = [mx[0], max(mx[1], ac), max(mx[2], ac), mx[3]]
+    return np.array([np.max(np.abs(a[:, v] - b[:, v])) / sc[v] for v in range(4)])
+
+
+def _run(w, Q, dt, shape=None, steps=2):
+    m = adg.Mesh(w["phys"], w["mesh"], fixed_dt=True)
+    if shape:
+        m.set_launch(*shape)
+    m.set_state(Q, t=0.0, dt=dt)
+    for _ in range(steps):
+        m.step()
+    torch.cuda.synchronize()
+    return m.Q.clone()
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 6])
+def test_launch_shapes_are_bitwise_equal(N):
+    w = I.bubble(7, N)      # 49 cells: ragged for every packing
+    Q = I.perturb(O.ic(w["phys"], w["mesh"], "bubbles", w["bubbles"]), seed=N)
+    dt = 0.5 * O.dt(w["phys"], w["mesh"], Q)
+    base = _run(w, Q, dt)
+    n = N + 1
+    for cpw in (1, 2, 4):
+        if cpw * n * n > 64:
+            continue
+        for wpb in (1, 2, 4):
+            got = _run(w, Q, dt, (cpw, wpb))
+            assert torch.equal(got, base), (cpw, wpb)
+
+
+def test_invalid_launch_shape_rejected():
+    w = I.bubble(3, 6)
+    m = adg.Mesh(w["phys"], w["mesh"])
+    with pytest.raises(adg.AdgError):
+        m.set_launch(2, 1)    # 2 * 49 > 64
+    with pytest.raises(adg.AdgError):
+        m.set_launch(1, 3)
+
+
+def test_autotune_keeps_state_and_results():
+    w = I.bubble(9, 3)
+    m = adg.Mesh(w["phys"], w["mesh"])
+    m.init_state("bubbles", w["bubbles"])
+    m.compute_dt()
+    Q0, c0 = m.Q.clone(), m.clock.clone()
+    cpw, wpb = m.autotune(reps=2)
+    assert torch.equal(m.Q, Q0) and torch.equal(m.clock, c0)
+    assert cpw in (1, 2, 4) and wpb in (1, 2, 4)
+    m.step()
+    ref = adg.Mesh(w["phys"], w["mesh"])
+    ref.set_state(Q0)
+    ref.clock.copy_(c0)
+    ref.step()
+    assert torch.equal(m.Q, ref.Q)
+
+
+def _small_batch():
+    ws = I.batch_scenarios(6, seed=7)
+    # shrink grids to keep the test fast but keep the order mix and raggedness
+    for k, w in enumerate(ws):
+        nx = [5, 9, 4, 7, 3, 6][k]
+        w["mesh"]["nx"] = w["mesh"]["nz"] = nx
+    return ws
+
+
+def test_batch_matches_single_runs_bitwise():
+    ws = _small_batch()
+    b = adg.Batch(ws)
+    for s, w in enumerate(ws):
+        b.init_state(s, "bubbles", w["bubbles"])
+    b.compute_dt()
+    for _ in range(3):
+        b.step()
+    torch.cuda.synchronize()
+    for s, w in enumerate(ws):
+        m = adg.Mesh(w["phys"], w["mesh"])
+        m.init_state("bubbles", w["bubbles"])
+        m.compute_dt()
+        for _ in range(3):
+            m.step()
+        torch.cuda.synchronize()
+        assert torch.equal(b.state(s), m.Q), s
+        assert torch.equal(b.clock[s], m.clock), s
+
+
+def test_batch_graph_replay_equals_eager():
+    ws = _small_batch()
+    eager, graph = adg.Batch(ws), adg.Batch(ws)
+    for b in (eager, graph):
+        for s, w in enumerate(ws):
+            b.init_state(s, "bubbles", w["bubbles"])
+        b.compute_dt()
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    for k in range(4):
+        eager.step()
+        with torch.cuda.stream(stream):
+            graph.step_graph(stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        # eager work and synchronisation between replays
+        assert torch.equal(eager.Q, graph.Q), k
+        assert torch.equal(eager.clock, graph.clock), k
+
+
+def test_batch_autotune_then_step_unchanged():
+    ws = _small_batch()
+    a, b = adg.Batch(ws), adg.Batch(ws)
+    for bb in (a, b):
+        for s, w in enumerate(ws):
+            bb.init_state(s, "bubbles", w["bubbles"])
+        bb.compute_dt()
+    cpw, wpb = b.autotune(reps=2)
+    assert len(cpw) == b.n_groups
+    a.step()
+    b.step()
+    torch.cuda.synchronize()
+    assert torch.equal(a.Q, b.Q) and torch.equal(a.clock, b.clock)
+
+
+def test_batch_rejects_mixed_physics():
+    ws = _small_batch()
+    ws[1]["phys"] = dict(ws[1]["phys"], mu=2e-3)
+    with pytest.raises(adg.AdgError):
+        adg.Batch(ws)
+
+
+# ------------------------------------------------------------ adaptive meshes
+def amr_case(kind, N):
+    if kind == "periodic":
+        w = I.mms_small(N=N, nx=4, mu=0.02)
+        w["phys"]["mms"] = 0
+        mesh = dict(w["mesh"], max_level=1, leaves=I.refined_leaves(4, 4, [(1, 1), (2, 1), (3, 3), (0, 0)]))
+        return w["phys"], mesh, I.random_state_cfd(len(mesh["leaves"]), N, seed=50 + N)
+    w = I.bubble(6, N, bubbles=[I.cosine_bubble(), I.cold_bubble()])
+    mesh = dict(w["mesh"], max_level=1, leaves=I.refined_leaves(6, 6, [(2, 1), (3, 1), (2, 2), (0, 5), (5, 0)]))
+    Q = O.ic(w["phys"], mesh, "bubbles", w["bubbles"])
+    return w["phys"], mesh, I.perturb(Q, seed=60 + N)
+
+
+@pytest.mark.parametrize("kind", ["periodic", "walls"])
+@pytest.mark.parametrize("N", [1, 3, 6])
+def test_adaptive_step_matches_oracle(kind, N):
+    phys, mesh, Q = amr_case(kind, N)
+    dt = 0.5 * O.dt(phys, mesh, Q)
+    m = adg.Mesh(phys, mesh, fixed_dt=True)
+    m.set_state(Q, t=0.2, dt=dt)
+    m.step()
+    ref = O.step(phys, mesh, Q, 0.2, dt)
+    got = m.Q.cpu().numpy()
+    assert np.all(relerr(got, ref) <= TOL), relerr(got, ref)
+
+
+def test_adaptive_periodic_conservation_on_gpu():
+    phys, mesh, Q = amr_case("periodic", 4)
+    b = O.basis(4)
+    W = np.outer(b["w"], b["w"])
+    h = np.array([1.0 / 4 / 3 ** l for (l, _, _) in mesh["leaves"]])
+    Wc = W[None] * (h ** 2)[:, None, None]
+    m = adg.Mesh(phys, mesh, fixed_dt=True)
+    m.set_state(Q, t=0.0, dt=0.5 * O.dt(phys, mesh, Q))
+    for _ in range(3):
+        m.step()
+    before = np.einsum("cvji,cji->v", Q, Wc)
+    after = np.einsum("cvji,cji->v", m.Q.cpu().numpy(), Wc)
+    assert np.all(np.abs(after - before) <= 1e-13 * np.abs(before).max())
+
+
+def test_adaptive_initial_state_matches_oracle():
+    phys, mesh, _ = amr_case("walls", 6)
+    w = I.bubble(6, 6, bubbles=[I.cosine_bubble(), I.cold_bubble()])
+    m = adg.Mesh(phys, mesh)
+    m.init_state("bubbles", w["bubbles"])
+    ref = O.ic(phys, mesh, "bubbles", w["bubbles"])
+    assert np.all(relerr(m.Q.cpu().numpy(), ref) <= 1e-14)
