@@ -27,7 +27,7 @@
  *     (allocated in adg_init_mesh, freed in adg_destroy).
  *   - Streams: `stream` is a hipStream_t passed as void* (NULL = default
  *     stream).  Enqueuing calls are asynchronous and capturable in a HIP
- *     graph, except adg_regrid and adg_check_health, which synchronise.
+ *     graph, except adg_regrid_apply and adg_check_health, which synchronise.
  *   - Errors: every call returns an adg status; parameter and launch errors
  *     are reported immediately, with a message from adg_last_error().  Device
  *     state errors (non-finite values, rho <= 0, p <= 0) are reported by
@@ -165,6 +165,29 @@ const char* adg_last_error(void);
 /* Read back the handle's GL nodes/weights and matrices (n, n, n*n, n*n):
  * D[i*n+j] = phi_j'(xi_i), P = K1^{-1} W of the time predictor. */
 int adg_basis(const adg_mesh* m, double* xi, double* w, double* D, double* P);
+
+/* Leaf list of the current mesh (host arrays of n_cells entries, may be
+ * NULL), in cell order. */
+int adg_get_leaves(const adg_mesh* m, int32_t* level, int32_t* i, int32_t* j);
+
+/* Regrid, step 1 (host only): from per-cell flags (host int8[C]: +1 refine,
+ * -1 coarsen, 0 keep; e.g. the output of adg_tv_indicator copied to the
+ * host) build the new leaf list: refine is dropped at max_level and coarsen
+ * at level 0; a family of nine siblings becomes its parent only if all nine
+ * are leaves flagged coarsen (paper, Section 3); refined leaves are replaced
+ * by their 3x3 children.  New order: old leaves in order, children row by
+ * row in place of their parent, a coarsened family at its first sibling.
+ * Returns the new cell count and workspace size.  EUNSUPPORTED if the result
+ * has neighbours more than one level apart. */
+int adg_regrid_plan(adg_mesh* m, const int8_t* flags_host, int* n_cells_new, size_t* ws_bytes_new);
+
+/* Regrid, step 2: transfer the bound state into Q_new (caller-owned,
+ * n_cells_new*4*n*n doubles, must not alias Q): copy for kept leaves, exact
+ * interpolation of the parent polynomial for new children, L2 projection of
+ * the nine children for a new parent; then rebuild the face tables and bind
+ * (Q_new, workspace_new, clock).  Synchronises the stream.  The old Q and
+ * workspace are the caller's to free. */
+int adg_regrid_apply(adg_mesh* m, double* Q_new, void* workspace_new, double* clock, void* stream);
 
 /* Launch shape of the predictor and corrector: cells per wavefront (1, 2 or
  * 4, with cells_per_wave * n^2 <= 64) and wavefronts per workgroup (1, 2 or

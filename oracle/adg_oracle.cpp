@@ -951,4 +951,91 @@ int oracle_ic(const double* prm, const int* mi, const double* md, const int* lev
   return 0;
 }
 
+// Regrid after the refinement criterion (paper, Section 3): a flag +1 splits
+// a leaf into its 3x3 children (not beyond the finest level), -1 marks it for
+// coarsening; the nine children of a parent are merged into the parent only
+// when all nine are leaves and all are marked (and never below level 0).
+// Leaves are emitted in old order: children row by row in place of a split
+// leaf, a merged parent at the position of its first child.  States: a child
+// takes the parent polynomial at its nodes; a merged parent takes the L2
+// projection of its children (GL quadrature on each child).  Outputs are
+// sized for 9*C leaves; *C_new is set.
+int oracle_regrid(const double* prm, const int* mi, const double* md, const int* lev, const int* ci,
+                  const int* cj, const double* Q, const int8_t* flags, int* nlev, int* nci, int* ncj,
+                  double* Qn, int* C_new) {
+  Params P = read_params(prm);
+  Basis B = make_basis(P.N);
+  Mesh M = build_mesh(mi, md, lev, ci, cj);
+  if (!M.ok) return -1;
+  const int C = (int)M.cells.size(), n = P.n, sl = 4 * n * n, L = M.L;
+  // which parents merge: all nine children present as leaves and flagged -1
+  auto parent_merges = [&](int l, int i, int j) {
+    if (l == 0) return false;
+    int pi = i / 3, pj = j / 3, found = 0;
+    for (int c = 0; c < C; ++c) {
+      const Cell& k = M.cells[c];
+      if (k.level == l && k.i / 3 == pi && k.j / 3 == pj) {
+        if (flags[c] != -1) return false;
+        ++found;
+      }
+    }
+    return found == 9;
+  };
+  std::vector<int> done;   // parents already emitted, as (l, i, j) triples
+  int out = 0;
+  for (int c = 0; c < C; ++c) {
+    const Cell& k = M.cells[c];
+    if (flags[c] == -1 && k.level > 0 && parent_merges(k.level, k.i, k.j)) {
+      int pl = k.level - 1, pi = k.i / 3, pj = k.j / 3;
+      bool seen = false;
+      for (size_t q = 0; q < done.size(); q += 3)
+        if (done[q] == pl && done[q + 1] == pi && done[q + 2] == pj) seen = true;
+      if (seen) continue;
+      done.push_back(pl); done.push_back(pi); done.push_back(pj);
+      nlev[out] = pl; nci[out] = pi; ncj[out] = pj;
+      double* dst = Qn + (size_t)out * sl;
+      for (int t = 0; t < sl; ++t) dst[t] = 0.0;
+      for (int c2 = 0; c2 < C; ++c2) {
+        const Cell& ch = M.cells[c2];
+        if (ch.level != k.level || ch.i / 3 != pi || ch.j / 3 != pj) continue;
+        int a = ch.i - 3 * pi, b = ch.j - 3 * pj;
+        for (int v = 0; v < 4; ++v)
+          for (int jj = 0; jj < n; ++jj)
+            for (int ii = 0; ii < n; ++ii) {
+              double s = 0.0;
+              for (int l2 = 0; l2 < n; ++l2)
+                for (int m2 = 0; m2 < n; ++m2)
+                  s += (B.w[m2] * B.w[l2] / 9.0) * phi_at(B, ii, (a + B.xi[m2]) / 3.0) *
+                       phi_at(B, jj, (b + B.xi[l2]) / 3.0) * Q[(size_t)c2 * sl + (v * n + l2) * n + m2];
+              dst[(v * n + jj) * n + ii] += s / (B.w[ii] * B.w[jj]);
+            }
+      }
+      ++out;
+    } else if (flags[c] == 1 && k.level < L) {
+      for (int b = 0; b < 3; ++b)
+        for (int a = 0; a < 3; ++a) {
+          nlev[out] = k.level + 1; nci[out] = 3 * k.i + a; ncj[out] = 3 * k.j + b;
+          double* dst = Qn + (size_t)out * sl;
+          for (int v = 0; v < 4; ++v)
+            for (int jj = 0; jj < n; ++jj)
+              for (int ii = 0; ii < n; ++ii) {
+                double s = 0.0;
+                for (int l2 = 0; l2 < n; ++l2)
+                  for (int m2 = 0; m2 < n; ++m2)
+                    s += phi_at(B, m2, (a + B.xi[ii]) / 3.0) * phi_at(B, l2, (b + B.xi[jj]) / 3.0) *
+                         Q[(size_t)c * sl + (v * n + l2) * n + m2];
+                dst[(v * n + jj) * n + ii] = s;
+              }
+          ++out;
+        }
+    } else {
+      nlev[out] = k.level; nci[out] = k.i; ncj[out] = k.j;
+      for (int t = 0; t < sl; ++t) Qn[(size_t)out * sl + t] = Q[(size_t)c * sl + t];
+      ++out;
+    }
+  }
+  *C_new = out;
+  return 0;
+}
+
 }  // extern "C"

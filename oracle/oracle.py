@@ -64,6 +64,7 @@ def lib():
                                               dp, i8p, dp]
         L.oracle_ic.argtypes = [dp] + mesh + [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, dp]
         L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_regrid.argtypes = [dp] + mesh + [dp, i8p, ip, ip, ip, dp, ip]
         _lib = L
     return _lib
 
@@ -215,3 +216,19 @@ def ic(phys: dict, mesh: dict, kind: str = "bubbles", bubbles=(), t0: float = 0.
     k = 1 if kind == "mms" else 0
     _check(lib().oracle_ic(_dp(p), *m.args, k, bb.shape[0], _dp(bb), float(t0), _dp(Q)), "ic")
     return Q
+
+
+def regrid(phys: dict, mesh: dict, Q: np.ndarray, flags) -> tuple:
+    """Returns (new leaf list [(level, i, j)], new state)."""
+    p, m = params(phys), _Mesh(mesh)
+    n = int(phys["N"]) + 1
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    f = np.ascontiguousarray(np.asarray(flags, dtype=np.int8))
+    cap = 9 * m.C
+    nl, ni, nj = (np.zeros(cap, dtype=np.int32) for _ in range(3))
+    Qn = np.zeros((cap, 4, n, n))
+    cn = np.zeros(1, dtype=np.int32)
+    _check(lib().oracle_regrid(_dp(p), *m.args, _dp(Q), f.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                               _ip(nl), _ip(ni), _ip(nj), _dp(Qn), _ip(cn)), "regrid")
+    C = int(cn[0])
+    return [(int(nl[c]), int(ni[c]), int(nj[c])) for c in range(C)], Qn[:C].copy()

@@ -24,7 +24,8 @@ EXPORTED = [
     "adg_tv_indicator", "adg_check_health", "adg_last_error", "adg_basis", "adg_set_launch",
     "adg_autotune", "adg_batch_create", "adg_batch_destroy", "adg_batch_info", "adg_batch_scenario",
     "adg_batch_set_state", "adg_batch_init_state", "adg_batch_compute_dt", "adg_batch_step",
-    "adg_batch_step_graph", "adg_batch_autotune", "adg_batch_set_launch",
+    "adg_batch_step_graph", "adg_batch_autotune", "adg_batch_set_launch", "adg_get_leaves",
+    "adg_regrid_plan", "adg_regrid_apply",
 ]
 
 
@@ -94,6 +95,10 @@ def lib():
             getattr(L, name).argtypes = [vp, vp]
         L.adg_batch_autotune.argtypes = [vp, ctypes.c_int, vp, ip, ip]
         L.adg_batch_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        L.adg_get_leaves.argtypes = [vp, i32p, i32p, i32p]
+        L.adg_regrid_plan.argtypes = [vp, vp, ip, ctypes.POINTER(ctypes.c_size_t)]
+        L.adg_regrid_apply.argtypes = [vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -219,6 +224,31 @@ class Mesh:
 
     def check_health(self, stream=None):
         _check(lib().adg_check_health(self.h, _stream_ptr(stream)))
+
+    def leaves(self):
+        lv = np.zeros((self.C, 3), dtype=np.int32)
+        cols = [np.zeros(self.C, dtype=np.int32) for _ in range(3)]
+        p = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        _check(lib().adg_get_leaves(self.h, p(cols[0]), p(cols[1]), p(cols[2])))
+        for k in range(3):
+            lv[:, k] = cols[k]
+        return lv
+
+    def regrid(self, flags, stream=None):
+        """Regrid with per-cell flags (host array or tensor of -1/0/+1); the
+        state moves to newly allocated buffers.  Returns the new cell count."""
+        import torch
+        f = np.ascontiguousarray(np.asarray(flags.cpu() if torch.is_tensor(flags) else flags, dtype=np.int8))
+        if f.shape != (self.C,):
+            raise ValueError("flags must have one entry per cell")
+        nc, wb = ctypes.c_int(), ctypes.c_size_t()
+        _check(lib().adg_regrid_plan(self.h, ctypes.c_void_p(f.ctypes.data), ctypes.byref(nc), ctypes.byref(wb)))
+        Qn = torch.empty((nc.value, 4, self.n, self.n), dtype=torch.float64, device=self.device)
+        wsn = torch.empty(max(wb.value, 256), dtype=torch.uint8, device=self.device)
+        _check(lib().adg_regrid_apply(self.h, ctypes.c_void_p(Qn.data_ptr()), ctypes.c_void_p(wsn.data_ptr()),
+                                      ctypes.c_void_p(self.clock.data_ptr()), _stream_ptr(stream)))
+        self.Q, self.ws, self.C, self.ws_bytes = Qn, wsn, nc.value, wb.value
+        return self.C
 
     def set_launch(self, cells_per_wave: int, waves_per_block: int):
         _check(lib().adg_set_launch(self.h, int(cells_per_wave), int(waves_per_block)))

@@ -103,6 +103,9 @@ struct adg_mesh {
   double* clock = nullptr;
   // workspace partition (byte offsets)
   size_t off_qs = 0, off_fd = 0, off_dtc = 0, off_health = 0, ws_bytes = 0;
+  // pending regrid (from adg_regrid_plan)
+  bool plan_ready = false;
+  std::vector<int> plan_lev, plan_ci, plan_cj, plan_ops;
 };
 
 namespace adg {

@@ -20,6 +20,11 @@ int launch_init_state(const Group& g, int c0, int count, int kind, int nbub, con
 int launch_tv(const Group& g, const HostBasis& B, int var, double Tr, double Tc, double* tv, int8_t* flags,
               double* stats, hipStream_t s);
 int launch_health(const Group& g, int* flag, hipStream_t s);
+int launch_regrid(int n, int C, const int* ops, const double* Qold, double* Qnew, const double* gtab,
+                  hipStream_t s);
+int regrid_plan(const std::vector<int>& lev, const std::vector<int>& ci, const std::vector<int>& cj,
+                const int8_t* flags, int L, std::vector<int>& nlev, std::vector<int>& nci, std::vector<int>& ncj,
+                std::vector<int>& ops);
 
 static thread_local std::string g_err;
 
@@ -407,6 +412,21 @@ static int autotune_group(Group& g, hipStream_t s, int reps, float* best_ms) {
   return check_launch("autotune");
 }
 
+// workspace: Q* [C][4][n][n], face data [C][4][2][4][n], CFL candidates, health flag
+static size_t workspace_size(int C_, int n, size_t* off_qs, size_t* off_fd, size_t* off_dtc, size_t* off_h) {
+  const size_t C = (size_t)C_;
+  size_t off = 0;
+  *off_qs = off; off = align256(off + sizeof(double) * C * 4 * n * n);
+  *off_fd = off; off = align256(off + sizeof(double) * C * 32 * n);
+  *off_dtc = off; off = align256(off + sizeof(double) * C);
+  *off_h = off; off = align256(off + sizeof(int));
+  return off;
+}
+
+static void layout_workspace(adg_mesh* m) {
+  m->ws_bytes = workspace_size(m->g.C, m->g.n, &m->off_qs, &m->off_fd, &m->off_dtc, &m->off_health);
+}
+
 }  // namespace adg
 
 using namespace adg;
@@ -435,14 +455,7 @@ int adg_init_mesh(const adg_params* prm, const adg_mesh_desc* mesh, adg_mesh** o
   g.C = m->hm.C; g.ph = make_phys(*prm);
   rc = upload_group(g, m->hm.geom, m->hm.nbr, m->basis.gtab, nullptr);
   if (rc) { delete m; return rc; }
-  // workspace: Q* [C][4][n][n], face data [C][4][2][4][n], CFL candidates, health flag
-  const size_t C = (size_t)g.C;
-  size_t off = 0;
-  m->off_qs = off; off = align256(off + sizeof(double) * C * 4 * n * n);
-  m->off_fd = off; off = align256(off + sizeof(double) * C * 32 * n);
-  m->off_dtc = off; off = align256(off + sizeof(double) * C);
-  m->off_health = off; off = align256(off + sizeof(int));
-  m->ws_bytes = off;
+  layout_workspace(m);
   *out = m;
   return ADG_OK;
 }
@@ -553,6 +566,74 @@ int adg_basis(const adg_mesh* m, double* xi, double* w, double* D, double* P) {
   if (D) std::memcpy(D, m->basis.D.data(), sizeof(double) * n * n);
   if (P) std::memcpy(P, m->basis.P.data(), sizeof(double) * n * n);
   return ADG_OK;
+}
+
+int adg_get_leaves(const adg_mesh* m, int32_t* level, int32_t* i, int32_t* j) {
+  if (!m) return fail(ADG_EINVAL, "null handle");
+  for (int c = 0; c < m->hm.C; ++c) {
+    if (level) level[c] = m->hm.lev[c];
+    if (i) i[c] = m->hm.ci[c];
+    if (j) j[c] = m->hm.cj[c];
+  }
+  return ADG_OK;
+}
+
+int adg_regrid_plan(adg_mesh* m, const int8_t* flags_host, int* n_cells_new, size_t* ws_bytes_new) {
+  if (!m || !flags_host) return fail(ADG_EINVAL, "null argument");
+  m->plan_ready = false;
+  int rc = regrid_plan(m->hm.lev, m->hm.ci, m->hm.cj, flags_host, m->desc.max_level, m->plan_lev, m->plan_ci,
+                       m->plan_cj, m->plan_ops);
+  if (rc) return rc;
+  // the new leaves must form a valid mesh (at most one level between neighbours)
+  adg_mesh_desc d = m->desc;
+  d.n_leaves = (int)m->plan_lev.size();
+  d.leaf_level = m->plan_lev.data(); d.leaf_i = m->plan_ci.data(); d.leaf_j = m->plan_cj.data();
+  HostMesh probe;
+  rc = build_mesh(d, probe);
+  if (rc) return fail(ADG_EUNSUPPORTED, std::string("regrid result is not a valid mesh: ") + g_err);
+  size_t a, b, c, e;
+  if (n_cells_new) *n_cells_new = d.n_leaves;
+  if (ws_bytes_new) *ws_bytes_new = workspace_size(d.n_leaves, m->g.n, &a, &b, &c, &e);
+  m->plan_ready = true;
+  return ADG_OK;
+}
+
+int adg_regrid_apply(adg_mesh* m, double* Q_new, void* workspace_new, double* clock, void* stream) {
+  int rc = need_state(m);
+  if (rc) return rc;
+  if (!m->plan_ready) return fail(ADG_ESTATE, "no regrid plan (adg_regrid_plan)");
+  if (!Q_new || !workspace_new || !clock) return fail(ADG_EINVAL, "null buffer");
+  if (Q_new == m->Q) return fail(ADG_EINVAL, "Q_new must not alias the current state");
+  hipStream_t s = (hipStream_t)stream;
+  const int Cn = (int)m->plan_lev.size();
+  int* d_ops = nullptr;
+  if (hipMalloc(&d_ops, sizeof(int) * m->plan_ops.size()) != hipSuccess) return fail(ADG_ENOMEM, "alloc ops");
+  if (hipMemcpy(d_ops, m->plan_ops.data(), sizeof(int) * m->plan_ops.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d_ops);
+    return fail(ADG_EHIP, "upload ops");
+  }
+  rc = launch_regrid(m->g.n, Cn, d_ops, m->Q, Q_new, m->g.d_gtab, s);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(d_ops);
+  if (rc) return rc;
+  // rebuild the mesh tables for the new leaves
+  adg_mesh_desc d = m->desc;
+  d.n_leaves = Cn;
+  d.leaf_level = m->plan_lev.data(); d.leaf_i = m->plan_ci.data(); d.leaf_j = m->plan_cj.data();
+  HostMesh H;
+  rc = build_mesh(d, H);
+  if (rc) return rc;
+  Group g = m->g;
+  g.d_geom = nullptr; g.d_nbr = nullptr; g.d_gtab = nullptr; g.d_scen = nullptr;
+  g.C = H.C;
+  rc = upload_group(g, H.geom, H.nbr, m->basis.gtab, nullptr);
+  if (rc) return rc;
+  free_group(m->g);
+  m->g = g;
+  m->hm = std::move(H);
+  m->plan_ready = false;
+  layout_workspace(m);
+  return adg_set_state(m, Q_new, workspace_new, clock);
 }
 
 int adg_set_launch(adg_mesh* m, int cells_per_wave, int waves_per_block) {

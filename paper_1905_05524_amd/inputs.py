@@ -67,9 +67,15 @@ def bubble27():
 
 
 def amr27():
+    """27x27 coarse cells of 37.04 m, one 3-way refinement level, warm cosine
+    and cold Gaussian bubbles, N=6; regrid every 10 steps with the TV of theta.
+    Thresholds: T_refine = 0, T_coarsen = -0.4 (T_refine refines 153 coarse
+    cells of the initial state: 1953 leaves)."""
     w = bubble(27, 6, bubbles=[cosine_bubble(), cold_bubble()], steps=200)
     w["mesh"]["max_level"] = 1
+    w["mesh"]["leaves"] = uniform_leaves(27, 27)
     w["name"] = "amr27x27_L1_N6"
+    w["T_refine"], w["T_coarsen"], w["regrid_every"] = 0.0, -0.4, 10
     return w
 
 

@@ -1,0 +1,122 @@
+"""GPU tests of the adaptive-mesh path: regrid (leaf rule and state
+transfer) against the oracle, and the refinement cycle of the adaptive
+workload (TV indicator -> flags -> regrid -> steps), each stage compared with
+the oracle fed the GPU's previous state."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_1905_05524_amd import adg
+from paper_1905_05524_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def relerr(a, b):
+    a = np.asarray(a).reshape(a.shape[0], 4, -1)
+    b = np.asarray(b).reshape(b.shape[0], 4, -1)
+    mx = [np.max(np.abs(b[:, v])) for v in range(4)]
+    ac = math.sqrt(mx[0] * mx[3])
+    sc = [mx[0], max(mx[1], ac), max(mx[2], ac), mx[3]]
+    return np.array([np.max(np.abs(a[:, v] - b[:, v])) / sc[v] for v in range(4)])
+
+
+def leaves_of(m):
+    return [tuple(int(x) for x in r) for r in m.leaves()]
+
+
+@pytest.mark.parametrize("N", [2, 5])
+def test_regrid_matches_oracle(N):
+    w = I.bubble(4, N)
+    leaves = I.refined_leaves(4, 4, [(1, 1), (2, 2), (0, 3)])
+    mesh = dict(w["mesh"], max_level=1, leaves=leaves)
+    Q = I.perturb(O.ic(w["phys"], mesh, "bubbles", w["bubbles"]), seed=N)
+    rng = np.random.default_rng(N)
+    flags = rng.integers(-1, 2, len(leaves)).astype(np.int8)
+    fam = [c for c, (l, i, j) in enumerate(leaves) if l == 1 and (i // 3, j // 3) == (2, 2)]
+    flags[fam] = -1                      # one family merges
+    m = adg.Mesh(w["phys"], mesh)
+    m.set_state(Q)
+    C = m.regrid(flags)
+    ref_leaves, ref_Q = O.regrid(w["phys"], mesh, Q, flags)
+    assert leaves_of(m) == ref_leaves and C == len(ref_leaves)
+    assert np.all(relerr(m.Q.cpu().numpy(), ref_Q) <= 1e-13)
+    # the handle's faces follow the new mesh: one step matches the oracle
+    new_mesh = dict(mesh, leaves=ref_leaves)
+    Qg = m.Q.cpu().numpy().copy()
+    dt = 0.5 * O.dt(w["phys"], new_mesh, Qg)
+    m.clock[0], m.clock[1] = 0.0, dt
+    m.step()
+    ref = O.step(w["phys"], new_mesh, Qg, 0.0, dt)
+    got = m.Q.cpu().numpy()
+    assert np.all(relerr(got, ref) <= 1e-11)
+
+
+def _tv(m, var, Tr, Tc):
+    tv = torch.zeros(m.C, dtype=torch.float64, device="cuda")
+    fl = torch.zeros(m.C, dtype=torch.int8, device="cuda")
+    st = torch.zeros(3, dtype=torch.float64, device="cuda")
+    m.tv_indicator(var, Tr, Tc, tv, fl, st)
+    torch.cuda.synchronize()
+    return tv.cpu().numpy(), fl.cpu().numpy(), st.cpu().numpy()
+
+
+def test_refinement_cycle_matches_oracle():
+    """9x9 coarse, one level, N=4, both bubbles: initial refinement from the
+    analytic state, then two cycles of 3 steps + regrid."""
+    w = I.bubble(9, 4, bubbles=[I.cosine_bubble(), I.cold_bubble()])
+    mesh = dict(w["mesh"], max_level=1, leaves=I.uniform_leaves(9, 9))
+    Tr, Tc = 0.0, -0.4
+    m = adg.Mesh(w["phys"], mesh)
+    m.init_state("bubbles", w["bubbles"])
+    for cycle in range(3):
+        cur = dict(mesh, leaves=leaves_of(m))
+        Q = m.Q.cpu().numpy().copy()
+        tv, fl, st = _tv(m, adg.ADG_VAR_THETA, Tr, Tc)
+        rtv, rfl, rst = O.tv(w["phys"], cur, Q, O.VAR_THETA, Tr, Tc)
+        near = np.abs(rtv - (rst[1] + Tr * rst[2])) <= 1e-9 * max(1.0, abs(rst[1]))
+        near |= np.abs(rtv - (rst[1] + Tc * rst[2])) <= 1e-9 * max(1.0, abs(rst[1]))
+        assert np.all((fl == rfl) | near), cycle
+        m.regrid(fl)
+        ref_leaves, ref_Q = O.regrid(w["phys"], cur, Q, fl)
+        assert leaves_of(m) == ref_leaves, cycle
+        assert np.all(relerr(m.Q.cpu().numpy(), ref_Q) <= 1e-13), cycle
+        if cycle == 0:
+            # initial refinement: the analytic state on the refined mesh
+            m.init_state("bubbles", w["bubbles"])
+            m.compute_dt()
+        cur = dict(mesh, leaves=ref_leaves)
+        for s in range(3):
+            Q0 = m.Q.cpu().numpy().copy()
+            t, dt = m.t, m.dt
+            m.step()
+            ref = O.step(w["phys"], cur, Q0, t, dt)
+            assert np.all(relerr(m.Q.cpu().numpy(), ref) <= 1e-11), (cycle, s)
+    assert m.C != 81
+
+
+def test_adaptive_workload_initial_refinement():
+    """27x27 coarse cells, N=6, thresholds of the adaptive workload: the
+    initial refinement from the analytic state gives 1953 leaves, the same
+    leaves as the oracle, and a step on them matches the oracle."""
+    w = I.amr27()
+    m = adg.Mesh(w["phys"], w["mesh"])
+    m.init_state("bubbles", w["bubbles"])
+    Q = m.Q.cpu().numpy().copy()
+    tv, fl, st = _tv(m, adg.ADG_VAR_THETA, w["T_refine"], w["T_coarsen"])
+    m.regrid(fl)
+    ref_leaves, _ = O.regrid(w["phys"], w["mesh"], Q, fl)
+    assert leaves_of(m) == ref_leaves
+    assert m.C == 1953
+    m.init_state("bubbles", w["bubbles"])
+    m.compute_dt()
+    Q0 = m.Q.cpu().numpy().copy()
+    t, dt = m.t, m.dt
+    m.step()
+    cur = dict(w["mesh"], leaves=ref_leaves)
+    ref = O.step(w["phys"], cur, Q0, t, dt)
+    assert np.all(relerr(m.Q.cpu().numpy(), ref) <= 1e-11)

@@ -115,3 +115,76 @@ def test_smooth_field_across_levels_matches_uniform_closely():
     idx = [j * 3 * nx + i for (l, i, j) in mesh["leaves"] if l == 1]
     d = np.max(np.abs((out[fam] - Q[fam]) - (ref[idx] - Qf[idx])))
     assert d <= 0.05 * np.max(np.abs(ref[idx] - Qf[idx]))
+
+
+# ------------------------------------------------------------------ regrid
+def poly_state(mesh, N, deg):
+    """Nodal values of a fixed polynomial field of total degree deg."""
+    b = O.basis(N)
+    out = []
+    for (l, i, j) in mesh["leaves"]:
+        h = mesh["Lx"] / mesh["nx"] / 3 ** l
+        X = i * h + h * b["xi"][None, :]
+        Z = j * h + h * b["xi"][:, None]
+        f = lambda k: sum((0.3 + 0.1 * a + 0.05 * k) * X ** a * Z ** (min(deg, 3) - a if a <= min(deg, 3) else 0)
+                          for a in range(deg + 1)) + 1.0
+        out.append(np.stack([f(0), f(1), f(2), 2.0 + f(3)]))
+    return np.array(out)
+
+
+def test_regrid_refine_is_exact_on_polynomials():
+    N = 3
+    mesh = dict(nx=3, nz=3, max_level=1, Lx=1.0, Lz=1.0, bc=[I.BC_PERIODIC] * 4, leaves=I.uniform_leaves(3, 3))
+    Q = poly_state(mesh, N, 3)
+    flags = np.zeros(9, dtype=np.int8)
+    flags[[1, 4]] = 1
+    leaves, Qn = O.regrid(cfd(N), mesh, Q, flags)
+    assert len(leaves) == 9 - 2 + 18
+    expect = poly_state(dict(mesh, leaves=leaves), N, 3)
+    assert np.max(np.abs(Qn - expect)) <= 1e-13
+
+
+def test_regrid_coarsen_is_l2_projection_and_conservative():
+    N = 2
+    leaves = I.refined_leaves(3, 3, [(1, 1), (0, 2)])
+    mesh = dict(nx=3, nz=3, max_level=1, Lx=1.0, Lz=1.0, bc=[I.BC_PERIODIC] * 4, leaves=leaves)
+    Q = I.random_state_cfd(len(leaves), N, seed=8)
+    flags = np.zeros(len(leaves), dtype=np.int8)
+    fam = [c for c, (l, i, j) in enumerate(leaves) if l == 1 and i // 3 == 1 and j // 3 == 1]
+    flags[fam] = -1
+    new, Qn = O.regrid(cfd(N), mesh, Q, flags)
+    assert len(new) == len(leaves) - 8
+    W0, W1 = weights(mesh, N), weights(dict(mesh, leaves=new), N)
+    assert np.allclose(np.einsum("cvji,cji->v", Q, W0), np.einsum("cvji,cji->v", Qn, W1), rtol=0, atol=1e-14)
+    # a polynomial state is reproduced exactly by the projection
+    P = poly_state(mesh, N, 2)
+    _, Pn = O.regrid(cfd(N), mesh, P, flags)
+    assert np.max(np.abs(Pn - poly_state(dict(mesh, leaves=new), N, 2))) <= 1e-13
+
+
+def test_regrid_refine_then_coarsen_is_identity():
+    N = 4
+    mesh = dict(nx=2, nz=2, max_level=1, Lx=1.0, Lz=1.0, bc=[I.BC_WALL] * 4, leaves=I.uniform_leaves(2, 2))
+    Q = I.random_state_cfd(4, N, seed=3)
+    l1, Q1 = O.regrid(cfd(N), mesh, Q, np.array([1, 0, 1, 0], dtype=np.int8))
+    f2 = np.array([-1 if l == 1 else 0 for (l, _, _) in l1], dtype=np.int8)
+    l2, Q2 = O.regrid(cfd(N), dict(mesh, leaves=l1), Q1, f2)
+    assert l2 == [(0, i, j) for j in range(2) for i in range(2)]
+    assert np.max(np.abs(Q2 - Q)) <= 1e-13 * np.max(np.abs(Q))
+
+
+def test_regrid_rules():
+    N = 1
+    leaves = I.refined_leaves(2, 2, [(0, 0)])
+    mesh = dict(nx=2, nz=2, max_level=1, Lx=1.0, Lz=1.0, bc=[I.BC_WALL] * 4, leaves=leaves)
+    Q = I.random_state_cfd(len(leaves), N, seed=1)
+    # 8 of 9 siblings flagged: nothing merges; refine at max level dropped;
+    # coarsen at level 0 dropped
+    f = np.array([-1 if l == 0 else (1 if (i, j) == (0, 0) else -1) for (l, i, j) in leaves], dtype=np.int8)
+    new, Qn = O.regrid(cfd(N), mesh, Q, f)
+    assert new == leaves
+    assert np.array_equal(Qn, Q)
+    # all nine flagged: merged at the position of the first child
+    f = np.array([0 if l == 0 else -1 for (l, i, j) in leaves], dtype=np.int8)
+    new, _ = O.regrid(cfd(N), mesh, Q, f)
+    assert new == [(0, 1, 0), (0, 0, 1), (0, 1, 1), (0, 0, 0)]
