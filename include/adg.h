@@ -199,6 +199,38 @@ int adg_set_launch(adg_mesh* m, int cells_per_wave, int waves_per_block);
  * unchanged), keep the fastest and return it.  Synchronises the stream. */
 int adg_autotune(adg_mesh* m, int reps, void* stream, int* cells_per_wave, int* waves_per_block);
 
+/* --------------------------------------------------------------- adjoint
+ * Hand-written reverse mode of one step with a frozen time step (clock[1];
+ * clock[0] is the step's start time), of the initial state built from a
+ * potential-temperature perturbation, and of the potential-temperature loss.
+ * Conforming meshes only (EUNSUPPORTED otherwise).  Non-smooth points: the
+ * Rusanov speed takes the subgradient of the first maximum over the face
+ * nodes in the order (lower side nodes 0..n-1, upper side nodes 0..n-1);
+ * d|x|/dx = 0 at x = 0. */
+
+/* Size of the adjoint workspace (Picard iterate store of one step, face
+ * adjoints, loss partials). */
+int adg_adjoint_workspace_bytes(const adg_mesh* m, size_t* bytes);
+
+/* lam_n = (dQ^{n+1}/dQ^n)^T lam_np1 for the step that starts from the
+ * checkpoint Q_n (device [C][4][n][n]).  Recomputes that step's predictor
+ * (overwrites the bound workspace); lam_n must not alias lam_np1. */
+int adg_step_adjoint(adg_mesh* m, const double* Q_n, const double* lam_np1, double* lam_n, void* adj_ws,
+                     void* stream);
+
+/* Bound Q <- initial state of the nodal perturbation theta_prime (device
+ * [C][n][n]): hydrostatic background of constant potential temperature,
+ * theta = theta_bg + theta' at fixed pressure, at rest (paper, Section 4.2).
+ * grad = (dQ/dtheta')^T lam (device [C][n][n]). */
+int adg_ic_theta(adg_mesh* m, const double* theta_prime, void* stream);
+int adg_ic_theta_adjoint(adg_mesh* m, const double* theta_prime, const double* lam, double* grad, void* stream);
+
+/* loss (device double[1]) = sqrt(sum_cells h^2 sum_ji w_i w_j (theta - theta_bg)^2)
+ * of the bound Q; the adjoint writes lam = grad_loss[0] * dloss/dQ (device
+ * [C][4][n][n]) given the loss value. */
+int adg_loss_theta(adg_mesh* m, double* loss, void* adj_ws, void* stream);
+int adg_loss_theta_adjoint(adg_mesh* m, const double* loss, const double* grad_loss, double* lam, void* stream);
+
 /* ---------------------------------------------------------------- batches
  * Many independent scenarios (own mesh, own order, own clock) stepped
  * together.  All scenarios share the physical parameters; orders may differ.

@@ -764,6 +764,48 @@ T cell_tv(const Params& P, const Basis& B, const Cell& c, const T* Qc, int var) 
   return c.h * tv;
 }
 
+// Initial state from a nodal potential-temperature perturbation theta' at
+// fixed background pressure (paper, Section 4.2): theta = theta_bg + theta',
+// T = theta * Exner, rho = p_bar/(R T), at rest, E = p_bar/(gamma-1) + rho g z.
+template <class T>
+void ic_theta(const Params& P, const Basis& B, const Mesh& M, const T* thp, T* Q) {
+  const int n = P.n, sl = 4 * n * n;
+  for (size_t c = 0; c < M.cells.size(); ++c) {
+    const Cell& cc = M.cells[c];
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        double z = cc.z0 + cc.h * B.xi[j];
+        double pi = 1.0 - P.g * z / (P.cp * P.theta_bg);
+        double pb = P.p0 * std::pow(pi, P.cp / P.R);
+        T th = P.theta_bg + thp[c * n * n + j * n + i];
+        T rho = pb / (P.R * (th * pi));
+        T* q = Q + c * sl;
+        q[(0 * n + j) * n + i] = rho;
+        q[(1 * n + j) * n + i] = T(0.0);
+        q[(2 * n + j) * n + i] = T(0.0);
+        q[(3 * n + j) * n + i] = pb / (P.gamma - 1.0) + rho * (P.g * z);
+      }
+  }
+}
+
+// L = sqrt(sum_cells h^2 sum_ji w_i w_j (theta - theta_bg)^2)
+template <class T>
+T loss_theta(const Params& P, const Basis& B, const Mesh& M, const T* Q) {
+  const int n = P.n, sl = 4 * n * n;
+  T acc = 0.0;
+  for (size_t c = 0; c < M.cells.size(); ++c) {
+    const Cell& cc = M.cells[c];
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        T q[4];
+        for (int v = 0; v < 4; ++v) q[v] = Q[c * sl + (v * n + j) * n + i];
+        T d = theta_of(P, q, cc.z0 + cc.h * B.xi[j]) - P.theta_bg;
+        acc += (cc.h * cc.h * B.w[i] * B.w[j]) * (d * d);
+      }
+  }
+  return sqrt(acc);
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -948,6 +990,48 @@ int oracle_ic(const double* prm, const int* mi, const double* md, const int* lev
         for (int v = 0; v < 4; ++v) Q[c * sl + (v * n + j) * n + i] = q[v];
       }
   }
+  return 0;
+}
+
+// Directional derivative of one step (frozen dt) by forward-mode dual
+// numbers: Qout = step(Q), dQout = step'(Q) dQ.
+int oracle_step_jvp(const double* prm, const int* mi, const double* md, const int* lev, const int* ci,
+                    const int* cj, const double* Q, const double* dQ, double t, double dt, double* Qout,
+                    double* dQout) {
+  Params P = read_params(prm);
+  Basis B = make_basis(P.N);
+  Mesh M = build_mesh(mi, md, lev, ci, cj);
+  if (!M.ok) return -1;
+  const size_t tot = M.cells.size() * 4 * P.n * P.n;
+  std::vector<Dual> Qd(tot), Od(tot);
+  for (size_t k = 0; k < tot; ++k) Qd[k] = Dual(Q[k], dQ[k]);
+  step<Dual>(P, B, M, Qd.data(), t, dt, Od.data(), nullptr, nullptr);
+  for (size_t k = 0; k < tot; ++k) { Qout[k] = Od[k].v; dQout[k] = Od[k].d; }
+  return 0;
+}
+
+// Loss after K steps (frozen dt) from the initial perturbation theta', and
+// its directional derivative along dtheta (forward-mode dual numbers).
+int oracle_rollout_jvp(const double* prm, const int* mi, const double* md, const int* lev, const int* ci,
+                       const int* cj, const double* thp, const double* dthp, double t0, double dt, int K,
+                       double* L, double* dL) {
+  Params P = read_params(prm);
+  Basis B = make_basis(P.N);
+  Mesh M = build_mesh(mi, md, lev, ci, cj);
+  if (!M.ok) return -1;
+  const size_t nodes = M.cells.size() * P.n * P.n, tot = 4 * nodes;
+  std::vector<Dual> th(nodes), Q(tot), Qn(tot);
+  for (size_t k = 0; k < nodes; ++k) th[k] = Dual(thp[k], dthp ? dthp[k] : 0.0);
+  ic_theta<Dual>(P, B, M, th.data(), Q.data());
+  double t = t0;
+  for (int s = 0; s < K; ++s) {
+    step<Dual>(P, B, M, Q.data(), t, dt, Qn.data(), nullptr, nullptr);
+    std::swap(Q, Qn);
+    t += dt;
+  }
+  Dual l = loss_theta<Dual>(P, B, M, Q.data());
+  *L = l.v;
+  *dL = l.d;
   return 0;
 }
 

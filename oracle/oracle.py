@@ -65,6 +65,9 @@ def lib():
         L.oracle_ic.argtypes = [dp] + mesh + [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, dp]
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_regrid.argtypes = [dp] + mesh + [dp, i8p, ip, ip, ip, dp, ip]
+        L.oracle_step_jvp.argtypes = [dp] + mesh + [dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.oracle_rollout_jvp.argtypes = [dp] + mesh + [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                                       dp, dp]
         _lib = L
     return _lib
 
@@ -232,3 +235,26 @@ def regrid(phys: dict, mesh: dict, Q: np.ndarray, flags) -> tuple:
                                _ip(nl), _ip(ni), _ip(nj), _dp(Qn), _ip(cn)), "regrid")
     C = int(cn[0])
     return [(int(nl[c]), int(ni[c]), int(nj[c])) for c in range(C)], Qn[:C].copy()
+
+
+def step_jvp(phys: dict, mesh: dict, Q: np.ndarray, dQ: np.ndarray, t: float, dt: float):
+    """(step(Q), d step(Q)[dQ]) with a frozen dt, by dual numbers."""
+    p, m = params(phys), _Mesh(mesh)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    dQ = np.ascontiguousarray(dQ, dtype=np.float64)
+    out, dout = np.zeros_like(Q), np.zeros_like(Q)
+    _check(lib().oracle_step_jvp(_dp(p), *m.args, _dp(Q), _dp(dQ), float(t), float(dt), _dp(out), _dp(dout)),
+           "step_jvp")
+    return out, dout
+
+
+def rollout_jvp(phys: dict, mesh: dict, theta_p: np.ndarray, dtheta=None, t0: float = 0.0, dt: float = 0.0,
+                K: int = 1):
+    """(L, dL): loss after K steps from theta' and its derivative along dtheta."""
+    p, m = params(phys), _Mesh(mesh)
+    th = np.ascontiguousarray(theta_p, dtype=np.float64)
+    d = np.ascontiguousarray(dtheta, dtype=np.float64) if dtheta is not None else np.zeros_like(th)
+    L, dL = np.zeros(1), np.zeros(1)
+    _check(lib().oracle_rollout_jvp(_dp(p), *m.args, _dp(th), _dp(d), float(t0), float(dt), int(K), _dp(L),
+                                    _dp(dL)), "rollout_jvp")
+    return float(L[0]), float(dL[0])

@@ -25,7 +25,8 @@ EXPORTED = [
     "adg_autotune", "adg_batch_create", "adg_batch_destroy", "adg_batch_info", "adg_batch_scenario",
     "adg_batch_set_state", "adg_batch_init_state", "adg_batch_compute_dt", "adg_batch_step",
     "adg_batch_step_graph", "adg_batch_autotune", "adg_batch_set_launch", "adg_get_leaves",
-    "adg_regrid_plan", "adg_regrid_apply",
+    "adg_regrid_plan", "adg_regrid_apply", "adg_adjoint_workspace_bytes", "adg_step_adjoint",
+    "adg_ic_theta", "adg_ic_theta_adjoint", "adg_loss_theta", "adg_loss_theta_adjoint",
 ]
 
 
@@ -99,6 +100,12 @@ def lib():
         L.adg_get_leaves.argtypes = [vp, i32p, i32p, i32p]
         L.adg_regrid_plan.argtypes = [vp, vp, ip, ctypes.POINTER(ctypes.c_size_t)]
         L.adg_regrid_apply.argtypes = [vp, vp, vp, vp, vp]
+        L.adg_adjoint_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.adg_step_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.adg_ic_theta.argtypes = [vp, vp, vp]
+        L.adg_ic_theta_adjoint.argtypes = [vp, vp, vp, vp, vp]
+        L.adg_loss_theta.argtypes = [vp, vp, vp, vp]
+        L.adg_loss_theta_adjoint.argtypes = [vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -249,6 +256,39 @@ class Mesh:
                                       ctypes.c_void_p(self.clock.data_ptr()), _stream_ptr(stream)))
         self.Q, self.ws, self.C, self.ws_bytes = Qn, wsn, nc.value, wb.value
         return self.C
+
+    # -- adjoint ---------------------------------------------------------------
+    def adjoint_workspace(self):
+        import torch
+        if getattr(self, "_adj_ws", None) is None:
+            b = ctypes.c_size_t()
+            _check(lib().adg_adjoint_workspace_bytes(self.h, ctypes.byref(b)))
+            self._adj_ws = torch.empty(max(b.value, 256), dtype=torch.uint8, device=self.device)
+        return self._adj_ws
+
+    def step_adjoint(self, Q_n, lam_np1, lam_n, stream=None):
+        ws = self.adjoint_workspace()
+        _check(lib().adg_step_adjoint(self.h, ctypes.c_void_p(Q_n.data_ptr()), ctypes.c_void_p(lam_np1.data_ptr()),
+                                      ctypes.c_void_p(lam_n.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                      _stream_ptr(stream)))
+
+    def ic_theta(self, theta_prime, stream=None):
+        _check(lib().adg_ic_theta(self.h, ctypes.c_void_p(theta_prime.data_ptr()), _stream_ptr(stream)))
+
+    def ic_theta_adjoint(self, theta_prime, lam, grad, stream=None):
+        _check(lib().adg_ic_theta_adjoint(self.h, ctypes.c_void_p(theta_prime.data_ptr()),
+                                          ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                                          _stream_ptr(stream)))
+
+    def loss_theta(self, out, stream=None):
+        ws = self.adjoint_workspace()
+        _check(lib().adg_loss_theta(self.h, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                    _stream_ptr(stream)))
+
+    def loss_theta_adjoint(self, loss, grad_loss, lam, stream=None):
+        _check(lib().adg_loss_theta_adjoint(self.h, ctypes.c_void_p(loss.data_ptr()),
+                                            ctypes.c_void_p(grad_loss.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
+                                            _stream_ptr(stream)))
 
     def set_launch(self, cells_per_wave: int, waves_per_block: int):
         _check(lib().adg_set_launch(self.h, int(cells_per_wave), int(waves_per_block)))

@@ -22,6 +22,12 @@ int launch_tv(const Group& g, const HostBasis& B, int var, double Tr, double Tc,
 int launch_health(const Group& g, int* flag, hipStream_t s);
 int launch_regrid(int n, int C, const int* ops, const double* Qold, double* Qnew, const double* gtab,
                   hipStream_t s);
+int launch_step_adjoint(const Group& g, const double* Qn, const double* lam_in, double* lam_out, double* store,
+                        double* lamG, double* lamFD, hipStream_t s);
+int launch_ic_theta(const Group& g, const double* thp, hipStream_t s);
+int launch_ic_theta_adj(const Group& g, const double* thp, const double* lam, double* grad, hipStream_t s);
+int launch_loss(const Group& g, double* part, double* out, hipStream_t s);
+int launch_loss_adj(const Group& g, const double* L, const double* gL, double* lam, hipStream_t s);
 int regrid_plan(const std::vector<int>& lev, const std::vector<int>& ci, const std::vector<int>& cj,
                 const int8_t* flags, int L, std::vector<int>& nlev, std::vector<int>& nci, std::vector<int>& ncj,
                 std::vector<int>& ops);
@@ -634,6 +640,81 @@ int adg_regrid_apply(adg_mesh* m, double* Q_new, void* workspace_new, double* cl
   m->plan_ready = false;
   layout_workspace(m);
   return adg_set_state(m, Q_new, workspace_new, clock);
+}
+
+// adjoint workspace: iterate store [C][I][n][4][n][n], face-flux adjoint
+// halves [C][4][4][n], face-data adjoints [C][4][2][4][n], loss partials [C]
+static void adj_layout(const adg_mesh* m, size_t* off_store, size_t* off_g, size_t* off_fd, size_t* off_part,
+                       size_t* total) {
+  const size_t C = (size_t)m->g.C, n = (size_t)m->g.n, I = (size_t)m->g.iters;
+  size_t off = 0;
+  *off_store = off; off = align256(off + sizeof(double) * C * I * n * 4 * n * n);
+  *off_g = off; off = align256(off + sizeof(double) * C * 16 * n);
+  *off_fd = off; off = align256(off + sizeof(double) * C * 32 * n);
+  *off_part = off; off = align256(off + sizeof(double) * C);
+  *total = off;
+}
+
+static int adjoint_supported(const adg_mesh* m) {
+  for (size_t k = 0; k < m->hm.nbr.size(); k += 4)
+    if (m->hm.nbr[k] == kFineSide || m->hm.nbr[k] == kCoarseSide)
+      return fail(ADG_EUNSUPPORTED, "the adjoint supports conforming meshes only");
+  return ADG_OK;
+}
+
+int adg_adjoint_workspace_bytes(const adg_mesh* m, size_t* bytes) {
+  if (!m || !bytes) return fail(ADG_EINVAL, "null argument");
+  size_t a, b, c, d;
+  adj_layout(m, &a, &b, &c, &d, bytes);
+  return ADG_OK;
+}
+
+int adg_step_adjoint(adg_mesh* m, const double* Q_n, const double* lam_np1, double* lam_n, void* adj_ws,
+                     void* stream) {
+  int rc = need_state(m);
+  if (!rc) rc = adjoint_supported(m);
+  if (rc) return rc;
+  if (!Q_n || !lam_np1 || !lam_n || !adj_ws) return fail(ADG_EINVAL, "null buffer");
+  if (lam_n == lam_np1) return fail(ADG_EINVAL, "lam_n must not alias lam_np1");
+  if (((uintptr_t)adj_ws & 255) != 0) return fail(ADG_EINVAL, "adjoint workspace must be 256-byte aligned");
+  size_t os, og, ofd, op, tot;
+  adj_layout(m, &os, &og, &ofd, &op, &tot);
+  char* w = static_cast<char*>(adj_ws);
+  return launch_step_adjoint(m->g, Q_n, lam_np1, lam_n, reinterpret_cast<double*>(w + os),
+                             reinterpret_cast<double*>(w + og), reinterpret_cast<double*>(w + ofd),
+                             (hipStream_t)stream);
+}
+
+int adg_ic_theta(adg_mesh* m, const double* theta_prime, void* stream) {
+  int rc = need_state(m);
+  if (rc) return rc;
+  if (!m->prm.gravity) return fail(ADG_EINVAL, "the theta' initial state needs gravity (background)");
+  if (!theta_prime) return fail(ADG_EINVAL, "null buffer");
+  return launch_ic_theta(m->g, theta_prime, (hipStream_t)stream);
+}
+
+int adg_ic_theta_adjoint(adg_mesh* m, const double* theta_prime, const double* lam, double* grad, void* stream) {
+  int rc = need_state(m);
+  if (rc) return rc;
+  if (!m->prm.gravity) return fail(ADG_EINVAL, "the theta' initial state needs gravity (background)");
+  if (!theta_prime || !lam || !grad) return fail(ADG_EINVAL, "null buffer");
+  return launch_ic_theta_adj(m->g, theta_prime, lam, grad, (hipStream_t)stream);
+}
+
+int adg_loss_theta(adg_mesh* m, double* loss, void* adj_ws, void* stream) {
+  int rc = need_state(m);
+  if (rc) return rc;
+  if (!loss || !adj_ws) return fail(ADG_EINVAL, "null buffer");
+  size_t os, og, ofd, op, tot;
+  adj_layout(m, &os, &og, &ofd, &op, &tot);
+  return launch_loss(m->g, reinterpret_cast<double*>(static_cast<char*>(adj_ws) + op), loss, (hipStream_t)stream);
+}
+
+int adg_loss_theta_adjoint(adg_mesh* m, const double* loss, const double* grad_loss, double* lam, void* stream) {
+  int rc = need_state(m);
+  if (rc) return rc;
+  if (!loss || !grad_loss || !lam) return fail(ADG_EINVAL, "null buffer");
+  return launch_loss_adj(m->g, loss, grad_loss, lam, (hipStream_t)stream);
 }
 
 int adg_set_launch(adg_mesh* m, int cells_per_wave, int waves_per_block) {

@@ -106,6 +106,7 @@ struct StepArgs {
   const double* geom;   // [C][4]
   const int* nbr;       // [C][4][4]
   const double* gtab;
+  double* iter_store;   // optional [C][iters][n][4][n][n]: Picard iterates q^1..q^I (adjoint)
   int C, iters;
 };
 
@@ -236,6 +237,13 @@ __global__ __launch_bounds__(kWave * WPB) void k_predictor(Phys ph, StepArgs a) 
       for (int b = 0; b < n; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v) sq[b * sl + v * nn + l] = fma(dt, acc[b][v], Qn[v]);
+      if (a.iter_store && valid) {
+        double* st = a.iter_store + ((size_t)c * a.iters + it) * n * sl;
+#pragma unroll
+        for (int b = 0; b < n; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) st[b * sl + v * nn + l] = sq[b * sl + v * nn + l];
+      }
     }
     wave_sync();
   }
@@ -590,6 +598,7 @@ StepArgs make_args(const Group& g) {
   a.Qin = g.Q; a.Qout = g.Q; a.Qs = g.Qs; a.FD = g.FD; a.dtc = g.dtc;
   a.clock = g.clock; a.scen = g.d_scen; a.geom = g.d_geom; a.nbr = g.d_nbr; a.gtab = g.d_gtab;
   a.C = g.C; a.iters = g.iters;
+  a.iter_store = nullptr;
   return a;
 }
 
@@ -669,6 +678,29 @@ static int dt_n(const Group& g, hipStream_t s) {
   }
 
 int launch_predictor(const Group& g, hipStream_t s) { ADG_DISPATCH_N(pred_n, g, s); }
+
+template <int n>
+static int pred_store_n(const Group& g, double* store, hipStream_t s) {
+  using L = Lay<n, 1>;
+  if (g.C == 0) return ADG_OK;
+  StepArgs a = make_args(g);
+  a.iter_store = store;
+  const size_t lds = sizeof(double) * (size_t)L::pred_cell;
+  hipLaunchKernelGGL((k_predictor<n, 1, 1>), dim3(g.C), dim3(kWave), lds, s, g.ph, a);
+  return check_launch("predictor(store)");
+}
+int launch_predictor_store(const Group& g, double* store, hipStream_t s) {
+  switch (g.n) {
+    case 2: return pred_store_n<2>(g, store, s);
+    case 3: return pred_store_n<3>(g, store, s);
+    case 4: return pred_store_n<4>(g, store, s);
+    case 5: return pred_store_n<5>(g, store, s);
+    case 6: return pred_store_n<6>(g, store, s);
+    case 7: return pred_store_n<7>(g, store, s);
+    case 8: return pred_store_n<8>(g, store, s);
+    default: return fail(ADG_EUNSUPPORTED, "order not supported");
+  }
+}
 int launch_corrector(const Group& g, hipStream_t s) { ADG_DISPATCH_N(corr_n, g, s); }
 int launch_cell_dt(const Group& g, hipStream_t s) { ADG_DISPATCH_N(dt_n, g, s); }
 
