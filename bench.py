@@ -28,6 +28,34 @@ if ROOT not in sys.path:
 FP64_PEAK_TFLOPS = 78.6     # 256 CU * 4 SIMD * 16 lanes * 2 flop * 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 TV_EVERY = 10
+KERNEL_SOURCES = ("paper_1905_05524_amd/csrc/step.hip", "paper_1905_05524_amd/csrc/adg_internal.h",
+                  "paper_1905_05524_amd/build.py")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bubble81_N6.json")
+
+
+def kernel_source_hash():
+    """Digest of the sources the step kernels are built from; counter data
+    taken on other sources no longer describe the kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary (already scaled by the copy calibration), or
+    None when the summary is missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash() or kernel not in d:
+        return None
+    return d[kernel]["traffic_bytes"]
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -119,6 +147,89 @@ def batched_leg(steps=20, warmup=3):
             "autotuned_cells_per_wave": cpw, "autotuned_waves_per_block": wpb}
 
 
+def amr_leg(steps=200):
+    """Adaptive workload: 27x27 coarse cells, one 3-way level, N=6, warm and
+    cold bubbles; initial refinement from the analytic state; TV indicator,
+    flags and regrid every 10 steps.  Timed end to end (including the
+    host-side regrid plan and the device-to-host flag copy)."""
+    import torch
+    from paper_1905_05524_amd import adg, model
+    from paper_1905_05524_amd import inputs as I
+    w = I.amr27()
+    N = w["phys"]["N"]
+    m = adg.Mesh(w["phys"], w["mesh"])
+    m.init_state("bubbles", w["bubbles"])
+
+    def indicator():
+        tv = torch.zeros(m.C, dtype=torch.float64, device="cuda")
+        fl = torch.zeros(m.C, dtype=torch.int8, device="cuda")
+        st = torch.zeros(3, dtype=torch.float64, device="cuda")
+        m.tv_indicator(adg.ADG_VAR_THETA, w["T_refine"], w["T_coarsen"], tv, fl, st)
+        return fl
+
+    m.regrid(indicator())
+    m.init_state("bubbles", w["bubbles"])
+    m.compute_dt()
+    c0 = m.C
+    torch.cuda.synchronize()
+    dof_updates, cells = 0, []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        m.step()
+        dof_updates += model.dofs(m.C, N)
+        if (k + 1) % w["regrid_every"] == 0 and k + 1 < steps:
+            m.regrid(indicator())
+            cells.append(m.C)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    m.check_health()
+    return {"workload": "amr27x27_L1_N6: 27x27 coarse cells of 37.04 m, one 3-way level, warm cosine + cold "
+                        "Gaussian bubble, regrid every 10 steps (TV of theta, T_refine 0, T_coarsen -0.4)",
+            "steps": steps, "initial_leaves": c0, "leaves_min": min(cells + [c0]), "leaves_max": max(cells + [c0]),
+            "leaves_final": m.C, "s_per_step_incl_regrid": t / steps, "dof_updates_per_s": dof_updates / t,
+            "sim_time_s": m.t}
+
+
+def adjoint_leg(steps=50):
+    """Forward + hand-written adjoint: 27x27 cells, N=6, 50 steps with a
+    checkpoint every step, gradient of the final theta' L2 norm with respect
+    to the initial nodal theta'."""
+    import numpy as np
+    import torch
+    from paper_1905_05524_amd import adg, model
+    from paper_1905_05524_amd import inputs as I
+    from paper_1905_05524_amd.autodiff import theta_rollout
+    w = I.bubble27()
+    N = w["phys"]["N"]
+    m = adg.Mesh(w["phys"], w["mesh"], fixed_dt=True)
+    m.init_state("bubbles", w["bubbles"])
+    m.compute_dt()
+    dt = m.dt
+    C, n = m.C, N + 1
+    th = torch.zeros((C, n, n), dtype=torch.float64, device="cuda")
+    th[:, :, :] = 0.1
+    th.requires_grad_(True)
+    # warm-up
+    L = theta_rollout(th, m, 2, dt)
+    L.backward()
+    torch.cuda.synchronize()
+    th.grad = None
+    t0 = time.perf_counter()
+    L = theta_rollout(th, m, steps, dt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fwd, bwd = (t1 - t0) / steps, (t2 - t1) / steps
+    aflops = model.adjoint_flops(N) * C
+    return {"workload": "bubble27x27_N6 forward + adjoint, 50 steps, frozen dt, checkpoint every step",
+            "cells": C, "steps": steps, "forward_ms_per_step": fwd * 1e3, "adjoint_ms_per_step": bwd * 1e3,
+            "fwd_plus_adj_ms_per_step": (fwd + bwd) * 1e3,
+            "adjoint_fp64_frac": aflops / bwd / 1e12 / FP64_PEAK_TFLOPS,
+            "grad_norm": float(th.grad.norm())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,7 +237,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 10 device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        nb = args.copy_calibration << 20
+        a = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nb, "copies": 10}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); "
               "the data-parallel path shards by domain decomposition, not measured here.", file=sys.stderr)
@@ -203,7 +326,9 @@ def main():
                                "no-slip walls, mu=1e-3, CFL 0.5; TV indicator every 10 steps",
                    "cells": C, "order": N, "dof": dof, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic(f"k_predictor<{N + 1}"),
+                     "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
                      "kernel": f"k_predictor<{N + 1}>", "kernel_ms": pred_ms,
                      "flops_per_launch": pflops},
         "extra": {"corrector_ms": corr_ms,
@@ -213,6 +338,8 @@ def main():
     }
     if not args.no_batch:
         out["extra"]["batched"] = batched_leg()
+        out["extra"]["adaptive"] = amr_leg()
+        out["extra"]["adjoint"] = adjoint_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -32,6 +32,24 @@ def predictor_flops(N: int, iters: int = 0) -> int:
     return I * sweep + final + epi
 
 
+VJP_FLOPS = 260   # reverse of the flux/source function (forward recomputation included)
+
+
+def adjoint_flops(N: int, iters: int = 0) -> int:
+    """Reverse of one step per cell: the predictor recomputed with its
+    iterates, then per time slice of every reverse sweep the residual
+    adjoint through D^T (16 n^3), the gradients recomputed (16 n^3), the
+    pointwise VJP, the gradient adjoints through D^T (16 n^3), and per sweep
+    the time matrix (8 n^3 per slice); the final pass likewise without the
+    residual part; the face and lifting adjoints are small."""
+    n = N + 1
+    I = iters or n
+    c = VJP_FLOPS
+    sweep = n * (48 * n ** 3 + (c + 12) * n ** 2) + 8 * n ** 4
+    final = n * (32 * n ** 3 + (c + 12) * n ** 2) + 16 * n ** 3
+    return predictor_flops(N, iters) + I * sweep + final + corrector_flops(N)
+
+
 def corrector_flops(N: int) -> int:
     n = N + 1
     return 4 * n * (2 * 2 * 14 + 16 + 4) + 4 * n * n * 8
