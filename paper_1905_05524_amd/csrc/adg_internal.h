@@ -33,7 +33,13 @@ struct Tab {
 //   xi[n], w[n], L0[n] = e0/w, L1[n] = e1/w, e0[n], e1[n],
 //   Pk[3][n][n]  sub-face k prolongation phi_m((k+xi_q)/3) at [k][q][m],
 //   Rk[3][n][n]  restriction (w_q/3) phi_m((k+xi_q)/3)/w_m at [k][m][q],
-//   D[n][n], Pt[n][n] (time matrix transposed: Pt[b][a] = P[a][b]), Dw[n][n].
+//   D[n][n], Pt[n][n] (time matrix transposed: Pt[b][a] = P[a][b]), Dw[n][n],
+//   even-odd forms of D and Dw (see EvenOdd below),
+//   LU[n*n+n]: the time matrix K1 = L U (unit lower L, no pivoting: for
+//   Gauss-Legendre nodes the factors stay bounded, |U_ii| >= 1 up to n = 8)
+//   stored in the order the in-place solve of K1 y = W r reads it: for each
+//   row i, w_i then L[i][0..i-1]; then for each row i from n-1 down to 0,
+//   1/U_ii then U[i][i+1..n-1]/U_ii.
 struct GTab {
   static constexpr int XI = 0, W = 1, L0 = 2, L1 = 3, E0 = 4, E1 = 5;
   static __host__ __device__ inline int pk(int n) { return 6 * n; }
@@ -41,8 +47,22 @@ struct GTab {
   static __host__ __device__ inline int d(int n) { return 6 * n + 6 * n * n; }
   static __host__ __device__ inline int pt(int n) { return 6 * n + 7 * n * n; }
   static __host__ __device__ inline int dw(int n) { return 6 * n + 8 * n * n; }
-  static __host__ __device__ inline int size(int n) { return 6 * n + 9 * n * n; }
+  static __host__ __device__ inline int eo_size(int n) { return 2 * (n / 2) * (n / 2) + 2 * (n / 2); }
+  static __host__ __device__ inline int eo_d(int n) { return 6 * n + 9 * n * n; }
+  static __host__ __device__ inline int eo_dw(int n) { return 6 * n + 9 * n * n + eo_size(n); }
+  static __host__ __device__ inline int lu(int n) { return 6 * n + 9 * n * n + 2 * eo_size(n); }
+  static __host__ __device__ inline int size(int n) { return 7 * n + 10 * n * n + 2 * eo_size(n); }
 };
+
+// Even-odd form of an n x n matrix T with T[n-1-i][n-1-m] = -T[i][m] (the
+// Gauss-Legendre derivative matrix and the volume matrix are centro-
+// antisymmetric), h = n/2, mid = (n-1)/2 for odd n:
+//   A[i][m] = (T[i][m] - T[i][n-1-m]) / 2,  B[i][m] = (T[i][m] + T[i][n-1-m]) / 2
+//   (i, m < h), C[i] = T[i][mid], M[m] = T[mid][m] (odd n only).
+// With e_m = x_m + x_{n-1-m}, o_m = x_m - x_{n-1-m}: S_i = sum_m A[i][m] o_m,
+// T_i = sum_m B[i][m] e_m + C[i] x_mid, (T x)_i = S_i + T_i,
+// (T x)_{n-1-i} = S_i - T_i, (T x)_mid = sum_m M[m] o_m.  Stored as
+// A[h][h], B[h][h], C[h], M[h].
 
 struct Phys {
   double gamma, gm1, R, iR, cp, Pr, mu, kappa, g, p0, theta;
@@ -50,6 +70,7 @@ struct Phys {
   double lv_coef;                         // lambda_v = lv_coef / rho
   double mms_amp, mms_u, mms_w, mms_kx, mms_kz, mms_p;
   double cfl;
+  double geff;                            // g with gravity on, 0 otherwise
   int gravity, mms, fixed_dt, N;
 };
 
@@ -125,7 +146,7 @@ __device__ inline void background(const Phys& ph, double z, double& rb, double& 
 }
 
 __device__ inline double pressure(const Phys& ph, double rho, double mx, double mz, double E, double z) {
-  double geo = ph.gravity ? rho * (ph.g * z) : 0.0;
+  const double geo = rho * (ph.geff * z);   // 0 without gravity
   return ph.gm1 * (E - 0.5 * (mx * mx + mz * mz) / rho - geo);
 }
 
@@ -155,16 +176,17 @@ __device__ inline void flux_source(const Phys& ph, const double q[4], const doub
   const double rho = q[0], mx = q[1], mz = q[2], E = q[3];
   const double ir = 1.0 / rho;
   const double u = mx * ir, w = mz * ir;
-  const double gzz = ph.gravity ? ph.g * z : 0.0;
+  // branch-free in the gravity switch: geff = 0 and rb = pb = 0 without it
+  const double gzz = ph.geff * z;
   const double p = ph.gm1 * (E - 0.5 * (mx * u + mz * w) - rho * gzz);
-  const double pm = ph.gravity ? p - pb : p;
+  const double pm = p - pb;
   const double T = p * ir * ph.iR;
   const double dux = (gx[1] - u * gx[0]) * ir, duz = (gz[1] - u * gz[0]) * ir;
   const double dwx = (gx[2] - w * gx[0]) * ir, dwz = (gz[2] - w * gz[0]) * ir;
   const double hv2 = 0.5 * (u * u + w * w) + gzz;
   double dpx = ph.gm1 * (gx[3] - hv2 * gx[0] - rho * (u * dux + w * dwx));
   double dpz = ph.gm1 * (gz[3] - hv2 * gz[0] - rho * (u * duz + w * dwz));
-  if (ph.gravity) dpz -= ph.gm1 * rho * ph.g;
+  dpz -= ph.gm1 * rho * ph.geff;
   const double dTx = (dpx - ph.R * T * gx[0]) * ir * ph.iR;
   const double dTz = (dpz - ph.R * T * gz[0]) * ir * ph.iR;
   const double div = dux + dwz;
@@ -180,7 +202,7 @@ __device__ inline void flux_source(const Phys& ph, const double q[4], const doub
   Fz[1] = mx * w + sxz;
   Fz[2] = mz * w + pm + szz;
   Fz[3] = w * H + u * sxz + w * szz - ph.kappa * dTz;
-  Sw = ph.gravity ? -ph.g * (rho - rb) : 0.0;
+  Sw = -ph.geff * (rho - rb);
 }
 
 // max over the 64 lanes of a wavefront (butterfly, fixed order)

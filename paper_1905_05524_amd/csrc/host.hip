@@ -165,6 +165,50 @@ static void build_basis(int n, HostBasis& B) {
       B.gtab[GTab::pt(n) + j * n + i] = B.P[i * n + j];
       B.gtab[GTab::dw(n) + i * n + j] = B.Dw[i * n + j];
     }
+  // unpivoted LU of K1 for the in-place time solve (layout with GTab::lu)
+  {
+    std::vector<long double> Lm(n * n, 0.0L), Um(n * n, 0.0L);
+    for (int k = 0; k < n; ++k) {
+      for (int c = k; c < n; ++c) {
+        long double acc = e1[k] * e1[c] - w[c] * D[c * n + k];
+        for (int j = 0; j < k; ++j) acc -= Lm[k * n + j] * Um[j * n + c];
+        Um[k * n + c] = acc;
+      }
+      for (int r = k + 1; r < n; ++r) {
+        long double acc = e1[r] * e1[k] - w[k] * D[k * n + r];
+        for (int j = 0; j < k; ++j) acc -= Lm[r * n + j] * Um[j * n + k];
+        Lm[r * n + k] = acc / Um[k * n + k];
+      }
+    }
+    double* t = B.gtab.data() + GTab::lu(n);
+    int o = 0;
+    for (int i = 0; i < n; ++i) {
+      t[o++] = (double)w[i];
+      for (int j = 0; j < i; ++j) t[o++] = (double)Lm[i * n + j];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      t[o++] = (double)(1.0L / Um[i * n + i]);
+      for (int j = i + 1; j < n; ++j) t[o++] = (double)(Um[i * n + j] / Um[i * n + i]);
+    }
+  }
+  // even-odd forms of D and Dw
+  const int hh = n / 2, mid = (n - 1) / 2;
+  for (int which = 0; which < 2; ++which) {
+    auto T = [&](int i, int j) -> long double {
+      return which == 0 ? D[i * n + j] : w[j] * D[j * n + i] / w[i];
+    };
+    double* e = B.gtab.data() + (which == 0 ? GTab::eo_d(n) : GTab::eo_dw(n));
+    for (int i = 0; i < hh; ++i) {
+      for (int m = 0; m < hh; ++m) {
+        e[i * hh + m] = (double)((T(i, m) - T(i, n - 1 - m)) / 2.0L);
+        e[hh * hh + i * hh + m] = (double)((T(i, m) + T(i, n - 1 - m)) / 2.0L);
+      }
+      if (n % 2) {
+        e[2 * hh * hh + i] = (double)T(i, mid);
+        e[2 * hh * hh + hh + i] = (double)T(mid, i);
+      }
+    }
+  }
   for (int s = 0; s < 3; ++s)
     for (int q = 0; q < n; ++q)
       for (int mm = 0; mm < n; ++mm) {
@@ -304,7 +348,7 @@ static Phys make_phys(const adg_params& p) {
   ph.lv_coef = std::max(4.0 * p.mu / 3.0, p.gamma * p.mu / p.Pr);
   ph.mms_amp = p.mms_amp; ph.mms_u = p.mms_u; ph.mms_w = p.mms_w;
   ph.mms_kx = p.mms_kx; ph.mms_kz = p.mms_kz; ph.mms_p = p.mms_p;
-  ph.cfl = p.cfl; ph.gravity = p.gravity ? 1 : 0; ph.mms = p.mms ? 1 : 0; ph.fixed_dt = p.fixed_dt ? 1 : 0;
+  ph.cfl = p.cfl; ph.geff = p.gravity ? p.g : 0.0; ph.gravity = p.gravity ? 1 : 0; ph.mms = p.mms ? 1 : 0; ph.fixed_dt = p.fixed_dt ? 1 : 0;
   ph.N = p.order;
   return ph;
 }

@@ -25,20 +25,31 @@ __device__ inline void wave_sync() {
 template <int n>
 struct Half { static constexpr int nh = (n + 1) / 2; };
 
+// Predictor LDS layout per cell.  Each time slice is kept twice: as
+// [4 vars][z][x] and transposed as [4 vars][x][z], so that every line job
+// (one lane per direction, variable and line: x lines in the first layout, z
+// lines in the second) reads and writes n consecutive values.  Gradients,
+// fluxes and divergences follow the same pairing: the x parts in the first
+// layout, the z parts in the transposed one.  With 64-bit accesses served in
+// four passes of 16 lanes over 32 four-byte banks, lines that start n
+// doubles apart are conflict-free for odd n in the job order used here.
 template <int n, int CPW>
 struct Lay {
   static constexpr int nn = n * n, sl = 4 * nn;
+  static constexpr int T = sl;                             // transposed copy of a region
+  static constexpr int F0 = 2 * sl;                        // gradients / fluxes region
+  static constexpr int pred_cell = 6 * sl + (n > 5 ? n : 5) * nn;   // predictor LDS doubles per cell
   static constexpr int jobs = 8 * n * CPW;                 // line jobs per wavefront
   static constexpr int rounds = (jobs + kWave - 1) / kWave;
-  static constexpr int pred_cell = (n + 4) * sl;           // predictor LDS doubles per cell
   static constexpr int corr_cell = 16 * n + 24 * n + 48 * n;  // sG, sL/sV, sGs
 };
 
-// Line job of one lane in one round: direction, base offset and stride in a
-// [4][n][n] slice, cell slot.
+// Line job of one lane in one round: direction, variable, line, cell slot and
+// the offset of its first value within a region (x lines in the first
+// layout, z lines in the transposed one; unit stride in both).
 template <int n>
 struct LineJob {
-  int dir, base, stride, slot, v, line;
+  int dir, base, slot, v, line;
   bool active;
   __device__ LineJob(int job, int cpw) {
     constexpr int nn = n * n;
@@ -48,51 +59,62 @@ struct LineJob {
     dir = jj / (4 * n);
     v = (jj % (4 * n)) / n;
     line = jj % n;
-    base = v * nn + (dir == 0 ? line * n : line);
-    stride = dir == 0 ? 1 : n;
+    base = (dir ? 4 * nn : 0) + v * nn + line * n;
   }
 };
 
-// Half tables: for Gauss-Legendre nodes (symmetric about 1/2) the derivative
-// matrix is centro-antisymmetric, D[n-1-i][n-1-m] = -D[i][m], and so is the
-// volume matrix Dw.  Only the first nh = ceil(n/2) rows are kept; row n-1-i is
-// applied as minus row i on the reversed input line.
+// Even-odd tables of a centro-antisymmetric n x n matrix in VGPRs (layout
+// and formulas with GTab).  The empty asm marks every value as lane-varying
+// so the compiler keeps the tables in vector registers.
 template <int n>
-__device__ inline void line_apply(const double (&M)[Half<n>::nh][n], int base, int stride, const double* src,
-                                  double* dst) {
-  constexpr int nh = Half<n>::nh;
-  double in[n];
+struct EOTab {
+  static constexpr int h = n / 2;
+  double A[h][h], B[h][h], C[h], M[h];
+};
+template <int n>
+__device__ inline void load_eo(const double* g, EOTab<n>& T) {
+  constexpr int h = n / 2;
 #pragma unroll
-  for (int m = 0; m < n; ++m) in[m] = src[base + m * stride];
+  for (int i = 0; i < h; ++i) {
 #pragma unroll
-  for (int i = 0; i < nh; ++i) {
-    double s = 0.0;
-#pragma unroll
-    for (int m = 0; m < n; ++m) s = fma(M[i][m], in[m], s);
-    dst[base + i * stride] = s;
-  }
-#pragma unroll
-  for (int i = 0; i < n / 2; ++i) {
-    double s = 0.0;
-#pragma unroll
-    for (int m = 0; m < n; ++m) s = fma(M[i][m], in[n - 1 - m], s);
-    dst[base + (n - 1 - i) * stride] = -s;
+    for (int m = 0; m < h; ++m) {
+      T.A[i][m] = g[i * h + m];
+      T.B[i][m] = g[h * h + i * h + m];
+      asm volatile("" : "+v"(T.A[i][m]), "+v"(T.B[i][m]));
+    }
+    if constexpr (n % 2) {   // the short middle column and row may live in scalar registers
+      T.C[i] = g[2 * h * h + i];
+      T.M[i] = g[2 * h * h + h + i];
+    }
   }
 }
 
-// Load the first nh rows of an n x n table into VGPRs.  The empty asm marks
-// every value as lane-varying, so the compiler keeps the table in vector
-// registers instead of scalar registers (which cannot hold it and would
-// spill into lanes).
+// dst line = T * src line (n consecutive values at base); src may equal dst.
 template <int n>
-__device__ inline void load_vtab(const double* g, double (&M)[Half<n>::nh][n]) {
+__device__ inline void line_eo(const EOTab<n>& T, int base, const double* src, double* dst) {
+  constexpr int stride = 1;
+  constexpr int h = n / 2, mid = (n - 1) / 2;
+  double in[n];
 #pragma unroll
-  for (int i = 0; i < Half<n>::nh; ++i)
+  for (int m = 0; m < n; ++m) in[m] = src[base + m * stride];
+  double e[h], o[h];
 #pragma unroll
-    for (int m = 0; m < n; ++m) {
-      M[i][m] = g[i * n + m];
-      asm volatile("" : "+v"(M[i][m]));
-    }
+  for (int m = 0; m < h; ++m) { e[m] = in[m] + in[n - 1 - m]; o[m] = in[m] - in[n - 1 - m]; }
+#pragma unroll
+  for (int i = 0; i < h; ++i) {
+    double S = T.A[i][0] * o[0], U = T.B[i][0] * e[0];
+#pragma unroll
+    for (int m = 1; m < h; ++m) { S = fma(T.A[i][m], o[m], S); U = fma(T.B[i][m], e[m], U); }
+    if constexpr (n % 2) U = fma(T.C[i], in[mid], U);
+    dst[base + i * stride] = S + U;
+    dst[base + (n - 1 - i) * stride] = S - U;
+  }
+  if constexpr (n % 2) {
+    double S = T.M[0] * o[0];
+#pragma unroll
+    for (int m = 1; m < h; ++m) S = fma(T.M[m], o[m], S);
+    dst[base + mid * stride] = S;
+  }
 }
 
 struct StepArgs {
@@ -111,35 +133,42 @@ struct StepArgs {
 };
 
 // ------------------------------------------------------------------ predictor
-// flux and source of one time node at this lane's node: q from the iterate
-// slice qb, gradients from sg; fluxes to sf
+// Flux and source of one time node at this lane's node: state q (registers),
+// gradients from the gradient region (x parts at node offset l of the first
+// layout, z parts at offset tl of the transposed one); the fluxes overwrite
+// the gradients in place (each lane reads and writes only its own node)
+// unless store is false.
 template <int n>
-__device__ inline double node_flux(const Phys& ph, const double* qb, const double* sg, double* sf, int l,
-                                   double ih, double z, double rb, double pb, double q[4], double Fx[4],
-                                   double Fz[4]) {
-  constexpr int nn = n * n, sl = 4 * nn;
+__device__ inline double node_flux(const Phys& ph, const double q[4], double* sf, int l, int tl, double ih,
+                                   double z, double rb, double pb, double Fx[4], double Fz[4], bool store) {
+  constexpr int nn = n * n, T = 4 * nn;
   double gx[4], gz[4], Sw;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    q[v] = qb[v * nn + l];
-    gx[v] = sg[v * nn + l] * ih;
-    gz[v] = sg[sl + v * nn + l] * ih;
+    gx[v] = sf[v * nn + l] * ih;
+    gz[v] = sf[T + v * nn + tl] * ih;
   }
   flux_source(ph, q, gx, gz, z, rb, pb, Fx, Fz, Sw);
+  if (store) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v) { sf[v * nn + l] = Fx[v]; sf[sl + v * nn + l] = Fz[v]; }
+    for (int v = 0; v < 4; ++v) { sf[v * nn + l] = Fx[v]; sf[T + v * nn + tl] = Fz[v]; }
+  }
   return Sw;
 }
 
-// Per cell: the Picard iterate of all n time nodes lives in LDS
-// (sq[b][v][j][i]); each sweep walks the time nodes b in a runtime loop:
-// gradients by line jobs, flux and source per node, divergence by line jobs
-// (in place), and the rank-1 update acc[a] += P[a][b] R(b) held per node in
-// registers.  Then time averages, the volume term and the face data.
+// Per cell: lane l < n*n owns spatial node l = (j, i) and holds, in
+// registers, the Picard iterate at all n time nodes, X[b][v] (the time-node
+// loop is unrolled so the array is statically indexed).  Per sweep and time
+// node b: the slice X[b] goes to LDS (both layouts), gradients by line jobs,
+// flux and source per node (fluxes over the gradients), divergence by line
+// jobs in place, and the residual R(b) replaces X[b] (the old iterate at b is
+// no longer needed).  At the end of the sweep the time solve
+// X[a] = Q^n + dt sum_b P[a][b] R(b) runs per node in registers.  Then time
+// averages, the volume term and the face data.
 template <int n, int CPW, int WPB>
 __global__ __launch_bounds__(kWave * WPB) void k_predictor(Phys ph, StepArgs a) {
   using L = Lay<n, CPW>;
-  constexpr int nn = L::nn, sl = L::sl;
+  constexpr int nn = L::nn, sl = L::sl, T = L::T, F0 = L::F0;
   extern __shared__ double lds[];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   double* wl = lds + (size_t)wave * CPW * L::pred_cell;
@@ -151,159 +180,221 @@ __global__ __launch_bounds__(kWave * WPB) void k_predictor(Phys ph, StepArgs a) 
   const int c = cell0 + (node ? slot : 0);
   const bool valid = node && c < a.C;
   const int cc = valid ? c : 0;
-  double* sq = wl + (node ? slot : 0) * L::pred_cell;
-  double* sg = sq + n * sl;
-  double* sf = sg + 2 * sl;
   const int jz = l / n, ix = l % n;
+  const int tl = ix * n + jz;                           // node offset in the transposed layout
+  double* sq = wl + (node ? slot : 0) * L::pred_cell;   // slice, both layouts
+  double* sf = sq + F0;                                 // gradients / fluxes, both layouts
+  double* sm = sq + F0 + 4 * sl;                        // [n][n*n] manufactured source (if any)
   const double* gt = a.gtab;
 
   const int s = a.scen ? a.scen[cc] : 0;
   const double t0 = a.clock[4 * s + 0], dt = a.clock[4 * s + 1];
   const double x0 = a.geom[4 * cc + 0], z0 = a.geom[4 * cc + 1], h = a.geom[4 * cc + 2];
   const double ih = 1.0 / h;
-  const double x = x0 + h * gt[GTab::XI * n + ix];
   const double z = z0 + h * gt[GTab::XI * n + jz];
   double rb, pb;
   background(ph, z, rb, pb);
 
-  double Dv[Half<n>::nh][n];
-  load_vtab<n>(gt + GTab::d(n), Dv);
+  EOTab<n> Dt;
+  load_eo<n>(gt + GTab::eo_d(n), Dt);
 
-  double Qn[4];
-  {
-    const double* Qc = a.Qin + (size_t)cc * sl;
+  // Q^n of this node (lanes past the last cell read cell 0 and store nothing);
+  // it is re-read from memory where needed rather than held in registers
+  const double* Qc = a.Qin + (size_t)cc * sl + l;
+  double X[n][4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Qn[v] = valid ? Qc[v * nn + l] : (v == 0 || v == 3 ? 1.0 : 0.0);
+  for (int v = 0; v < 4; ++v) {
+    const double q = Qc[v * nn];
+#pragma unroll
+    for (int b = 0; b < n; ++b) X[b][v] = q;
   }
-  if (node) {
-#pragma unroll
-    for (int b = 0; b < n; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) sq[b * sl + v * nn + l] = Qn[v];
+
+  // manufactured energy source at the n time nodes (it does not depend on
+  // the state), evaluated once
+  if (ph.mms && node) {
+    const double x = x0 + h * gt[GTab::XI * n + ix];
+#pragma unroll 1
+    for (int b = 0; b < n; ++b) sm[b * nn + l] = mms_source(ph, x, z, t0 + gt[GTab::XI * n + b] * dt);
   }
-  wave_sync();
 
   // line-job roles (rounds of 64 jobs)
   const LineJob<n> J0(lane, CPW), J1(lane + kWave, CPW);
   double* jl0 = wl + (J0.active ? J0.slot : 0) * L::pred_cell;
   double* jl1 = wl + (J1.active ? J1.slot : 0) * L::pred_cell;
-  // src/dst are offsets in a cell's region; direction d adds d * (dir stride)
-  auto lines = [&](int src_off, int dst_off, int src_dir_stride, int dst_dir_stride) {
-    if (J0.active)
-      line_apply<n>(Dv, J0.base, J0.stride, jl0 + src_off + J0.dir * src_dir_stride,
-                    jl0 + dst_off + J0.dir * dst_dir_stride);
-    if (L::rounds > 1 && J1.active)
-      line_apply<n>(Dv, J1.base, J1.stride, jl1 + src_off + J1.dir * src_dir_stride,
-                    jl1 + dst_off + J1.dir * dst_dir_stride);
+  // line jobs from region src_off to region dst_off of the cell
+  auto lines = [&](int src_off, int dst_off) {
+    if (J0.active) line_eo<n>(Dt, J0.base, jl0 + src_off, jl0 + dst_off);
+    if (L::rounds > 1 && J1.active) line_eo<n>(Dt, J1.base, jl1 + src_off, jl1 + dst_off);
   };
-  constexpr int OFF_G = n * sl, OFF_F = (n + 2) * sl;
+  auto put_slice = [&](const double q[4]) {
+    if (node) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { sq[v * nn + l] = q[v]; sq[T + v * nn + tl] = q[v]; }
+    }
+  };
 
-  for (int it = 0; it < a.iters; ++it) {
-    double acc[n][4];
-#pragma unroll
-    for (int b = 0; b < n; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[b][v] = 0.0;
 #pragma unroll 1
+  for (int it = 0; it < a.iters; ++it) {
+#pragma unroll
     for (int b = 0; b < n; ++b) {
-      lines(b * sl, OFF_G, 0, sl);           // gradients of time node b
+      put_slice(X[b]);
+      wave_sync();
+      lines(0, F0);                          // gradients of time node b
       wave_sync();
       double Sw = 0.0;
       if (node) {
-        double q[4], Fx[4], Fz[4];
-        Sw = node_flux<n>(ph, sq + b * sl, sg, sf, l, ih, z, rb, pb, q, Fx, Fz);
+        double Fx[4], Fz[4];
+        Sw = node_flux<n>(ph, X[b], sf, l, tl, ih, z, rb, pb, Fx, Fz, true);
       }
       wave_sync();
-      lines(OFF_F, OFF_F, sl, sl);           // divergence parts, in place
+      lines(F0, F0);                         // divergence parts, in place
       wave_sync();
       if (node) {
-        double R[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) R[v] = -(sf[v * nn + l] + sf[sl + v * nn + l]) * ih;
-        R[2] += Sw;
-        if (ph.mms) R[3] += mms_source(ph, x, z, t0 + gt[GTab::XI * n + b] * dt);
-        const double* pc = gt + GTab::pt(n) + b * n;
+        for (int v = 0; v < 4; ++v) X[b][v] = -(sf[v * nn + l] + sf[T + v * nn + tl]) * ih;
+        X[b][2] += Sw;
+        if (ph.mms) X[b][3] += sm[b * nn + l];
+      }
+    }
+    // time solve per node, in place: X[a] = Q^n + dt (K1^{-1} W R)[a] by
+    // forward and back substitution with the unpivoted LU factors of K1
+    // (equal to applying P = K1^{-1} W).  The table is read in order through
+    // scalar loads; each entry serves the four variables.
+    {
+      const double* lu0 = gt + GTab::lu(n);
+      asm volatile("" : "+s"(lu0));
+      typedef const __attribute__((address_space(4))) double* cptr;
+      cptr t = (cptr)lu0;
+      int o = 0;
 #pragma unroll
-        for (int a2 = 0; a2 < n; ++a2) {
-          const double p = pc[a2];
+      for (int i = 0; i < n; ++i) {             // z_i = w_i R_i - sum_{j<i} L_ij z_j
+        const double wi = t[o++];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[a2][v] = fma(p, R[v], acc[a2][v]);
+        for (int v = 0; v < 4; ++v) X[i][v] *= wi;
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+          const double Lij = t[o++];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) X[i][v] = fma(-Lij, X[j][v], X[i][v]);
         }
       }
-      wave_sync();
+#pragma unroll
+      for (int i = n - 1; i >= 0; --i) {       // y_i = z_i / U_ii - sum_{j>i} (U_ij / U_ii) y_j
+        const double iu = t[o++];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[i][v] *= iu;
+#pragma unroll
+        for (int j = i + 1; j < n; ++j) {
+          const double Uij = t[o++];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) X[i][v] = fma(-Uij, X[j][v], X[i][v]);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double qn = Qc[v * nn];
+#pragma unroll
+        for (int i = 0; i < n; ++i) X[i][v] = fma(dt, X[i][v], qn);
+      }
     }
-    if (node) {
+    if (a.iter_store && valid) {
+      double* st = a.iter_store + ((size_t)c * a.iters + it) * n * sl;
 #pragma unroll
       for (int b = 0; b < n; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) sq[b * sl + v * nn + l] = fma(dt, acc[b][v], Qn[v]);
-      if (a.iter_store && valid) {
-        double* st = a.iter_store + ((size_t)c * a.iters + it) * n * sl;
-#pragma unroll
-        for (int b = 0; b < n; ++b)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) st[b * sl + v * nn + l] = sq[b * sl + v * nn + l];
-      }
+        for (int v = 0; v < 4; ++v) st[b * sl + v * nn + l] = X[b][v];
     }
-    wave_sync();
   }
 
-  // time averages of q, F and S on the last iterate
-  double Qb[4] = {0, 0, 0, 0}, Fbx[4] = {0, 0, 0, 0}, Fbz[4] = {0, 0, 0, 0}, Sbw = 0.0, SbE = 0.0;
-#pragma unroll 1
+  // time averages on the last iterate.  The averaged state and the averaged
+  // manufactured source do not need the fluxes: they go to the (now unused)
+  // source region first, so that only the flux averages are carried in
+  // registers through the final pass.
+  if (node) {
+    double SbE = 0.0;
+    if (ph.mms) {
+#pragma unroll
+      for (int b = 0; b < n; ++b) SbE = fma(gt[GTab::W * n + b], sm[b * nn + l], SbE);
+    }
+    double Qb[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int b = 0; b < n; ++b) {
+      const double wb = gt[GTab::W * n + b];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Qb[v] = fma(wb, X[b][v], Qb[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sm[v * nn + l] = Qb[v];
+    sm[4 * nn + l] = SbE;
+  }
+  // flux averages accumulate in LDS (own node only), in the layouts the
+  // line jobs of the volume term read: x fluxes in the first, z fluxes in
+  // the transposed one
+  double* sa = sq + F0 + 2 * sl;
+  double Sbw = 0.0;
+#pragma unroll
   for (int b = 0; b < n; ++b) {
-    lines(b * sl, OFF_G, 0, sl);
+    put_slice(X[b]);
+    wave_sync();
+    lines(0, F0);
     wave_sync();
     if (node) {
-      double q[4], Fx[4], Fz[4];
-      const double Sw = node_flux<n>(ph, sq + b * sl, sg, sf, l, ih, z, rb, pb, q, Fx, Fz);
+      double Fx[4], Fz[4];
+      const double Sw = node_flux<n>(ph, X[b], sf, l, tl, ih, z, rb, pb, Fx, Fz, false);
       const double wb = gt[GTab::W * n + b];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        Qb[v] = fma(wb, q[v], Qb[v]);
-        Fbx[v] = fma(wb, Fx[v], Fbx[v]);
-        Fbz[v] = fma(wb, Fz[v], Fbz[v]);
+        if (b == 0) {
+          sa[v * nn + l] = wb * Fx[v];
+          sa[T + v * nn + tl] = wb * Fz[v];
+        } else {
+          sa[v * nn + l] = fma(wb, Fx[v], sa[v * nn + l]);
+          sa[T + v * nn + tl] = fma(wb, Fz[v], sa[T + v * nn + tl]);
+        }
       }
       Sbw = fma(wb, Sw, Sbw);
-      if (ph.mms) SbE = fma(wb, mms_source(ph, x, z, t0 + gt[GTab::XI * n + b] * dt), SbE);
-    }
-    wave_sync();
-  }
-
-  // volume term and face data: averaged state to slot 0, averaged fluxes to sf
-  if (node) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      sq[v * nn + l] = Qb[v];
-      sf[v * nn + l] = Fbx[v];
-      sf[sl + v * nn + l] = Fbz[v];
     }
   }
   wave_sync();
+
+  // face data and volume term: averaged state to the slice region, averaged
+  // fluxes to the flux region; each line job extrapolates its line to both
+  // faces, then replaces the flux line by its volume contraction (in place:
+  // lines are disjoint).
+  double SbE = 0.0;
+  if (node) {
+    double Qb[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Qb[v] = sm[v * nn + l];
+    SbE = sm[4 * nn + l];
+    put_slice(Qb);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { sf[v * nn + l] = sa[v * nn + l]; sf[T + v * nn + tl] = sa[T + v * nn + tl]; }
+  }
+  wave_sync();
   {
-    double Wv[Half<n>::nh][n];
-    load_vtab<n>(gt + GTab::dw(n), Wv);
+    EOTab<n> Wt;
+    load_eo<n>(gt + GTab::eo_dw(n), Wt);
 #pragma unroll
     for (int r = 0; r < L::rounds; ++r) {
       const LineJob<n>& J = r == 0 ? J0 : J1;
       double* jl = r == 0 ? jl0 : jl1;
       if (!J.active) continue;
       const int cj = cell0 + J.slot;
-      const double* src = jl + OFF_F + J.dir * sl;
-      line_apply<n>(Wv, J.base, J.stride, src, jl + OFF_G + J.dir * sl);
-      if (cj >= a.C) continue;
       double q0 = 0, q1 = 0, f0 = 0, f1 = 0;
 #pragma unroll
       for (int m = 0; m < n; ++m) {
         const double e0 = gt[GTab::E0 * n + m], e1 = gt[GTab::E1 * n + m];
-        const double iq = jl[J.base + m * J.stride], iF = src[J.base + m * J.stride];
+        const double iq = jl[J.base + m], iF = jl[F0 + J.base + m];
         q0 = fma(e0, iq, q0); q1 = fma(e1, iq, q1);
         f0 = fma(e0, iF, f0); f1 = fma(e1, iF, f1);
       }
+      line_eo<n>(Wt, J.base, jl + F0, jl + F0);
+      if (cj >= a.C) continue;
       double* fd = a.FD + (size_t)cj * 32 * n;
-      const int fl = 2 * J.dir, fu = 2 * J.dir + 1;
-      fd[((fl * 2 + 0) * 4 + J.v) * n + J.line] = q0;
-      fd[((fl * 2 + 1) * 4 + J.v) * n + J.line] = f0;
+      const int fl0 = 2 * J.dir, fu = 2 * J.dir + 1;
+      fd[((fl0 * 2 + 0) * 4 + J.v) * n + J.line] = q0;
+      fd[((fl0 * 2 + 1) * 4 + J.v) * n + J.line] = f0;
       fd[((fu * 2 + 0) * 4 + J.v) * n + J.line] = q1;
       fd[((fu * 2 + 1) * 4 + J.v) * n + J.line] = f1;
     }
@@ -314,7 +405,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_predictor(Phys ph, StepArgs a) 
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const double S = (v == 2) ? Sbw : (v == 3 ? SbE : 0.0);
-      qs[v * nn + l] = Qn[v] + dt * ((sg[v * nn + l] + sg[sl + v * nn + l]) * ih + S);
+      qs[v * nn + l] = Qc[v * nn] + dt * ((sf[v * nn + l] + sf[T + v * nn + tl]) * ih + S);
     }
   }
 }
