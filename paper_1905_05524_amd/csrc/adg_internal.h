@@ -166,17 +166,33 @@ __device__ inline double mms_source(const Phys& ph, double x, double z, double t
   return -ph.kappa * lapT;
 }
 
+// Reciprocal of a positive normal double: the hardware estimate refined by
+// two Newton steps r <- r + r (1 - x r) (quadratic convergence; the result
+// is within an ulp or so of 1/x, not necessarily correctly rounded).
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Flux (hyperbolic + viscous) in x and z and the gravity source of the
 // vertical momentum at one node (eqs. equation-set, eos, temperature,
-// stress-tensor, heat-conduction-coeff, momentum-equation-split).  q: conserved state; gx, gz: its physical gradients;
-// rb, pb: background density and pressure at the node height z.
+// stress-tensor, heat-conduction-coeff, momentum-equation-split).
+// q: conserved state; gx, gz: its gradients in reference coordinates, i.e.
+// h times the physical ones.  Every gradient enters the flux linearly through
+// the stress and the heat flux, so the 1/h is carried by mu_h = mu / h and
+// kappa_h = kappa / h, and the hydrostatic term of the vertical pressure
+// gradient by gh = g h (0 without gravity).  rb, pb: background density and
+// pressure at the node height z.
 __device__ inline void flux_source(const Phys& ph, const double q[4], const double gx[4],
-                                   const double gz[4], double z, double rb, double pb,
-                                   double Fx[4], double Fz[4], double& Sw) {
+                                   const double gz[4], double z, double rb, double pb, double mu_h,
+                                   double kappa_h, double gh, double Fx[4], double Fz[4], double& Sw) {
   const double rho = q[0], mx = q[1], mz = q[2], E = q[3];
-  const double ir = 1.0 / rho;
+  const double ir = recip(rho);
   const double u = mx * ir, w = mz * ir;
-  // branch-free in the gravity switch: geff = 0 and rb = pb = 0 without it
+  // branch-free in the gravity switch: geff = gh = 0 and rb = pb = 0 without it
   const double gzz = ph.geff * z;
   const double p = ph.gm1 * (E - 0.5 * (mx * u + mz * w) - rho * gzz);
   const double pm = p - pb;
@@ -184,24 +200,23 @@ __device__ inline void flux_source(const Phys& ph, const double q[4], const doub
   const double dux = (gx[1] - u * gx[0]) * ir, duz = (gz[1] - u * gz[0]) * ir;
   const double dwx = (gx[2] - w * gx[0]) * ir, dwz = (gz[2] - w * gz[0]) * ir;
   const double hv2 = 0.5 * (u * u + w * w) + gzz;
-  double dpx = ph.gm1 * (gx[3] - hv2 * gx[0] - rho * (u * dux + w * dwx));
-  double dpz = ph.gm1 * (gz[3] - hv2 * gz[0] - rho * (u * duz + w * dwz));
-  dpz -= ph.gm1 * rho * ph.geff;
+  const double dpx = ph.gm1 * (gx[3] - hv2 * gx[0] - rho * (u * dux + w * dwx));
+  const double dpz = ph.gm1 * (gz[3] - hv2 * gz[0] - rho * (u * duz + w * dwz) - rho * gh);
   const double dTx = (dpx - ph.R * T * gx[0]) * ir * ph.iR;
   const double dTz = (dpz - ph.R * T * gz[0]) * ir * ph.iR;
   const double div = dux + dwz;
-  const double sxx = ph.mu * ((2.0 / 3.0) * div - 2.0 * dux);
-  const double szz = ph.mu * ((2.0 / 3.0) * div - 2.0 * dwz);
-  const double sxz = -ph.mu * (duz + dwx);
+  const double sxx = mu_h * ((2.0 / 3.0) * div - 2.0 * dux);
+  const double szz = mu_h * ((2.0 / 3.0) * div - 2.0 * dwz);
+  const double sxz = -mu_h * (duz + dwx);
   const double H = E + p;
   Fx[0] = mx;
   Fx[1] = mx * u + pm + sxx;
   Fx[2] = mz * u + sxz;
-  Fx[3] = u * H + u * sxx + w * sxz - ph.kappa * dTx;
+  Fx[3] = u * H + u * sxx + w * sxz - kappa_h * dTx;
   Fz[0] = mz;
   Fz[1] = mx * w + sxz;
   Fz[2] = mz * w + pm + szz;
-  Fz[3] = w * H + u * sxz + w * szz - ph.kappa * dTz;
+  Fz[3] = w * H + u * sxz + w * szz - kappa_h * dTz;
   Sw = -ph.geff * (rho - rb);
 }
 

@@ -117,6 +117,14 @@ __device__ inline void line_eo(const EOTab<n>& T, int base, const double* src, d
   }
 }
 
+// A wave-uniform double moved to scalar registers.
+__device__ inline double uniform(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 struct StepArgs {
   const double* Qin;    // [C][4][n][n]
   double* Qout;         // corrector output (may alias Qin)
@@ -134,21 +142,22 @@ struct StepArgs {
 
 // ------------------------------------------------------------------ predictor
 // Flux and source of one time node at this lane's node: state q (registers),
-// gradients from the gradient region (x parts at node offset l of the first
+// reference-coordinate gradients from the gradient region (x parts at node offset l of the first
 // layout, z parts at offset tl of the transposed one); the fluxes overwrite
 // the gradients in place (each lane reads and writes only its own node)
 // unless store is false.
 template <int n>
-__device__ inline double node_flux(const Phys& ph, const double q[4], double* sf, int l, int tl, double ih,
-                                   double z, double rb, double pb, double Fx[4], double Fz[4], bool store) {
+__device__ inline double node_flux(const Phys& ph, const double q[4], double* sf, int l, int tl, double mu_h,
+                                   double kappa_h, double gh, double z, double rb, double pb, double Fx[4],
+                                   double Fz[4], bool store) {
   constexpr int nn = n * n, T = 4 * nn;
   double gx[4], gz[4], Sw;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    gx[v] = sf[v * nn + l] * ih;
-    gz[v] = sf[T + v * nn + tl] * ih;
+    gx[v] = sf[v * nn + l];
+    gz[v] = sf[T + v * nn + tl];
   }
-  flux_source(ph, q, gx, gz, z, rb, pb, Fx, Fz, Sw);
+  flux_source(ph, q, gx, gz, z, rb, pb, mu_h, kappa_h, gh, Fx, Fz, Sw);
   if (store) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) { sf[v * nn + l] = Fx[v]; sf[T + v * nn + tl] = Fz[v]; }
@@ -187,10 +196,14 @@ __global__ __launch_bounds__(kWave * WPB) void k_predictor(Phys ph, StepArgs a) 
   double* sm = sq + F0 + 4 * sl;                        // [n][n*n] manufactured source (if any)
   const double* gt = a.gtab;
 
-  const int s = a.scen ? a.scen[cc] : 0;
+  // cell-level values: with one cell per wavefront they are read through a
+  // wave-uniform index (scalar registers)
+  const int cu = (CPW == 1) ? (cell0 < a.C ? cell0 : a.C - 1) : cc;
+  const int s = a.scen ? a.scen[cu] : 0;
   const double t0 = a.clock[4 * s + 0], dt = a.clock[4 * s + 1];
-  const double x0 = a.geom[4 * cc + 0], z0 = a.geom[4 * cc + 1], h = a.geom[4 * cc + 2];
-  const double ih = 1.0 / h;
+  const double x0 = a.geom[4 * cu + 0], z0 = a.geom[4 * cu + 1], h = a.geom[4 * cu + 2];
+  double ih = 1.0 / h, mu_h = ph.mu * ih, kappa_h = ph.kappa * ih, gh = ph.geff * h;
+  if constexpr (CPW == 1) { ih = uniform(ih); mu_h = uniform(mu_h); kappa_h = uniform(kappa_h); gh = uniform(gh); }
   const double z = z0 + h * gt[GTab::XI * n + jz];
   double rb, pb;
   background(ph, z, rb, pb);
@@ -244,16 +257,16 @@ __global__ __launch_bounds__(kWave * WPB) void k_predictor(Phys ph, StepArgs a) 
       double Sw = 0.0;
       if (node) {
         double Fx[4], Fz[4];
-        Sw = node_flux<n>(ph, X[b], sf, l, tl, ih, z, rb, pb, Fx, Fz, true);
+        Sw = node_flux<n>(ph, X[b], sf, l, tl, mu_h, kappa_h, gh, z, rb, pb, Fx, Fz, true);
       }
       wave_sync();
       lines(F0, F0);                         // divergence parts, in place
       wave_sync();
-      if (node) {
+      if (node) {   // scaled residual R' = div F - h S, with R = -R' / h
 #pragma unroll
-        for (int v = 0; v < 4; ++v) X[b][v] = -(sf[v * nn + l] + sf[T + v * nn + tl]) * ih;
-        X[b][2] += Sw;
-        if (ph.mms) X[b][3] += sm[b * nn + l];
+        for (int v = 0; v < 4; ++v) X[b][v] = sf[v * nn + l] + sf[T + v * nn + tl];
+        X[b][2] = fma(-h, Sw, X[b][2]);
+        if (ph.mms) X[b][3] = fma(-h, sm[b * nn + l], X[b][3]);
       }
     }
     // time solve per node, in place: X[a] = Q^n + dt (K1^{-1} W R)[a] by
@@ -290,11 +303,12 @@ __global__ __launch_bounds__(kWave * WPB) void k_predictor(Phys ph, StepArgs a) 
           for (int v = 0; v < 4; ++v) X[i][v] = fma(-Uij, X[j][v], X[i][v]);
         }
       }
+      const double sdt = (CPW == 1) ? uniform(-dt * ih) : -dt * ih;   // R = -R' / h
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const double qn = Qc[v * nn];
 #pragma unroll
-        for (int i = 0; i < n; ++i) X[i][v] = fma(dt, X[i][v], qn);
+        for (int i = 0; i < n; ++i) X[i][v] = fma(sdt, X[i][v], qn);
       }
     }
     if (a.iter_store && valid) {
@@ -340,7 +354,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_predictor(Phys ph, StepArgs a) 
     wave_sync();
     if (node) {
       double Fx[4], Fz[4];
-      const double Sw = node_flux<n>(ph, X[b], sf, l, tl, ih, z, rb, pb, Fx, Fz, false);
+      const double Sw = node_flux<n>(ph, X[b], sf, l, tl, mu_h, kappa_h, gh, z, rb, pb, Fx, Fz, false);
       const double wb = gt[GTab::W * n + b];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
