@@ -94,6 +94,7 @@ struct Group {
   double* clock = nullptr;    // [S][4]
   // launch shape: cells per wavefront, wavefronts per workgroup
   int cpw = 1, wpb = 1;
+  int nc = 0;                 // the mesh has 1:3 non-conforming faces
 };
 
 // Host copies of the basis of one order.

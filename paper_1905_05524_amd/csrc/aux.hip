@@ -109,27 +109,48 @@ __device__ inline void chan_merge(double& na, double& ma, double& qa, double nb,
   na = nt;
 }
 
+__device__ inline void chan_shfl(double& na, double& ma, double& qa, int o) {
+  const double nb = __shfl_xor(na, o, kWave), mb = __shfl_xor(ma, o, kWave), qb = __shfl_xor(qa, o, kWave);
+  // both partners merge (lower lane's partial first) so they hold the same result
+  const bool low = (threadIdx.x & o) == 0;
+  double n1 = low ? na : nb, m1 = low ? ma : mb, q1 = low ? qa : qb;
+  chan_merge(n1, m1, q1, low ? nb : na, low ? mb : ma, low ? qb : qa);
+  na = n1; ma = m1; qa = q1;
+}
+
+// One workgroup: each thread folds the cells t, t + 1024, ... in one at a
+// time (Welford's update, the Chan merge of a single value: exact for equal
+// values, so a constant field keeps sigma = 0); partials are merged by Chan's
+// formulas in a fixed butterfly within each wavefront, then across the 16
+// wavefronts in order.
 __global__ __launch_bounds__(kStatThreads) void k_stats_flags(const double* tv, int C, double Tr, double Tc,
                                                                  int8_t* flags, double* stats) {
-  __shared__ double sn[kStatThreads], sm[kStatThreads], sq[kStatThreads];
+  constexpr int nw = kStatThreads / kWave;
+  __shared__ double sn[nw], sm[nw], sq[nw], sres[2];
   const int t = threadIdx.x;
-  const int chunk = (C + kStatThreads - 1) / kStatThreads;
-  const int lo = t * chunk, hi = min(C, lo + chunk);
   double na = 0.0, ma = 0.0, qa = 0.0;
-  for (int c = lo; c < hi; ++c) chan_merge(na, ma, qa, 1.0, tv[c], 0.0);
-  sn[t] = na; sm[t] = ma; sq[t] = qa;
-  __syncthreads();
-  for (int w = 1; w < kStatThreads; w *= 2) {
-    if ((t % (2 * w)) == 0 && t + w < kStatThreads) {
-      double a = sn[t], b = sm[t], q = sq[t];
-      chan_merge(a, b, q, sn[t + w], sm[t + w], sq[t + w]);
-      sn[t] = a; sm[t] = b; sq[t] = q;
-    }
-    __syncthreads();
+  for (int c = t; c < C; c += kStatThreads) {
+    const double x = tv[c];
+    const double nt = na + 1.0;
+    const double d = x - ma;
+    const double r = 1.0 / nt;
+    ma = fma(d, r, ma);
+    qa = fma(d * d, na * r, qa);
+    na = nt;
   }
-  const double cnt = sn[0], mean = sm[0];
-  const double sigma = cnt > 0.0 ? sqrt(sq[0] / cnt) : 0.0;
-  if (t == 0) { stats[0] = cnt; stats[1] = mean; stats[2] = sigma; }
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) chan_shfl(na, ma, qa, o);
+  if ((t & (kWave - 1)) == 0) { sn[t / kWave] = na; sm[t / kWave] = ma; sq[t / kWave] = qa; }
+  __syncthreads();
+  if (t == 0) {
+    double cn = sn[0], cm = sm[0], cq = sq[0];
+    for (int w = 1; w < nw; ++w) chan_merge(cn, cm, cq, sn[w], sm[w], sq[w]);
+    const double sigma = cn > 0.0 ? sqrt(cq / cn) : 0.0;
+    stats[0] = cn; stats[1] = cm; stats[2] = sigma;
+    sres[0] = cm; sres[1] = sigma;
+  }
+  __syncthreads();
+  const double mean = sres[0], sigma = sres[1];
   const double thr_r = mean + Tr * sigma, thr_c = mean + Tc * sigma;
   for (int c = t; c < C; c += kStatThreads) {
     int8_t f = 0;

@@ -365,6 +365,9 @@ static void free_group(Group& g) {
 static int upload_group(Group& g, const std::vector<double>& geom, const std::vector<int>& nbr,
                         const std::vector<double>& gtab, const std::vector<int>* scen) {
   const size_t C = (size_t)g.C;
+  g.nc = 0;
+  for (size_t k = 0; k < 4 * C; ++k)
+    if (nbr[4 * k] == kFineSide || nbr[4 * k] == kCoarseSide) { g.nc = 1; break; }
   hipError_t e = hipSuccess;
   if (C) {
     e = hipMalloc(&g.d_geom, sizeof(double) * 4 * C);

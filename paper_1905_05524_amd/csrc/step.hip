@@ -492,7 +492,7 @@ __device__ inline void rusanov_flux(double s, const double QL[4], const double F
 // 1:3 face: the coarse neighbour's face polynomial at this sub-face; coarse
 // side: the three sub-face fluxes restricted by L2 projection.  Both sides of
 // a face evaluate the identical expressions, so the fluxes agree bitwise.
-template <int n, int CPW, int WPB>
+template <int n, int CPW, int WPB, bool NC>
 __global__ __launch_bounds__(kWave * WPB) void k_corrector(Phys ph, StepArgs a) {
   using L = Lay<n, CPW>;
   constexpr int nn = L::nn, sl = L::sl;
@@ -523,18 +523,18 @@ __global__ __launch_bounds__(kWave * WPB) void k_corrector(Phys ph, StepArgs a) 
     const int* nb = a.nbr + (size_t)fc * 16 + f * 4;
     kind = nb[0]; nb1 = nb[1]; nb2 = nb[2]; nb3 = nb[3];
     hf = a.geom[4 * fc + 2]; z0f = a.geom[4 * fc + 1];
-    if (kind != kCoarseSide) {
+    if (!NC || kind != kCoarseSide) {
       const double zf = (d == 0) ? z0f + hf * gt[GTab::XI * n + k] : z0f + ((f & 1) ? hf : 0.0);
       load_face<n>(a.FD, fc, f, k, Qm, Fm);
       if (kind == kConforming) load_face<n>(a.FD, nb1, f ^ 1, k, Qo, Fo);
-      else if (kind == kFineSide) prolong_face<n>(a.FD, gt, nb1, f ^ 1, nb2, k, Qo, Fo);
+      else if (NC && kind == kFineSide) prolong_face<n>(a.FD, gt, nb1, f ^ 1, nb2, k, Qo, Fo);
       else wall_ghost(ph, d, zf, Qm, Fm, Qo, Fo);
       double l1, v1, l2, v2;
       eig(ph, d, Qm, zf, l1, v1);
       eig(ph, d, Qo, zf, l2, v2);
       sL[(f * 3) * n + k] = fmax(l1, l2);
       sV[(f * 3) * n + k] = fmax(v1, v2);
-    } else {
+    } else if constexpr (NC) {
       for (int s = 0; s < 3; ++s) {
         const int fine = s == 0 ? nb1 : (s == 1 ? nb2 : nb3);
         const double zf = (d == 0) ? z0f + hf * (s + gt[GTab::XI * n + k]) / 3.0 : z0f + ((f & 1) ? hf : 0.0);
@@ -551,7 +551,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_corrector(Phys ph, StepArgs a) 
   }
   wave_sync();
   if (fl) {
-    if (kind != kCoarseSide) {
+    if (!NC || kind != kCoarseSide) {
       double lam = sL[(f * 3) * n], lv = sV[(f * 3) * n];
 #pragma unroll
       for (int m = 1; m < n; ++m) { lam = fmax(lam, sL[(f * 3) * n + m]); lv = fmax(lv, sV[(f * 3) * n + m]); }
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_corrector(Phys ph, StepArgs a) 
       else rusanov_flux(s, Qm, Fm, Qo, Fo, G);
 #pragma unroll
       for (int v = 0; v < 4; ++v) sG[(f * 4 + v) * n + k] = G[v];
-    } else {
+    } else if constexpr (NC) {
       const double hfine = hf / 3.0;
       for (int s = 0; s < 3; ++s) {
         const int fine = s == 0 ? nb1 : (s == 1 ? nb2 : nb3);
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_corrector(Phys ph, StepArgs a) 
     }
   }
   wave_sync();
-  if (fl && kind == kCoarseSide) {
+  if (NC && fl && kind == kCoarseSide) {
     // L2 restriction to the coarse face node m = k
     const double* Rk = gt + GTab::rk(n);
     double G[4] = {0.0, 0.0, 0.0, 0.0};
@@ -631,12 +631,19 @@ __global__ __launch_bounds__(kWave * WPB) void k_corrector(Phys ph, StepArgs a) 
   if (!ph.fixed_dt) {
     // maxima of lambda and lambda_v over the nodes of each cell slot (a
     // contiguous lane range), then the CFL rule on the cell maxima
-    slam[wave][0][lane] = lam_n;
-    slam[wave][1][lane] = lv_n;
-    wave_sync();
+    double lm, vm;
+    if constexpr (CPW == 1) {
+      lm = wave_max(lam_n);   // lanes without a node hold 0
+      vm = wave_max(lv_n);
+    } else {
+      slam[wave][0][lane] = lam_n;
+      slam[wave][1][lane] = lv_n;
+      wave_sync();
+      lm = lam_n; vm = lv_n;
+      if (valid && l == 0)
+        for (int j = 1; j < nn; ++j) { lm = fmax(lm, slam[wave][0][lane + j]); vm = fmax(vm, slam[wave][1][lane + j]); }
+    }
     if (valid && l == 0) {
-      double lm = lam_n, vm = lv_n;
-      for (int j = 1; j < nn; ++j) { lm = fmax(lm, slam[wave][0][lane + j]); vm = fmax(vm, slam[wave][1][lane + j]); }
       const double h = a.geom[4 * c + 2];
       const double o = 2.0 * ph.N + 1.0;
       a.dtc[c] = ph.cfl * h / (2.0 * o * (lm + 2.0 * vm * o / h));
@@ -676,15 +683,23 @@ __global__ __launch_bounds__(kWave) void k_cell_dt(Phys ph, StepArgs a) {
 // Clock update, one workgroup per scenario: if advance, t += dt and
 // steps += 1; if update, dt <- min of the CFL candidates of the scenario's
 // cells [beg[s], end[s]) (min is exact, so the result is order independent).
-constexpr int kReduceThreads = 256;
+constexpr int kReduceThreads = 1024;
 __global__ __launch_bounds__(kReduceThreads) void k_clock(double* clock, const double* dtc, const int* beg,
                                                            const int* end, int C, int advance, int update) {
   __shared__ double sm[kReduceThreads / kWave];
   const int s = blockIdx.x, t = threadIdx.x;
   const int b0 = beg ? beg[s] : 0, b1 = end ? end[s] : C;
   double m = __builtin_inf();
-  if (update)
-    for (int c = b0 + t; c < b1; c += kReduceThreads) m = fmin(m, dtc[c]);
+  if (update) {
+    // four independent loads in flight per thread
+    int c = b0 + t;
+    for (; c + 3 * kReduceThreads < b1; c += 4 * kReduceThreads) {
+      const double a0 = dtc[c], a1 = dtc[c + kReduceThreads], a2 = dtc[c + 2 * kReduceThreads],
+                   a3 = dtc[c + 3 * kReduceThreads];
+      m = fmin(m, fmin(fmin(a0, a1), fmin(a2, a3)));
+    }
+    for (; c < b1; c += kReduceThreads) m = fmin(m, dtc[c]);
+  }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) m = fmin(m, __shfl_xor(m, o, kWave));
   if ((t & (kWave - 1)) == 0) sm[t / kWave] = m;
@@ -724,7 +739,13 @@ static int launch_corr_t(const Group& g, hipStream_t s) {
   const int per_block = CPW * WPB;
   const int blocks = (g.C + per_block - 1) / per_block;
   if (blocks == 0) return ADG_OK;
-  hipLaunchKernelGGL((k_corrector<n, CPW, WPB>), dim3(blocks), dim3(kWave * WPB), lds, s, g.ph, make_args(g));
+  // meshes without 1:3 faces take the variant without their code paths
+  if (g.nc)
+    hipLaunchKernelGGL((k_corrector<n, CPW, WPB, true>), dim3(blocks), dim3(kWave * WPB), lds, s, g.ph,
+                       make_args(g));
+  else
+    hipLaunchKernelGGL((k_corrector<n, CPW, WPB, false>), dim3(blocks), dim3(kWave * WPB), lds, s, g.ph,
+                       make_args(g));
   return check_launch("corrector");
 }
 
