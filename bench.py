@@ -138,7 +138,7 @@ def batched_leg(steps=20, warmup=3):
     dof = sum(model.dofs(w["mesh"]["nx"] * w["mesh"]["nz"], w["phys"]["N"]) for w in ws)
     flops = sum(model.step_flops(w["phys"]["N"]) * w["mesh"]["nx"] * w["mesh"]["nz"] for w in ws)
     return {"workload": "batch64: 64 cosine-bubble scenarios from seed 190505524, k x k grids k in 9..81, "
-                        "N in 3..6, walls, mu=1e-3, CFL 0.5 each with its own clock",
+                        "N in 3..6, walls, mu=1e-3, Courant factor 0.4, each with its own clock",
             "cells": sum(w["mesh"]["nx"] * w["mesh"]["nz"] for w in ws), "dof": dof, "steps": steps,
             "batched_graph_s_per_step": t_batch / steps, "sequential_s_per_step": t_seq / steps,
             "speedup_batched_vs_sequential": t_seq / t_batch,
@@ -323,7 +323,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "bubble81x81_N6: cosine warm bubble, 81x81 cells of 12.35 m, N=6, "
-                               "no-slip walls, mu=1e-3, CFL 0.5; TV indicator every 10 steps",
+                               "no-slip walls, mu=1e-3, Courant factor 0.4; TV indicator every 10 steps",
                    "cells": C, "order": N, "dof": dof, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS,

@@ -11,7 +11,7 @@ Workloads follow the paper's scenarios (Krenz, Rannabauer, Bader 2019):
                     its manufactured heat-flux source (CFD constants gamma=1.4,
                     Pr=0.7, c_v=1 of the convergence section)
   * ``bubble81``    2D cosine warm bubble (stratified-flow section) on 81x81
-                    cells of 12.35 m, N=6, no-slip walls
+                    cells of 12.35 m, N=6, no-slip walls, Courant factor 0.4
   * ``amr27``       the same box on 27x27 coarse cells with one 3-way
                     refinement level and a second, cold Gaussian bubble
   * ``bubble27``    81x81's box on 27x27 cells (adjoint workload)
@@ -49,8 +49,16 @@ def cold_bubble(A=-0.15, a=0.0, s=50.0, xc=560.0, zc=640.0):
     return (SHAPE_PLATEAU_GAUSS, A, a, s, xc, zc)
 
 
+# Courant factor of the bubble workloads.  With the time-step rule
+# dt = cfl h / (2 (2N+1) (lambda + 2 lambda_v (2N+1) / h)), the order-6 scheme
+# is unstable at cfl = 0.5 (the 81x81 bubble blows up after about 200 steps,
+# 27x27 after about 150) and stable at 0.45 and below over thousands of
+# steps; 0.4 keeps a margin.
+BUBBLE_CFL = 0.4
+
+
 def bubble(nx: int = 81, N: int = 6, mu: float = 1e-3, bubbles=None, steps: int = 100):
-    phys = dict(ATMO, N=N, picard_iters=0, mu=mu, mms=0, cfl=0.5)
+    phys = dict(ATMO, N=N, picard_iters=0, mu=mu, mms=0, cfl=BUBBLE_CFL)
     mesh = dict(nx=nx, nz=nx, max_level=0, x0=0.0, z0=0.0, Lx=1000.0, Lz=1000.0,
                 bc=[BC_WALL] * 4)
     bl = [cosine_bubble()] if bubbles is None else list(bubbles)

@@ -313,3 +313,22 @@ def test_step_is_deterministic():
         for _ in range(3):
             m.step()
     assert torch.equal(a.Q, b.Q) and torch.equal(a.clock, b.clock)
+
+
+def test_bubble81_long_run_stays_bounded():
+    """1000 steps of the 81x81, N=6 bubble at the workloads' Courant factor
+    (five times the step count at which factor 0.5 blows up): the state stays
+    healthy and the flow small."""
+    w = I.bubble81()
+    m = adg.Mesh(w["phys"], w["mesh"])
+    m.init_state("bubbles", w["bubbles"])
+    m.compute_dt()
+    rho0 = m.Q[:, 0].clone()
+    for _ in range(1000):
+        m.step()
+    m.check_health()
+    Q = m.Q
+    assert float(Q[:, 1:3].abs().max()) < 0.1
+    assert float(Q[:, 0].min()) > float(rho0.min()) - 1e-3
+    assert float(Q[:, 0].max()) < float(rho0.max()) + 1e-3
+    assert m.t > 0.5

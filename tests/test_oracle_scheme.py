@@ -168,3 +168,17 @@ def test_dof_count_matches_paper():
     s = g["scalability_run"]
     dof = s["cells_per_side"] ** 2 * (s["order"] + 1) ** 2 * 4
     assert abs(dof / 1e6 - s["approx_mdof"]) < 0.5
+
+
+def test_bubble_courant_factor_is_stable():
+    """The bubble workloads' Courant factor keeps the order-6 scheme stable:
+    300 steps of the 27x27 bubble (twice the time in which the same run at
+    factor 0.5 blows up) stay bounded with a small flow (|m| < 0.1 kg/m^2/s
+    for a 0.5 K bubble) and the density within the initial range."""
+    w = I.bubble(27, 6)
+    Q0 = O.ic(w["phys"], w["mesh"], "bubbles", w["bubbles"])
+    Q, t = O.run(w["phys"], w["mesh"], Q0, 0.0, 300)
+    assert t > 0.3
+    assert np.isfinite(Q).all()
+    assert np.max(np.abs(Q[:, 1:3])) < 0.1
+    assert Q[:, 0].min() > Q0[:, 0].min() - 1e-3 and Q[:, 0].max() < Q0[:, 0].max() + 1e-3
