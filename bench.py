@@ -239,7 +239,13 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 10 device-to-device copies of MIB MiB (counter calibration)")
+    ap.add_argument("--leg", choices=["batched", "adaptive", "adjoint"], default=None,
+                    help="only run this leg and print its JSON (for profiling)")
     args = ap.parse_args()
+    if args.leg:
+        fn = {"batched": batched_leg, "adaptive": amr_leg, "adjoint": adjoint_leg}[args.leg]
+        print(json.dumps({args.leg: fn()}), flush=True)
+        return
     if args.copy_calibration:
         import torch
         nb = args.copy_calibration << 20
