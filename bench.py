@@ -230,6 +230,58 @@ def adjoint_leg(steps=50):
             "grad_norm": float(th.grad.norm())}
 
 
+def convergence_leg(T=0.05, grids=(9, 18, 36), orders=(1, 2, 3, 4, 5, 6)):
+    """Convergence study on the manufactured solution (periodic unit square,
+    advected density wave with its heat-flux source): L2 error of rho at
+    t = T against the exact solution, for each order and grid, with the
+    experimental order of convergence between successive grids; plus the
+    step throughput of the 9x9, N=2 workload (10 steps, Courant factor 0.5)."""
+    import math
+    import torch
+    from paper_1905_05524_amd import adg, model
+    from paper_1905_05524_amd import inputs as I
+    out = {"workload": "mms: periodic [0,1]^2, rho = 1 + 0.1 sin 2pi x sin 2pi z, u = w = 0.5, p = 1, "
+                       "mu = 0.01, Courant factor 0.4 (stable at every order); L2 error of rho at t = 0.05",
+           "orders": {}}
+    for N in orders:
+        errs = []
+        for nx in grids:
+            w = I.mms_small(N=N, nx=nx)
+            w["phys"]["cfl"] = 0.4
+            m = adg.Mesh(w["phys"], w["mesh"], fixed_dt=True)
+            m.init_state("mms")
+            m.compute_dt()
+            ns = int(math.ceil(T / m.dt))
+            m.set_state(m.Q.clone(), t=0.0, dt=T / ns)
+            for _ in range(ns):
+                m.step()
+            ex = adg.Mesh(w["phys"], w["mesh"])
+            ex.init_state("mms", t0=T)
+            wq = torch.as_tensor(m.basis()["w"], dtype=torch.float64, device="cuda")
+            W = torch.outer(wq, wq) / nx ** 2
+            e = float(torch.sqrt(torch.sum(W[None] * (m.Q[:, 0] - ex.Q[:, 0]) ** 2)))
+            errs.append({"nx": nx, "steps": ns, "l2_rho": e})
+        eoc = [math.log2(errs[k]["l2_rho"] / errs[k + 1]["l2_rho"]) for k in range(len(errs) - 1)]
+        out["orders"][str(N)] = {"errors": errs, "eoc": eoc}
+    # throughput of the small workload: 9x9 cells, N = 2, 10 steps
+    w = I.mms_small(N=2, nx=9)
+    m = adg.Mesh(w["phys"], w["mesh"])
+    m.init_state("mms")
+    m.compute_dt()
+    s = torch.cuda.current_stream()
+    for _ in range(10):
+        m.step(s)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(10):
+        m.step(s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    out["mms9x9_N2"] = {"ms_per_step": ms, "dof_updates_per_s": model.dofs(81, 2) / (ms / 1e3)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,11 +291,12 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 10 device-to-device copies of MIB MiB (counter calibration)")
-    ap.add_argument("--leg", choices=["batched", "adaptive", "adjoint"], default=None,
+    ap.add_argument("--leg", choices=["batched", "adaptive", "adjoint", "convergence"], default=None,
                     help="only run this leg and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.leg:
-        fn = {"batched": batched_leg, "adaptive": amr_leg, "adjoint": adjoint_leg}[args.leg]
+        fn = {"batched": batched_leg, "adaptive": amr_leg, "adjoint": adjoint_leg,
+              "convergence": convergence_leg}[args.leg]
         print(json.dumps({args.leg: fn()}), flush=True)
         return
     if args.copy_calibration:
@@ -346,6 +399,7 @@ def main():
         out["extra"]["batched"] = batched_leg()
         out["extra"]["adaptive"] = amr_leg()
         out["extra"]["adjoint"] = adjoint_leg()
+        out["extra"]["convergence"] = convergence_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
