@@ -1044,6 +1044,119 @@ int oracle_rollout_jvp(const double* prm, const int* mi, const double* md, const
 // takes the parent polynomial at its nodes; a merged parent takes the L2
 // projection of its children (GL quadrature on each child).  Outputs are
 // sized for 9*C leaves; *C_new is set.
+}  // extern "C"
+
+namespace {
+
+// Regrid decisions with 2:1 balance (neighbouring leaves differ by at most
+// one level after the regrid).  Reading of the paper's rule (refine wins;
+// a family coarsens only if all nine siblings are leaves flagged coarsen)
+// extended by the balance the 1:3 face coupling needs:
+//   1. clamp: refine at the finest level and coarsen at level 0 become keep;
+//   2. refinement closure: a leaf that is not refined but touches, across a
+//      face, a leaf whose new level exceeds its own level by two, is refined;
+//      repeated until nothing changes;
+//   3. coarsening: every complete family of leaves flagged coarsen (none of
+//      them refined by step 2) is a candidate; a candidate whose parent would
+//      touch, across one of its faces, a leaf of new level above the parent's
+//      level + 1 keeps its children; repeated until nothing changes.
+// Returns per leaf: 1 refine, -1 coarsen (with its family), 0 keep.
+// Brute force on the finest grid: the leaves across a face are read from an
+// owner map of the finest cells.
+std::vector<int> balanced_decisions(const Mesh& M, const int8_t* flags) {
+  const int C = (int)M.cells.size(), L = M.L;
+  const int F = ipow3(L), NXf = M.nx * F, NZf = M.nz * F;
+  std::vector<int> owner((size_t)NXf * NZf, -1);
+  for (int c = 0; c < C; ++c) {
+    const Cell& k = M.cells[c];
+    const int sz = ipow3(L - k.level);
+    for (int b = 0; b < sz; ++b)
+      for (int a = 0; a < sz; ++a) owner[(size_t)(k.j * sz + b) * NXf + (k.i * sz + a)] = c;
+  }
+  std::vector<int> f(C), nl(C);
+  for (int c = 0; c < C; ++c) {
+    int v = flags[c];
+    if (v == 1 && M.cells[c].level == L) v = 0;
+    if (v == -1 && M.cells[c].level == 0) v = 0;
+    f[c] = v;
+  }
+  auto newlevel = [&](int c) { return M.cells[c].level + (f[c] == 1 ? 1 : 0) - (f[c] == -2 ? 1 : 0); };
+  // highest new level among the leaves across face fc of the box (level l, i, j); -1 at a wall
+  auto across = [&](int l, int i, int j, int fc) {
+    const int sz = ipow3(L - l);
+    int best = -1;
+    for (int t = 0; t < sz; ++t) {
+      int X, Z;
+      if (fc == 0) { X = i * sz - 1; Z = j * sz + t; }
+      else if (fc == 1) { X = (i + 1) * sz; Z = j * sz + t; }
+      else if (fc == 2) { X = i * sz + t; Z = j * sz - 1; }
+      else { X = i * sz + t; Z = (j + 1) * sz; }
+      if (X < 0 || X >= NXf || Z < 0 || Z >= NZf) {
+        if (M.bc[fc] != BC_PERIODIC) return -1;
+        X = (X + NXf) % NXf; Z = (Z + NZf) % NZf;
+      }
+      best = std::max(best, newlevel(owner[(size_t)Z * NXf + X]));
+    }
+    return best;
+  };
+  // 2. refinement closure
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (int c = 0; c < C; ++c) {
+      const Cell& k = M.cells[c];
+      if (f[c] == 1) continue;
+      for (int fc = 0; fc < 4; ++fc)
+        if (across(k.level, k.i, k.j, fc) > k.level + 1) { f[c] = 1; changed = true; break; }
+    }
+  }
+  // 3. coarsening candidates: complete families flagged -1 (marked -2)
+  for (int c = 0; c < C; ++c) {
+    const Cell& k = M.cells[c];
+    if (f[c] != -1) continue;
+    int found = 0;
+    bool all = true;
+    for (int c2 = 0; c2 < C; ++c2) {
+      const Cell& s2 = M.cells[c2];
+      if (s2.level == k.level && s2.i / 3 == k.i / 3 && s2.j / 3 == k.j / 3) {
+        ++found;
+        if (f[c2] != -1 && f[c2] != -2) all = false;
+      }
+    }
+    if (found == 9 && all) {
+      for (int c2 = 0; c2 < C; ++c2) {
+        const Cell& s2 = M.cells[c2];
+        if (s2.level == k.level && s2.i / 3 == k.i / 3 && s2.j / 3 == k.j / 3) f[c2] = -2;
+      }
+    }
+  }
+  for (int c = 0; c < C; ++c)
+    if (f[c] == -1) f[c] = 0;
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (int c = 0; c < C; ++c) {
+      const Cell& k = M.cells[c];
+      if (f[c] != -2) continue;
+      const int pl = k.level - 1, pi = k.i / 3, pj = k.j / 3;
+      bool ok = true;
+      for (int fc = 0; fc < 4 && ok; ++fc)
+        if (across(pl, pi, pj, fc) > pl + 1) ok = false;
+      if (!ok) {
+        for (int c2 = 0; c2 < C; ++c2) {
+          const Cell& s2 = M.cells[c2];
+          if (s2.level == k.level && s2.i / 3 == pi && s2.j / 3 == pj) f[c2] = 0;
+        }
+        changed = true;
+      }
+    }
+  }
+  for (int c = 0; c < C; ++c) nl[c] = f[c] == -2 ? -1 : f[c];
+  return nl;
+}
+
+}  // namespace
+
+extern "C" {
+
 int oracle_regrid(const double* prm, const int* mi, const double* md, const int* lev, const int* ci,
                   const int* cj, const double* Q, const int8_t* flags, int* nlev, int* nci, int* ncj,
                   double* Qn, int* C_new) {
@@ -1052,24 +1165,15 @@ int oracle_regrid(const double* prm, const int* mi, const double* md, const int*
   Mesh M = build_mesh(mi, md, lev, ci, cj);
   if (!M.ok) return -1;
   const int C = (int)M.cells.size(), n = P.n, sl = 4 * n * n, L = M.L;
-  // which parents merge: all nine children present as leaves and flagged -1
-  auto parent_merges = [&](int l, int i, int j) {
-    if (l == 0) return false;
-    int pi = i / 3, pj = j / 3, found = 0;
-    for (int c = 0; c < C; ++c) {
-      const Cell& k = M.cells[c];
-      if (k.level == l && k.i / 3 == pi && k.j / 3 == pj) {
-        if (flags[c] != -1) return false;
-        ++found;
-      }
-    }
-    return found == 9;
-  };
+  for (int c = 0; c < C; ++c)
+    if (flags[c] < -1 || flags[c] > 1) return -1;
+  const std::vector<int> dec = balanced_decisions(M, flags);
+  (void)L;
   std::vector<int> done;   // parents already emitted, as (l, i, j) triples
   int out = 0;
   for (int c = 0; c < C; ++c) {
     const Cell& k = M.cells[c];
-    if (flags[c] == -1 && k.level > 0 && parent_merges(k.level, k.i, k.j)) {
+    if (dec[c] == -1) {   // the family merges; emitted at its first leaf
       int pl = k.level - 1, pi = k.i / 3, pj = k.j / 3;
       bool seen = false;
       for (size_t q = 0; q < done.size(); q += 3)
@@ -1095,7 +1199,7 @@ int oracle_regrid(const double* prm, const int* mi, const double* md, const int*
             }
       }
       ++out;
-    } else if (flags[c] == 1 && k.level < L) {
+    } else if (dec[c] == 1) {
       for (int b = 0; b < 3; ++b)
         for (int a = 0; a < 3; ++a) {
           nlev[out] = k.level + 1; nci[out] = 3 * k.i + a; ncj[out] = 3 * k.j + b;

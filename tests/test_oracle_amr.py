@@ -188,3 +188,114 @@ def test_regrid_rules():
     f = np.array([0 if l == 0 else -1 for (l, i, j) in leaves], dtype=np.int8)
     new, _ = O.regrid(cfd(N), mesh, Q, f)
     assert new == [(0, 1, 0), (0, 0, 1), (0, 1, 1), (0, 0, 0)]
+
+
+# ------------------------------------------------------------ two levels
+def two_level(leaves, nx=3):
+    return dict(nx=nx, nz=nx, max_level=2, x0=0.0, z0=0.0, Lx=1.0, Lz=1.0, bc=[I.BC_WALL] * 4,
+                leaves=leaves)
+
+
+def _children(l, i, j):
+    return [(l + 1, 3 * i + a, 3 * j + b) for b in range(3) for a in range(3)]
+
+
+def _state(leaves, N=1, seed=3):
+    return I.random_state_cfd(len(leaves), N, seed=seed)
+
+
+def test_refinement_ripples_to_keep_levels_balanced():
+    """Refining the left-middle child of the refined centre cell would put a
+    level-2 cell next to the level-0 cell on its left: that cell is refined
+    too, and nothing else."""
+    base = [(0, i, j) for j in range(3) for i in range(3) if (i, j) != (1, 1)] + _children(0, 1, 1)
+    mesh = two_level(base)
+    flags = np.zeros(len(base), dtype=np.int8)
+    flags[base.index((1, 3, 4))] = 1
+    leaves, _ = O.regrid(cfd(1), mesh, _state(base), flags)
+    expect = []
+    for lf in base:
+        if lf in ((0, 0, 1), (1, 3, 4)):
+            expect += _children(*lf)
+        else:
+            expect.append(lf)
+    assert leaves == expect
+    assert len(leaves) == 33
+    O.mesh_kinds(dict(mesh, leaves=leaves))   # a valid (balanced) mesh
+
+
+def _two_level_base():
+    """3x3 coarse cells; the left-middle and the centre cell refined, the
+    centre's left-middle child refined again."""
+    leaves = []
+    for j in range(3):
+        for i in range(3):
+            if (i, j) in ((0, 1), (1, 1)):
+                continue
+            leaves.append((0, i, j))
+    leaves += _children(0, 0, 1)
+    for ch in _children(0, 1, 1):
+        leaves += _children(*ch) if ch == (1, 3, 4) else [ch]
+    return leaves
+
+
+def test_coarsening_that_breaks_balance_is_cancelled():
+    base = _two_level_base()
+    mesh = two_level(base)
+    O.mesh_kinds(mesh)
+    flags = np.zeros(len(base), dtype=np.int8)
+    for ch in _children(0, 0, 1):       # the left family asks to coarsen
+        flags[base.index(ch)] = -1
+    leaves, Qn = O.regrid(cfd(1), mesh, _state(base), flags)
+    assert leaves == base               # its parent would touch level 2: kept
+    assert np.array_equal(Qn, _state(base))
+
+
+def test_coarsenings_that_restore_balance_together_are_accepted():
+    base = _two_level_base()
+    mesh = two_level(base)
+    flags = np.zeros(len(base), dtype=np.int8)
+    for ch in _children(0, 0, 1) + _children(1, 3, 4):
+        flags[base.index(ch)] = -1
+    leaves, _ = O.regrid(cfd(1), mesh, _state(base), flags)
+    expect = [(0, i, j) for j in range(3) for i in range(3) if (i, j) != (1, 1)]
+    got = set(leaves)
+    assert got == set(expect) | set(_children(0, 1, 1))
+    assert len(leaves) == 8 + 9
+
+
+def test_unbalanced_mesh_is_rejected():
+    """The validity check used below: a level-2 cell next to a level-0 cell."""
+    leaves = [(0, i, j) for j in range(3) for i in range(3) if (i, j) != (1, 1)]
+    for ch in _children(0, 1, 1):
+        leaves += _children(*ch) if ch == (1, 3, 4) else [ch]
+    with pytest.raises(Exception):
+        O.mesh_kinds(two_level(leaves))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_random_two_level_regrids_stay_balanced(seed):
+    """Random flags on random two-level meshes: the result is a valid mesh
+    (neighbours differ by at most one level), every leaf flagged refine below
+    the top level is refined, and a family coarsens only when all nine
+    siblings asked for it."""
+    rng = np.random.default_rng(seed)
+    leaves = [(0, i, j) for j in range(4) for i in range(4)]
+    mesh = dict(nx=4, nz=4, max_level=2, x0=0.0, z0=0.0, Lx=1.0, Lz=1.0, bc=[I.BC_PERIODIC, I.BC_PERIODIC,
+                I.BC_WALL, I.BC_WALL], leaves=leaves)
+    for rnd in range(4):
+        C = len(leaves)
+        flags = rng.choice(np.array([-1, 0, 1], dtype=np.int8), size=C, p=[0.4, 0.3, 0.3])
+        new, _ = O.regrid(cfd(1), mesh, _state(leaves, seed=rnd), flags)
+        O.mesh_kinds(dict(mesh, leaves=new))
+        newset = set(new)
+        for lf, fl in zip(leaves, flags):
+            if fl == 1 and lf[0] < 2:
+                assert set(_children(*lf)) <= newset
+            if lf not in newset and lf[0] > 0 and not set(_children(*lf)) <= newset:
+                # coarsened: its whole family asked for it
+                fam = [s for s in leaves if s[0] == lf[0] and (s[1] // 3, s[2] // 3) == (lf[1] // 3, lf[2] // 3)]
+                assert len(fam) == 9
+                assert all(flags[leaves.index(s)] == -1 for s in fam)
+        leaves = new
+        mesh = dict(mesh, leaves=leaves)
