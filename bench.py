@@ -147,15 +147,18 @@ def batched_leg(steps=20, warmup=3):
             "autotuned_cells_per_wave": cpw, "autotuned_waves_per_block": wpb}
 
 
-def amr_leg(steps=200):
-    """Adaptive workload: 27x27 coarse cells, one 3-way level, N=6, warm and
-    cold bubbles; initial refinement from the analytic state; TV indicator,
-    flags and regrid every 10 steps.  Timed end to end (including the
-    host-side regrid plan and the device-to-host flag copy)."""
+def amr_leg(workload="amr27", steps=200):
+    """Adaptive workloads, timed end to end (including the host-side regrid
+    plan and the device-to-host flag copy):
+      amr27: 27x27 coarse cells, one 3-way level, N=6, warm and cold bubbles;
+      amr9:  the paper's colliding bubbles on 9x9 coarse cells, two levels.
+    Initial refinement from the analytic state; TV indicator, flags and
+    regrid every 10 steps."""
+    import numpy as np
     import torch
     from paper_1905_05524_amd import adg, model
     from paper_1905_05524_amd import inputs as I
-    w = I.amr27()
+    w = {"amr27": I.amr27, "amr9": I.amr9}[workload]()
     N = w["phys"]["N"]
     m = adg.Mesh(w["phys"], w["mesh"])
     m.init_state("bubbles", w["bubbles"])
@@ -167,8 +170,9 @@ def amr_leg(steps=200):
         m.tv_indicator(adg.ADG_VAR_THETA, w["T_refine"], w["T_coarsen"], tv, fl, st)
         return fl
 
-    m.regrid(indicator())
-    m.init_state("bubbles", w["bubbles"])
+    for _ in range(w.get("initial_passes", 1)):
+        m.regrid(indicator())
+        m.init_state("bubbles", w["bubbles"])
     m.compute_dt()
     c0 = m.C
     torch.cuda.synchronize()
@@ -183,11 +187,16 @@ def amr_leg(steps=200):
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     m.check_health()
-    return {"workload": "amr27x27_L1_N6: 27x27 coarse cells of 37.04 m, one 3-way level, warm cosine + cold "
-                        "Gaussian bubble, regrid every 10 steps (TV of theta, T_refine 0, T_coarsen -0.4)",
+    levels = np.bincount([int(r[0]) for r in m.leaves()], minlength=w["mesh"]["max_level"] + 1)
+    names = {"amr27": "amr27x27_L1_N6: 27x27 coarse cells of 37.04 m, one 3-way level, warm cosine + cold "
+                      "Gaussian bubble, regrid every 10 steps (TV of theta, T_refine 0, T_coarsen -0.4)",
+             "amr9": "amr9x9_L2_N6: colliding bubbles, 9x9 coarse cells of 111.1 m, two 3-way levels "
+                     "(37.04 m, 12.35 m), 3 initial refinement passes, regrid every 10 steps "
+                     "(TV of theta, T_refine 1.0, T_coarsen -0.5)"}
+    return {"workload": names[workload],
             "steps": steps, "initial_leaves": c0, "leaves_min": min(cells + [c0]), "leaves_max": max(cells + [c0]),
-            "leaves_final": m.C, "s_per_step_incl_regrid": t / steps, "dof_updates_per_s": dof_updates / t,
-            "sim_time_s": m.t}
+            "leaves_final": m.C, "leaves_per_level_final": levels.tolist(),
+            "s_per_step_incl_regrid": t / steps, "dof_updates_per_s": dof_updates / t, "sim_time_s": m.t}
 
 
 def adjoint_leg(steps=50):
@@ -291,12 +300,12 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 10 device-to-device copies of MIB MiB (counter calibration)")
-    ap.add_argument("--leg", choices=["batched", "adaptive", "adjoint", "convergence"], default=None,
+    ap.add_argument("--leg", choices=["batched", "adaptive", "adaptive2", "adjoint", "convergence"], default=None,
                     help="only run this leg and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.leg:
-        fn = {"batched": batched_leg, "adaptive": amr_leg, "adjoint": adjoint_leg,
-              "convergence": convergence_leg}[args.leg]
+        fn = {"batched": batched_leg, "adaptive": amr_leg, "adaptive2": lambda: amr_leg("amr9"),
+              "adjoint": adjoint_leg, "convergence": convergence_leg}[args.leg]
         print(json.dumps({args.leg: fn()}), flush=True)
         return
     if args.copy_calibration:
@@ -397,7 +406,8 @@ def main():
     }
     if not args.no_batch:
         out["extra"]["batched"] = batched_leg()
-        out["extra"]["adaptive"] = amr_leg()
+        out["extra"]["adaptive"] = amr_leg("amr27")
+        out["extra"]["adaptive_two_levels"] = amr_leg("amr9")
         out["extra"]["adjoint"] = adjoint_leg()
         out["extra"]["convergence"] = convergence_leg()
     if not args.no_cpu_baseline:

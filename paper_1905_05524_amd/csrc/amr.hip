@@ -1,15 +1,18 @@
 // Adaptive mesh refinement: the regrid plan (host) and the state transfer
 // kernel (gfx950).
 //
-// Plan (paper, Section 3: refinement criterion, subcells are coarsened only
-// when all of them are marked): flags +1 refine, -1 coarsen, 0 keep; refine
-// is dropped at the finest level, coarsen at the coarsest; a family of nine
-// siblings is replaced by its parent only if all nine are leaves flagged
-// coarsen.  New leaf order: old leaves in order; a refined leaf is replaced
+// Plan (Numerics, refinement criterion: subcells are coarsened only when all
+// of them are marked): flags +1 refine, -1 coarsen, 0 keep; refine is dropped
+// at the finest level, coarsen at the coarsest; a family of nine siblings is
+// replaced by its parent only if all nine are leaves flagged coarsen; with
+// several levels, refinements and coarsenings are adjusted to keep
+// neighbouring leaves within one level (regrid_plan).  New leaf order: old leaves in order; a refined leaf is replaced
 // by its children (row by row), a coarsened family by its parent at the
 // position of its first sibling.
 // Transfer: copy; prolongation to a child by exact interpolation of the
 // parent polynomial; restriction of nine children by L2 projection.
+#include <algorithm>
+#include <tuple>
 #include <unordered_map>
 
 #include "adg_internal.h"
@@ -96,10 +99,83 @@ int launch_regrid(int n, int C, const int* ops, const double* Qold, double* Qnew
 
 static long long fkey(int l, int i, int j) { return ((long long)l << 52) ^ ((long long)i << 26) ^ (long long)j; }
 
+// Regrid decisions with 2:1 balance, so that neighbouring leaves differ by
+// at most one level after the regrid (the 1:3 face coupling needs it):
+//   1. refine is dropped at the finest level, coarsen at level 0;
+//   2. refinement closure: a leaf not refined that would touch, across a
+//      face, a leaf two or more levels finer after the regrid is refined;
+//      repeated to a fixed point;
+//   3. coarsening: a complete family of nine leaves flagged coarsen (none
+//      refined by step 2) is a candidate; a candidate whose parent would
+//      touch, across a face, a leaf more than one level finer keeps its
+//      children; repeated to a fixed point (cancelling only raises levels).
+// Leaves across a face are found through the leaf map: the neighbouring box
+// at the same level, then its ancestors (a coarser leaf covers it), else its
+// descendants along the shared face.
+namespace {
+
+struct LeafMap {
+  std::unordered_map<long long, int> idx;
+  const std::vector<int>& lev;
+  const std::vector<int>& ci;
+  const std::vector<int>& cj;
+  int nx, nz;
+  const int* bc;
+  LeafMap(const std::vector<int>& l, const std::vector<int>& i, const std::vector<int>& j, int nx_, int nz_,
+          const int* bc_)
+      : lev(l), ci(i), cj(j), nx(nx_), nz(nz_), bc(bc_) {
+    idx.reserve(l.size() * 2);
+    for (size_t c = 0; c < l.size(); ++c) idx[fkey(l[c], i[c], j[c])] = (int)c;
+  }
+  int find(int l, int i, int j) const {
+    auto it = idx.find(fkey(l, i, j));
+    return it == idx.end() ? -1 : it->second;
+  }
+};
+
+int pow3i(int e) { int r = 1; while (e-- > 0) r *= 3; return r; }
+
+// highest new level over the leaves inside box (l, i, j) that touch its side
+// `side` (0: low x, 1: high x, 2: low z, 3: high z)
+template <class NL>
+int max_on_side(const LeafMap& M, const NL& nl, int l, int i, int j, int side, int L) {
+  const int c = M.find(l, i, j);
+  if (c >= 0) return nl(c);
+  if (l >= L) return -1;   // not a leaf and cannot be split further: covered by an ancestor
+  int best = -1;
+  for (int t = 0; t < 3; ++t) {
+    const int a = side == 0 ? 0 : side == 1 ? 2 : t;
+    const int b = side == 2 ? 0 : side == 3 ? 2 : t;
+    best = std::max(best, max_on_side(M, nl, l + 1, 3 * i + a, 3 * j + b, side, L));
+  }
+  return best;
+}
+
+// highest new level over the leaves across face f of box (l, i, j); -1 at a wall
+template <class NL>
+int across_face(const LeafMap& M, const NL& nl, int l, int i, int j, int f, int L) {
+  const int NX = M.nx * pow3i(l), NZ = M.nz * pow3i(l);
+  int i2 = i + (f == 0 ? -1 : f == 1 ? 1 : 0), j2 = j + (f == 2 ? -1 : f == 3 ? 1 : 0);
+  if (i2 < 0 || i2 >= NX || j2 < 0 || j2 >= NZ) {
+    if (M.bc[f] == ADG_BC_WALL) return -1;
+    i2 = (i2 + NX) % NX; j2 = (j2 + NZ) % NZ;
+  }
+  // a coarser (or equal) leaf covering the neighbouring box
+  for (int la = l, ia = i2, ja = j2; la >= 0; --la, ia /= 3, ja /= 3) {
+    const int c = M.find(la, ia, ja);
+    if (c >= 0) return nl(c);
+  }
+  // finer leaves: those of the neighbouring box on the side facing this box
+  const int side = f == 0 ? 1 : f == 1 ? 0 : f == 2 ? 3 : 2;
+  return max_on_side(M, nl, l, i2, j2, side, L);
+}
+
+}  // namespace
+
 // New leaf list and transfer ops from the old leaves and flags.
 int regrid_plan(const std::vector<int>& lev, const std::vector<int>& ci, const std::vector<int>& cj,
-                const int8_t* flags, int L, std::vector<int>& nlev, std::vector<int>& nci, std::vector<int>& ncj,
-                std::vector<int>& ops) {
+                const int8_t* flags, int L, int nx, int nz, const int* bc, std::vector<int>& nlev,
+                std::vector<int>& nci, std::vector<int>& ncj, std::vector<int>& ops) {
   const int C = (int)lev.size();
   std::vector<int> eff(C);
   for (int c = 0; c < C; ++c) {
@@ -109,14 +185,60 @@ int regrid_plan(const std::vector<int>& lev, const std::vector<int>& ci, const s
     if (f == -1 && lev[c] == 0) f = 0;
     eff[c] = f;
   }
-  // families whose nine children are all leaves flagged coarsen
-  std::unordered_map<long long, int> cnt;
-  std::unordered_map<long long, int> child_of;   // child key -> old index
-  for (int c = 0; c < C; ++c)
-    if (lev[c] > 0) {
-      child_of[fkey(lev[c], ci[c], cj[c])] = c;
-      if (eff[c] == -1) cnt[fkey(lev[c] - 1, ci[c] / 3, cj[c] / 3)] += 1;
+  const LeafMap M(lev, ci, cj, nx, nz, bc);
+  // new level: +1 refine, -1 accepted coarsening (coded 2 below)
+  std::vector<int> coarsen(C, 0);
+  auto nl = [&](int c) { return lev[c] + (eff[c] == 1 ? 1 : 0) - coarsen[c]; };
+  // refinement closure
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (int c = 0; c < C; ++c) {
+      if (eff[c] == 1) continue;
+      for (int f = 0; f < 4; ++f)
+        if (across_face(M, nl, lev[c], ci[c], cj[c], f, L) > lev[c] + 1) {
+          eff[c] = 1;
+          changed = true;
+          break;
+        }
     }
+  }
+  // coarsening candidates: families whose nine children are leaves flagged coarsen
+  std::unordered_map<long long, int> cnt;
+  for (int c = 0; c < C; ++c)
+    if (lev[c] > 0 && eff[c] == -1) cnt[fkey(lev[c] - 1, ci[c] / 3, cj[c] / 3)] += 1;
+  std::vector<long long> fams;
+  for (const auto& kv : cnt)
+    if (kv.second == 9) fams.push_back(kv.first);
+  std::sort(fams.begin(), fams.end());
+  auto family = [&](long long pk, int* out) {
+    // the nine children (row by row) of parent key pk, as leaf indices
+    const int pl = (int)(pk >> 52);
+    const long long rest = pk ^ ((long long)pl << 52);
+    const int pi = (int)(rest >> 26), pj = (int)(rest & ((1LL << 26) - 1));
+    for (int b = 0; b < 3; ++b)
+      for (int a = 0; a < 3; ++a) out[3 * b + a] = M.find(pl + 1, 3 * pi + a, 3 * pj + b);
+    return std::make_tuple(pl, pi, pj);
+  };
+  for (long long pk : fams) {
+    int kids[9];
+    family(pk, kids);
+    for (int k = 0; k < 9; ++k) coarsen[kids[k]] = 1;
+  }
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (long long pk : fams) {
+      int kids[9];
+      auto [pl, pi, pj] = family(pk, kids);
+      if (!coarsen[kids[0]]) continue;
+      bool ok = true;
+      for (int f = 0; f < 4 && ok; ++f)
+        if (across_face(M, nl, pl, pi, pj, f, L) > pl + 1) ok = false;
+      if (!ok) {
+        for (int k = 0; k < 9; ++k) coarsen[kids[k]] = 0;
+        changed = true;
+      }
+    }
+  }
   std::unordered_map<long long, int> emitted;
   nlev.clear(); nci.clear(); ncj.clear(); ops.clear();
   auto emit = [&](int l, int i, int j, int op, int a, int b, const int* src, int ns) {
@@ -127,19 +249,14 @@ int regrid_plan(const std::vector<int>& lev, const std::vector<int>& ci, const s
   };
   for (int c = 0; c < C; ++c) {
     const int l = lev[c], i = ci[c], j = cj[c];
-    if (l > 0) {
+    if (coarsen[c]) {
       const long long pk = fkey(l - 1, i / 3, j / 3);
-      auto it = cnt.find(pk);
-      if (it != cnt.end() && it->second == 9) {
-        if (emitted.count(pk)) continue;
-        emitted[pk] = 1;
-        int src[9];
-        for (int b = 0; b < 3; ++b)
-          for (int a = 0; a < 3; ++a)
-            src[3 * b + a] = child_of.at(fkey(l, 3 * (i / 3) + a, 3 * (j / 3) + b));
-        emit(l - 1, i / 3, j / 3, kRestrict, 0, 0, src, 9);
-        continue;
-      }
+      if (emitted.count(pk)) continue;
+      emitted[pk] = 1;
+      int src[9];
+      family(pk, src);
+      emit(l - 1, i / 3, j / 3, kRestrict, 0, 0, src, 9);
+      continue;
     }
     if (eff[c] == 1) {
       for (int b = 0; b < 3; ++b)

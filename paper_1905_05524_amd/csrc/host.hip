@@ -29,8 +29,8 @@ int launch_ic_theta_adj(const Group& g, const double* thp, const double* lam, do
 int launch_loss(const Group& g, double* part, double* out, hipStream_t s);
 int launch_loss_adj(const Group& g, const double* L, const double* gL, double* lam, hipStream_t s);
 int regrid_plan(const std::vector<int>& lev, const std::vector<int>& ci, const std::vector<int>& cj,
-                const int8_t* flags, int L, std::vector<int>& nlev, std::vector<int>& nci, std::vector<int>& ncj,
-                std::vector<int>& ops);
+                const int8_t* flags, int L, int nx, int nz, const int* bc, std::vector<int>& nlev,
+                std::vector<int>& nci, std::vector<int>& ncj, std::vector<int>& ops);
 
 static thread_local std::string g_err;
 
@@ -634,7 +634,8 @@ int adg_get_leaves(const adg_mesh* m, int32_t* level, int32_t* i, int32_t* j) {
 int adg_regrid_plan(adg_mesh* m, const int8_t* flags_host, int* n_cells_new, size_t* ws_bytes_new) {
   if (!m || !flags_host) return fail(ADG_EINVAL, "null argument");
   m->plan_ready = false;
-  int rc = regrid_plan(m->hm.lev, m->hm.ci, m->hm.cj, flags_host, m->desc.max_level, m->plan_lev, m->plan_ci,
+  int rc = regrid_plan(m->hm.lev, m->hm.ci, m->hm.cj, flags_host, m->desc.max_level, m->desc.nx, m->desc.nz,
+                       m->desc.bc, m->plan_lev, m->plan_ci,
                        m->plan_cj, m->plan_ops);
   if (rc) return rc;
   // the new leaves must form a valid mesh (at most one level between neighbours)

@@ -120,3 +120,66 @@ def test_adaptive_workload_initial_refinement():
     cur = dict(w["mesh"], leaves=ref_leaves)
     ref = O.step(w["phys"], cur, Q0, t, dt)
     assert np.all(relerr(m.Q.cpu().numpy(), ref) <= 1e-11)
+
+
+def _two_level_random(seed):
+    rng = np.random.default_rng(seed)
+    mesh = dict(nx=4, nz=4, max_level=2, x0=0.0, z0=0.0, Lx=1.0, Lz=1.0,
+                bc=[I.BC_PERIODIC, I.BC_PERIODIC, I.BC_WALL, I.BC_WALL], leaves=I.uniform_leaves(4, 4))
+    return rng, mesh
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_two_level_regrids_match_oracle(seed):
+    """Random flags on meshes of up to two levels (with the 2:1 balance of
+    the regrid plan): the library's leaves equal the oracle's, the state
+    transfer agrees, and a step on the new mesh matches the oracle."""
+    rng, mesh = _two_level_random(seed)
+    N = 2
+    phys = dict(I.CFD, N=N, picard_iters=0, mu=0.02, mms=0, cfl=0.5)
+    m = adg.Mesh(phys, mesh)
+    m.set_state(I.random_state_cfd(16, N, seed=seed))
+    for rnd in range(4):
+        cur = dict(mesh, leaves=leaves_of(m))
+        Q = m.Q.cpu().numpy().copy()
+        flags = rng.choice(np.array([-1, 0, 1], dtype=np.int8), size=m.C, p=[0.4, 0.3, 0.3])
+        m.regrid(flags)
+        ref_leaves, ref_Q = O.regrid(phys, cur, Q, flags)
+        assert leaves_of(m) == ref_leaves, rnd
+        assert np.all(relerr(m.Q.cpu().numpy(), ref_Q) <= 1e-13), rnd
+        new_mesh = dict(mesh, leaves=ref_leaves)
+        Qg = m.Q.cpu().numpy().copy()
+        dt = 0.5 * O.dt(phys, new_mesh, Qg)
+        m.clock[0], m.clock[1] = 0.0, dt
+        m.step()
+        ref = O.step(phys, new_mesh, Qg, 0.0, dt)
+        assert np.all(relerr(m.Q.cpu().numpy(), ref) <= 1e-11), rnd
+    assert max(l for l, _, _ in leaves_of(m)) == 2
+
+
+def test_colliding_bubbles_initial_refinement_matches_oracle():
+    """The paper's colliding bubbles on 9x9 coarse cells with two levels:
+    three passes of indicator -> flags -> regrid -> analytic state, each
+    compared with the oracle fed the GPU's state; the mesh reaches level 2
+    (905 leaves)."""
+    w = I.amr9()
+    m = adg.Mesh(w["phys"], w["mesh"])
+    m.init_state("bubbles", w["bubbles"])
+    for p in range(w["initial_passes"]):
+        cur = dict(w["mesh"], leaves=leaves_of(m))
+        Q = m.Q.cpu().numpy().copy()
+        tv, fl, st = _tv(m, adg.ADG_VAR_THETA, w["T_refine"], w["T_coarsen"])
+        rtv, rfl, rst = O.tv(w["phys"], cur, Q, O.VAR_THETA, w["T_refine"], w["T_coarsen"])
+        assert np.array_equal(fl, rfl), p
+        m.regrid(fl)
+        ref_leaves, _ = O.regrid(w["phys"], cur, Q, fl)
+        assert leaves_of(m) == ref_leaves, p
+        m.init_state("bubbles", w["bubbles"])
+    assert m.C == 905
+    assert max(l for l, _, _ in leaves_of(m)) == 2
+    m.compute_dt()
+    Q0 = m.Q.cpu().numpy().copy()
+    t, dt = m.t, m.dt
+    m.step()
+    ref = O.step(w["phys"], dict(w["mesh"], leaves=leaves_of(m)), Q0, t, dt)
+    assert np.all(relerr(m.Q.cpu().numpy(), ref) <= 1e-11)
