@@ -1227,3 +1227,433 @@ int oracle_regrid(const double* prm, const int* mi, const double* md, const int*
 }
 
 }  // extern "C"
+
+// ========================================================================= 3D
+// The same scheme in three space dimensions on uniform grids of cubes
+// (periodic or wall boundaries, no adaptivity): conserved variables
+// (rho, rho u, rho v, rho w, rho E), gravity along -z.  Every definition is
+// the 2D one with the third direction added: the flux and source of the
+// equation set, the element-local predictor, time averages, face
+// extrapolation, the viscous Rusanov flux with the wall ghost state, the
+// corrector, and the time step with d = 3 in the Courant rule.
+// Layout: Q[cell][var][k][j][i] (z, y, x nodes; x fastest), cells
+// c = (k * ny + j) * nx + i; faces 0/1: -x/+x, 2/3: -y/+y, 4/5: -z/+z; face
+// nodes ordered by the two tangential directions in (z, y, x) order.
+namespace {
+
+struct Mesh3 {
+  int nx, ny, nz, bc[6];
+  double x0, y0, z0, h;
+  int C() const { return nx * ny * nz; }
+};
+
+Mesh3 read_mesh3(const int* mi, const double* md) {
+  Mesh3 M;
+  M.nx = mi[0]; M.ny = mi[1]; M.nz = mi[2];
+  for (int f = 0; f < 6; ++f) M.bc[f] = mi[3 + f];
+  M.x0 = md[0]; M.y0 = md[1]; M.z0 = md[2]; M.h = md[3];
+  return M;
+}
+
+// flux F[d][v] (d = x, y, z) and source S[v] at one point; g[d][v] are the
+// physical gradients of the conserved variables
+void pointwise3(const Params& P, const double q[5], const double g[3][5], double z, double rho_b, double p_b,
+                double F[3][5], double S[5]) {
+  const double gm1 = P.gamma - 1.0;
+  const double rho = q[0], E = q[4];
+  const double m[3] = {q[1], q[2], q[3]};
+  const double u[3] = {m[0] / rho, m[1] / rho, m[2] / rho};
+  const double geo = P.gravity ? rho * (P.g * z) : 0.0;
+  const double p = gm1 * (E - 0.5 * (m[0] * u[0] + m[1] * u[1] + m[2] * u[2]) - geo);
+  const double pm = P.gravity ? p - p_b : p;
+  const double Tm = p / (rho * P.R);
+  double du[3][3];   // du[a][d] = d u_a / d x_d
+  for (int a = 0; a < 3; ++a)
+    for (int d = 0; d < 3; ++d) du[a][d] = (g[d][1 + a] - u[a] * g[d][0]) / rho;
+  const double v2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  double dT[3];
+  for (int d = 0; d < 3; ++d) {
+    double dp = gm1 * (g[d][4] - 0.5 * v2 * g[d][0] - rho * (u[0] * du[0][d] + u[1] * du[1][d] + u[2] * du[2][d]));
+    if (P.gravity) {
+      dp = dp - gm1 * (P.g * z) * g[d][0];
+      if (d == 2) dp = dp - gm1 * rho * P.g;
+    }
+    dT[d] = (dp - P.R * Tm * g[d][0]) / (rho * P.R);
+  }
+  const double div = du[0][0] + du[1][1] + du[2][2];
+  double sig[3][3];   // sigma = mu (2/3 div I - (grad v + grad v^T))
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) sig[a][b] = P.mu * ((a == b ? (2.0 / 3.0) * div : 0.0) - (du[a][b] + du[b][a]));
+  for (int d = 0; d < 3; ++d) {
+    F[d][0] = m[d];
+    for (int a = 0; a < 3; ++a) F[d][1 + a] = m[a] * u[d] + (a == d ? pm : 0.0) + sig[a][d];
+    F[d][4] = u[d] * (E + p) + (u[0] * sig[0][d] + u[1] * sig[1][d] + u[2] * sig[2][d]) - P.kappa * dT[d];
+  }
+  for (int v = 0; v < 5; ++v) S[v] = 0.0;
+  S[3] = P.gravity ? -P.g * (rho - rho_b) : 0.0;
+}
+
+double pressure3(const Params& P, const double q[5], double z) {
+  const double geo = P.gravity ? q[0] * (P.g * z) : 0.0;
+  return (P.gamma - 1.0) * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0] - geo);
+}
+
+inline size_t at3(int n, int v, int k, int j, int i) { return (((size_t)v * n + k) * n + j) * n + i; }
+
+// Predictor of one cell (cell origin x0, y0, z0): time averages Qb, Fb[d],
+// Sb, then the partial update Qs = Q + dt ((1/h) sum_d volume_d(Fb_d) + Sb)
+// and the face data FD[6][2][5][n][n] (averaged state, averaged normal flux).
+void predictor3_cell(const Params& P, const Basis& B, double x0, double y0, double z0, double h,
+                     const double* Q, double dt, double* Qs, double* FD) {
+  const int n = P.n, nd = 5 * n * n * n;
+  std::vector<double> q((size_t)n * nd), qn((size_t)n * nd), R((size_t)n * nd);
+  for (int a = 0; a < n; ++a)
+    for (int t = 0; t < nd; ++t) q[(size_t)a * nd + t] = Q[t];
+  auto residual = [&](const double* qa, double* Fout /*[3][nd] or null*/, double* Sout, double* Ra) {
+    std::vector<double> g(3 * (size_t)nd), F(3 * (size_t)nd), S(nd);
+    for (int v = 0; v < 5; ++v)
+      for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+          for (int i = 0; i < n; ++i) {
+            double sx = 0.0, sy = 0.0, sz = 0.0;
+            for (int m = 0; m < n; ++m) {
+              sx += B.D[i * n + m] * qa[at3(n, v, k, j, m)];
+              sy += B.D[j * n + m] * qa[at3(n, v, k, m, i)];
+              sz += B.D[k * n + m] * qa[at3(n, v, m, j, i)];
+            }
+            g[0 * (size_t)nd + at3(n, v, k, j, i)] = sx / h;
+            g[1 * (size_t)nd + at3(n, v, k, j, i)] = sy / h;
+            g[2 * (size_t)nd + at3(n, v, k, j, i)] = sz / h;
+          }
+    for (int k = 0; k < n; ++k) {
+      const double z = z0 + h * B.xi[k];
+      double rb, pb;
+      background(P, z, rb, pb);
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double qq[5], gg[3][5], FF[3][5], SS[5];
+          for (int v = 0; v < 5; ++v) {
+            qq[v] = qa[at3(n, v, k, j, i)];
+            for (int d = 0; d < 3; ++d) gg[d][v] = g[d * (size_t)nd + at3(n, v, k, j, i)];
+          }
+          pointwise3(P, qq, gg, z, rb, pb, FF, SS);
+          for (int v = 0; v < 5; ++v) {
+            for (int d = 0; d < 3; ++d) F[d * (size_t)nd + at3(n, v, k, j, i)] = FF[d][v];
+            S[at3(n, v, k, j, i)] = SS[v];
+          }
+        }
+    }
+    if (Fout) for (size_t t = 0; t < 3 * (size_t)nd; ++t) Fout[t] = F[t];
+    if (Sout) for (int t = 0; t < nd; ++t) Sout[t] = S[t];
+    if (Ra)
+      for (int v = 0; v < 5; ++v)
+        for (int k = 0; k < n; ++k)
+          for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+              double dv = 0.0;
+              for (int m = 0; m < n; ++m) {
+                dv += B.D[i * n + m] * F[0 * (size_t)nd + at3(n, v, k, j, m)];
+                dv += B.D[j * n + m] * F[1 * (size_t)nd + at3(n, v, k, m, i)];
+                dv += B.D[k * n + m] * F[2 * (size_t)nd + at3(n, v, m, j, i)];
+              }
+              Ra[at3(n, v, k, j, i)] = S[at3(n, v, k, j, i)] - dv / h;
+            }
+  };
+  for (int it = 0; it < P.iters; ++it) {
+    for (int b = 0; b < n; ++b) residual(&q[(size_t)b * nd], nullptr, nullptr, &R[(size_t)b * nd]);
+    for (int a = 0; a < n; ++a)
+      for (int t = 0; t < nd; ++t) {
+        double s = 0.0;
+        for (int b = 0; b < n; ++b) s += B.P[a * n + b] * R[(size_t)b * nd + t];
+        qn[(size_t)a * nd + t] = Q[t] + dt * s;
+      }
+    q.swap(qn);
+  }
+  std::vector<double> Qb(nd, 0.0), Fb(3 * (size_t)nd, 0.0), Sb(nd, 0.0), Fa(3 * (size_t)nd), Sa(nd);
+  for (int b = 0; b < n; ++b) {
+    residual(&q[(size_t)b * nd], Fa.data(), Sa.data(), nullptr);
+    for (int t = 0; t < nd; ++t) {
+      Qb[t] += B.w[b] * q[(size_t)b * nd + t];
+      Sb[t] += B.w[b] * Sa[t];
+    }
+    for (size_t t = 0; t < 3 * (size_t)nd; ++t) Fb[t] += B.w[b] * Fa[t];
+  }
+  // partial update: volume term (1/w_i) sum_m w_m D_mi Fb[..m..] along each direction
+  for (int v = 0; v < 5; ++v)
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double vx = 0.0, vy = 0.0, vz = 0.0;
+          for (int m = 0; m < n; ++m) {
+            vx += B.w[m] * B.D[m * n + i] * Fb[0 * (size_t)nd + at3(n, v, k, j, m)];
+            vy += B.w[m] * B.D[m * n + j] * Fb[1 * (size_t)nd + at3(n, v, k, m, i)];
+            vz += B.w[m] * B.D[m * n + k] * Fb[2 * (size_t)nd + at3(n, v, m, j, i)];
+          }
+          const double vol = vx / B.w[i] + vy / B.w[j] + vz / B.w[k];
+          Qs[at3(n, v, k, j, i)] = Q[at3(n, v, k, j, i)] + dt * (vol / h + Sb[at3(n, v, k, j, i)]);
+        }
+  // face data: extrapolation along the normal of the averaged state and normal flux
+  const int fs = 2 * 5 * n * n;
+  for (int f = 0; f < 6; ++f) {
+    const int d = f / 2;
+    const std::vector<double>& e = (f % 2) ? B.e1 : B.e0;
+    for (int v = 0; v < 5; ++v)
+      for (int s = 0; s < n; ++s)
+        for (int t = 0; t < n; ++t) {
+          double aq = 0.0, af = 0.0;
+          for (int m = 0; m < n; ++m) {
+            size_t idx;
+            if (d == 0) idx = at3(n, v, s, t, m);        // (k, j) face node, x along m
+            else if (d == 1) idx = at3(n, v, s, m, t);   // (k, i)
+            else idx = at3(n, v, m, s, t);               // (j, i)
+            aq += e[m] * Qb[idx];
+            af += e[m] * Fb[d * (size_t)nd + idx];
+          }
+          FD[(size_t)f * fs + ((0 * 5 + v) * n + s) * n + t] = aq;
+          FD[(size_t)f * fs + ((1 * 5 + v) * n + s) * n + t] = af;
+        }
+  }
+}
+
+// z coordinate of face node (s, t) of face f of a cell at height z0
+double face_z3(const Basis& B, int f, double z0, double h, int s, int t) {
+  (void)t;
+  if (f == 4) return z0;
+  if (f == 5) return z0 + h;
+  return z0 + h * B.xi[s];   // x and y faces: s runs along z
+}
+
+// ghost state and flux at a no-slip wall with normal direction d
+void wall_ghost3(const Params& P, int d, double zf, const double Qi[5], const double Fi[5], double Qg[5],
+                 double Fg[5]) {
+  const double u[3] = {Qi[1] / Qi[0], Qi[2] / Qi[0], Qi[3] / Qi[0]};
+  double rb, pb;
+  if (P.gravity) background(P, zf, rb, pb);
+  else { rb = Qi[0]; pb = pressure3(P, Qi, zf); }
+  const double geo = P.gravity ? rb * (P.g * zf) : 0.0;
+  Qg[0] = rb;
+  for (int a = 0; a < 3; ++a) Qg[1 + a] = -(rb * u[a]);
+  Qg[4] = pb / (P.gamma - 1.0) + 0.5 * rb * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) + geo;
+  const double qbg = (P.gravity && d == 2) ? P.kappa * P.g / P.cp : 0.0;
+  Fg[0] = -Fi[0];
+  for (int a = 0; a < 3; ++a) Fg[1 + a] = Fi[1 + a];
+  Fg[4] = 2.0 * qbg - Fi[4];
+}
+
+int cell3(const Mesh3& M, int i, int j, int k) { return (k * M.ny + j) * M.nx + i; }
+
+// one step: predictor of every cell, then per face the Rusanov flux and the
+// corrector (lifting of the six face fluxes)
+void step3(const Params& P, const Basis& B, const Mesh3& M, const double* Q, double t, double dt, double* out) {
+  (void)t;
+  const int n = P.n, nd = 5 * n * n * n, C = M.C(), fs = 2 * 5 * n * n;
+  std::vector<double> Qs((size_t)C * nd), FD((size_t)C * 6 * fs);
+#pragma omp parallel for schedule(dynamic)
+  for (int c = 0; c < C; ++c) {
+    const int i = c % M.nx, j = (c / M.nx) % M.ny, k = c / (M.nx * M.ny);
+    predictor3_cell(P, B, M.x0 + i * M.h, M.y0 + j * M.h, M.z0 + k * M.h, M.h, Q + (size_t)c * nd, dt,
+                    &Qs[(size_t)c * nd], &FD[(size_t)c * 6 * fs]);
+  }
+  const double PI = 3.14159265358979323846;
+  const double eta = (2.0 * P.N + 1.0) / (M.h * std::sqrt(PI / 2.0));
+#pragma omp parallel for schedule(dynamic)
+  for (int c = 0; c < C; ++c) {
+    const int ci = c % M.nx, cj = (c / M.nx) % M.ny, ck = c / (M.nx * M.ny);
+    const double z0 = M.z0 + ck * M.h;
+    std::vector<double> G((size_t)6 * 5 * n * n);
+    for (int f = 0; f < 6; ++f) {
+      const int d = f / 2, hi = f % 2;
+      int ni = ci + (d == 0 ? (hi ? 1 : -1) : 0), nj = cj + (d == 1 ? (hi ? 1 : -1) : 0),
+          nk = ck + (d == 2 ? (hi ? 1 : -1) : 0);
+      const int dims[3] = {M.nx, M.ny, M.nz};
+      int* nn3[3] = {&ni, &nj, &nk};
+      bool wall = false;
+      if (*nn3[d] < 0 || *nn3[d] >= dims[d]) {
+        if (M.bc[f] == BC_WALL) wall = true;
+        else *nn3[d] = (*nn3[d] + dims[d]) % dims[d];
+      }
+      const double* own = &FD[((size_t)c * 6 + f) * fs];
+      std::vector<double> other(fs);
+      if (wall) {
+        for (int s = 0; s < n; ++s)
+          for (int tt = 0; tt < n; ++tt) {
+            double Qi[5], Fi[5], Qg[5], Fg[5];
+            for (int v = 0; v < 5; ++v) {
+              Qi[v] = own[((0 * 5 + v) * n + s) * n + tt];
+              Fi[v] = own[((1 * 5 + v) * n + s) * n + tt];
+            }
+            wall_ghost3(P, d, face_z3(B, f, z0, M.h, s, tt), Qi, Fi, Qg, Fg);
+            for (int v = 0; v < 5; ++v) {
+              other[((0 * 5 + v) * n + s) * n + tt] = Qg[v];
+              other[((1 * 5 + v) * n + s) * n + tt] = Fg[v];
+            }
+          }
+      } else {
+        const int o = cell3(M, ni, nj, nk);
+        const double* src = &FD[((size_t)o * 6 + (f ^ 1)) * fs];
+        for (int q = 0; q < fs; ++q) other[q] = src[q];
+      }
+      // L = lower side (-axis), R = upper side
+      const double* QL = hi ? own : other.data();
+      const double* QR = hi ? other.data() : own;
+      double lam = 0.0, lv = 0.0;
+      bool first = true;
+      for (int side = 0; side < 2; ++side) {
+        const double* Qx = side ? QR : QL;
+        for (int s = 0; s < n; ++s)
+          for (int tt = 0; tt < n; ++tt) {
+            double q[5];
+            for (int v = 0; v < 5; ++v) q[v] = Qx[((0 * 5 + v) * n + s) * n + tt];
+            const double p = pressure3(P, q, face_z3(B, f, z0, M.h, s, tt));
+            const double l = std::fabs(q[1 + d] / q[0]) + std::sqrt(P.gamma * p / q[0]);
+            const double lvk = lambda_visc(P, q[0]);
+            if (first || l > lam) lam = l;
+            if (first || lvk > lv) lv = lvk;
+            first = false;
+          }
+      }
+      const double sp = lam + 2.0 * eta * lv;
+      for (int v = 0; v < 5; ++v)
+        for (int q = 0; q < n * n; ++q) {
+          const double qL = QL[(0 * 5 + v) * n * n + q], qR = QR[(0 * 5 + v) * n * n + q];
+          const double fL = QL[(1 * 5 + v) * n * n + q], fR = QR[(1 * 5 + v) * n * n + q];
+          G[((size_t)f * 5 + v) * n * n + q] = 0.5 * (fL + fR) - 0.5 * sp * (qR - qL);
+        }
+    }
+    for (int v = 0; v < 5; ++v)
+      for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+          for (int i = 0; i < n; ++i) {
+            auto g = [&](int f, int s, int tt) { return G[((size_t)f * 5 + v) * n * n + s * n + tt]; };
+            const double lx = (B.e1[i] * g(1, k, j) - B.e0[i] * g(0, k, j)) / B.w[i];
+            const double ly = (B.e1[j] * g(3, k, i) - B.e0[j] * g(2, k, i)) / B.w[j];
+            const double lz = (B.e1[k] * g(5, j, i) - B.e0[k] * g(4, j, i)) / B.w[k];
+            out[(size_t)c * nd + at3(n, v, k, j, i)] = Qs[(size_t)c * nd + at3(n, v, k, j, i)] - dt / M.h * (lx + ly + lz);
+          }
+  }
+}
+
+double dt3(const Params& P, const Basis& B, const Mesh3& M, const double* Q) {
+  const int n = P.n, nd = 5 * n * n * n;
+  double dt = 1e300;
+  for (int c = 0; c < M.C(); ++c) {
+    const int ck = c / (M.nx * M.ny);
+    double lam = 0.0, lv = 0.0;
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double q[5];
+          for (int v = 0; v < 5; ++v) q[v] = Q[(size_t)c * nd + at3(n, v, k, j, i)];
+          const double z = M.z0 + ck * M.h + M.h * B.xi[k];
+          const double cs = std::sqrt(P.gamma * pressure3(P, q, z) / q[0]);
+          const double l = std::max(std::fabs(q[1]), std::max(std::fabs(q[2]), std::fabs(q[3]))) / q[0] + cs;
+          lam = std::max(lam, l);
+          lv = std::max(lv, lambda_visc(P, q[0]));
+        }
+    const double o = 2.0 * P.N + 1.0;
+    dt = std::min(dt, P.cfl * M.h / (3.0 * o * (lam + 2.0 * lv * o / M.h)));
+  }
+  return dt;
+}
+
+}  // namespace
+
+extern "C" {
+
+int oracle3_step(const double* prm, const int* mi, const double* md, const double* Q, double t, double dt,
+                 double* out) {
+  Params P = read_params(prm);
+  Basis B = make_basis(P.N);
+  step3(P, B, read_mesh3(mi, md), Q, t, dt, out);
+  return 0;
+}
+
+int oracle3_predictor(const double* prm, const int* mi, const double* md, const double* Q, double dt, double* Qs,
+                      double* FD) {
+  Params P = read_params(prm);
+  Basis B = make_basis(P.N);
+  Mesh3 M = read_mesh3(mi, md);
+  const int n = P.n, nd = 5 * n * n * n, fs = 2 * 5 * n * n;
+#pragma omp parallel for schedule(dynamic)
+  for (int c = 0; c < M.C(); ++c) {
+    const int i = c % M.nx, j = (c / M.nx) % M.ny, k = c / (M.nx * M.ny);
+    predictor3_cell(P, B, M.x0 + i * M.h, M.y0 + j * M.h, M.z0 + k * M.h, M.h, Q + (size_t)c * nd, dt,
+                    Qs + (size_t)c * nd, FD + (size_t)c * 6 * fs);
+  }
+  return 0;
+}
+
+int oracle3_dt(const double* prm, const int* mi, const double* md, const double* Q, double* out) {
+  Params P = read_params(prm);
+  Basis B = make_basis(P.N);
+  *out = dt3(P, B, read_mesh3(mi, md), Q);
+  return 0;
+}
+
+int oracle3_run(const double* prm, const int* mi, const double* md, double* Q, double* t, double dt, int nsteps) {
+  Params P = read_params(prm);
+  Basis B = make_basis(P.N);
+  Mesh3 M = read_mesh3(mi, md);
+  const size_t tot = (size_t)M.C() * 5 * P.n * P.n * P.n;
+  std::vector<double> Qn(tot);
+  for (int s = 0; s < nsteps; ++s) {
+    const double h = dt > 0 ? dt : dt3(P, B, M, Q);
+    step3(P, B, M, Q, *t, h, Qn.data());
+    std::memcpy(Q, Qn.data(), tot * sizeof(double));
+    *t += h;
+  }
+  return 0;
+}
+
+// Initial states by nodal interpolation.  kind 0: background atmosphere
+// perturbed in theta by bubbles [shape, A, a, s, xc, yc, zc] (shape 0:
+// cosine (A/2)(1 + cos(pi r / a)) for r <= a; 1: A for r <= a, else
+// A exp(-(r - a)^2 / s^2)), at rest, pressure unperturbed; kind 1: the ABC
+// flow at time t0 (rho = 1, velocity exp(-mu t) (sin z + cos y,
+// sin x + cos z, sin y + cos x), p = 100/gamma - exp(-2 mu t)(cos x sin y +
+// sin x cos z + sin z cos y)).
+int oracle3_ic(const double* prm, const int* mi, const double* md, int kind, int nb, const double* bub, double t0,
+               double* Q) {
+  Params P = read_params(prm);
+  Basis B = make_basis(P.N);
+  Mesh3 M = read_mesh3(mi, md);
+  const int n = P.n, nd = 5 * n * n * n;
+  const double PI = 3.14159265358979323846;
+  for (int c = 0; c < M.C(); ++c) {
+    const int ci = c % M.nx, cj = (c / M.nx) % M.ny, ck = c / (M.nx * M.ny);
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          const double x = M.x0 + M.h * (ci + B.xi[i]), y = M.y0 + M.h * (cj + B.xi[j]),
+                       z = M.z0 + M.h * (ck + B.xi[k]);
+          double q[5];
+          if (kind == 0) {
+            double th = 0.0;
+            for (int b = 0; b < nb; ++b) {
+              const double* bb = bub + 7 * b;
+              const double dx = x - bb[4], dy = y - bb[5], dz = z - bb[6];
+              const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+              if ((int)bb[0] == 0) th += r <= bb[2] ? 0.5 * bb[1] * (1.0 + std::cos(PI * r / bb[2])) : 0.0;
+              else th += r <= bb[2] ? bb[1] : bb[1] * std::exp(-(r - bb[2]) * (r - bb[2]) / (bb[3] * bb[3]));
+            }
+            const double pi = 1.0 - P.g * z / (P.cp * P.theta_bg);
+            const double pb = P.p0 * std::pow(pi, P.cp / P.R);
+            const double rho = pb / (P.R * (P.theta_bg + th) * pi);
+            q[0] = rho; q[1] = q[2] = q[3] = 0.0;
+            q[4] = pb / (P.gamma - 1.0) + rho * P.g * z;
+          } else {
+            const double a = std::exp(-P.mu * t0), a2 = std::exp(-2.0 * P.mu * t0);
+            const double u = a * (std::sin(z) + std::cos(y)), v = a * (std::sin(x) + std::cos(z)),
+                         w = a * (std::sin(y) + std::cos(x));
+            const double p = 100.0 / P.gamma - a2 * (std::cos(x) * std::sin(y) + std::sin(x) * std::cos(z) +
+                                                     std::sin(z) * std::cos(y));
+            q[0] = 1.0; q[1] = u; q[2] = v; q[3] = w;
+            q[4] = p / (P.gamma - 1.0) + 0.5 * (u * u + v * v + w * w);
+          }
+          for (int vv = 0; vv < 5; ++vv) Q[(size_t)c * nd + at3(n, vv, k, j, i)] = q[vv];
+        }
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -68,6 +68,12 @@ def lib():
         L.oracle_step_jvp.argtypes = [dp] + mesh + [dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
         L.oracle_rollout_jvp.argtypes = [dp] + mesh + [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                                        dp, dp]
+        m3 = [ip, dp]
+        L.oracle3_step.argtypes = [dp] + m3 + [dp, ctypes.c_double, ctypes.c_double, dp]
+        L.oracle3_predictor.argtypes = [dp] + m3 + [dp, ctypes.c_double, dp, dp]
+        L.oracle3_dt.argtypes = [dp] + m3 + [dp, dp]
+        L.oracle3_run.argtypes = [dp] + m3 + [dp, dp, ctypes.c_double, ctypes.c_int]
+        L.oracle3_ic.argtypes = [dp] + m3 + [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, dp]
         _lib = L
     return _lib
 
@@ -258,3 +264,67 @@ def rollout_jvp(phys: dict, mesh: dict, theta_p: np.ndarray, dtheta=None, t0: fl
     _check(lib().oracle_rollout_jvp(_dp(p), *m.args, _dp(th), _dp(d), float(t0), float(dt), int(K), _dp(L),
                                     _dp(dL)), "rollout_jvp")
     return float(L[0]), float(dL[0])
+
+
+# ------------------------------------------------------------------------ 3D
+# mesh3: dict(nx, ny, nz, x0, y0, z0, h, bc=[-x, +x, -y, +y, -z, +z]);
+# state Q[cell][5][n][n][n] (z, y, x nodes), cells c = (k * ny + j) * nx + i.
+def _mesh3(mesh3: dict):
+    mi = np.array([mesh3["nx"], mesh3["ny"], mesh3["nz"]] + list(mesh3["bc"]), dtype=np.int32)
+    md = np.array([mesh3["x0"], mesh3["y0"], mesh3["z0"], mesh3["h"]], dtype=np.float64)
+    return mi, md
+
+
+def _cells3(mesh3):
+    return mesh3["nx"] * mesh3["ny"] * mesh3["nz"]
+
+
+def step3(phys: dict, mesh3: dict, Q: np.ndarray, t: float, dt: float) -> np.ndarray:
+    p = params(phys)
+    mi, md = _mesh3(mesh3)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    out = np.zeros_like(Q)
+    _check(lib().oracle3_step(_dp(p), _ip(mi), _dp(md), _dp(Q), float(t), float(dt), _dp(out)), "step3")
+    return out
+
+
+def predictor3(phys: dict, mesh3: dict, Q: np.ndarray, dt: float):
+    """(Q*, FD[C][6 faces][2][5][n][n])."""
+    p = params(phys)
+    mi, md = _mesh3(mesh3)
+    n = int(phys["N"]) + 1
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    Qs = np.zeros_like(Q)
+    FD = np.zeros((Q.shape[0], 6, 2, 5, n, n))
+    _check(lib().oracle3_predictor(_dp(p), _ip(mi), _dp(md), _dp(Q), float(dt), _dp(Qs), _dp(FD)), "predictor3")
+    return Qs, FD
+
+
+def dt3(phys: dict, mesh3: dict, Q: np.ndarray) -> float:
+    p = params(phys)
+    mi, md = _mesh3(mesh3)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    out = np.zeros(1)
+    _check(lib().oracle3_dt(_dp(p), _ip(mi), _dp(md), _dp(Q), _dp(out)), "dt3")
+    return float(out[0])
+
+
+def run3(phys: dict, mesh3: dict, Q: np.ndarray, t: float, nsteps: int, dt: float = 0.0):
+    p = params(phys)
+    mi, md = _mesh3(mesh3)
+    Q = np.array(Q, dtype=np.float64, copy=True, order="C")
+    tt = np.array([t], dtype=np.float64)
+    _check(lib().oracle3_run(_dp(p), _ip(mi), _dp(md), _dp(Q), _dp(tt), float(dt), int(nsteps)), "run3")
+    return Q, float(tt[0])
+
+
+def ic3(phys: dict, mesh3: dict, kind: str = "bubbles", bubbles=(), t0: float = 0.0) -> np.ndarray:
+    """kind 'bubbles' (7 numbers per bubble: shape, A, a, s, xc, yc, zc) or 'abc'."""
+    p = params(phys)
+    mi, md = _mesh3(mesh3)
+    n = int(phys["N"]) + 1
+    Q = np.zeros((_cells3(mesh3), 5, n, n, n))
+    bb = np.ascontiguousarray(np.asarray(bubbles, dtype=np.float64).reshape(-1, 7))
+    k = 1 if kind == "abc" else 0
+    _check(lib().oracle3_ic(_dp(p), _ip(mi), _dp(md), k, bb.shape[0], _dp(bb), float(t0), _dp(Q)), "ic3")
+    return Q
