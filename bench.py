@@ -291,6 +291,77 @@ def convergence_leg(T=0.05, grids=(9, 18, 36), orders=(1, 2, 3, 4, 5, 6)):
     return out
 
 
+def three_d_leg(steps=50, warmup=5):
+    """The 3D cosine bubble at the paper's resolution (the 1000 m cube on 25^3
+    cells of 40 m, N = 3, mu = 0.005, no-slip walls): DOF-updates/s of the
+    whole step, predictor and corrector times from HIP events on the launch
+    stream, the predictor against the FP64 peak; then the ABC flow (27^3
+    cells, N = 3) run to t = 0.1 with the relative L2 error of the velocity
+    against the analytic field, the paper's comparison time."""
+    import math
+    import torch
+    from paper_1905_05524_amd import adg, model
+    from paper_1905_05524_amd import inputs as I
+    w = I.bubble3d()
+    N = w["phys"]["N"]
+    m = adg.Mesh3(w["phys"], w["mesh"])
+    m.init_state("bubbles", w["bubbles"])
+    m.compute_dt()
+    s = torch.cuda.current_stream()
+    for _ in range(warmup):
+        m.step(s)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b, c in ev:
+        a.record(s)
+        m.predictor(s)
+        b.record(s)
+        m.corrector(s)
+        c.record(s)
+    torch.cuda.synchronize()
+    m.check_health(s)
+    total_ms = ev[0][0].elapsed_time(ev[-1][2])
+    pred_ms = sum(a.elapsed_time(b) for a, b, _ in ev) / steps
+    corr_ms = sum(b.elapsed_time(c) for _, b, c in ev) / steps
+    C = m.C
+    pflops = model.predictor3_flops(N) * C
+    out = {"workload": "bubble3d_25^3_N3: cosine warm bubble in the 1000 m cube, 25^3 cells of 40 m, N=3, "
+                       "mu=0.005, no-slip walls, Courant factor 0.4",
+           "cells": C, "dof": model.dofs3(C, N), "steps": steps,
+           "ms_per_step": total_ms / steps,
+           "dof_updates_per_s": model.dofs3(C, N) * steps / (total_ms / 1e3),
+           "predictor_ms": pred_ms, "corrector_ms": corr_ms,
+           "predictor_tflops": pflops / (pred_ms / 1e3) / 1e12,
+           "predictor_frac_fp64_peak": pflops / (pred_ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+           "corrector_GBps": model.corrector3_bytes(N) * C / (corr_ms / 1e3) / 1e9,
+           "sim_time_s": m.t}
+    # ABC flow to t = 0.1 against the analytic velocity (qualitative in the paper)
+    wa = I.abc3d()
+    a = adg.Mesh3(wa["phys"], wa["mesh"], fixed_dt=True)
+    a.init_state("abc")
+    a.compute_dt()
+    ns = int(math.ceil(wa["t_end"] / a.dt))
+    a.set_state(a.Q.clone(), t=0.0, dt=wa["t_end"] / ns)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(ns):
+        a.step(s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    a.check_health(s)
+    ex = adg.Mesh3(wa["phys"], wa["mesh"])
+    ex.init_state("abc", t0=wa["t_end"])
+    torch.cuda.synchronize()
+    vel = a.Q[:, 1:4] / a.Q[:, 0:1]
+    err = float(torch.sqrt(torch.sum((vel - ex.Q[:, 1:4]) ** 2) / torch.sum(ex.Q[:, 1:4] ** 2)))
+    out["abc"] = {"workload": "ABC flow, periodic [-pi,pi]^3, 27^3 cells, N=3, mu=0.01, to t=0.1",
+                  "steps": ns, "ms_per_step": e0.elapsed_time(e1) / ns,
+                  "dof_updates_per_s": model.dofs3(a.C, wa["phys"]["N"]) * ns / (e0.elapsed_time(e1) / 1e3),
+                  "rel_l2_velocity_error_vs_analytic": err}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,12 +371,13 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 10 device-to-device copies of MIB MiB (counter calibration)")
-    ap.add_argument("--leg", choices=["batched", "adaptive", "adaptive2", "adjoint", "convergence"], default=None,
+    ap.add_argument("--leg", choices=["batched", "adaptive", "adaptive2", "adjoint", "convergence", "three_d"],
+                    default=None,
                     help="only run this leg and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.leg:
         fn = {"batched": batched_leg, "adaptive": amr_leg, "adaptive2": lambda: amr_leg("amr9"),
-              "adjoint": adjoint_leg, "convergence": convergence_leg}[args.leg]
+              "adjoint": adjoint_leg, "convergence": convergence_leg, "three_d": three_d_leg}[args.leg]
         print(json.dumps({args.leg: fn()}), flush=True)
         return
     if args.copy_calibration:
@@ -410,6 +482,7 @@ def main():
         out["extra"]["adaptive_two_levels"] = amr_leg("amr9")
         out["extra"]["adjoint"] = adjoint_leg()
         out["extra"]["convergence"] = convergence_leg()
+        out["extra"]["three_d"] = three_d_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -27,6 +27,9 @@ EXPORTED = [
     "adg_batch_step_graph", "adg_batch_autotune", "adg_batch_set_launch", "adg_get_leaves",
     "adg_regrid_plan", "adg_regrid_apply", "adg_adjoint_workspace_bytes", "adg_step_adjoint",
     "adg_ic_theta", "adg_ic_theta_adjoint", "adg_loss_theta", "adg_loss_theta_adjoint",
+    "adg3_init_mesh", "adg3_destroy", "adg3_mesh_info", "adg3_workspace_bytes", "adg3_set_state",
+    "adg3_init_state", "adg3_compute_dt", "adg3_predictor", "adg3_corrector", "adg3_step",
+    "adg3_check_health",
 ]
 
 
@@ -56,6 +59,13 @@ class adg_mesh_desc(ctypes.Structure):
         ("max_level", ctypes.c_int), ("bc", ctypes.c_int * 4), ("n_leaves", ctypes.c_int),
         ("leaf_level", ctypes.POINTER(ctypes.c_int32)), ("leaf_i", ctypes.POINTER(ctypes.c_int32)),
         ("leaf_j", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+class adg3_mesh_desc(ctypes.Structure):
+    _fields_ = [
+        ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("z0", ctypes.c_double), ("h", ctypes.c_double),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("bc", ctypes.c_int * 6),
     ]
 
 
@@ -106,6 +116,14 @@ def lib():
         L.adg_ic_theta_adjoint.argtypes = [vp, vp, vp, vp, vp]
         L.adg_loss_theta.argtypes = [vp, vp, vp, vp]
         L.adg_loss_theta_adjoint.argtypes = [vp, vp, vp, vp, vp]
+        L.adg3_init_mesh.argtypes = [ctypes.POINTER(adg_params), ctypes.POINTER(adg3_mesh_desc), ctypes.POINTER(vp)]
+        L.adg3_destroy.argtypes = [vp]
+        L.adg3_mesh_info.argtypes = [vp, ip, ip]
+        L.adg3_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.adg3_set_state.argtypes = [vp, vp, vp, vp]
+        L.adg3_init_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, vp]
+        for name in ("adg3_compute_dt", "adg3_predictor", "adg3_corrector", "adg3_step", "adg3_check_health"):
+            getattr(L, name).argtypes = [vp, vp]
         _lib = L
     return _lib
 
@@ -315,6 +333,108 @@ class Mesh:
         n = self.n
         off = _align256(self.C * 4 * n * n * 8)
         return self.ws[off:off + self.C * 32 * n * 8].view(torch.float64).view(self.C, 4, 2, 4, n)
+
+    @property
+    def t(self):
+        return float(self.clock[0].item())
+
+    @property
+    def dt(self):
+        return float(self.clock[1].item())
+
+
+def make_mesh3_desc(mesh: dict) -> adg3_mesh_desc:
+    d = adg3_mesh_desc()
+    d.x0, d.y0, d.z0 = (float(mesh.get(k, 0.0)) for k in ("x0", "y0", "z0"))
+    d.h = float(mesh["h"])
+    d.nx, d.ny, d.nz = int(mesh["nx"]), int(mesh["ny"]), int(mesh["nz"])
+    for k, b in enumerate(mesh.get("bc", [ADG_BC_WALL] * 6)):
+        d.bc[k] = int(b)
+    return d
+
+
+class Mesh3:
+    """Handle of a three-dimensional uniform grid + parameters (C ABI in
+    ``include/adg3.h``); state buffers are torch tensors owned here."""
+
+    def __init__(self, phys: dict, mesh: dict, fixed_dt: bool = False, device="cuda"):
+        import torch
+        self.phys, self.mesh_desc = dict(phys), dict(mesh)
+        self._p = make_params(phys, fixed_dt)
+        self._d = make_mesh3_desc(mesh)
+        h = ctypes.c_void_p()
+        _check(lib().adg3_init_mesh(ctypes.byref(self._p), ctypes.byref(self._d), ctypes.byref(h)))
+        self.h = h
+        nc, nn = ctypes.c_int(), ctypes.c_int()
+        _check(lib().adg3_mesh_info(h, ctypes.byref(nc), ctypes.byref(nn)))
+        self.C, self.n = nc.value, nn.value
+        wb = ctypes.c_size_t()
+        _check(lib().adg3_workspace_bytes(h, ctypes.byref(wb)))
+        self.ws_bytes = wb.value
+        self.device = torch.device(device)
+        n = self.n
+        self.Q = torch.zeros((self.C, 5, n, n, n), dtype=torch.float64, device=self.device)
+        self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)
+        self.clock = torch.zeros(4, dtype=torch.float64, device=self.device)
+        _check(lib().adg3_set_state(self.h, ctypes.c_void_p(self.Q.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+                                    ctypes.c_void_p(self.clock.data_ptr())))
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().adg3_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def init_state(self, kind="bubbles", bubbles=(), t0=0.0, stream=None):
+        bb = np.ascontiguousarray(np.asarray(bubbles, dtype=np.float64).reshape(-1, 7))
+        _check(lib().adg3_init_state(self.h, 1 if kind == "abc" else 0, bb.shape[0],
+                                     bb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(t0),
+                                     _stream_ptr(stream)))
+
+    def set_state(self, Q, t=None, dt=None):
+        """Copy a state (numpy or tensor [C,5,n,n,n]) into the bound buffer."""
+        import torch
+        self.Q.copy_(torch.as_tensor(np.asarray(Q) if not torch.is_tensor(Q) else Q, dtype=torch.float64))
+        if t is not None:
+            self.clock[0] = float(t)
+        if dt is not None:
+            self.clock[1] = float(dt)
+
+    def compute_dt(self, stream=None):
+        _check(lib().adg3_compute_dt(self.h, _stream_ptr(stream)))
+
+    def predictor(self, stream=None):
+        _check(lib().adg3_predictor(self.h, _stream_ptr(stream)))
+
+    def corrector(self, stream=None):
+        _check(lib().adg3_corrector(self.h, _stream_ptr(stream)))
+
+    def step(self, stream=None):
+        _check(lib().adg3_step(self.h, _stream_ptr(stream)))
+
+    def check_health(self, stream=None):
+        _check(lib().adg3_check_health(self.h, _stream_ptr(stream)))
+
+    # -- views of the workspace (predictor outputs) --------------------------
+    def qstar(self):
+        import torch
+        n = self.n
+        return self.ws[:self.C * 5 * n ** 3 * 8].view(torch.float64).view(self.C, 5, n, n, n)
+
+    def face_data(self):
+        import torch
+        n = self.n
+        off = _align256(self.C * 5 * n ** 3 * 8)
+        return self.ws[off:off + self.C * 60 * n * n * 8].view(torch.float64).view(self.C, 6, 2, 5, n, n)
+
+    def cell_dt(self):
+        import torch
+        n = self.n
+        off = _align256(self.C * 5 * n ** 3 * 8)
+        off = _align256(off + self.C * 60 * n * n * 8)
+        return self.ws[off:off + self.C * 8].view(torch.float64)
 
     @property
     def t(self):

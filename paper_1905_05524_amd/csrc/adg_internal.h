@@ -136,6 +136,34 @@ void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
 int check_launch(const char* what);
 
+// Gauss-Legendre basis of n nodes and its device tables (computed in long
+// double, stored in double).
+void build_basis(int n, HostBasis& B);
+// parameter checks shared by the 2D and 3D handles
+int validate_params(const adg_params* p);
+Phys make_phys(const adg_params& p);
+
+template <int n>
+inline Tab<n> tab_of(const HostBasis& B) {
+  Tab<n> T;
+  for (int i = 0; i < n; ++i) {
+    T.w[i] = B.w[i]; T.e0[i] = B.e0[i]; T.e1[i] = B.e1[i];
+    for (int j = 0; j < n; ++j) {
+      T.D[i][j] = B.D[i * n + j]; T.P[i][j] = B.P[i * n + j]; T.Dw[i][j] = B.Dw[i * n + j];
+    }
+  }
+  return T;
+}
+
+// wavefront-scope barrier for LDS hand-offs between lanes of one wavefront:
+// LDS operations of a wavefront execute in order, so a compiler fence and a
+// wave barrier are enough.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------- physics
 // Hydrostatic background of constant potential temperature:
 // Exner pi = 1 - g z/(cp theta), p = p0 pi^(cp/R), rho = p/(R theta pi).

@@ -191,18 +191,6 @@ int launch_init_state(const Group& g, int c0, int count, int kind, int nbub, con
 }
 
 template <int n>
-static Tab<n> tab_of(const HostBasis& B) {
-  Tab<n> T;
-  for (int i = 0; i < n; ++i) {
-    T.w[i] = B.w[i]; T.e0[i] = B.e0[i]; T.e1[i] = B.e1[i];
-    for (int j = 0; j < n; ++j) {
-      T.D[i][j] = B.D[i * n + j]; T.P[i][j] = B.P[i * n + j]; T.Dw[i][j] = B.Dw[i * n + j];
-    }
-  }
-  return T;
-}
-
-template <int n>
 static int launch_tv_n(const Group& g, const HostBasis& B, int var, double* tv, hipStream_t s) {
   hipLaunchKernelGGL(k_tv<n>, dim3(g.C), dim3(kWave), 0, s, tab_of<n>(B), g.ph, g.Q, g.d_geom, g.d_gtab, var, tv);
   return check_launch("tv");

@@ -91,7 +91,7 @@ static long double bary_phi(const std::vector<long double>& x, const std::vector
   return num / den;
 }
 
-static void build_basis(int n, HostBasis& B) {
+void build_basis(int n, HostBasis& B) {
   B.n = n;
   std::vector<long double> x, w;
   gauss_legendre(n, x, w);
@@ -306,7 +306,7 @@ static int build_mesh(const adg_mesh_desc& d, HostMesh& H) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static int validate_params(const adg_params* p) {
+int validate_params(const adg_params* p) {
   if (!p) return fail(ADG_EINVAL, "null params");
   if (p->order < 1 || p->order > kMaxN - 1) return fail(ADG_EINVAL, "order must be in 1..7");
   if (p->picard_iters < 0) return fail(ADG_EINVAL, "picard_iters < 0");
@@ -339,7 +339,7 @@ static int validate_mesh(const adg_mesh_desc* d) {
   return ADG_OK;
 }
 
-static Phys make_phys(const adg_params& p) {
+Phys make_phys(const adg_params& p) {
   Phys ph{};
   ph.gamma = p.gamma; ph.gm1 = p.gamma - 1.0; ph.R = p.R; ph.iR = 1.0 / p.R; ph.cp = p.cp; ph.Pr = p.Pr;
   ph.mu = p.mu; ph.kappa = p.mu * p.cp / p.Pr; ph.g = p.g; ph.p0 = p.p0; ph.theta = p.theta_bg;

@@ -13,15 +13,6 @@
 
 namespace adg {
 
-// wavefront-scope barrier for LDS hand-offs between lanes of one wavefront:
-// LDS operations of a wavefront execute in order, so a compiler fence and a
-// wave barrier are enough.
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <int n>
 struct Half { static constexpr int nh = (n + 1) / 2; };
 

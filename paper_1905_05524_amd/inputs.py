@@ -18,6 +18,10 @@ Workloads follow the paper's scenarios (Krenz, Rannabauer, Bader 2019):
                     refinement levels (the paper's AMR run)
   * ``bubble27``    81x81's box on 27x27 cells (adjoint workload)
   * ``batch64``     64 random bubble scenarios (grids 9..81, N in 3..6)
+  * ``bubble3d``    3D cosine bubble in the 1000 m cube on 25^3 cells of 40 m,
+                    N=3, mu = 0.005, no-slip walls
+  * ``abc3d``       the ABC flow on the periodic cube [-pi, pi]^3, 27^3
+                    cells, N=3, mu = 0.01
 """
 from __future__ import annotations
 
@@ -176,3 +180,55 @@ def refined_leaves(nx: int, nz: int, refine):
     for (i, j) in sorted(rs, key=lambda t: (t[1], t[0])):
         out += [(1, 3 * i + a, 3 * j + b) for b in range(3) for a in range(3)]
     return out
+
+
+# ------------------------------------------------------------------------ 3D
+def cosine_bubble3(A=0.5, a=250.0, xc=500.0, yc=500.0, zc=350.0):
+    """Bubble of the 3D cosine-bubble run: (shape, A, a, s, xc, yc, zc)."""
+    return (SHAPE_COSINE, A, a, 0.0, xc, yc, zc)
+
+
+def mesh3(n: int, L: float, x0: float = 0.0, bc: int = BC_WALL, ny: int = None):
+    """n x ny x n cubes of edge L / n with lower corner (x0, x0, x0)."""
+    return dict(nx=n, ny=n if ny is None else ny, nz=n, x0=x0, y0=x0, z0=x0, h=L / n, bc=[bc] * 6)
+
+
+def bubble3d(n: int = 25, N: int = 3, mu: float = 0.005, steps: int = 50):
+    """3D cosine bubble (stratified-flow section): the 1000 m cube with
+    no-slip walls on n^3 cells (n = 25: 40 m cells), order N = 3, mu = 0.005,
+    bubble A = 0.5 K, a = 250 m at (500, 500, 350) m."""
+    phys = dict(ATMO, N=N, picard_iters=0, mu=mu, mms=0, cfl=BUBBLE_CFL)
+    return dict(name=f"bubble3d_{n}^3_N{N}", phys=phys, mesh=mesh3(n, 1000.0), ic="bubbles",
+                bubbles=[cosine_bubble3()], steps=steps)
+
+
+def abc3d(n: int = 27, N: int = 3, mu: float = 0.01):
+    """ABC flow (CFD section): periodic cube [-pi, pi]^3 on n^3 cells, order
+    N = 3, mu = 0.01, CFD gas constants; the paper compares at t = 0.1."""
+    phys = dict(CFD, N=N, picard_iters=0, mu=mu, mms=0, cfl=0.5)
+    return dict(name=f"abc3d_{n}^3_N{N}", phys=phys, mesh=mesh3(n, 2.0 * math.pi, x0=-math.pi, bc=BC_PERIODIC),
+                ic="abc", bubbles=[], t_end=0.1)
+
+
+def random_state_cfd3(C: int, N: int, seed: int):
+    """Random 3D conserved state in CFD units with a safely positive
+    pressure: rho in [0.8,1.2], momenta in [-0.3,0.3], energy in [2.2,2.8]."""
+    rng = np.random.default_rng(seed)
+    n = N + 1
+    Q = np.empty((C, 5, n, n, n))
+    Q[:, 0] = 1.0 + 0.2 * rng.uniform(-1, 1, (C, n, n, n))
+    Q[:, 1:4] = 0.3 * rng.uniform(-1, 1, (C, 3, n, n, n))
+    Q[:, 4] = 2.5 + 0.3 * rng.uniform(-1, 1, (C, n, n, n))
+    return Q
+
+
+def perturb3(Q: np.ndarray, seed: int, rel: float = 1e-3, vel: float = 0.5):
+    """Seeded noise on a 3D state: relative noise `rel` on density and
+    energy, momentum noise of `vel` times the local density."""
+    rng = np.random.default_rng(seed)
+    P = np.array(Q, dtype=np.float64, copy=True)
+    P[:, 0] *= 1.0 + rel * rng.uniform(-1, 1, P[:, 0].shape)
+    P[:, 4] *= 1.0 + rel * rng.uniform(-1, 1, P[:, 4].shape)
+    for v in (1, 2, 3):
+        P[:, v] += vel * Q[:, 0] * rng.uniform(-1, 1, P[:, v].shape)
+    return P

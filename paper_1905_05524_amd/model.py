@@ -76,3 +76,45 @@ def tv_bytes(N: int) -> int:
 
 def dofs(cells: int, N: int) -> int:
     return cells * (N + 1) ** 2 * 4
+
+
+# ------------------------------------------------------------------------ 3D
+# Three-dimensional step (n^3 nodes, 5 variables), same conventions:
+# predictor, per sweep and time slice:
+#     gradients   3 dirs * 5 vars * n^3 outputs * n MACs     = 30 n^4
+#     pointwise   flux + source (FLUX3_FLOPS), residual scaling 6
+#     divergence  30 n^4
+#   per sweep: n * (60 n^4 + (FLUX3_FLOPS + 6) n^3) + 10 n^5 + 5 n^3
+#     (time matrix: 5 vars * n targets * n slices MACs per node, plus Q)
+#   final pass: n * (30 n^4 + (FLUX3_FLOPS + 42) n^3)   (42: 21 averages)
+#   epilogue:   30 n^4 (volume term) + 15 n^3 (Q*) + 120 n^3 (60 n^2 face
+#               values of n MACs)
+# Bytes: predictor reads Q (5 n^3), writes Q* (5 n^3) and the face data
+# (60 n^2); corrector reads Q* (5 n^3), its own and the neighbours' face
+# data (120 n^2), writes Q (5 n^3) and one CFL candidate.
+
+FLUX3_FLOPS = 180   # counted operation by operation in the 3D flux/source function
+
+
+def predictor3_flops(N: int, iters: int = 0) -> int:
+    n = N + 1
+    I = iters or n
+    c = FLUX3_FLOPS
+    sweep = n * (60 * n ** 4 + (c + 6) * n ** 3) + 10 * n ** 5 + 5 * n ** 3
+    final = n * (30 * n ** 4 + (c + 42) * n ** 3)
+    epi = 30 * n ** 4 + 135 * n ** 3
+    return I * sweep + final + epi
+
+
+def predictor3_bytes(N: int) -> int:
+    n = N + 1
+    return 8 * (10 * n ** 3 + 60 * n * n)
+
+
+def corrector3_bytes(N: int) -> int:
+    n = N + 1
+    return 8 * (10 * n ** 3 + 120 * n * n + 1)
+
+
+def dofs3(cells: int, N: int) -> int:
+    return cells * (N + 1) ** 3 * 5

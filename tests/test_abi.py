@@ -13,9 +13,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_functions():
-    src = open(os.path.join(ROOT, "include", "adg.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(adg_[a-z_]+)\s*\(", src)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(adg3?_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -66,3 +70,45 @@ def test_null_arguments_rejected():
     assert L.adg_step(None, None) == adg.ADG_EINVAL
     assert L.adg_destroy(None) == adg.ADG_EINVAL
     assert L.adg_set_state(None, None, None, None) == adg.ADG_EINVAL
+
+
+def _init3(phys, mesh):
+    p = adg.make_params(phys)
+    d = adg.make_mesh3_desc(mesh)
+    h = ctypes.c_void_p()
+    rc = adg.lib().adg3_init_mesh(ctypes.byref(p), ctypes.byref(d), ctypes.byref(h))
+    return rc, adg.lib().adg_last_error().decode()
+
+
+@pytest.mark.parametrize("change,msg", [
+    (dict(N=0), "order"), (dict(N=6), "order"), (dict(gamma=1.0), "gas"), (dict(cfl=0.0), "cfl"),
+])
+def test_invalid_params_rejected_3d(change, msg):
+    w = I.bubble3d()
+    rc, err = _init3(dict(w["phys"], **change), w["mesh"])
+    assert rc == adg.ADG_EINVAL and msg in err
+
+
+def test_manufactured_source_unsupported_in_3d():
+    w = I.bubble3d()
+    rc, err = _init3(dict(w["phys"], mms=1), w["mesh"])
+    assert rc == adg.ADG_EUNSUPPORTED and "two-dimensional" in err
+
+
+@pytest.mark.parametrize("change,msg", [
+    (dict(nx=0), "domain"), (dict(h=0.0), "domain"), (dict(h=float("nan")), "domain"),
+    (dict(bc=[0, 1, 1, 1, 1, 1]), "pairs"), (dict(bc=[1, 1, 1, 1, 1, 7]), "bc"),
+    (dict(nx=1024, ny=1024, nz=64), "too many"),
+])
+def test_invalid_mesh_rejected_3d(change, msg):
+    w = I.bubble3d()
+    rc, err = _init3(w["phys"], dict(w["mesh"], **change))
+    assert rc == adg.ADG_EINVAL and msg in err
+
+
+def test_null_arguments_rejected_3d():
+    L = adg.lib()
+    assert L.adg3_step(None, None) == adg.ADG_EINVAL
+    assert L.adg3_destroy(None) == adg.ADG_EINVAL
+    assert L.adg3_set_state(None, None, None, None) == adg.ADG_EINVAL
+    assert L.adg3_init_mesh(None, None, None) == adg.ADG_EINVAL
