@@ -9,7 +9,8 @@
 // one wavefront and the LDS hand-offs between its nodes need only a
 // wavefront barrier; otherwise cells straddle wavefronts and the workgroup
 // synchronises.  Threads past CB * nd (when nd does not divide the
-// workgroup) follow the barriers, read slot 0 and write nothing.  Tensor-product contractions along x, y and z read n values of an
+// workgroup) mirror the threads of slot 0: same cell, same node, hence the
+// same values written to the same LDS addresses, and no global stores.  Tensor-product contractions along x, y and z read n values of an
 // LDS slice per output; the space-time iterate of a node (n time levels x 5
 // variables) stays in registers.
 #include "adg3_internal.h"
@@ -167,6 +168,27 @@ __device__ inline double div3(const double* sF, int v, int i, int j, int k, cons
   return s;
 }
 
+// Face data FD[f][kind][v][s][t] of one cell from its averaged state sq
+// ([5][nd]) and fluxes sF ([3][5][nd]) in LDS: kind 0 the state, 1 the normal
+// flux, extrapolated along the face normal with the boundary values of the
+// basis.  The cell's nd threads (r = node index) share the 60 n^2 outputs.
+template <int n>
+__device__ inline void face_data3(const Tab<n>& tb, const double* sq, const double* sF, double* FDc, int r) {
+  constexpr int nn = n * n, nd = nn * n;
+  for (int o = r; o < 60 * nn; o += nd) {
+    const int f = o / (10 * nn), rem = o - f * 10 * nn;
+    const int kind = rem / (5 * nn), v = (rem / nn) % 5, st = rem % nn, s = st / n, t = st % n;
+    const int d = f >> 1;
+    const double* src = kind ? sF + (d * 5 + v) * nd : sq + v * nd;
+    const int base = d == 0 ? (s * n + t) * n : (d == 1 ? s * nn + t : s * n + t);
+    const int stride = d == 0 ? 1 : (d == 1 ? n : nn);
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < n; ++m) acc = fma((f & 1) ? tb.e1[m] : tb.e0[m], src[base + m * stride], acc);
+    FDc[o] = acc;
+  }
+}
+
 // Space-time predictor (Section 3): Picard sweeps
 //   X_a = Q + dt sum_b P_ab R(X_b),  R = S - div F,  P = K1^{-1} W,
 // from X_a = Q, then the time averages of state, flux and source, the update
@@ -178,12 +200,13 @@ __global__ __launch_bounds__(kThreads3) void k_pred3(Phys ph, Tab<n> tb, Args3 a
   constexpr int nn = G::nn, nd = G::nd;
   constexpr bool WL = G::WL;
   extern __shared__ double lds[];
-  const int tid = threadIdx.x, slot = tid / nd, r = tid - slot * nd;
-  const bool inslot = !G::spare || slot < G::CB;
+  const int tid = threadIdx.x, r = tid % nd;
+  const bool mirror = G::spare && tid >= G::CB * nd;
+  const int slot = mirror ? 0 : tid / nd;
   const int cell = blockIdx.x * G::CB + slot;
-  const bool valid = inslot && cell < a.C;
-  const int c = valid ? cell : a.C - 1;   // loads stay in bounds; nothing is stored for such threads
-  double* sq = lds + (inslot ? slot : 0) * G::pred_slot;
+  const bool valid = !mirror && cell < a.C;
+  const int c = cell < a.C ? cell : a.C - 1;   // loads stay in bounds; only valid threads store
+  double* sq = lds + slot * G::pred_slot;
   double* sF = sq + 5 * nd;
   const int i = r % n, j = (r / n) % n, k = r / nn;
   const double h = a.h;
@@ -212,17 +235,15 @@ __global__ __launch_bounds__(kThreads3) void k_pred3(Phys ph, Tab<n> tb, Args3 a
   for (int it = 0; it < a.iters; ++it) {
 #pragma unroll
     for (int b = 0; b < n; ++b) {
-      if (inslot)
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sq[v * nd + r] = X[b][v];
+      for (int v = 0; v < 5; ++v) sq[v * nd + r] = X[b][v];
       sync3<WL>();
       double F[3][5], Sw;
       grad_flux3<n>(ph, sq, i, j, k, Di, Dj, Dk, X[b], z, rb, pb, mu_h, kappa_h, gh, F, Sw);
-      if (inslot)
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
+      for (int d = 0; d < 3; ++d)
 #pragma unroll
-          for (int v = 0; v < 5; ++v) sF[(d * 5 + v) * nd + r] = F[d][v];
+        for (int v = 0; v < 5; ++v) sF[(d * 5 + v) * nd + r] = F[d][v];
       sync3<WL>();
 #pragma unroll
       for (int v = 0; v < 5; ++v) R[b][v] = sdt * div3<n>(sF, v, i, j, k, Di, Dj, Dk);
@@ -251,9 +272,8 @@ __global__ __launch_bounds__(kThreads3) void k_pred3(Phys ph, Tab<n> tb, Args3 a
 #pragma unroll
   for (int b = 0; b < n; ++b) {
     double* buf = (b & 1) ? sF : sq;
-    if (inslot)
 #pragma unroll
-      for (int v = 0; v < 5; ++v) buf[v * nd + r] = X[b][v];
+    for (int v = 0; v < 5; ++v) buf[v * nd + r] = X[b][v];
     sync3<WL>();
     double F[3][5], Sw;
     grad_flux3<n>(ph, buf, i, j, k, Di, Dj, Dk, X[b], z, rb, pb, mu_h, kappa_h, gh, F, Sw);
@@ -267,13 +287,12 @@ __global__ __launch_bounds__(kThreads3) void k_pred3(Phys ph, Tab<n> tb, Args3 a
     Sb = fma(w, Sw, Sb);
   }
   sync3<WL>();
-  if (inslot)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      sq[v * nd + r] = Qb[v];
+  for (int v = 0; v < 5; ++v) {
+    sq[v * nd + r] = Qb[v];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) sF[(d * 5 + v) * nd + r] = Fb[d][v];
-    }
+    for (int d = 0; d < 3; ++d) sF[(d * 5 + v) * nd + r] = Fb[d][v];
+  }
   sync3<WL>();
 
   // volume term (Dw[i][m] = w_m D[m][i] / w_i along each direction) and Q*
@@ -292,22 +311,209 @@ __global__ __launch_bounds__(kThreads3) void k_pred3(Phys ph, Tab<n> tb, Args3 a
       const double vol = div3<n>(sF, v, i, j, k, Wi, Wj, Wk);
       Qsc[v * nd + r] = Q0[v] + dt * (vol * ih + (v == 3 ? Sb : 0.0));
     }
-    // face data FD[f][kind][v][s][t]: kind 0 the state, 1 the normal flux,
-    // extrapolated along the face normal with the boundary values of the basis
-    double* FDc = a.FD + (size_t)c * 60 * nn;
-    for (int o = r; o < 60 * nn; o += nd) {
-      const int f = o / (10 * nn), rem = o - f * 10 * nn;
-      const int kind = rem / (5 * nn), v = (rem / nn) % 5, st = rem % nn, s = st / n, t = st % n;
-      const int d = f >> 1;
-      const double* src = kind ? sF + (d * 5 + v) * nd : sq + v * nd;
-      const int base = d == 0 ? (s * n + t) * n : (d == 1 ? s * nn + t : s * n + t);
-      const int stride = d == 0 ? 1 : (d == 1 ? n : nn);
-      double acc = 0.0;
+    face_data3<n>(tb, sq, sF, a.FD + (size_t)c * 60 * nn, r);
+  }
+}
+
+// ------------------------------------------------ predictor, n = 4 (N = 3)
+// One cell per wavefront, lane l = 16 k + 4 j + i.  The contractions along x
+// and y run on the lanes of a quad (x) and of a 16-lane row (y) through the
+// DPP network: rotation r brings each lane the value of the node r steps
+// further along the line, multiplied by the matching entry of the lane's
+// derivative-matrix row.  Only the z contractions go through LDS (one slice
+// of 5 variables, read 4 values per output), so an LDS round trip per time
+// level moves 10 writes and 40 reads per lane instead of 20 and 120.
+
+// lane exchange of a double through the DPP network (two 32-bit moves; every
+// lane of a quad or row has a source, so no lane keeps an old value)
+template <int ctrl>
+__device__ inline double dpp_d(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), ctrl, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), ctrl, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+// quad_perm control word: lane i of every quad reads lane (i + r) & 3
+template <int r>
+constexpr int quad_rot() {
+  return ((0 + r) & 3) | (((1 + r) & 3) << 2) | (((2 + r) & 3) << 4) | (((3 + r) & 3) << 6);
+}
+constexpr int kRowRor = 0x120;   // row_ror:s control word base (rotation by s lanes within a row of 16)
+
+// sum_r c[r] x(node r steps along x), the r = 0 term the lane's own value
+__device__ inline double cx4(const double c[4], double x) {
+  double s = c[0] * x;
+  s = fma(c[1], dpp_d<quad_rot<1>()>(x), s);
+  s = fma(c[2], dpp_d<quad_rot<2>()>(x), s);
+  s = fma(c[3], dpp_d<quad_rot<3>()>(x), s);
+  return s;
+}
+// the same along y (rows of 16 lanes hold the 4 x 4 nodes of one z level)
+__device__ inline double cy4(const double c[4], double x) {
+  double s = c[0] * x;
+  s = fma(c[1], dpp_d<kRowRor + 4>(x), s);
+  s = fma(c[2], dpp_d<kRowRor + 8>(x), s);
+  s = fma(c[3], dpp_d<kRowRor + 12>(x), s);
+  return s;
+}
+// z contraction of a [nd] LDS slice at node (j, i) = l & 15
+__device__ inline double cz4(const double c[4], const double* s, int ji) {
+  double acc = c[0] * s[ji];
+  acc = fma(c[1], s[16 + ji], acc);
+  acc = fma(c[2], s[32 + ji], acc);
+  acc = fma(c[3], s[48 + ji], acc);
+  return acc;
+}
+
+// rows of a node-indexed matrix table T (n = 4) matched to the lane
+// exchanges: cx[r] = T[i][i'] and cy[r] = T[j][j'] with i', j' the node
+// indices that rotation r delivers (found by sending the indices themselves
+// through the same exchange), cz[m] = T[k][m]
+__device__ inline void rot_rows4(const double* T, int i, int j, int k, double cx[4], double cy[4], double cz[4]) {
+  const int pi1 = __builtin_amdgcn_mov_dpp(i, quad_rot<1>(), 0xF, 0xF, true);
+  const int pi2 = __builtin_amdgcn_mov_dpp(i, quad_rot<2>(), 0xF, 0xF, true);
+  const int pi3 = __builtin_amdgcn_mov_dpp(i, quad_rot<3>(), 0xF, 0xF, true);
+  const int pj1 = __builtin_amdgcn_mov_dpp(j, kRowRor + 4, 0xF, 0xF, true);
+  const int pj2 = __builtin_amdgcn_mov_dpp(j, kRowRor + 8, 0xF, 0xF, true);
+  const int pj3 = __builtin_amdgcn_mov_dpp(j, kRowRor + 12, 0xF, 0xF, true);
+  cx[0] = T[i * 4 + i]; cx[1] = T[i * 4 + pi1]; cx[2] = T[i * 4 + pi2]; cx[3] = T[i * 4 + pi3];
+  cy[0] = T[j * 4 + j]; cy[1] = T[j * 4 + pj1]; cy[2] = T[j * 4 + pj2]; cy[3] = T[j * 4 + pj3];
 #pragma unroll
-      for (int m = 0; m < n; ++m) acc = fma((f & 1) ? tb.e1[m] : tb.e0[m], src[base + m * stride], acc);
-      FDc[o] = acc;
+  for (int m = 0; m < 4; ++m) cz[m] = T[k * 4 + m];
+}
+
+__global__ __launch_bounds__(kThreads3, 3) void k_pred3_w64(Phys ph, Tab<4> tb, Args3 a) {
+  constexpr int n = 4, nd = 64;
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x, slot = tid >> 6, r = tid & 63;
+  const int cell = blockIdx.x * (kThreads3 / kWave) + slot;
+  const bool valid = cell < a.C;
+  const int c = valid ? cell : a.C - 1;   // loads stay in bounds; nothing is stored for such lanes
+  double* sq = lds + slot * 20 * nd;      // state slice [5][nd]; the averaged state in the epilogue
+  double* sF = sq + 5 * nd;               // z fluxes [5][nd]; all averaged fluxes [3][5][nd] in the epilogue
+  const int i = r & 3, j = (r >> 2) & 3, k = r >> 4, ji = r & 15;
+  const double h = a.h;
+  const int ck = c / (a.nx * a.ny);
+  const double z = (a.z0 + ck * h) + h * a.gtab[GTab::XI * n + k];
+  double rb, pb;
+  background(ph, z, rb, pb);
+  const double mu_h = ph.mu / h, kappa_h = ph.kappa / h, gh = ph.geff * h;
+  const double dt = a.clock[1], sdt = -dt / h;
+  double Cx[4], Cy[4], Cz[4];
+  rot_rows4(a.gtab + GTab::d(n), i, j, k, Cx, Cy, Cz);
+  const double* Qc = a.Q + (size_t)c * 5 * nd;
+  double Q0[5], X[n][5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) Q0[v] = Qc[v * nd + r];
+#pragma unroll
+  for (int b = 0; b < n; ++b)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) X[b][v] = Q0[v];
+
+  auto grad_flux = [&](const double q[5], double F[3][5], double& Sw) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sq[v * nd + r] = q[v];
+    wave_sync();
+    double g[3][5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      g[0][v] = cx4(Cx, q[v]);
+      g[1][v] = cy4(Cy, q[v]);
+      g[2][v] = cz4(Cz, sq + v * nd, ji);
+    }
+    flux_source3(ph, q, g, z, rb, pb, mu_h, kappa_h, gh, F, Sw);
+  };
+
+  for (int it = 0; it < a.iters; ++it) {
+#pragma unroll
+    for (int b = 0; b < n; ++b) {
+      double F[3][5], Sw;
+      grad_flux(X[b], F, Sw);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sF[v * nd + r] = F[2][v];
+      wave_sync();
+      // the residual of time level b (times dt) replaces its iterate
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        X[b][v] = sdt * (cx4(Cx, F[0][v]) + cy4(Cy, F[1][v]) + cz4(Cz, sF + v * nd, ji));
+      X[b][3] = fma(dt, Sw, X[b][3]);
+      wave_sync();
+    }
+    // X <- Q + K1^{-1} W X: in-place solve with the unpivoted LU factors
+    const double* lu = a.gtab + GTab::lu(n);
+    int o = 0;
+#pragma unroll
+    for (int ii = 0; ii < n; ++ii) {
+      const double wi = lu[o++];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) X[ii][v] *= wi;
+#pragma unroll
+      for (int jj = 0; jj < ii; ++jj) {
+        const double l = lu[o++];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) X[ii][v] = fma(-l, X[jj][v], X[ii][v]);
+      }
+    }
+#pragma unroll
+    for (int ii = n - 1; ii >= 0; --ii) {
+      const double iu = lu[o++];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) X[ii][v] *= iu;
+#pragma unroll
+      for (int jj = ii + 1; jj < n; ++jj) {
+        const double u = lu[o++];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) X[ii][v] = fma(-u, X[jj][v], X[ii][v]);
+      }
+    }
+#pragma unroll
+    for (int a2 = 0; a2 < n; ++a2)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) X[a2][v] += Q0[v];
+  }
+
+  // time averages
+  double Qb[5], Fb[3][5], Sb = 0.0;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    Qb[v] = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) Fb[d][v] = 0.0;
+  }
+#pragma unroll
+  for (int b = 0; b < n; ++b) {
+    double F[3][5], Sw;
+    grad_flux(X[b], F, Sw);
+    const double w = tb.w[b];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      Qb[v] = fma(w, X[b][v], Qb[v]);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) Fb[d][v] = fma(w, F[d][v], Fb[d][v]);
+    }
+    Sb = fma(w, Sw, Sb);
+    wave_sync();
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    sq[v * nd + r] = Qb[v];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) sF[(d * 5 + v) * nd + r] = Fb[d][v];
+  }
+  wave_sync();
+
+  // volume term with the weighted transposed derivative matrix, and Q*
+  double Wx[4], Wy[4], Wz[4];
+  rot_rows4(a.gtab + GTab::dw(n), i, j, k, Wx, Wy, Wz);
+  const double ih = 1.0 / h;
+  if (valid) {
+    double* Qsc = a.Qs + (size_t)c * 5 * nd;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double vol = cx4(Wx, Fb[0][v]) + cy4(Wy, Fb[1][v]) + cz4(Wz, sF + (10 + v) * nd, ji);
+      Qsc[v * nd + r] = Q0[v] + dt * (vol * ih + (v == 3 ? Sb : 0.0));
     }
   }
+  if (valid) face_data3<n>(tb, sq, sF, a.FD + (size_t)c * 60 * 16, r);
 }
 
 // ---------------------------------------------------------------- corrector
@@ -322,19 +528,20 @@ __global__ __launch_bounds__(kThreads3) void k_corr3(Phys ph, Args3 a) {
   constexpr int nn = G::nn, nd = G::nd, NJ = 6 * nn, IT = (NJ + nd - 1) / nd;
   constexpr bool WL = G::WL;
   extern __shared__ double lds[];
-  const int tid = threadIdx.x, slot = tid / nd, r = tid - slot * nd;
-  const bool inslot = !G::spare || slot < G::CB;
+  const int tid = threadIdx.x, r = tid % nd;
+  const bool mirror = G::spare && tid >= G::CB * nd;
+  const int slot = mirror ? 0 : tid / nd;
   const int cell = blockIdx.x * G::CB + slot;
-  const bool valid = inslot && cell < a.C;
-  const int c = valid ? cell : a.C - 1;
-  double* sG = lds + (inslot ? slot : 0) * G::corr_slot;
+  const bool valid = !mirror && cell < a.C;
+  const int c = cell < a.C ? cell : a.C - 1;
+  double* sG = lds + slot * G::corr_slot;
   double* sl = sG + 30 * nn;
   double* sv = sl + 6 * nn;
   unsigned long long* smax = reinterpret_cast<unsigned long long*>(sv + 6 * nn);
   const int ci = c % a.nx, cj = (c / a.nx) % a.ny, ck = c / (a.nx * a.ny);
   const double h = a.h, dt = a.clock[1];
   const double zc = a.z0 + ck * h;
-  if (inslot && r == 0) { smax[0] = 0ull; smax[1] = 0ull; }
+  if (r == 0) { smax[0] = 0ull; smax[1] = 0ull; }
 
   double qL[IT][5], qR[IT][5], fL[IT][5], fR[IT][5];
 #pragma unroll
@@ -372,13 +579,13 @@ __global__ __launch_bounds__(kThreads3) void k_corr3(Phys ph, Args3 a) {
     double l1, v1, l2, v2;
     eig3(ph, d, qL[it], zf, l1, v1);
     eig3(ph, d, qR[it], zf, l2, v2);
-    if (act && inslot) { sl[q] = fmax(l1, l2); sv[q] = fmax(v1, v2); }
+    if (act) { sl[q] = fmax(l1, l2); sv[q] = fmax(v1, v2); }
   }
   sync3<WL>();
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int q = r + it * nd;
-    if (q < NJ && inslot) {
+    if (q < NJ) {
       const int f = q / nn, st = q - f * nn;
       double lm = sl[f * nn], vm = sv[f * nn];
       for (int m = 1; m < nn; ++m) { lm = fmax(lm, sl[f * nn + m]); vm = fmax(vm, sv[f * nn + m]); }
@@ -523,7 +730,10 @@ static int pred3_n(const Phys& ph, const HostBasis& B, const Args3& a, hipStream
   using G = Cfg3<n>;
   const int blocks = (a.C + G::CB - 1) / G::CB;
   const size_t lds = sizeof(double) * (size_t)G::CB * G::pred_slot;
-  hipLaunchKernelGGL(k_pred3<n>, dim3(blocks), dim3(kThreads3), lds, s, ph, tab_of<n>(B), a);
+  if constexpr (n == 4)
+    hipLaunchKernelGGL(k_pred3_w64, dim3(blocks), dim3(kThreads3), lds, s, ph, tab_of<n>(B), a);
+  else
+    hipLaunchKernelGGL(k_pred3<n>, dim3(blocks), dim3(kThreads3), lds, s, ph, tab_of<n>(B), a);
   return check_launch("predictor3");
 }
 template <int n>
