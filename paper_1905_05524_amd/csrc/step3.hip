@@ -471,14 +471,11 @@ __global__ __launch_bounds__(kThreads3, 3) void k_pred3_w64(Phys ph, Tab<4> tb, 
       for (int v = 0; v < 5; ++v) X[a2][v] += Q0[v];
   }
 
-  // time averages
-  double Qb[5], Fb[3][5], Sb = 0.0;
+  // time averages; the averaged fluxes accumulate in the lane's own LDS
+  // words [3][5][nd] (registers are short here), the state in registers
+  double Qb[5], Sb = 0.0;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    Qb[v] = 0.0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) Fb[d][v] = 0.0;
-  }
+  for (int v = 0; v < 5; ++v) Qb[v] = 0.0;
 #pragma unroll
   for (int b = 0; b < n; ++b) {
     double F[3][5], Sw;
@@ -488,32 +485,38 @@ __global__ __launch_bounds__(kThreads3, 3) void k_pred3_w64(Phys ph, Tab<4> tb, 
     for (int v = 0; v < 5; ++v) {
       Qb[v] = fma(w, X[b][v], Qb[v]);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) Fb[d][v] = fma(w, F[d][v], Fb[d][v]);
+      for (int d = 0; d < 3; ++d) {
+        double* acc = sF + (d * 5 + v) * nd + r;
+        *acc = b == 0 ? w * F[d][v] : fma(w, F[d][v], *acc);
+      }
     }
     Sb = fma(w, Sw, Sb);
     wave_sync();
   }
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    sq[v * nd + r] = Qb[v];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) sF[(d * 5 + v) * nd + r] = Fb[d][v];
-  }
+  for (int v = 0; v < 5; ++v) sq[v * nd + r] = Qb[v];
   wave_sync();
 
+  // Lane indices and cell again from the thread id: kept live across the
+  // sweeps they would occupy registers that the sweeps need (and spill).
+  int t2 = threadIdx.x;
+  asm volatile("" : "+v"(t2));
+  const int r2 = t2 & 63, i2 = r2 & 3, j2 = (r2 >> 2) & 3, k2 = r2 >> 4;
+  const int cell2 = blockIdx.x * (kThreads3 / kWave) + (t2 >> 6);
   // volume term with the weighted transposed derivative matrix, and Q*
   double Wx[4], Wy[4], Wz[4];
-  rot_rows4(a.gtab + GTab::dw(n), i, j, k, Wx, Wy, Wz);
+  rot_rows4(a.gtab + GTab::dw(n), i2, j2, k2, Wx, Wy, Wz);
   const double ih = 1.0 / h;
-  if (valid) {
-    double* Qsc = a.Qs + (size_t)c * 5 * nd;
+  if (cell2 < a.C) {
+    double* Qsc = a.Qs + (size_t)cell2 * 5 * nd;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      const double vol = cx4(Wx, Fb[0][v]) + cy4(Wy, Fb[1][v]) + cz4(Wz, sF + (10 + v) * nd, ji);
-      Qsc[v * nd + r] = Q0[v] + dt * (vol * ih + (v == 3 ? Sb : 0.0));
+      const double vol = cx4(Wx, sF[v * nd + r2]) + cy4(Wy, sF[(5 + v) * nd + r2]) +
+                         cz4(Wz, sF + (10 + v) * nd, r2 & 15);
+      Qsc[v * nd + r2] = Q0[v] + dt * (vol * ih + (v == 3 ? Sb : 0.0));
     }
+    face_data3<n>(tb, sq, sF, a.FD + (size_t)cell2 * 60 * 16, r2);
   }
-  if (valid) face_data3<n>(tb, sq, sF, a.FD + (size_t)c * 60 * 16, r);
 }
 
 // ---------------------------------------------------------------- corrector
