@@ -1657,3 +1657,249 @@ int oracle3_ic(const double* prm, const int* mi, const double* md, int kind, int
 }
 
 }  // extern "C"
+
+// ============================================================ finite volume
+// The engine's second scheme (Numerics): MUSCL-Hancock finite volumes
+// stabilised with the van Albada limiter, run without viscosity for the
+// colliding bubbles (stratified-flow section).  Uniform grid of nx x nz
+// square cells of edge h, one value per cell, Q[c][4], c = j * nx + i, the
+// value standing for the cell centre.  The pointwise physics, the Rusanov
+// flux and the wall ghost are those of the DG scheme at one node (N = 0,
+// mu = 0).  One step:
+//   1. slopes of the conserved variables per direction, limited with van
+//      Albada (at a wall, the neighbour is the wall ghost state at the ghost
+//      cell's centre);
+//   2. Hancock half step: the four face values Q -+ slope/2 all move by
+//      dt/(2h) times the flux differences across the cell (each flux at its
+//      face height) plus dt/2 times the source of the cell value;
+//   3. Rusanov flux of the evolved face values of the two cells of a face
+//      (the wall ghost of the evolved value at a wall);
+//   4. Q <- Q - dt/h (flux differences) + dt * source of the half-step cell
+//      value (Q plus the half-step increment).
+// Time step: the Courant rule of the DG scheme at N = 0 without viscosity,
+// dt = cfl h / (2 lambda), lambda = max over cells of max(|u|,|w|) + c.
+namespace {
+
+struct FVMesh {
+  int nx, nz, bc[4];   // bc: west, east, south, north
+  double x0, z0, h;
+  int C() const { return nx * nz; }
+};
+
+FVMesh read_fv_mesh(const int* mi, const double* md) {
+  FVMesh M;
+  M.nx = mi[0]; M.nz = mi[1];
+  for (int f = 0; f < 4; ++f) M.bc[f] = mi[2 + f];
+  M.x0 = md[0]; M.z0 = md[1]; M.h = md[2];
+  return M;
+}
+
+// the parameters of the scheme at one node without viscosity
+Params fv_params(const double* prm) {
+  Params P = read_params(prm);
+  P.N = 0; P.n = 1; P.iters = 1;
+  P.mu = 0.0; P.kappa = 0.0; P.mms = false;
+  return P;
+}
+
+// van Albada limited slope from the backward and forward differences a, b:
+// a b (a + b) / (a^2 + b^2) when a b > 0, else 0; that is b phi(a / b) with
+// phi(r) = (r^2 + r) / (r^2 + 1) on r > 0.
+double van_albada(double a, double b) {
+  if (!(a * b > 0.0)) return 0.0;
+  return a * b * (a + b) / (a * a + b * b);
+}
+
+// inviscid flux along d (0: x, 1: z) and the vertical-momentum source at height z
+void fv_flux(const Params& P, const double q[4], double z, int d, double F[4], double* Sw) {
+  double rb, pb;
+  background(P, z, rb, pb);
+  const double zero[4] = {0.0, 0.0, 0.0, 0.0};
+  double Fx[4], Fz[4], S[4];
+  pointwise<double>(P, q, zero, zero, 0.0, z, 0.0, rb, pb, Fx, Fz, S);
+  for (int v = 0; v < 4; ++v) F[v] = d == 0 ? Fx[v] : Fz[v];
+  if (Sw) *Sw = S[2];
+}
+
+// ghost state at a wall for a state q at height z (the DG wall ghost)
+void fv_ghost_state(const Params& P, int d, const double q[4], double z, double g[4]) {
+  double F0[4] = {0.0, 0.0, 0.0, 0.0}, Fg[4];
+  wall_ghost<double>(P, d, &z, q, F0, g, Fg);
+}
+
+double fv_zc(const FVMesh& M, int j) { return M.z0 + (j + 0.5) * M.h; }
+
+// Hancock half step of every cell: evolved face values E[c][4 faces][4]
+// (faces: west, east, south, north) and the half-step increment inc[c][4].
+void fv_predict(const Params& P, const FVMesh& M, const double* Q, double dt, double* E, double* inc) {
+  const double h = M.h;
+  for (int j = 0; j < M.nz; ++j)
+    for (int i = 0; i < M.nx; ++i) {
+      const int c = j * M.nx + i;
+      const double* q = Q + 4 * c;
+      const double zc = fv_zc(M, j);
+      double slope[2][4];
+      for (int d = 0; d < 2; ++d) {
+        double lo[4], hi[4];
+        for (int side = 0; side < 2; ++side) {
+          double* nb = side ? hi : lo;
+          const int f = 2 * d + side;
+          int ni = i + (d == 0 ? (side ? 1 : -1) : 0), nj = j + (d == 1 ? (side ? 1 : -1) : 0);
+          const bool out = ni < 0 || ni >= M.nx || nj < 0 || nj >= M.nz;
+          if (out && M.bc[f] == BC_WALL) {
+            // ghost cell centre: mirror of the cell centre across the face
+            const double zg = d == 1 ? zc + (side ? h : -h) : zc;
+            fv_ghost_state(P, d, q, zg, nb);
+          } else {
+            ni = (ni + M.nx) % M.nx; nj = (nj + M.nz) % M.nz;
+            for (int v = 0; v < 4; ++v) nb[v] = Q[4 * (nj * M.nx + ni) + v];
+          }
+        }
+        for (int v = 0; v < 4; ++v) slope[d][v] = van_albada(q[v] - lo[v], hi[v] - q[v]);
+      }
+      double fv[4][4];   // face values: west, east, south, north
+      for (int v = 0; v < 4; ++v) {
+        fv[0][v] = q[v] - 0.5 * slope[0][v];
+        fv[1][v] = q[v] + 0.5 * slope[0][v];
+        fv[2][v] = q[v] - 0.5 * slope[1][v];
+        fv[3][v] = q[v] + 0.5 * slope[1][v];
+      }
+      const double zf[4] = {zc, zc, zc - 0.5 * h, zc + 0.5 * h};
+      double F[4][4], Sw;
+      for (int f = 0; f < 4; ++f) fv_flux(P, fv[f], zf[f], f / 2, F[f], nullptr);
+      double Fc[4];
+      fv_flux(P, q, zc, 0, Fc, &Sw);
+      double* ic = inc + 4 * c;
+      for (int v = 0; v < 4; ++v) {
+        ic[v] = dt / (2.0 * h) * ((F[0][v] - F[1][v]) + (F[2][v] - F[3][v]));
+        if (v == 2) ic[v] += 0.5 * dt * Sw;
+      }
+      for (int f = 0; f < 4; ++f)
+        for (int v = 0; v < 4; ++v) E[(4 * c + f) * 4 + v] = fv[f][v] + ic[v];
+    }
+}
+
+void fv_step(const Params& P, const FVMesh& M, const double* Q, double dt, double* out) {
+  const int C = M.C();
+  const double h = M.h;
+  std::vector<double> E((size_t)C * 16), inc((size_t)C * 4);
+  fv_predict(P, M, Q, dt, E.data(), inc.data());
+  for (int j = 0; j < M.nz; ++j)
+    for (int i = 0; i < M.nx; ++i) {
+      const int c = j * M.nx + i;
+      const double zc = fv_zc(M, j);
+      double G[4][4];
+      for (int f = 0; f < 4; ++f) {
+        const int d = f / 2, hi = f % 2;
+        const double zf = d == 0 ? zc : zc + (hi ? 0.5 * h : -0.5 * h);
+        const double* own = &E[(4 * c + f) * 4];
+        double Fo[4];
+        fv_flux(P, own, zf, d, Fo, nullptr);
+        double Qn[4], Fn[4];
+        int ni = i + (d == 0 ? (hi ? 1 : -1) : 0), nj = j + (d == 1 ? (hi ? 1 : -1) : 0);
+        const bool out = ni < 0 || ni >= M.nx || nj < 0 || nj >= M.nz;
+        if (out && M.bc[f] == BC_WALL) {
+          wall_ghost<double>(P, d, &zf, own, Fo, Qn, Fn);
+        } else {
+          ni = (ni + M.nx) % M.nx; nj = (nj + M.nz) % M.nz;
+          const double* oth = &E[(4 * (nj * M.nx + ni) + (f ^ 1)) * 4];
+          for (int v = 0; v < 4; ++v) Qn[v] = oth[v];
+          fv_flux(P, Qn, zf, d, Fn, nullptr);
+        }
+        const double zz[1] = {zf};
+        if (hi) rusanov<double>(P, d, h, zz, own, Fo, Qn, Fn, G[f]);
+        else rusanov<double>(P, d, h, zz, Qn, Fn, own, Fo, G[f]);
+      }
+      double qh[4], F0[4], Sh;
+      for (int v = 0; v < 4; ++v) qh[v] = Q[4 * c + v] + inc[4 * c + v];
+      fv_flux(P, qh, zc, 0, F0, &Sh);
+      for (int v = 0; v < 4; ++v) {
+        double val = Q[4 * c + v] - dt / h * ((G[1][v] - G[0][v]) + (G[3][v] - G[2][v]));
+        if (v == 2) val += dt * Sh;
+        out[4 * c + v] = val;
+      }
+    }
+}
+
+double fv_dt(const Params& P, const FVMesh& M, const double* Q) {
+  double lam = 0.0;
+  for (int j = 0; j < M.nz; ++j)
+    for (int i = 0; i < M.nx; ++i) {
+      const double* q = Q + 4 * (j * M.nx + i);
+      const double c = std::sqrt(P.gamma * pressure(P, q, fv_zc(M, j)) / q[0]);
+      lam = std::max(lam, std::max(std::fabs(q[1]), std::fabs(q[2])) / q[0] + c);
+    }
+  return P.cfl * M.h / (2.0 * lam);
+}
+
+}  // namespace
+
+extern "C" {
+
+double oracle_van_albada(double a, double b) { return van_albada(a, b); }
+
+int oracle_fv_predict(const double* prm, const int* mi, const double* md, const double* Q, double dt, double* E,
+                      double* inc) {
+  fv_predict(fv_params(prm), read_fv_mesh(mi, md), Q, dt, E, inc);
+  return 0;
+}
+
+int oracle_fv_step(const double* prm, const int* mi, const double* md, const double* Q, double dt, double* out) {
+  fv_step(fv_params(prm), read_fv_mesh(mi, md), Q, dt, out);
+  return 0;
+}
+
+int oracle_fv_dt(const double* prm, const int* mi, const double* md, const double* Q, double* out) {
+  *out = fv_dt(fv_params(prm), read_fv_mesh(mi, md), Q);
+  return 0;
+}
+
+int oracle_fv_run(const double* prm, const int* mi, const double* md, double* Q, double* t, double dt, int nsteps) {
+  const Params P = fv_params(prm);
+  const FVMesh M = read_fv_mesh(mi, md);
+  std::vector<double> Qn((size_t)M.C() * 4);
+  for (int s = 0; s < nsteps; ++s) {
+    const double h = dt > 0 ? dt : fv_dt(P, M, Q);
+    fv_step(P, M, Q, h, Qn.data());
+    std::memcpy(Q, Qn.data(), Qn.size() * sizeof(double));
+    *t += h;
+  }
+  return 0;
+}
+
+// Cell values at the centres: kind 0 the background perturbed by bubbles
+// [shape, A, a, s, xc, zc] (as the DG initial state), kind 1 the advected
+// density wave of the manufactured solution at time t0 (without its source).
+int oracle_fv_ic(const double* prm, const int* mi, const double* md, int kind, int nb, const double* bub, double t0,
+                 double* Q) {
+  const Params P = read_params(prm);
+  const FVMesh M = read_fv_mesh(mi, md);
+  const double PI = 3.14159265358979323846;
+  for (int j = 0; j < M.nz; ++j)
+    for (int i = 0; i < M.nx; ++i) {
+      const double x = M.x0 + (i + 0.5) * M.h, z = M.z0 + (j + 0.5) * M.h;
+      double* q = Q + 4 * (j * M.nx + i);
+      if (kind == 1) {
+        const double X = x - P.mms_u * t0, Z = z - P.mms_w * t0;
+        const double rho = 1.0 + P.mms_amp * std::sin(P.mms_kx * X) * std::sin(P.mms_kz * Z);
+        q[0] = rho; q[1] = rho * P.mms_u; q[2] = rho * P.mms_w;
+        q[3] = P.mms_p / (P.gamma - 1.0) + 0.5 * rho * (P.mms_u * P.mms_u + P.mms_w * P.mms_w);
+        continue;
+      }
+      double th = 0.0;
+      for (int b = 0; b < nb; ++b) {
+        const double* bb = bub + 6 * b;
+        const double r = std::sqrt((x - bb[4]) * (x - bb[4]) + (z - bb[5]) * (z - bb[5]));
+        if ((int)bb[0] == 0) { if (r <= bb[2]) th += 0.5 * bb[1] * (1.0 + std::cos(PI * r / bb[2])); }
+        else th += (r <= bb[2]) ? bb[1] : bb[1] * std::exp(-(r - bb[2]) * (r - bb[2]) / (bb[3] * bb[3]));
+      }
+      const double pi = 1.0 - P.g * z / (P.cp * P.theta_bg);
+      const double pb = P.p0 * std::pow(pi, P.cp / P.R);
+      const double rho = pb / (P.R * (P.theta_bg + th) * pi);
+      q[0] = rho; q[1] = 0.0; q[2] = 0.0;
+      q[3] = pb / (P.gamma - 1.0) + rho * P.g * z;
+    }
+  return 0;
+}
+
+}  // extern "C"

@@ -74,6 +74,13 @@ def lib():
         L.oracle3_dt.argtypes = [dp] + m3 + [dp, dp]
         L.oracle3_run.argtypes = [dp] + m3 + [dp, dp, ctypes.c_double, ctypes.c_int]
         L.oracle3_ic.argtypes = [dp] + m3 + [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, dp]
+        L.oracle_van_albada.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.oracle_van_albada.restype = ctypes.c_double
+        L.oracle_fv_predict.argtypes = [dp] + m3 + [dp, ctypes.c_double, dp, dp]
+        L.oracle_fv_step.argtypes = [dp] + m3 + [dp, ctypes.c_double, dp]
+        L.oracle_fv_dt.argtypes = [dp] + m3 + [dp, dp]
+        L.oracle_fv_run.argtypes = [dp] + m3 + [dp, dp, ctypes.c_double, ctypes.c_int]
+        L.oracle_fv_ic.argtypes = [dp] + m3 + [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, dp]
         _lib = L
     return _lib
 
@@ -327,4 +334,68 @@ def ic3(phys: dict, mesh3: dict, kind: str = "bubbles", bubbles=(), t0: float = 
     bb = np.ascontiguousarray(np.asarray(bubbles, dtype=np.float64).reshape(-1, 7))
     k = 1 if kind == "abc" else 0
     _check(lib().oracle3_ic(_dp(p), _ip(mi), _dp(md), k, bb.shape[0], _dp(bb), float(t0), _dp(Q)), "ic3")
+    return Q
+
+
+# ------------------------------------------------------------- finite volume
+# MUSCL-Hancock scheme on a uniform grid; the mesh is the 2D dict
+# (nx, nz, x0, z0, Lx, Lz, bc[4]); states are Q[C][4] cell values.
+def _fv_mesh(mesh: dict):
+    mi = np.array([mesh["nx"], mesh["nz"]] + list(mesh["bc"]), dtype=np.int32)
+    md = np.array([mesh.get("x0", 0.0), mesh.get("z0", 0.0), mesh["Lx"] / mesh["nx"]], dtype=np.float64)
+    return mi, md
+
+
+def van_albada(a: float, b: float) -> float:
+    return float(lib().oracle_van_albada(float(a), float(b)))
+
+
+def fv_predict(phys: dict, mesh: dict, Q: np.ndarray, dt: float):
+    """Evolved face values E[C][4 faces (W, E, S, N)][4] and the half-step
+    increment inc[C][4]."""
+    p = params(phys)
+    mi, md = _fv_mesh(mesh)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    E = np.zeros((Q.shape[0], 4, 4))
+    inc = np.zeros((Q.shape[0], 4))
+    _check(lib().oracle_fv_predict(_dp(p), _ip(mi), _dp(md), _dp(Q), float(dt), _dp(E), _dp(inc)), "fv_predict")
+    return E, inc
+
+
+def fv_step(phys: dict, mesh: dict, Q: np.ndarray, dt: float) -> np.ndarray:
+    p = params(phys)
+    mi, md = _fv_mesh(mesh)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    out = np.zeros_like(Q)
+    _check(lib().oracle_fv_step(_dp(p), _ip(mi), _dp(md), _dp(Q), float(dt), _dp(out)), "fv_step")
+    return out
+
+
+def fv_dt(phys: dict, mesh: dict, Q: np.ndarray) -> float:
+    p = params(phys)
+    mi, md = _fv_mesh(mesh)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    out = np.zeros(1)
+    _check(lib().oracle_fv_dt(_dp(p), _ip(mi), _dp(md), _dp(Q), _dp(out)), "fv_dt")
+    return float(out[0])
+
+
+def fv_run(phys: dict, mesh: dict, Q: np.ndarray, t: float, nsteps: int, dt: float = 0.0):
+    p = params(phys)
+    mi, md = _fv_mesh(mesh)
+    Q = np.array(Q, dtype=np.float64, copy=True, order="C")
+    tt = np.array([t], dtype=np.float64)
+    _check(lib().oracle_fv_run(_dp(p), _ip(mi), _dp(md), _dp(Q), _dp(tt), float(dt), int(nsteps)), "fv_run")
+    return Q, float(tt[0])
+
+
+def fv_ic(phys: dict, mesh: dict, kind: str = "bubbles", bubbles=(), t0: float = 0.0) -> np.ndarray:
+    """Cell-centre values: kind 'bubbles' (6 numbers per bubble) or 'wave'
+    (the manufactured density wave at t0, without its source)."""
+    p = params(phys)
+    mi, md = _fv_mesh(mesh)
+    Q = np.zeros((mesh["nx"] * mesh["nz"], 4))
+    bb = np.ascontiguousarray(np.asarray(bubbles, dtype=np.float64).reshape(-1, 6))
+    _check(lib().oracle_fv_ic(_dp(p), _ip(mi), _dp(md), 1 if kind == "wave" else 0, bb.shape[0], _dp(bb),
+                              float(t0), _dp(Q)), "fv_ic")
     return Q
