@@ -30,6 +30,9 @@ EXPORTED = [
     "adg3_init_mesh", "adg3_destroy", "adg3_mesh_info", "adg3_workspace_bytes", "adg3_set_state",
     "adg3_init_state", "adg3_compute_dt", "adg3_predictor", "adg3_corrector", "adg3_step",
     "adg3_check_health",
+    "adg_fv_init", "adg_fv_destroy", "adg_fv_info", "adg_fv_workspace_bytes", "adg_fv_set_state",
+    "adg_fv_init_state", "adg_fv_compute_dt", "adg_fv_predictor", "adg_fv_corrector", "adg_fv_step",
+    "adg_fv_check_health",
 ]
 
 
@@ -66,6 +69,13 @@ class adg3_mesh_desc(ctypes.Structure):
     _fields_ = [
         ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("z0", ctypes.c_double), ("h", ctypes.c_double),
         ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("bc", ctypes.c_int * 6),
+    ]
+
+
+class adg_fv_desc(ctypes.Structure):
+    _fields_ = [
+        ("x0", ctypes.c_double), ("z0", ctypes.c_double), ("h", ctypes.c_double),
+        ("nx", ctypes.c_int), ("nz", ctypes.c_int), ("bc", ctypes.c_int * 4),
     ]
 
 
@@ -123,6 +133,15 @@ def lib():
         L.adg3_set_state.argtypes = [vp, vp, vp, vp]
         L.adg3_init_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, vp]
         for name in ("adg3_compute_dt", "adg3_predictor", "adg3_corrector", "adg3_step", "adg3_check_health"):
+            getattr(L, name).argtypes = [vp, vp]
+        L.adg_fv_init.argtypes = [ctypes.POINTER(adg_params), ctypes.POINTER(adg_fv_desc), ctypes.POINTER(vp)]
+        L.adg_fv_destroy.argtypes = [vp]
+        L.adg_fv_info.argtypes = [vp, ip]
+        L.adg_fv_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.adg_fv_set_state.argtypes = [vp, vp, vp, vp]
+        L.adg_fv_init_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, vp]
+        for name in ("adg_fv_compute_dt", "adg_fv_predictor", "adg_fv_corrector", "adg_fv_step",
+                     "adg_fv_check_health"):
             getattr(L, name).argtypes = [vp, vp]
         _lib = L
     return _lib
@@ -435,6 +454,94 @@ class Mesh3:
         off = _align256(self.C * 5 * n ** 3 * 8)
         off = _align256(off + self.C * 60 * n * n * 8)
         return self.ws[off:off + self.C * 8].view(torch.float64)
+
+    @property
+    def t(self):
+        return float(self.clock[0].item())
+
+    @property
+    def dt(self):
+        return float(self.clock[1].item())
+
+
+def make_fv_desc(mesh: dict) -> adg_fv_desc:
+    """Finite-volume grid from the 2D mesh dict (nx, nz, x0, z0, Lx, Lz, bc)."""
+    d = adg_fv_desc()
+    d.x0, d.z0 = float(mesh.get("x0", 0.0)), float(mesh.get("z0", 0.0))
+    d.h = float(mesh["Lx"]) / int(mesh["nx"]) if int(mesh["nx"]) > 0 else 0.0
+    d.nx, d.nz = int(mesh["nx"]), int(mesh["nz"])
+    for k, b in enumerate(mesh.get("bc", [ADG_BC_WALL] * 4)):
+        d.bc[k] = int(b)
+    return d
+
+
+class FV:
+    """Handle of the MUSCL-Hancock finite-volume scheme (C ABI in
+    ``include/adg_fv.h``); Q [C][4] and the workspace are torch tensors."""
+
+    def __init__(self, phys: dict, mesh: dict, fixed_dt: bool = False, device="cuda"):
+        import torch
+        self.phys, self.mesh_desc = dict(phys), dict(mesh)
+        self._p = make_params(dict(phys, N=0), fixed_dt)
+        self._d = make_fv_desc(mesh)
+        h = ctypes.c_void_p()
+        _check(lib().adg_fv_init(ctypes.byref(self._p), ctypes.byref(self._d), ctypes.byref(h)))
+        self.h = h
+        nc = ctypes.c_int()
+        _check(lib().adg_fv_info(h, ctypes.byref(nc)))
+        self.C = nc.value
+        wb = ctypes.c_size_t()
+        _check(lib().adg_fv_workspace_bytes(h, ctypes.byref(wb)))
+        self.ws_bytes = wb.value
+        self.device = torch.device(device)
+        self.Q = torch.zeros((self.C, 4), dtype=torch.float64, device=self.device)
+        self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)
+        self.clock = torch.zeros(4, dtype=torch.float64, device=self.device)
+        _check(lib().adg_fv_set_state(self.h, ctypes.c_void_p(self.Q.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+                                      ctypes.c_void_p(self.clock.data_ptr())))
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().adg_fv_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def init_state(self, kind="bubbles", bubbles=(), t0=0.0, stream=None):
+        bb = np.ascontiguousarray(np.asarray(bubbles, dtype=np.float64).reshape(-1, 6))
+        _check(lib().adg_fv_init_state(self.h, 1 if kind == "wave" else 0, bb.shape[0],
+                                       bb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(t0),
+                                       _stream_ptr(stream)))
+
+    def set_state(self, Q, t=None, dt=None):
+        import torch
+        self.Q.copy_(torch.as_tensor(np.asarray(Q) if not torch.is_tensor(Q) else Q, dtype=torch.float64))
+        if t is not None:
+            self.clock[0] = float(t)
+        if dt is not None:
+            self.clock[1] = float(dt)
+
+    def compute_dt(self, stream=None):
+        _check(lib().adg_fv_compute_dt(self.h, _stream_ptr(stream)))
+
+    def predictor(self, stream=None):
+        _check(lib().adg_fv_predictor(self.h, _stream_ptr(stream)))
+
+    def corrector(self, stream=None):
+        _check(lib().adg_fv_corrector(self.h, _stream_ptr(stream)))
+
+    def step(self, stream=None):
+        _check(lib().adg_fv_step(self.h, _stream_ptr(stream)))
+
+    def check_health(self, stream=None):
+        _check(lib().adg_fv_check_health(self.h, _stream_ptr(stream)))
+
+    def face_values(self):
+        """Evolved face values as [C][4 faces][4 vars] (a copy)."""
+        import torch
+        E = self.ws[:16 * self.C * 8].view(torch.float64).view(4, 4, self.C)
+        return E.permute(2, 0, 1).contiguous()
 
     @property
     def t(self):

@@ -1,0 +1,503 @@
+// MUSCL-Hancock finite volumes with the van Albada limiter (the engine's
+// second scheme, Section 3; run without viscosity on the colliding bubbles,
+// Section 4.2) for gfx950: kernels and the host side of include/adg_fv.h.
+//
+// Two kernels per step, one thread per cell, x fastest so that a wavefront
+// reads 64 consecutive cells (32 B each) and the x neighbours come from the
+// same cache lines:
+//   k_fv_predict  slopes, Hancock half step -> evolved face values and the
+//                 half-step increment (structure-of-arrays in the workspace,
+//                 one coalesced 512 B segment per face, variable and wave);
+//   k_fv_correct  Rusanov flux of the four faces from the cell's and its
+//                 neighbours' evolved values, update of Q in place (it reads
+//                 no other cell's Q), and the workgroup's time-step bound.
+// The background density and pressure of every row (centre, horizontal
+// faces, wall ghost centres) come from a host-built table, so no kernel
+// evaluates pow().
+#include <cmath>
+#include <new>
+
+#include "adg_fv.h"
+#include "adg_internal.h"
+
+namespace adg {
+
+int launch_clock(double* clock, const double* dtc, const int* beg, const int* end, int nscen, int C, int advance,
+                 int update, hipStream_t s);
+
+constexpr int kFvThreads = 256;
+constexpr int kFvBubbles = 16;
+
+// Row table: for row j, 5 heights x (z, rho_bar, p_bar): the cell centre,
+// the south and north faces, the south and north wall ghost centres.
+enum { kBgC = 0, kBgS = 1, kBgN = 2, kBgGS = 3, kBgGN = 4 };
+
+struct FvArgs {
+  double* Q;            // [C][4]
+  double* E;            // [4 faces][4 vars][C]
+  double* inc;          // [4 vars][C]
+  double* dtb;          // [blocks] time-step bounds
+  const double* clock;  // (t, dt, -, steps)
+  const double* bg;     // [nz][5][3]
+  int nx, nz, C, wall;  // wall: bit f set for a wall on face f (W, E, S, N)
+  double h;
+};
+
+struct FvBubbles {
+  int nb;
+  double b[kFvBubbles * 6];
+};
+
+__device__ inline double fv_pressure(const Phys& ph, const double q[4], double z) {
+  return pressure(ph, q[0], q[1], q[2], q[3], z);
+}
+
+// inviscid flux along d (0: x, 1: z) at height z with the perturbation
+// pressure p - p_bar in the momentum flux (pb = 0 without gravity)
+__device__ inline void fv_flux(const Phys& ph, const double q[4], double z, double pb, int d, double F[4]) {
+  const double ir = 1.0 / q[0];
+  const double u = q[1] * ir, w = q[2] * ir;
+  const double p = ph.gm1 * (q[3] - 0.5 * (q[1] * u + q[2] * w) - q[0] * (ph.geff * z));
+  const double pm = p - pb;
+  const double un = d ? w : u;
+  F[0] = q[1 + d];
+  F[1] = q[1] * un + (d == 0 ? pm : 0.0);
+  F[2] = q[2] * un + (d == 1 ? pm : 0.0);
+  F[3] = un * (q[3] + p);
+}
+
+// wall ghost state of q at height z (background rb, pb there)
+__device__ inline void fv_ghost(const Phys& ph, const double q[4], double z, double rb, double pb, double g[4]) {
+  const double u = q[1] / q[0], w = q[2] / q[0];
+  double r = rb, p = pb;
+  if (!ph.gravity) { r = q[0]; p = fv_pressure(ph, q, z); }
+  const double geo = ph.gravity ? r * (ph.g * z) : 0.0;
+  g[0] = r;
+  g[1] = -(r * u);
+  g[2] = -(r * w);
+  g[3] = p / ph.gm1 + 0.5 * r * (u * u + w * w) + geo;
+}
+
+__device__ inline double van_albada(double a, double b) {
+  if (!(a * b > 0.0)) return 0.0;
+  return a * b * (a + b) / (a * a + b * b);
+}
+
+__device__ inline double fv_speed(const Phys& ph, const double q[4], double z, int d) {
+  const double p = fv_pressure(ph, q, z);
+  return fabs(q[1 + d] / q[0]) + sqrt(ph.gamma * p / q[0]);
+}
+
+// G = (F_L + F_R)/2 - s/2 (Q_R - Q_L)
+__device__ inline void rusanov_fv(const Phys& ph, int d, double z, const double QL[4], const double FL[4],
+                                  const double QR[4], const double FR[4], double G[4]) {
+  const double s = fmax(fv_speed(ph, QL, z, d), fv_speed(ph, QR, z, d));
+  for (int v = 0; v < 4; ++v) G[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * s * (QR[v] - QL[v]);
+}
+
+__device__ inline void load4(const double* p, double q[4]) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  q[0] = a.x; q[1] = a.y; q[2] = b.x; q[3] = b.y;
+}
+
+// Steps 1-2 of the scheme for one cell per thread.
+__global__ __launch_bounds__(kFvThreads) void k_fv_predict(Phys ph, FvArgs a) {
+  const int c = blockIdx.x * kFvThreads + threadIdx.x;
+  if (c >= a.C) return;
+  const int i = c % a.nx, j = c / a.nx;
+  const double* bg = a.bg + 15 * j;
+  const double h = a.h, dt = a.clock[1];
+  double q[4], nb[4][4];   // neighbours W, E, S, N
+  load4(a.Q + 4 * (size_t)c, q);
+  if (i > 0) load4(a.Q + 4 * (size_t)(c - 1), nb[0]);
+  else if (a.wall & 1) fv_ghost(ph, q, bg[3 * kBgC], bg[3 * kBgC + 1], bg[3 * kBgC + 2], nb[0]);
+  else load4(a.Q + 4 * (size_t)(c + a.nx - 1), nb[0]);
+  if (i < a.nx - 1) load4(a.Q + 4 * (size_t)(c + 1), nb[1]);
+  else if (a.wall & 2) fv_ghost(ph, q, bg[3 * kBgC], bg[3 * kBgC + 1], bg[3 * kBgC + 2], nb[1]);
+  else load4(a.Q + 4 * (size_t)(c - a.nx + 1), nb[1]);
+  if (j > 0) load4(a.Q + 4 * (size_t)(c - a.nx), nb[2]);
+  else if (a.wall & 4) fv_ghost(ph, q, bg[3 * kBgGS], bg[3 * kBgGS + 1], bg[3 * kBgGS + 2], nb[2]);
+  else load4(a.Q + 4 * ((size_t)(a.nz - 1) * a.nx + i), nb[2]);
+  if (j < a.nz - 1) load4(a.Q + 4 * (size_t)(c + a.nx), nb[3]);
+  else if (a.wall & 8) fv_ghost(ph, q, bg[3 * kBgGN], bg[3 * kBgGN + 1], bg[3 * kBgGN + 2], nb[3]);
+  else load4(a.Q + 4 * (size_t)i, nb[3]);
+  double fv[4][4];   // face values W, E, S, N
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double sx = van_albada(q[v] - nb[0][v], nb[1][v] - q[v]);
+    const double sz = van_albada(q[v] - nb[2][v], nb[3][v] - q[v]);
+    fv[0][v] = q[v] - 0.5 * sx;
+    fv[1][v] = q[v] + 0.5 * sx;
+    fv[2][v] = q[v] - 0.5 * sz;
+    fv[3][v] = q[v] + 0.5 * sz;
+  }
+  double F[4][4];
+  fv_flux(ph, fv[0], bg[3 * kBgC], bg[3 * kBgC + 2], 0, F[0]);
+  fv_flux(ph, fv[1], bg[3 * kBgC], bg[3 * kBgC + 2], 0, F[1]);
+  fv_flux(ph, fv[2], bg[3 * kBgS], bg[3 * kBgS + 2], 1, F[2]);
+  fv_flux(ph, fv[3], bg[3 * kBgN], bg[3 * kBgN + 2], 1, F[3]);
+  const double Sw = -ph.geff * (q[0] - bg[3 * kBgC + 1]);
+  const double k = dt / (2.0 * h);
+  const size_t C = (size_t)a.C;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double inc = k * ((F[0][v] - F[1][v]) + (F[2][v] - F[3][v]));
+    if (v == 2) inc += 0.5 * dt * Sw;
+    a.inc[v * C + c] = inc;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) a.E[(size_t)(4 * f + v) * C + c] = fv[f][v] + inc;
+  }
+}
+
+// Steps 3-4 for one cell per thread, and the workgroup's time-step bound.
+__global__ __launch_bounds__(kFvThreads) void k_fv_correct(Phys ph, FvArgs a) {
+  __shared__ double smax[kFvThreads / kWave];
+  const int c = blockIdx.x * kFvThreads + threadIdx.x;
+  double lam = 0.0;
+  if (c < a.C) {
+    const int i = c % a.nx, j = c / a.nx;
+    const double* bg = a.bg + 15 * j;
+    const double h = a.h, dt = a.clock[1];
+    const size_t C = (size_t)a.C;
+    double G[4][4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int d = f >> 1, hi = f & 1;
+      const int row = d == 0 ? kBgC : (hi ? kBgN : kBgS);
+      const double zf = bg[3 * row], rbf = bg[3 * row + 1], pbf = bg[3 * row + 2];
+      double own[4], Fo[4], Qn[4], Fn[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) own[v] = a.E[(size_t)(4 * f + v) * C + c];
+      fv_flux(ph, own, zf, pbf, d, Fo);
+      int nbr;
+      bool wall = false;
+      if (d == 0) {
+        if (hi) { nbr = i < a.nx - 1 ? c + 1 : c - a.nx + 1; wall = i == a.nx - 1 && (a.wall & 2); }
+        else { nbr = i > 0 ? c - 1 : c + a.nx - 1; wall = i == 0 && (a.wall & 1); }
+      } else {
+        if (hi) { nbr = j < a.nz - 1 ? c + a.nx : i; wall = j == a.nz - 1 && (a.wall & 8); }
+        else { nbr = j > 0 ? c - a.nx : (a.nz - 1) * a.nx + i; wall = j == 0 && (a.wall & 4); }
+      }
+      if (wall) {
+        fv_ghost(ph, own, zf, rbf, pbf, Qn);
+        Fn[0] = -Fo[0]; Fn[1] = Fo[1]; Fn[2] = Fo[2]; Fn[3] = -Fo[3];
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Qn[v] = a.E[(size_t)(4 * (f ^ 1) + v) * C + nbr];
+        fv_flux(ph, Qn, zf, pbf, d, Fn);
+      }
+      if (hi) rusanov_fv(ph, d, zf, own, Fo, Qn, Fn, G[f]);
+      else rusanov_fv(ph, d, zf, Qn, Fn, own, Fo, G[f]);
+    }
+    double q[4];
+    load4(a.Q + 4 * (size_t)c, q);
+    const double rho_half = q[0] + a.inc[c];
+    const double Sh = -ph.geff * (rho_half - bg[3 * kBgC + 1]);
+    double out[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      out[v] = q[v] - dt / h * ((G[1][v] - G[0][v]) + (G[3][v] - G[2][v]));
+      if (v == 2) out[v] += dt * Sh;
+    }
+    double2* o = reinterpret_cast<double2*>(a.Q + 4 * (size_t)c);
+    o[0] = make_double2(out[0], out[1]);
+    o[1] = make_double2(out[2], out[3]);
+    const double cs = sqrt(ph.gamma * fv_pressure(ph, out, bg[3 * kBgC]) / out[0]);
+    lam = fmax(fabs(out[1]), fabs(out[2])) / out[0] + cs;
+  }
+  lam = wave_max(lam);
+  if ((threadIdx.x & (kWave - 1)) == 0) smax[threadIdx.x / kWave] = lam;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = smax[0];
+    for (int w = 1; w < kFvThreads / kWave; ++w) m = fmax(m, smax[w]);
+    a.dtb[blockIdx.x] = ph.cfl * a.h / (2.0 * m);
+  }
+}
+
+// time-step bound of every workgroup of cells from the current Q
+__global__ __launch_bounds__(kFvThreads) void k_fv_dt(Phys ph, FvArgs a) {
+  __shared__ double smax[kFvThreads / kWave];
+  const int c = blockIdx.x * kFvThreads + threadIdx.x;
+  double lam = 0.0;
+  if (c < a.C) {
+    double q[4];
+    load4(a.Q + 4 * (size_t)c, q);
+    const double cs = sqrt(ph.gamma * fv_pressure(ph, q, a.bg[15 * (c / a.nx)]) / q[0]);
+    lam = fmax(fabs(q[1]), fabs(q[2])) / q[0] + cs;
+  }
+  lam = wave_max(lam);
+  if ((threadIdx.x & (kWave - 1)) == 0) smax[threadIdx.x / kWave] = lam;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = smax[0];
+    for (int w = 1; w < kFvThreads / kWave; ++w) m = fmax(m, smax[w]);
+    a.dtb[blockIdx.x] = ph.cfl * a.h / (2.0 * m);
+  }
+}
+
+// cell-centre initial values (kind 0 bubbles, kind 1 advected density wave)
+__global__ void k_fv_init(Phys ph, FvArgs a, double x0, int kind, FvBubbles B, double t0) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.C) return;
+  const int i = c % a.nx, j = c / a.nx;
+  const double x = x0 + (i + 0.5) * a.h, z = a.bg[15 * j];
+  double q[4];
+  if (kind == 1) {
+    const double X = x - ph.mms_u * t0, Z = z - ph.mms_w * t0;
+    const double rho = 1.0 + ph.mms_amp * sin(ph.mms_kx * X) * sin(ph.mms_kz * Z);
+    q[0] = rho; q[1] = rho * ph.mms_u; q[2] = rho * ph.mms_w;
+    q[3] = ph.mms_p / ph.gm1 + 0.5 * rho * (ph.mms_u * ph.mms_u + ph.mms_w * ph.mms_w);
+  } else {
+    double th = 0.0;
+    for (int b = 0; b < B.nb; ++b) {
+      const double* bb = B.b + 6 * b;
+      const double r = sqrt((x - bb[4]) * (x - bb[4]) + (z - bb[5]) * (z - bb[5]));
+      if (bb[0] == 0.0) th += r <= bb[2] ? 0.5 * bb[1] * (1.0 + cos(M_PI * r / bb[2])) : 0.0;
+      else th += r <= bb[2] ? bb[1] : bb[1] * exp(-(r - bb[2]) * (r - bb[2]) / (bb[3] * bb[3]));
+    }
+    const double pi = 1.0 - ph.g * z / (ph.cp * ph.theta);
+    const double pb = a.bg[15 * j + 2];
+    const double rho = pb / (ph.R * (ph.theta + th) * pi);
+    q[0] = rho; q[1] = 0.0; q[2] = 0.0;
+    q[3] = pb / ph.gm1 + rho * ph.g * z;
+  }
+  double2* o = reinterpret_cast<double2*>(a.Q + 4 * (size_t)c);
+  o[0] = make_double2(q[0], q[1]);
+  o[1] = make_double2(q[2], q[3]);
+}
+
+__global__ void k_fv_health(Phys ph, FvArgs a, int* flag) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.C) return;
+  double q[4];
+  load4(a.Q + 4 * (size_t)c, q);
+  bool bad = !(isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && isfinite(q[3])) || !(q[0] > 0.0);
+  if (!bad) bad = !(fv_pressure(ph, q, a.bg[15 * (c / a.nx)]) > 0.0);
+  if (bad) atomicOr(flag, 1);
+}
+
+static size_t align256_fv(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace adg
+
+using namespace adg;
+
+struct adg_fv {
+  adg_params prm{};
+  adg_fv_desc desc{};
+  Phys ph{};
+  int C = 0, blocks = 0;
+  double* d_bg = nullptr;
+  double* Q = nullptr;
+  void* ws = nullptr;
+  double* clock = nullptr;
+  size_t off_e = 0, off_inc = 0, off_dtb = 0, off_h = 0, ws_bytes = 0;
+};
+
+namespace {
+
+int fv_validate(const adg_params* p, const adg_fv_desc* d) {
+  if (!p || !d) return fail(ADG_EINVAL, "null argument");
+  if (p->order != 0) return fail(ADG_EINVAL, "order must be 0 for the finite-volume scheme");
+  if (!(p->gamma > 1.0) || !(p->R > 0.0) || !(p->cp > 0.0)) return fail(ADG_EINVAL, "invalid gas constants");
+  if (p->gravity && (!(p->theta_bg > 0.0) || !(p->p0 > 0.0) || !(p->g >= 0.0)))
+    return fail(ADG_EINVAL, "invalid background atmosphere");
+  if (!(p->cfl > 0.0)) return fail(ADG_EINVAL, "cfl must be > 0");
+  if (p->mu != 0.0) return fail(ADG_EUNSUPPORTED, "the finite-volume scheme is inviscid (mu must be 0)");
+  if (p->mms) return fail(ADG_EUNSUPPORTED, "no manufactured source in the finite-volume scheme");
+  if (d->nx < 1 || d->nz < 1 || !(d->h > 0.0) || !std::isfinite(d->h) || !std::isfinite(d->x0) ||
+      !std::isfinite(d->z0))
+    return fail(ADG_EINVAL, "invalid domain");
+  for (int f = 0; f < 4; ++f)
+    if (d->bc[f] != ADG_BC_PERIODIC && d->bc[f] != ADG_BC_WALL) return fail(ADG_EINVAL, "invalid bc");
+  if ((d->bc[0] == ADG_BC_PERIODIC) != (d->bc[1] == ADG_BC_PERIODIC) ||
+      (d->bc[2] == ADG_BC_PERIODIC) != (d->bc[3] == ADG_BC_PERIODIC))
+    return fail(ADG_EINVAL, "periodic boundaries must come in pairs");
+  if ((long long)d->nx * d->nz > (1LL << 28)) return fail(ADG_EINVAL, "too many cells");
+  return ADG_OK;
+}
+
+// hydrostatic background of constant potential temperature at height z
+void fv_background(const adg_params& p, double z, double& rb, double& pb) {
+  if (!p.gravity) { rb = 0.0; pb = 0.0; return; }
+  const double pi = 1.0 - p.g * z / (p.cp * p.theta_bg);
+  pb = p.p0 * std::pow(pi, p.cp / p.R);
+  rb = pb / (p.R * p.theta_bg * pi);
+}
+
+FvArgs fv_args(const adg_fv* m) {
+  FvArgs a{};
+  char* ws = static_cast<char*>(m->ws);
+  a.Q = m->Q;
+  a.E = ws ? reinterpret_cast<double*>(ws + m->off_e) : nullptr;
+  a.inc = ws ? reinterpret_cast<double*>(ws + m->off_inc) : nullptr;
+  a.dtb = ws ? reinterpret_cast<double*>(ws + m->off_dtb) : nullptr;
+  a.clock = m->clock; a.bg = m->d_bg;
+  a.nx = m->desc.nx; a.nz = m->desc.nz; a.C = m->C; a.h = m->desc.h;
+  a.wall = 0;
+  for (int f = 0; f < 4; ++f)
+    if (m->desc.bc[f] == ADG_BC_WALL) a.wall |= 1 << f;
+  return a;
+}
+
+int fv_need_state(adg_fv* m) {
+  if (!m) return fail(ADG_EINVAL, "null handle");
+  if (!m->Q || !m->ws || !m->clock) return fail(ADG_ESTATE, "no state bound (adg_fv_set_state)");
+  return ADG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int adg_fv_init(const adg_params* prm, const adg_fv_desc* mesh, adg_fv** out) {
+  if (!out) return fail(ADG_EINVAL, "null out");
+  int rc = fv_validate(prm, mesh);
+  if (rc) return rc;
+  adg_fv* m = new (std::nothrow) adg_fv();
+  if (!m) return fail(ADG_ENOMEM, "out of host memory");
+  m->prm = *prm;
+  m->desc = *mesh;
+  m->C = mesh->nx * mesh->nz;
+  m->blocks = (m->C + kFvThreads - 1) / kFvThreads;
+  adg_params p1 = *prm;
+  p1.order = 1;   // make_phys reads the order only for the DG time-step rule
+  m->ph = make_phys(p1);
+  m->ph.N = 0;
+  // background table: centre, south face, north face, south and north ghost centres
+  const double h = mesh->h;
+  std::vector<double> bg((size_t)mesh->nz * 15);
+  for (int j = 0; j < mesh->nz; ++j) {
+    const double zc = mesh->z0 + (j + 0.5) * h;
+    const double zs[5] = {zc, zc - 0.5 * h, zc + 0.5 * h, zc - h, zc + h};
+    for (int k = 0; k < 5; ++k) {
+      double rb, pb;
+      fv_background(*prm, zs[k], rb, pb);
+      bg[15 * j + 3 * k] = zs[k];
+      bg[15 * j + 3 * k + 1] = rb;
+      bg[15 * j + 3 * k + 2] = pb;
+    }
+  }
+  if (hipMalloc(&m->d_bg, sizeof(double) * bg.size()) != hipSuccess) {
+    delete m;
+    return fail(ADG_ENOMEM, "device allocation failed");
+  }
+  if (hipMemcpy(m->d_bg, bg.data(), sizeof(double) * bg.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(m->d_bg);
+    delete m;
+    return fail(ADG_EHIP, "upload failed");
+  }
+  const size_t C = (size_t)m->C;
+  size_t off = 0;
+  m->off_e = off; off = align256_fv(off + sizeof(double) * 16 * C);
+  m->off_inc = off; off = align256_fv(off + sizeof(double) * 4 * C);
+  m->off_dtb = off; off = align256_fv(off + sizeof(double) * m->blocks);
+  m->off_h = off; off = align256_fv(off + sizeof(int));
+  m->ws_bytes = off;
+  *out = m;
+  return ADG_OK;
+}
+
+int adg_fv_destroy(adg_fv* m) {
+  if (!m) return fail(ADG_EINVAL, "null handle");
+  if (m->d_bg) (void)hipFree(m->d_bg);
+  delete m;
+  return ADG_OK;
+}
+
+int adg_fv_info(const adg_fv* m, int* n_cells) {
+  if (!m) return fail(ADG_EINVAL, "null handle");
+  if (n_cells) *n_cells = m->C;
+  return ADG_OK;
+}
+
+int adg_fv_workspace_bytes(const adg_fv* m, size_t* bytes) {
+  if (!m || !bytes) return fail(ADG_EINVAL, "null argument");
+  *bytes = m->ws_bytes;
+  return ADG_OK;
+}
+
+int adg_fv_set_state(adg_fv* m, double* Q, void* workspace, double* clock) {
+  if (!m) return fail(ADG_EINVAL, "null handle");
+  if (!Q || !workspace || !clock) return fail(ADG_EINVAL, "null buffer");
+  if (((uintptr_t)workspace & 255) != 0) return fail(ADG_EINVAL, "workspace must be 256-byte aligned");
+  if (((uintptr_t)Q & 15) != 0 || ((uintptr_t)clock & 7) != 0) return fail(ADG_EINVAL, "misaligned buffer");
+  m->Q = Q; m->ws = workspace; m->clock = clock;
+  return ADG_OK;
+}
+
+int adg_fv_init_state(adg_fv* m, int kind, int n_bubbles, const double* bubbles, double t0, void* stream) {
+  int rc = fv_need_state(m);
+  if (rc) return rc;
+  if (kind != 0 && kind != 1) return fail(ADG_EINVAL, "kind must be 0 (bubbles) or 1 (density wave)");
+  if (kind == 0 && !m->prm.gravity) return fail(ADG_EINVAL, "bubble states need gravity (background)");
+  if (n_bubbles < 0 || n_bubbles > kFvBubbles || (n_bubbles > 0 && !bubbles))
+    return fail(ADG_EINVAL, "bad bubble list");
+  FvBubbles B{};
+  B.nb = kind == 0 ? n_bubbles : 0;
+  for (int b = 0; b < B.nb; ++b) {
+    const double* bb = bubbles + 6 * b;
+    if (bb[0] != ADG_SHAPE_COSINE && bb[0] != ADG_SHAPE_PLATEAU_GAUSS) return fail(ADG_EINVAL, "bad bubble shape");
+    if (bb[0] == ADG_SHAPE_COSINE && !(bb[2] > 0.0)) return fail(ADG_EINVAL, "cosine bubble radius must be > 0");
+    if (bb[0] == ADG_SHAPE_PLATEAU_GAUSS && !(bb[3] > 0.0)) return fail(ADG_EINVAL, "decay s must be > 0");
+    for (int k = 0; k < 6; ++k) B.b[6 * b + k] = bb[k];
+  }
+  hipLaunchKernelGGL(k_fv_init, dim3(m->blocks), dim3(kFvThreads), 0, (hipStream_t)stream, m->ph, fv_args(m),
+                     m->desc.x0, kind, B, t0);
+  return check_launch("fv_init");
+}
+
+int adg_fv_compute_dt(adg_fv* m, void* stream) {
+  int rc = fv_need_state(m);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const FvArgs a = fv_args(m);
+  hipLaunchKernelGGL(k_fv_dt, dim3(m->blocks), dim3(kFvThreads), 0, s, m->ph, a);
+  rc = check_launch("fv_dt");
+  if (rc) return rc;
+  return launch_clock(m->clock, a.dtb, nullptr, nullptr, 1, m->blocks, 0, 1, s);
+}
+
+int adg_fv_predictor(adg_fv* m, void* stream) {
+  int rc = fv_need_state(m);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_fv_predict, dim3(m->blocks), dim3(kFvThreads), 0, (hipStream_t)stream, m->ph, fv_args(m));
+  return check_launch("fv_predict");
+}
+
+int adg_fv_corrector(adg_fv* m, void* stream) {
+  int rc = fv_need_state(m);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const FvArgs a = fv_args(m);
+  hipLaunchKernelGGL(k_fv_correct, dim3(m->blocks), dim3(kFvThreads), 0, s, m->ph, a);
+  rc = check_launch("fv_correct");
+  if (rc) return rc;
+  return launch_clock(m->clock, a.dtb, nullptr, nullptr, 1, m->blocks, 1, m->prm.fixed_dt ? 0 : 1, s);
+}
+
+int adg_fv_step(adg_fv* m, void* stream) {
+  int rc = adg_fv_predictor(m, stream);
+  if (rc) return rc;
+  return adg_fv_corrector(m, stream);
+}
+
+int adg_fv_check_health(adg_fv* m, void* stream) {
+  int rc = fv_need_state(m);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int* flag = reinterpret_cast<int*>(static_cast<char*>(m->ws) + m->off_h);
+  if (hipMemsetAsync(flag, 0, sizeof(int), s) != hipSuccess) return fail(ADG_EHIP, "memset");
+  hipLaunchKernelGGL(k_fv_health, dim3(m->blocks), dim3(kFvThreads), 0, s, m->ph, fv_args(m), flag);
+  rc = check_launch("fv_health");
+  if (rc) return rc;
+  int hf = 0;
+  if (hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return fail(ADG_EHIP, "copy");
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(ADG_EHIP, "sync");
+  if (hf) return fail(ADG_ESTATE, "state has non-finite values or non-positive density/pressure");
+  return ADG_OK;
+}
+
+}  // extern "C"

@@ -18,6 +18,8 @@ Workloads follow the paper's scenarios (Krenz, Rannabauer, Bader 2019):
                     refinement levels (the paper's AMR run)
   * ``bubble27``    81x81's box on 27x27 cells (adjoint workload)
   * ``batch64``     64 random bubble scenarios (grids 9..81, N in 3..6)
+  * ``fv630``       the colliding bubbles with the finite-volume scheme: 7^2
+                    patches of 90^2 cells = 630x630 cells of 1.59 m, inviscid
   * ``bubble3d``    3D cosine bubble in the 1000 m cube on 25^3 cells of 40 m,
                     N=3, mu = 0.005, no-slip walls
   * ``abc3d``       the ABC flow on the periodic cube [-pi, pi]^3, 27^3
@@ -180,6 +182,22 @@ def refined_leaves(nx: int, nz: int, refine):
     for (i, j) in sorted(rs, key=lambda t: (t[1], t[0])):
         out += [(1, 3 * i + a, 3 * j + b) for b in range(3) for a in range(3)]
     return out
+
+
+# ------------------------------------------------------------ finite volume
+# Courant factor of the finite-volume workloads (the N = 0 rule
+# dt = cfl h / (2 lambda)).
+FV_CFL = 0.9
+
+
+def fv_bubbles(n: int = 630, steps: int = 50):
+    """Colliding bubbles (warm plateau and cold Gaussian bubble of the AMR
+    run) with the MUSCL-Hancock scheme: 7^2 patches of 90^2 cells on the
+    1000 m box (n = 630: cells of 1.59 m), no viscosity, no-slip walls."""
+    phys = dict(ATMO, N=0, picard_iters=0, mu=0.0, mms=0, cfl=FV_CFL)
+    mesh = dict(nx=n, nz=n, max_level=0, x0=0.0, z0=0.0, Lx=1000.0, Lz=1000.0, bc=[BC_WALL] * 4)
+    return dict(name=f"fv{n}x{n}", phys=phys, mesh=mesh, ic="bubbles",
+                bubbles=[warm_plateau_bubble(), cold_bubble()], steps=steps)
 
 
 # ------------------------------------------------------------------------ 3D

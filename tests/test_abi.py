@@ -112,3 +112,38 @@ def test_null_arguments_rejected_3d():
     assert L.adg3_destroy(None) == adg.ADG_EINVAL
     assert L.adg3_set_state(None, None, None, None) == adg.ADG_EINVAL
     assert L.adg3_init_mesh(None, None, None) == adg.ADG_EINVAL
+
+
+def _init_fv(phys, mesh):
+    p = adg.make_params(dict(phys, N=phys.get("N", 0)))
+    d = adg.make_fv_desc(mesh)
+    h = ctypes.c_void_p()
+    rc = adg.lib().adg_fv_init(ctypes.byref(p), ctypes.byref(d), ctypes.byref(h))
+    return rc, adg.lib().adg_last_error().decode()
+
+
+@pytest.mark.parametrize("change,code,msg", [
+    (dict(N=1), adg.ADG_EINVAL, "order"), (dict(gamma=0.9), adg.ADG_EINVAL, "gas"),
+    (dict(cfl=0.0), adg.ADG_EINVAL, "cfl"), (dict(mu=1e-3), adg.ADG_EUNSUPPORTED, "inviscid"),
+    (dict(mms=1), adg.ADG_EUNSUPPORTED, "manufactured"),
+])
+def test_invalid_params_rejected_fv(change, code, msg):
+    w = I.fv_bubbles()
+    rc, err = _init_fv(dict(w["phys"], **change), w["mesh"])
+    assert rc == code and msg in err
+
+
+@pytest.mark.parametrize("change,msg", [
+    (dict(nx=0), "domain"), (dict(bc=[0, 1, 1, 1]), "pairs"), (dict(bc=[1, 1, 1, 9]), "bc"),
+])
+def test_invalid_mesh_rejected_fv(change, msg):
+    w = I.fv_bubbles()
+    rc, err = _init_fv(w["phys"], dict(w["mesh"], **change))
+    assert rc == adg.ADG_EINVAL and msg in err
+
+
+def test_null_arguments_rejected_fv():
+    L = adg.lib()
+    assert L.adg_fv_step(None, None) == adg.ADG_EINVAL
+    assert L.adg_fv_destroy(None) == adg.ADG_EINVAL
+    assert L.adg_fv_init(None, None, None) == adg.ADG_EINVAL
