@@ -364,6 +364,60 @@ def three_d_leg(steps=50, warmup=5, abc=True):
     return out
 
 
+def fv_leg(steps=200, warmup=10):
+    """The colliding bubbles with the MUSCL-Hancock scheme (7^2 patches of
+    90^2 cells: 630x630 cells of 1.59 m, inviscid, Courant factor 0.9):
+    cell updates per second of the fused step (adg_fv_step: one tile kernel
+    with the face values in LDS, a copy-back kernel that also reduces the
+    time-step bound, the clock), its rate against the step's minimum HBM
+    traffic (the state read and written once); then the split path
+    (predictor and corrector through the workspace) with its kernel times."""
+    import torch
+    from paper_1905_05524_amd import adg, model
+    from paper_1905_05524_amd import inputs as I
+    w = I.fv_bubbles()
+    m = adg.FV(w["phys"], w["mesh"])
+    m.init_state("bubbles", w["bubbles"])
+    m.compute_dt()
+    s = torch.cuda.current_stream()
+    for _ in range(warmup):
+        m.step(s)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(steps):
+        m.step(s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    m.check_health(s)
+    ms = e0.elapsed_time(e1) / steps
+    C = m.C
+    out = {"workload": "fv630x630: colliding bubbles, MUSCL-Hancock with van Albada, 630x630 cells of 1.59 m, "
+                       "inviscid, no-slip walls, Courant factor 0.9",
+           "cells": C, "steps": steps, "ms_per_step": ms,
+           "cell_updates_per_s": C / (ms / 1e3), "dof_updates_per_s": 4 * C / (ms / 1e3),
+           "min_traffic_bytes": model.fv_min_bytes() * C,
+           "GBps_vs_min_traffic": model.fv_min_bytes() * C / (ms / 1e3) / 1e9,
+           "sim_time_s": m.t}
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b, c in ev:
+        a.record(s)
+        m.predictor(s)
+        b.record(s)
+        m.corrector(s)
+        c.record(s)
+    torch.cuda.synchronize()
+    m.check_health(s)
+    p_ms = sum(a.elapsed_time(b) for a, b, _ in ev) / steps
+    c_ms = sum(b.elapsed_time(c) for _, b, c in ev) / steps
+    out["split"] = {"ms_per_step": ev[0][0].elapsed_time(ev[-1][2]) / steps, "predict_ms": p_ms,
+                    "correct_ms": c_ms,
+                    "predict_GBps": model.fv_predict_bytes() * C / (p_ms / 1e3) / 1e9,
+                    "correct_GBps": model.fv_correct_bytes() * C / (c_ms / 1e3) / 1e9}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -374,14 +428,14 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 10 device-to-device copies of MIB MiB (counter calibration)")
     ap.add_argument("--leg", choices=["batched", "adaptive", "adaptive2", "adjoint", "convergence", "three_d",
-                                      "bubble3d"],
+                                      "bubble3d", "fv"],
                     default=None,
                     help="only run this leg and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.leg:
         fn = {"batched": batched_leg, "adaptive": amr_leg, "adaptive2": lambda: amr_leg("amr9"),
               "adjoint": adjoint_leg, "convergence": convergence_leg, "three_d": three_d_leg,
-              "bubble3d": lambda: three_d_leg(abc=False)}[args.leg]
+              "bubble3d": lambda: three_d_leg(abc=False), "fv": fv_leg}[args.leg]
         print(json.dumps({args.leg: fn()}), flush=True)
         return
     if args.copy_calibration:
@@ -487,6 +541,7 @@ def main():
         out["extra"]["adjoint"] = adjoint_leg()
         out["extra"]["convergence"] = convergence_leg()
         out["extra"]["three_d"] = three_d_leg()
+        out["extra"]["finite_volume"] = fv_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -82,7 +82,7 @@ int adg_fv_workspace_bytes(const adg_fv* m, size_t* bytes);
  * step), workspace (adg_fv_workspace_bytes, 256-byte aligned), clock
  * double[4].  Workspace layout (offsets rounded up to 256 bytes): evolved
  * face values [4 faces (west, east, south, north)][4 vars][C], half-step
- * increments [4 vars][C], one time-step bound per workgroup of the
+ * density increments [C], one time-step bound per workgroup of the
  * corrector, a health flag. */
 int adg_fv_set_state(adg_fv* m, double* Q, void* workspace, double* clock);
 
@@ -107,7 +107,11 @@ int adg_fv_predictor(adg_fv* m, void* stream);
  * steps += 1 and, unless fixed_dt, dt <- the Courant step of the new Q. */
 int adg_fv_corrector(adg_fv* m, void* stream);
 
-/* One full step: adg_fv_predictor + adg_fv_corrector. */
+/* One full step with the arithmetic of adg_fv_predictor + adg_fv_corrector
+ * (and the same clock update), fused into one kernel on tiles of 32 x 8
+ * cells whose face values stay in on-chip memory, plus a copy-back kernel;
+ * the workspace's face-value area holds the new values in between (its
+ * contents afterwards are not the evolved face values). */
 int adg_fv_step(adg_fv* m, void* stream);
 
 /* Synchronises the stream, then ESTATE if any value of the bound Q is

@@ -2,15 +2,25 @@
 // second scheme, Section 3; run without viscosity on the colliding bubbles,
 // Section 4.2) for gfx950: kernels and the host side of include/adg_fv.h.
 //
-// Two kernels per step, one thread per cell, x fastest so that a wavefront
-// reads 64 consecutive cells (32 B each) and the x neighbours come from the
-// same cache lines:
-//   k_fv_predict  slopes, Hancock half step -> evolved face values and the
-//                 half-step increment (structure-of-arrays in the workspace,
-//                 one coalesced 512 B segment per face, variable and wave);
-//   k_fv_correct  Rusanov flux of the four faces from the cell's and its
-//                 neighbours' evolved values, update of Q in place (it reads
-//                 no other cell's Q), and the workgroup's time-step bound.
+// One thread per cell, x fastest so that a wavefront reads consecutive cells
+// (32 B each) and the x neighbours come from the same cache lines.
+// The step (adg_fv_step) is one fused kernel on tiles of 32 x 8 cells:
+//   k_fv_fused    each thread predicts its cell (slopes, Hancock half step),
+//                 the first 80 threads also the ring of cells around the tile
+//                 (only the face value the tile needs); the evolved face
+//                 values meet in LDS; each thread solves its four faces and
+//                 writes the new value to a second buffer (neighbouring
+//                 tiles still read the old one);
+//   k_fv_commit   copies the new values into Q and reduces the time-step
+//                 bound of each workgroup.
+// HBM traffic is the state read (plus the halo) and written twice.  The
+// split entry points keep the two halves apart, with the evolved face
+// values in the workspace (structure-of-arrays, one coalesced segment per
+// face, variable and wavefront):
+//   k_fv_predict  slopes and half step of every cell;
+//   k_fv_correct  face fluxes and update in place (a thread reads no other
+//                 cell's Q), and the workgroup's time-step bound.
+// Both paths share the per-cell device functions.
 // The background density and pressure of every row (centre, horizontal
 // faces, wall ghost centres) come from a host-built table, so no kernel
 // evaluates pow().
@@ -35,12 +45,12 @@ enum { kBgC = 0, kBgS = 1, kBgN = 2, kBgGS = 3, kBgGN = 4 };
 struct FvArgs {
   double* Q;            // [C][4]
   double* E;            // [4 faces][4 vars][C]
-  double* inc;          // [4 vars][C]
+  double* inc;          // [C] half-step density increment
   double* dtb;          // [blocks] time-step bounds
   const double* clock;  // (t, dt, -, steps)
   const double* bg;     // [nz][5][3]
   int nx, nz, C, wall;  // wall: bit f set for a wall on face f (W, E, S, N)
-  double h;
+  double h, ih;         // cell size and its reciprocal
 };
 
 struct FvBubbles {
@@ -49,13 +59,14 @@ struct FvBubbles {
 };
 
 __device__ inline double fv_pressure(const Phys& ph, const double q[4], double z) {
-  return pressure(ph, q[0], q[1], q[2], q[3], z);
+  return ph.gm1 * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) * recip(q[0]) - q[0] * (ph.geff * z));
 }
 
 // inviscid flux along d (0: x, 1: z) at height z with the perturbation
-// pressure p - p_bar in the momentum flux (pb = 0 without gravity)
-__device__ inline void fv_flux(const Phys& ph, const double q[4], double z, double pb, int d, double F[4]) {
-  const double ir = 1.0 / q[0];
+// pressure p - p_bar in the momentum flux (pb = 0 without gravity); returns
+// the signal speed |v_d| + c of the state
+__device__ inline double fv_flux(const Phys& ph, const double q[4], double z, double pb, int d, double F[4]) {
+  const double ir = recip(q[0]);
   const double u = q[1] * ir, w = q[2] * ir;
   const double p = ph.gm1 * (q[3] - 0.5 * (q[1] * u + q[2] * w) - q[0] * (ph.geff * z));
   const double pm = p - pb;
@@ -64,11 +75,13 @@ __device__ inline void fv_flux(const Phys& ph, const double q[4], double z, doub
   F[1] = q[1] * un + (d == 0 ? pm : 0.0);
   F[2] = q[2] * un + (d == 1 ? pm : 0.0);
   F[3] = un * (q[3] + p);
+  return fabs(un) + sqrt(ph.gamma * p * ir);
 }
 
 // wall ghost state of q at height z (background rb, pb there)
 __device__ inline void fv_ghost(const Phys& ph, const double q[4], double z, double rb, double pb, double g[4]) {
-  const double u = q[1] / q[0], w = q[2] / q[0];
+  const double ir = recip(q[0]);
+  const double u = q[1] * ir, w = q[2] * ir;
   double r = rb, p = pb;
   if (!ph.gravity) { r = q[0]; p = fv_pressure(ph, q, z); }
   const double geo = ph.gravity ? r * (ph.g * z) : 0.0;
@@ -80,18 +93,12 @@ __device__ inline void fv_ghost(const Phys& ph, const double q[4], double z, dou
 
 __device__ inline double van_albada(double a, double b) {
   if (!(a * b > 0.0)) return 0.0;
-  return a * b * (a + b) / (a * a + b * b);
+  return a * b * (a + b) * recip(a * a + b * b);
 }
 
-__device__ inline double fv_speed(const Phys& ph, const double q[4], double z, int d) {
-  const double p = fv_pressure(ph, q, z);
-  return fabs(q[1 + d] / q[0]) + sqrt(ph.gamma * p / q[0]);
-}
-
-// G = (F_L + F_R)/2 - s/2 (Q_R - Q_L)
-__device__ inline void rusanov_fv(const Phys& ph, int d, double z, const double QL[4], const double FL[4],
-                                  const double QR[4], const double FR[4], double G[4]) {
-  const double s = fmax(fv_speed(ph, QL, z, d), fv_speed(ph, QR, z, d));
+// G = (F_L + F_R)/2 - s/2 (Q_R - Q_L), s the larger of the two signal speeds
+__device__ inline void rusanov_fv(double s, const double QL[4], const double FL[4], const double QR[4],
+                                  const double FR[4], double G[4]) {
   for (int v = 0; v < 4; ++v) G[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * s * (QR[v] - QL[v]);
 }
 
@@ -101,13 +108,13 @@ __device__ inline void load4(const double* p, double q[4]) {
   q[0] = a.x; q[1] = a.y; q[2] = b.x; q[3] = b.y;
 }
 
-// Steps 1-2 of the scheme for one cell per thread.
-__global__ __launch_bounds__(kFvThreads) void k_fv_predict(Phys ph, FvArgs a) {
-  const int c = blockIdx.x * kFvThreads + threadIdx.x;
-  if (c >= a.C) return;
-  const int i = c % a.nx, j = c / a.nx;
+// Steps 1-2 of the scheme for cell (i, j) inside the domain: the evolved
+// face values fv[W, E, S, N][var] and the half-step density increment.
+__device__ inline void fv_predict_cell(const Phys& ph, const FvArgs& a, int i, int j, double dt, double fv[4][4],
+                                       double& inc0) {
+  const int c = j * a.nx + i;
   const double* bg = a.bg + 15 * j;
-  const double h = a.h, dt = a.clock[1];
+  const double h = a.h;
   double q[4], nb[4][4];   // neighbours W, E, S, N
   load4(a.Q + 4 * (size_t)c, q);
   if (i > 0) load4(a.Q + 4 * (size_t)(c - 1), nb[0]);
@@ -122,7 +129,6 @@ __global__ __launch_bounds__(kFvThreads) void k_fv_predict(Phys ph, FvArgs a) {
   if (j < a.nz - 1) load4(a.Q + 4 * (size_t)(c + a.nx), nb[3]);
   else if (a.wall & 8) fv_ghost(ph, q, bg[3 * kBgGN], bg[3 * kBgGN + 1], bg[3 * kBgGN + 2], nb[3]);
   else load4(a.Q + 4 * (size_t)i, nb[3]);
-  double fv[4][4];   // face values W, E, S, N
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const double sx = van_albada(q[v] - nb[0][v], nb[1][v] - q[v]);
@@ -138,103 +144,210 @@ __global__ __launch_bounds__(kFvThreads) void k_fv_predict(Phys ph, FvArgs a) {
   fv_flux(ph, fv[2], bg[3 * kBgS], bg[3 * kBgS + 2], 1, F[2]);
   fv_flux(ph, fv[3], bg[3 * kBgN], bg[3 * kBgN + 2], 1, F[3]);
   const double Sw = -ph.geff * (q[0] - bg[3 * kBgC + 1]);
-  const double k = dt / (2.0 * h);
-  const size_t C = (size_t)a.C;
+  const double k = 0.5 * dt * a.ih;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     double inc = k * ((F[0][v] - F[1][v]) + (F[2][v] - F[3][v]));
     if (v == 2) inc += 0.5 * dt * Sw;
-    a.inc[v * C + c] = inc;
+    if (v == 0) inc0 = inc;
 #pragma unroll
-    for (int f = 0; f < 4; ++f) a.E[(size_t)(4 * f + v) * C + c] = fv[f][v] + inc;
+    for (int f = 0; f < 4; ++f) fv[f][v] += inc;
   }
 }
 
-// Steps 3-4 for one cell per thread, and the workgroup's time-step bound.
-__global__ __launch_bounds__(kFvThreads) void k_fv_correct(Phys ph, FvArgs a) {
+// Steps 3-4 for cell (i, j): Rusanov flux of its four faces from its own
+// evolved face values and the facing values of its neighbours (nbv[f], or
+// the wall ghost where the face is a wall), and the update.
+__device__ inline void fv_update_cell(const Phys& ph, const FvArgs& a, int i, int j, double dt, const double fv[4][4],
+                                      const double nbv[4][4], double inc0, double out[4]) {
+  const double* bg = a.bg + 15 * j;
+  const bool wall[4] = {i == 0 && (a.wall & 1), i == a.nx - 1 && (a.wall & 2), j == 0 && (a.wall & 4),
+                        j == a.nz - 1 && (a.wall & 8)};
+  double G[4][4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const int d = f >> 1, hi = f & 1;
+    const int row = d == 0 ? kBgC : (hi ? kBgN : kBgS);
+    const double zf = bg[3 * row], rbf = bg[3 * row + 1], pbf = bg[3 * row + 2];
+    double Fo[4], Qn[4], Fn[4], sn;
+    const double so = fv_flux(ph, fv[f], zf, pbf, d, Fo);
+    if (wall[f]) {
+      fv_ghost(ph, fv[f], zf, rbf, pbf, Qn);
+      Fn[0] = -Fo[0]; Fn[1] = Fo[1]; Fn[2] = Fo[2]; Fn[3] = -Fo[3];
+      const double pg = fv_pressure(ph, Qn, zf), irg = recip(Qn[0]);
+      sn = fabs(Qn[1 + d] * irg) + sqrt(ph.gamma * pg * irg);
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Qn[v] = nbv[f][v];
+      sn = fv_flux(ph, Qn, zf, pbf, d, Fn);
+    }
+    const double sp = fmax(so, sn);
+    if (hi) rusanov_fv(sp, fv[f], Fo, Qn, Fn, G[f]);
+    else rusanov_fv(sp, Qn, Fn, fv[f], Fo, G[f]);
+  }
+  double q[4];
+  load4(a.Q + 4 * ((size_t)j * a.nx + i), q);
+  const double Sh = -ph.geff * ((q[0] + inc0) - bg[3 * kBgC + 1]);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    out[v] = q[v] - dt * a.ih * ((G[1][v] - G[0][v]) + (G[3][v] - G[2][v]));
+    if (v == 2) out[v] += dt * Sh;
+  }
+}
+
+// largest signal speed max(|u|,|w|) + c of a cell value at height z
+__device__ inline double fv_lambda(const Phys& ph, const double q[4], double z) {
+  const double ir = recip(q[0]);
+  const double cs = sqrt(ph.gamma * fv_pressure(ph, q, z) * ir);
+  return fmax(fabs(q[1]), fabs(q[2])) * ir + cs;
+}
+
+// workgroup maximum of lam -> time-step bound dtb[blockIdx]
+__device__ inline void fv_block_bound(const Phys& ph, const FvArgs& a, double lam, int block) {
   __shared__ double smax[kFvThreads / kWave];
+  lam = wave_max(lam);
+  if ((threadIdx.x & (kWave - 1)) == 0) smax[threadIdx.x / kWave] = lam;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = smax[0];
+    for (int w = 1; w < kFvThreads / kWave; ++w) m = fmax(m, smax[w]);
+    a.dtb[block] = ph.cfl * a.h / (2.0 * m);
+  }
+}
+
+// Steps 1-2, one thread per cell, face values to the workspace.
+__global__ __launch_bounds__(kFvThreads) void k_fv_predict(Phys ph, FvArgs a) {
+  const int c = blockIdx.x * kFvThreads + threadIdx.x;
+  if (c >= a.C) return;
+  double fv[4][4], inc0;
+  fv_predict_cell(ph, a, c % a.nx, c / a.nx, a.clock[1], fv, inc0);
+  const size_t C = (size_t)a.C;
+  a.inc[c] = inc0;   // the half-step density feeds the source of the update
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) a.E[(size_t)(4 * f + v) * C + c] = fv[f][v];
+}
+
+// Steps 3-4, one thread per cell, from the workspace's face values; Q is
+// updated in place (no thread reads another cell's Q), then the workgroup's
+// time-step bound of the new values.
+__global__ __launch_bounds__(kFvThreads) void k_fv_correct(Phys ph, FvArgs a) {
   const int c = blockIdx.x * kFvThreads + threadIdx.x;
   double lam = 0.0;
   if (c < a.C) {
     const int i = c % a.nx, j = c / a.nx;
-    const double* bg = a.bg + 15 * j;
-    const double h = a.h, dt = a.clock[1];
     const size_t C = (size_t)a.C;
-    double G[4][4];
+    const int nbr[4] = {i > 0 ? c - 1 : c + a.nx - 1, i < a.nx - 1 ? c + 1 : c - a.nx + 1,
+                        j > 0 ? c - a.nx : (a.nz - 1) * a.nx + i, j < a.nz - 1 ? c + a.nx : i};
+    double fv[4][4], nbv[4][4];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const int d = f >> 1, hi = f & 1;
-      const int row = d == 0 ? kBgC : (hi ? kBgN : kBgS);
-      const double zf = bg[3 * row], rbf = bg[3 * row + 1], pbf = bg[3 * row + 2];
-      double own[4], Fo[4], Qn[4], Fn[4];
+    for (int f = 0; f < 4; ++f)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) own[v] = a.E[(size_t)(4 * f + v) * C + c];
-      fv_flux(ph, own, zf, pbf, d, Fo);
-      int nbr;
-      bool wall = false;
-      if (d == 0) {
-        if (hi) { nbr = i < a.nx - 1 ? c + 1 : c - a.nx + 1; wall = i == a.nx - 1 && (a.wall & 2); }
-        else { nbr = i > 0 ? c - 1 : c + a.nx - 1; wall = i == 0 && (a.wall & 1); }
-      } else {
-        if (hi) { nbr = j < a.nz - 1 ? c + a.nx : i; wall = j == a.nz - 1 && (a.wall & 8); }
-        else { nbr = j > 0 ? c - a.nx : (a.nz - 1) * a.nx + i; wall = j == 0 && (a.wall & 4); }
+      for (int v = 0; v < 4; ++v) {
+        fv[f][v] = a.E[(size_t)(4 * f + v) * C + c];
+        nbv[f][v] = a.E[(size_t)(4 * (f ^ 1) + v) * C + nbr[f]];
       }
-      if (wall) {
-        fv_ghost(ph, own, zf, rbf, pbf, Qn);
-        Fn[0] = -Fo[0]; Fn[1] = Fo[1]; Fn[2] = Fo[2]; Fn[3] = -Fo[3];
-      } else {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Qn[v] = a.E[(size_t)(4 * (f ^ 1) + v) * C + nbr];
-        fv_flux(ph, Qn, zf, pbf, d, Fn);
-      }
-      if (hi) rusanov_fv(ph, d, zf, own, Fo, Qn, Fn, G[f]);
-      else rusanov_fv(ph, d, zf, Qn, Fn, own, Fo, G[f]);
-    }
-    double q[4];
-    load4(a.Q + 4 * (size_t)c, q);
-    const double rho_half = q[0] + a.inc[c];
-    const double Sh = -ph.geff * (rho_half - bg[3 * kBgC + 1]);
     double out[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      out[v] = q[v] - dt / h * ((G[1][v] - G[0][v]) + (G[3][v] - G[2][v]));
-      if (v == 2) out[v] += dt * Sh;
-    }
+    fv_update_cell(ph, a, i, j, a.clock[1], fv, nbv, a.inc[c], out);
     double2* o = reinterpret_cast<double2*>(a.Q + 4 * (size_t)c);
     o[0] = make_double2(out[0], out[1]);
     o[1] = make_double2(out[2], out[3]);
-    const double cs = sqrt(ph.gamma * fv_pressure(ph, out, bg[3 * kBgC]) / out[0]);
-    lam = fmax(fabs(out[1]), fabs(out[2])) / out[0] + cs;
+    lam = fv_lambda(ph, out, a.bg[15 * j]);
   }
-  lam = wave_max(lam);
-  if ((threadIdx.x & (kWave - 1)) == 0) smax[threadIdx.x / kWave] = lam;
+  fv_block_bound(ph, a, lam, blockIdx.x);
+}
+
+// One step fused into one kernel on tiles of kTX x kTZ cells: every thread
+// predicts its cell, the first threads also the ring of cells around the
+// tile (each only for the face value the tile needs); the evolved face
+// values meet in LDS; the update goes to Qn (other tiles still read Q).
+constexpr int kTX = 32, kTZ = 8;
+static_assert(kTX * kTZ == kFvThreads, "one thread per tile cell");
+
+__global__ __launch_bounds__(kFvThreads) void k_fv_fused(Phys ph, FvArgs a, double* Qn) {
+  // face values by face (W, E, S, N), variable, local row and column with a
+  // one-cell border for the ring: [4][4][kTZ + 2][kTX + 2]
+  __shared__ double sF[4][4][kTZ + 2][kTX + 2];
+  const int t = threadIdx.x, tx = t % kTX, tz = t / kTX;
+  const int x0 = blockIdx.x * kTX, z0 = blockIdx.y * kTZ;
+  const int ew = min(kTX, a.nx - x0), eh = min(kTZ, a.nz - z0);   // extent of the tile inside the domain
+  const double dt = a.clock[1];
+  const bool inside = tx < ew && tz < eh;
+  double fv[4][4], inc0 = 0.0;
+  if (inside) {
+    fv_predict_cell(ph, a, x0 + tx, z0 + tz, dt, fv, inc0);
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sF[f][v][tz + 1][tx + 1] = fv[f][v];
+  }
+  // ring: left and right columns (the face towards the tile), bottom and top rows
+  if (t < 2 * kTZ + 2 * kTX) {
+    int rx, rz, f;
+    if (t < kTZ) { rx = -1; rz = t; f = 1; }
+    else if (t < 2 * kTZ) { rx = ew; rz = t - kTZ; f = 0; }
+    else if (t < 2 * kTZ + kTX) { rx = t - 2 * kTZ; rz = -1; f = 3; }
+    else { rx = t - 2 * kTZ - kTX; rz = eh; f = 2; }
+    const bool used = (f < 2) ? rz < eh : rx < ew;
+    int gi = x0 + rx, gj = z0 + rz;
+    bool ok = used;
+    if (gi < 0 || gi >= a.nx) { ok = ok && !(a.wall & 3); gi = gi < 0 ? gi + a.nx : gi - a.nx; }
+    if (gj < 0 || gj >= a.nz) { ok = ok && !(a.wall & 12); gj = gj < 0 ? gj + a.nz : gj - a.nz; }
+    if (ok) {
+      double rv[4][4], rinc;
+      fv_predict_cell(ph, a, gi, gj, dt, rv, rinc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // f is known only at run time: select with constant indices so rv stays in registers
+        const double val = f == 0 ? rv[0][v] : (f == 1 ? rv[1][v] : (f == 2 ? rv[2][v] : rv[3][v]));
+        sF[f][v][rz + 1][rx + 1] = val;
+      }
+    }
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = smax[0];
-    for (int w = 1; w < kFvThreads / kWave; ++w) m = fmax(m, smax[w]);
-    a.dtb[blockIdx.x] = ph.cfl * a.h / (2.0 * m);
+  if (inside) {
+    double nbv[4][4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      nbv[0][v] = sF[1][v][tz + 1][tx];       // west neighbour's east value
+      nbv[1][v] = sF[0][v][tz + 1][tx + 2];   // east neighbour's west value
+      nbv[2][v] = sF[3][v][tz][tx + 1];       // south neighbour's north value
+      nbv[3][v] = sF[2][v][tz + 2][tx + 1];   // north neighbour's south value
+    }
+    double out[4];
+    fv_update_cell(ph, a, x0 + tx, z0 + tz, dt, fv, nbv, inc0, out);
+    double2* o = reinterpret_cast<double2*>(Qn + 4 * ((size_t)(z0 + tz) * a.nx + x0 + tx));
+    o[0] = make_double2(out[0], out[1]);
+    o[1] = make_double2(out[2], out[3]);
   }
+}
+
+// Q <- Qn, and the workgroup's time-step bound of the new values.
+__global__ __launch_bounds__(kFvThreads) void k_fv_commit(Phys ph, FvArgs a, const double* Qn) {
+  const int c = blockIdx.x * kFvThreads + threadIdx.x;
+  double lam = 0.0;
+  if (c < a.C) {
+    double q[4];
+    load4(Qn + 4 * (size_t)c, q);
+    double2* o = reinterpret_cast<double2*>(a.Q + 4 * (size_t)c);
+    o[0] = make_double2(q[0], q[1]);
+    o[1] = make_double2(q[2], q[3]);
+    lam = fv_lambda(ph, q, a.bg[15 * (c / a.nx)]);
+  }
+  fv_block_bound(ph, a, lam, blockIdx.x);
 }
 
 // time-step bound of every workgroup of cells from the current Q
 __global__ __launch_bounds__(kFvThreads) void k_fv_dt(Phys ph, FvArgs a) {
-  __shared__ double smax[kFvThreads / kWave];
   const int c = blockIdx.x * kFvThreads + threadIdx.x;
   double lam = 0.0;
   if (c < a.C) {
     double q[4];
     load4(a.Q + 4 * (size_t)c, q);
-    const double cs = sqrt(ph.gamma * fv_pressure(ph, q, a.bg[15 * (c / a.nx)]) / q[0]);
-    lam = fmax(fabs(q[1]), fabs(q[2])) / q[0] + cs;
+    lam = fv_lambda(ph, q, a.bg[15 * (c / a.nx)]);
   }
-  lam = wave_max(lam);
-  if ((threadIdx.x & (kWave - 1)) == 0) smax[threadIdx.x / kWave] = lam;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = smax[0];
-    for (int w = 1; w < kFvThreads / kWave; ++w) m = fmax(m, smax[w]);
-    a.dtb[blockIdx.x] = ph.cfl * a.h / (2.0 * m);
-  }
+  fv_block_bound(ph, a, lam, blockIdx.x);
 }
 
 // cell-centre initial values (kind 0 bubbles, kind 1 advected density wave)
@@ -335,7 +448,7 @@ FvArgs fv_args(const adg_fv* m) {
   a.inc = ws ? reinterpret_cast<double*>(ws + m->off_inc) : nullptr;
   a.dtb = ws ? reinterpret_cast<double*>(ws + m->off_dtb) : nullptr;
   a.clock = m->clock; a.bg = m->d_bg;
-  a.nx = m->desc.nx; a.nz = m->desc.nz; a.C = m->C; a.h = m->desc.h;
+  a.nx = m->desc.nx; a.nz = m->desc.nz; a.C = m->C; a.h = m->desc.h; a.ih = 1.0 / m->desc.h;
   a.wall = 0;
   for (int f = 0; f < 4; ++f)
     if (m->desc.bc[f] == ADG_BC_WALL) a.wall |= 1 << f;
@@ -392,7 +505,7 @@ int adg_fv_init(const adg_params* prm, const adg_fv_desc* mesh, adg_fv** out) {
   const size_t C = (size_t)m->C;
   size_t off = 0;
   m->off_e = off; off = align256_fv(off + sizeof(double) * 16 * C);
-  m->off_inc = off; off = align256_fv(off + sizeof(double) * 4 * C);
+  m->off_inc = off; off = align256_fv(off + sizeof(double) * C);
   m->off_dtb = off; off = align256_fv(off + sizeof(double) * m->blocks);
   m->off_h = off; off = align256_fv(off + sizeof(int));
   m->ws_bytes = off;
@@ -479,9 +592,19 @@ int adg_fv_corrector(adg_fv* m, void* stream) {
 }
 
 int adg_fv_step(adg_fv* m, void* stream) {
-  int rc = adg_fv_predictor(m, stream);
+  int rc = fv_need_state(m);
   if (rc) return rc;
-  return adg_fv_corrector(m, stream);
+  hipStream_t s = (hipStream_t)stream;
+  const FvArgs a = fv_args(m);
+  double* Qn = a.E;   // the fused step keeps its new values in the face-value area
+  const dim3 tiles((m->desc.nx + kTX - 1) / kTX, (m->desc.nz + kTZ - 1) / kTZ);
+  hipLaunchKernelGGL(k_fv_fused, tiles, dim3(kFvThreads), 0, s, m->ph, a, Qn);
+  rc = check_launch("fv_fused");
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_fv_commit, dim3(m->blocks), dim3(kFvThreads), 0, s, m->ph, a, (const double*)Qn);
+  rc = check_launch("fv_commit");
+  if (rc) return rc;
+  return launch_clock(m->clock, a.dtb, nullptr, nullptr, 1, m->blocks, 1, m->prm.fixed_dt ? 0 : 1, s);
 }
 
 int adg_fv_check_health(adg_fv* m, void* stream) {

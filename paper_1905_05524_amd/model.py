@@ -118,3 +118,24 @@ def corrector3_bytes(N: int) -> int:
 
 def dofs3(cells: int, N: int) -> int:
     return cells * (N + 1) ** 3 * 5
+
+
+# ------------------------------------------------------------- finite volume
+# MUSCL-Hancock, per cell and step (8-byte words, each read or written once):
+#   predict: read Q (4), write the evolved face values (16) and the half-step
+#            density increment (1);
+#   correct: read the face values of the cell and the facing values of its
+#            four neighbours (32), the increment (1) and Q (4), write Q (4).
+# The minimum for a step fused into one kernel is the state read and written
+# once: 8 words.
+
+def fv_predict_bytes() -> int:
+    return 8 * (4 + 16 + 1)
+
+
+def fv_correct_bytes() -> int:
+    return 8 * (32 + 1 + 4 + 4)
+
+
+def fv_min_bytes() -> int:
+    return 8 * 8

@@ -98,6 +98,21 @@ def test_step_and_time_step_match_oracle(case):
     assert abs(clock[1] - O.fv_dt(phys, m, ref)) <= 1e-13 * clock[1]
 
 
+def test_split_step_matches_oracle(case):
+    """The two-kernel path (face values through the workspace) gives the
+    step of the fused kernel and of the oracle."""
+    phys, m, Q = case
+    dt = 0.5 * O.fv_dt(phys, m, Q)
+    ref = O.fv_step(phys, m, Q, dt)
+    g = adg.FV(phys, m)
+    g.set_state(Q, t=0.0, dt=dt)
+    g.predictor()
+    g.corrector()
+    torch.cuda.synchronize()
+    assert np.all(relerr(g.Q.cpu().numpy(), ref) <= TOL)
+    assert abs(g.dt - O.fv_dt(phys, m, ref)) <= 1e-13 * g.dt
+
+
 def test_compute_dt_matches_oracle(case):
     phys, m, Q = case
     g = adg.FV(phys, m)
