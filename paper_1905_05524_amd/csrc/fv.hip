@@ -156,41 +156,45 @@ __device__ inline void fv_predict_cell(const Phys& ph, const FvArgs& a, int i, i
 }
 
 // Steps 3-4 for cell (i, j): Rusanov flux of its four faces from its own
-// evolved face values and the facing values of its neighbours (nbv[f], or
-// the wall ghost where the face is a wall), and the update.
-__device__ inline void fv_update_cell(const Phys& ph, const FvArgs& a, int i, int j, double dt, const double fv[4][4],
-                                      const double nbv[4][4], double inc0, double out[4]) {
+// evolved face value and the facing value of the neighbour (or the wall
+// ghost where the face is a wall), and the update.  fetch(f, own, nb) loads
+// face f's two values, so that only one face's data is live at a time.
+template <class Fetch>
+__device__ inline void fv_update_cell(const Phys& ph, const FvArgs& a, int i, int j, double dt, Fetch fetch,
+                                      double inc0, double out[4]) {
   const double* bg = a.bg + 15 * j;
   const bool wall[4] = {i == 0 && (a.wall & 1), i == a.nx - 1 && (a.wall & 2), j == 0 && (a.wall & 4),
                         j == a.nz - 1 && (a.wall & 8)};
-  double G[4][4];
+  double dx[4], dz[4];   // G_east - G_west, G_north - G_south
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     const int d = f >> 1, hi = f & 1;
     const int row = d == 0 ? kBgC : (hi ? kBgN : kBgS);
     const double zf = bg[3 * row], rbf = bg[3 * row + 1], pbf = bg[3 * row + 2];
-    double Fo[4], Qn[4], Fn[4], sn;
-    const double so = fv_flux(ph, fv[f], zf, pbf, d, Fo);
+    double own[4], Qn[4], Fo[4], Fn[4], G[4], sn;
+    fetch(f, own, Qn);
+    const double so = fv_flux(ph, own, zf, pbf, d, Fo);
     if (wall[f]) {
-      fv_ghost(ph, fv[f], zf, rbf, pbf, Qn);
+      fv_ghost(ph, own, zf, rbf, pbf, Qn);
       Fn[0] = -Fo[0]; Fn[1] = Fo[1]; Fn[2] = Fo[2]; Fn[3] = -Fo[3];
       const double pg = fv_pressure(ph, Qn, zf), irg = recip(Qn[0]);
       sn = fabs(Qn[1 + d] * irg) + sqrt(ph.gamma * pg * irg);
     } else {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Qn[v] = nbv[f][v];
       sn = fv_flux(ph, Qn, zf, pbf, d, Fn);
     }
     const double sp = fmax(so, sn);
-    if (hi) rusanov_fv(sp, fv[f], Fo, Qn, Fn, G[f]);
-    else rusanov_fv(sp, Qn, Fn, fv[f], Fo, G[f]);
+    if (hi) rusanov_fv(sp, own, Fo, Qn, Fn, G);
+    else rusanov_fv(sp, Qn, Fn, own, Fo, G);
+    double* acc = d == 0 ? dx : dz;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = hi ? G[v] + acc[v] : -G[v];
   }
   double q[4];
   load4(a.Q + 4 * ((size_t)j * a.nx + i), q);
   const double Sh = -ph.geff * ((q[0] + inc0) - bg[3 * kBgC + 1]);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    out[v] = q[v] - dt * a.ih * ((G[1][v] - G[0][v]) + (G[3][v] - G[2][v]));
+    out[v] = q[v] - dt * a.ih * (dx[v] + dz[v]);
     if (v == 2) out[v] += dt * Sh;
   }
 }
@@ -240,16 +244,15 @@ __global__ __launch_bounds__(kFvThreads) void k_fv_correct(Phys ph, FvArgs a) {
     const size_t C = (size_t)a.C;
     const int nbr[4] = {i > 0 ? c - 1 : c + a.nx - 1, i < a.nx - 1 ? c + 1 : c - a.nx + 1,
                         j > 0 ? c - a.nx : (a.nz - 1) * a.nx + i, j < a.nz - 1 ? c + a.nx : i};
-    double fv[4][4], nbv[4][4];
-#pragma unroll
-    for (int f = 0; f < 4; ++f)
+    auto fetch = [&](int f, double own[4], double nb[4]) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        fv[f][v] = a.E[(size_t)(4 * f + v) * C + c];
-        nbv[f][v] = a.E[(size_t)(4 * (f ^ 1) + v) * C + nbr[f]];
+        own[v] = a.E[(size_t)(4 * f + v) * C + c];
+        nb[v] = a.E[(size_t)(4 * (f ^ 1) + v) * C + nbr[f]];
       }
+    };
     double out[4];
-    fv_update_cell(ph, a, i, j, a.clock[1], fv, nbv, a.inc[c], out);
+    fv_update_cell(ph, a, i, j, a.clock[1], fetch, a.inc[c], out);
     double2* o = reinterpret_cast<double2*>(a.Q + 4 * (size_t)c);
     o[0] = make_double2(out[0], out[1]);
     o[1] = make_double2(out[2], out[3]);
@@ -274,14 +277,6 @@ __global__ __launch_bounds__(kFvThreads) void k_fv_fused(Phys ph, FvArgs a, doub
   const int ew = min(kTX, a.nx - x0), eh = min(kTZ, a.nz - z0);   // extent of the tile inside the domain
   const double dt = a.clock[1];
   const bool inside = tx < ew && tz < eh;
-  double fv[4][4], inc0 = 0.0;
-  if (inside) {
-    fv_predict_cell(ph, a, x0 + tx, z0 + tz, dt, fv, inc0);
-#pragma unroll
-    for (int f = 0; f < 4; ++f)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) sF[f][v][tz + 1][tx + 1] = fv[f][v];
-  }
   // ring: left and right columns (the face towards the tile), bottom and top rows
   if (t < 2 * kTZ + 2 * kTX) {
     int rx, rz, f;
@@ -305,18 +300,30 @@ __global__ __launch_bounds__(kFvThreads) void k_fv_fused(Phys ph, FvArgs a, doub
       }
     }
   }
+  double inc0 = 0.0;
+  if (inside) {
+    double fv[4][4];
+    fv_predict_cell(ph, a, x0 + tx, z0 + tz, dt, fv, inc0);
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sF[f][v][tz + 1][tx + 1] = fv[f][v];
+  }
   __syncthreads();
   if (inside) {
-    double nbv[4][4];
+    // face values from LDS, one face at a time: the cell's own (not held
+    // across the barrier) and the facing value of the neighbour (west
+    // neighbour's east value, east neighbour's west value, ...)
+    const int nzz[4] = {tz + 1, tz + 1, tz, tz + 2}, nxx[4] = {tx, tx + 2, tx + 1, tx + 1};
+    auto fetch = [&](int f, double own[4], double nb[4]) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      nbv[0][v] = sF[1][v][tz + 1][tx];       // west neighbour's east value
-      nbv[1][v] = sF[0][v][tz + 1][tx + 2];   // east neighbour's west value
-      nbv[2][v] = sF[3][v][tz][tx + 1];       // south neighbour's north value
-      nbv[3][v] = sF[2][v][tz + 2][tx + 1];   // north neighbour's south value
-    }
+      for (int v = 0; v < 4; ++v) {
+        own[v] = sF[f][v][tz + 1][tx + 1];
+        nb[v] = sF[f ^ 1][v][nzz[f]][nxx[f]];
+      }
+    };
     double out[4];
-    fv_update_cell(ph, a, x0 + tx, z0 + tz, dt, fv, nbv, inc0, out);
+    fv_update_cell(ph, a, x0 + tx, z0 + tz, dt, fetch, inc0, out);
     double2* o = reinterpret_cast<double2*>(Qn + 4 * ((size_t)(z0 + tz) * a.nx + x0 + tx));
     o[0] = make_double2(out[0], out[1]);
     o[1] = make_double2(out[2], out[3]);
