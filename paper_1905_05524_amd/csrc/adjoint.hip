@@ -147,6 +147,16 @@ __device__ inline void vtab_load(const double* g, double (&M)[HalfA<n>::nh][n]) 
     }
 }
 
+// the same table left to the compiler: its entries are uniform, so they can
+// live in scalar registers
+template <int n>
+__device__ inline void stab_load(const double* g, double (&M)[HalfA<n>::nh][n]) {
+#pragma unroll
+  for (int i = 0; i < HalfA<n>::nh; ++i)
+#pragma unroll
+    for (int m = 0; m < n; ++m) M[i][m] = g[i * n + m];
+}
+
 // out = M in along a line (M centro-antisymmetric, first nh rows stored)
 template <int n>
 __device__ inline void line_M(const double (&M)[HalfA<n>::nh][n], int base, int stride, const double* src,
@@ -397,15 +407,22 @@ __global__ __launch_bounds__(kWave) void k_face_adj(Phys ph, AdjArgs a) {
 }
 
 // ------------------------------------------------------- reverse predictor
+// One workgroup of n wavefronts per cell: wavefront b owns time level b.
+// The reverse of every time level of a sweep (and of the final pass) is
+// independent of the others once the sweep's residual adjoints are known, so
+// the n levels run side by side; the workgroup synchronises only where the
+// levels meet (the time matrix mixes them).  Each wavefront has its own LDS
+// slice buffers; the iterate adjoints Lq and the residual adjoints sR are
+// shared.
 template <int n>
-__global__ __launch_bounds__(kWave) void k_pred_adj(Phys ph, AdjArgs a) {
+__global__ __launch_bounds__(kWave * n) void k_pred_adj(Phys ph, AdjArgs a) {
   constexpr int nn = n * n, sl = 4 * nn;
   __shared__ double Lq[n * sl];        // adjoint of the iterate at every time node
-  __shared__ double sq[sl];            // state slice
-  __shared__ double sg[2][sl];         // its gradients
-  __shared__ double sA[2][sl];         // adjoint work (flux adjoints, then gradient adjoints)
   __shared__ double sR[n * sl];        // residual adjoints of one reverse sweep
-  const int c = blockIdx.x, lane = threadIdx.x;
+  __shared__ double sW[n][3 * sl];     // per wavefront: state slice, then gradients / adjoint work
+  const int c = blockIdx.x, b = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  double* sq = sW[b];
+  double* sg = sW[b] + sl;             // [2][sl]: gradients along x and z, reused for the adjoint work
   const bool node = lane < nn;
   const int l = node ? lane : 0;
   const int jz = l / n, ix = l % n;
@@ -421,27 +438,28 @@ __global__ __launch_bounds__(kWave) void k_pred_adj(Phys ph, AdjArgs a) {
   background(ph, z, rb, pb);
   (void)pb;
   double Dv[HalfA<n>::nh][n];
-  vtab_load<n>(gt + GTab::d(n), Dv);
+  stab_load<n>(gt + GTab::d(n), Dv);
   const double* Qc = a.Qn + (size_t)c * sl;
   const double* lin = a.lam_in + (size_t)c * sl;
   const double* lfd = a.lamFD + (size_t)c * 32 * n;
   const double* store = a.store + (size_t)c * a.iters * n * sl;
   const int I = a.iters;
 
-  // (a) adjoints of Q*, of the averaged state, fluxes and source
+  // (a) adjoints of Q*, of the averaged state, fluxes and source (every
+  // wavefront computes them for its own use)
   double aQn[4], aQb[4], aFbx[4], aFbz[4], aSb = 0.0;
   double lq[4];
   for (int v = 0; v < 4; ++v) lq[v] = node ? lin[v * nn + l] : 0.0;
-  for (int v = 0; v < 4; ++v) aQn[v] = lq[v];
+  for (int v = 0; v < 4; ++v) aQn[v] = b == 0 ? lq[v] : 0.0;   // direct part, counted once
   aSb = dt * lq[2];
   if (node)
     for (int v = 0; v < 4; ++v) sq[v * nn + l] = lq[v];
   wave_sync_a();
   {
     double Wv[HalfA<n>::nh][n];
-    vtab_load<n>(gt + GTab::dw(n), Wv);
+    stab_load<n>(gt + GTab::dw(n), Wv);
     // lambda_Fbar = (dt/h) Dw^T lambda_Q* along x (rows) and z (columns)
-    if (job) line_MT<n>(Wv, jbase, jstride, sq, sA[dir], dt * ih);
+    if (job) line_MT<n>(Wv, jbase, jstride, sq, sg + dir * sl, dt * ih);
   }
   wave_sync_a();
   if (node) {
@@ -451,95 +469,85 @@ __global__ __launch_bounds__(kWave) void k_pred_adj(Phys ph, AdjArgs a) {
       // face extrapolations: x faces use row jz, z faces column ix
       aQb[v] = e0i * lfd[(0 * 2 + 0) * 4 * n + v * n + jz] + e1i * lfd[(1 * 2 + 0) * 4 * n + v * n + jz] +
                e0j * lfd[(2 * 2 + 0) * 4 * n + v * n + ix] + e1j * lfd[(3 * 2 + 0) * 4 * n + v * n + ix];
-      aFbx[v] = sA[0][v * nn + l] + e0i * lfd[(0 * 2 + 1) * 4 * n + v * n + jz] +
+      aFbx[v] = sg[v * nn + l] + e0i * lfd[(0 * 2 + 1) * 4 * n + v * n + jz] +
                 e1i * lfd[(1 * 2 + 1) * 4 * n + v * n + jz];
-      aFbz[v] = sA[1][v * nn + l] + e0j * lfd[(2 * 2 + 1) * 4 * n + v * n + ix] +
+      aFbz[v] = sg[sl + v * nn + l] + e0j * lfd[(2 * 2 + 1) * 4 * n + v * n + ix] +
                 e1j * lfd[(3 * 2 + 1) * 4 * n + v * n + ix];
     }
   }
   wave_sync_a();
 
-  // reverse of "flux/source at iterate slice qb": given aF (x,z) and aSw per
-  // node, adds the state adjoint (direct + through the gradients) to Lq[b]
-  auto slice_vjp = [&](const double* qsrc, bool from_global, int b, const double aFx[4], const double aFz[4],
-                       double aSw, const double add[4], bool accumulate) {
+  // reverse of "flux/source at this wavefront's time level": given aF (x, z)
+  // and aSw per node, the state adjoint (direct + through the gradients)
+  // plus add[] becomes Lq[b]
+  auto slice_vjp = [&](const double* qsrc, const double aFx[4], const double aFz[4], double aSw,
+                       const double add[4]) {
     if (node)
-      for (int v = 0; v < 4; ++v) sq[v * nn + l] = from_global ? qsrc[v * nn + l] : Qc[v * nn + l];
+      for (int v = 0; v < 4; ++v) sq[v * nn + l] = qsrc[v * nn + l];
     wave_sync_a();
-    if (job) line_M<n>(Dv, jbase, jstride, sq, sg[dir], ih);     // gradients
+    if (job) line_M<n>(Dv, jbase, jstride, sq, sg + dir * sl, ih);     // gradients
     wave_sync_a();
-    double agx[4] = {0, 0, 0, 0}, agz[4] = {0, 0, 0, 0}, aq[4] = {0, 0, 0, 0};
+    double aq[4] = {0, 0, 0, 0};
     if (node) {
-      double q[4], gx[4], gz[4];
-      for (int v = 0; v < 4; ++v) { q[v] = sq[v * nn + l]; gx[v] = sg[0][v * nn + l]; gz[v] = sg[1][v * nn + l]; }
+      double q[4], gx[4], gz[4], agx[4], agz[4];
+      for (int v = 0; v < 4; ++v) { q[v] = sq[v * nn + l]; gx[v] = sg[v * nn + l]; gz[v] = sg[sl + v * nn + l]; }
       flux_source_vjp(ph, q, gx, gz, z, rb, aFx, aFz, aSw, aq, agx, agz);
-      for (int v = 0; v < 4; ++v) { sA[0][v * nn + l] = agx[v]; sA[1][v * nn + l] = agz[v]; }
+      for (int v = 0; v < 4; ++v) { sg[v * nn + l] = agx[v]; sg[sl + v * nn + l] = agz[v]; }
     }
     wave_sync_a();
     // gradient adjoints back to the state: (1/h) D^T along each direction
-    if (job) line_MT<n>(Dv, jbase, jstride, sA[dir], sA[dir], ih);
+    if (job) line_MT<n>(Dv, jbase, jstride, sg + dir * sl, sg + dir * sl, ih);
     wave_sync_a();
-    if (node) {
-      for (int v = 0; v < 4; ++v) {
-        const double val = aq[v] + sA[0][v * nn + l] + sA[1][v * nn + l] + add[v];
-        if (accumulate) Lq[b * sl + v * nn + l] += val;
-        else Lq[b * sl + v * nn + l] = val;
-      }
-    }
+    if (node)
+      for (int v = 0; v < 4; ++v) Lq[b * sl + v * nn + l] = aq[v] + sg[v * nn + l] + sg[sl + v * nn + l] + add[v];
     wave_sync_a();
   };
 
   // (b) final pass: F, S and q at the last iterate, averaged with w_b
-  for (int b = 0; b < n; ++b) {
+  {
     const double wb = gt[GTab::W * n + b];
     double aFx[4], aFz[4], add[4];
     for (int v = 0; v < 4; ++v) { aFx[v] = wb * aFbx[v]; aFz[v] = wb * aFbz[v]; add[v] = wb * aQb[v]; }
-    const double* qb = store + ((size_t)(I - 1) * n + b) * sl;
-    slice_vjp(qb, true, b, aFx, aFz, wb * aSb, add, false);
+    slice_vjp(store + ((size_t)(I - 1) * n + b) * sl, aFx, aFz, wb * aSb, add);
   }
+  __syncthreads();
 
   // (c) Picard sweeps in reverse: q^{k+1}[a] = Q^n + dt sum_b P[a][b] R(q^k[b])
+  const double* prow = gt + GTab::pt(n) + b * n;   // P[a][b] over a
   for (int it = I - 1; it >= 0; --it) {
+    if (node)
+      for (int v = 0; v < 4; ++v) {
+        aQn[v] += Lq[b * sl + v * nn + l];
+        double s = 0.0;
+        for (int a2 = 0; a2 < n; ++a2) s = fma(prow[a2], Lq[a2 * sl + v * nn + l], s);
+        sR[b * sl + v * nn + l] = dt * s;
+      }
+    __syncthreads();   // every level's Lq read before any is overwritten
+    // R = S - (1/h)(Dx Fx + Dz Fz): lambda_F = -(1/h) D^T lambda_R, lambda_Sw = lambda_R[2]
+    if (job) line_MT<n>(Dv, jbase, jstride, sR + b * sl, sg + dir * sl, -ih);
+    wave_sync_a();
+    double aFx[4], aFz[4];
+    for (int v = 0; v < 4; ++v) {
+      aFx[v] = node ? sg[v * nn + l] : 0.0;
+      aFz[v] = node ? sg[sl + v * nn + l] : 0.0;
+    }
+    const double aSw = node ? sR[b * sl + 2 * nn + l] : 0.0;
+    wave_sync_a();
+    const double zero[4] = {0, 0, 0, 0};
+    slice_vjp(it > 0 ? store + ((size_t)(it - 1) * n + b) * sl : Qc, aFx, aFz, aSw, zero);
+    __syncthreads();   // every level's Lq written before the next sweep reads them
+  }
+  // q^0[b] = Q^n for every b; sum the levels' shares through LDS
+  if (node)
+    for (int v = 0; v < 4; ++v) sR[b * sl + v * nn + l] = aQn[v] + Lq[b * sl + v * nn + l];
+  __syncthreads();
+  if (b == 0 && node) {
+    double* out = a.lam_out + (size_t)c * sl;
     for (int v = 0; v < 4; ++v) {
       double s = 0.0;
-      for (int a2 = 0; a2 < n; ++a2) s += node ? Lq[a2 * sl + v * nn + l] : 0.0;
-      aQn[v] += s;
+      for (int w = 0; w < n; ++w) s += sR[w * sl + v * nn + l];
+      out[v * nn + l] = s;
     }
-    if (node)
-      for (int b = 0; b < n; ++b) {
-        const double* prow = gt + GTab::pt(n) + b * n;   // P[a][b] over a
-        for (int v = 0; v < 4; ++v) {
-          double s = 0.0;
-          for (int a2 = 0; a2 < n; ++a2) s = fma(prow[a2], Lq[a2 * sl + v * nn + l], s);
-          sR[b * sl + v * nn + l] = dt * s;
-        }
-      }
-    wave_sync_a();
-    for (int b = 0; b < n; ++b) {
-      // R = S - (1/h)(Dx Fx + Dz Fz): lambda_F = -(1/h) D^T lambda_R, lambda_Sw = lambda_R[2]
-      double aFx[4], aFz[4];
-      if (job) line_MT<n>(Dv, jbase, jstride, sR + b * sl, sA[dir], -ih);
-      wave_sync_a();
-      for (int v = 0; v < 4; ++v) {
-        aFx[v] = node ? sA[0][v * nn + l] : 0.0;
-        aFz[v] = node ? sA[1][v * nn + l] : 0.0;
-      }
-      const double aSw = node ? sR[b * sl + 2 * nn + l] : 0.0;
-      wave_sync_a();
-      const double zero[4] = {0, 0, 0, 0};
-      const double* qb = it > 0 ? store + ((size_t)(it - 1) * n + b) * sl : nullptr;
-      slice_vjp(qb, it > 0, b, aFx, aFz, aSw, zero, false);
-    }
-  }
-  // q^0[b] = Q^n for every b
-  for (int v = 0; v < 4; ++v) {
-    double s = 0.0;
-    for (int b = 0; b < n; ++b) s += node ? Lq[b * sl + v * nn + l] : 0.0;
-    aQn[v] += s;
-  }
-  if (node) {
-    double* out = a.lam_out + (size_t)c * sl;
-    for (int v = 0; v < 4; ++v) out[v * nn + l] = aQn[v];
   }
 }
 
@@ -648,7 +656,7 @@ template <int n>
 static int adj_n(const Group& g, AdjArgs a, hipStream_t s) {
   hipLaunchKernelGGL(k_lift_adj<n>, dim3(g.C), dim3(kWave), 0, s, g.ph, a);
   hipLaunchKernelGGL(k_face_adj<n>, dim3(g.C), dim3(kWave), 0, s, g.ph, a);
-  hipLaunchKernelGGL(k_pred_adj<n>, dim3(g.C), dim3(kWave), 0, s, g.ph, a);
+  hipLaunchKernelGGL(k_pred_adj<n>, dim3(g.C), dim3(kWave * n), 0, s, g.ph, a);
   return check_launch("step adjoint");
 }
 
