@@ -237,3 +237,29 @@ def test_full_size_bubble_step_on_sampled_cells():
         c = (k * ny + j) * nx + i
         e = relerr(got[c][None], ref, scales(Q))
         assert np.all(e <= TOL), ((i, j, k), e)
+
+
+def test_large_grid_step_on_sampled_cells():
+    """64^3 cells at N = 3 (262,144 cells, 671 MB of state): one step,
+    sampled cells against the oracle on the 3 x 3 x 3 block around each."""
+    phys = dict(I.ATMO, N=3, picard_iters=0, mu=0.005, mms=0, cfl=0.4)
+    m = I.mesh3(64, 1000.0)
+    Q = O.ic3(phys, m, "bubbles", [I.cosine_bubble3()])
+    Q = I.perturb3(Q, seed=64, rel=1e-4, vel=0.05)
+    dt = O.dt3(phys, m, Q)
+    g = adg.Mesh3(phys, m, fixed_dt=True)
+    g.set_state(Q, t=0.0, dt=dt)
+    g.step()
+    torch.cuda.synchronize()
+    n = 4
+    G = Q.reshape(64, 64, 64, 5, n, n, n)
+    rng = np.random.default_rng(5)
+    cells = [(0, 0, 0), (63, 63, 63), (63, 0, 31)] + [tuple(int(v) for v in rng.integers(0, 64, 3)) for _ in range(3)]
+    for (i, j, k) in cells:
+        sm, lo, loc = sub_block(m, (i, j, k))
+        sub = G[lo[2]:lo[2] + sm["nz"], lo[1]:lo[1] + sm["ny"], lo[0]:lo[0] + sm["nx"]].reshape(-1, 5, n, n, n)
+        out = O.step3(phys, sm, np.ascontiguousarray(sub), 0.0, dt)
+        ref = out[(loc[2] * sm["ny"] + loc[1]) * sm["nx"] + loc[0]][None]
+        c = (k * 64 + j) * 64 + i
+        got = g.Q[c].cpu().numpy()[None]
+        assert np.all(relerr(got, ref, scales(Q)) <= TOL), (i, j, k)
