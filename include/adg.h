@@ -218,6 +218,24 @@ int adg_adjoint_workspace_bytes(const adg_mesh* m, size_t* bytes);
 int adg_step_adjoint(adg_mesh* m, const double* Q_n, const double* lam_np1, double* lam_n, void* adj_ws,
                      void* stream);
 
+/* The same step adjoint without the predictor recompute, for callers that
+ * kept the forward step's Picard iterates and face data in device memory
+ * (288 GB of HBM hold them for thousands of steps of a mid-size mesh):
+ *   adg_keep_bytes: sizes of one step's iterate store [C][I][n][4][n][n]
+ *     and face data [C][4][2][4][n];
+ *   adg_step_keep: one step like adg_step (predictor, corrector, clock),
+ *     writing that step's iterates to store and its face data to fd
+ *     (caller-owned device buffers of those sizes); the bound workspace's
+ *     face data are not used;
+ *   adg_step_adjoint_kept: as adg_step_adjoint for the step that started
+ *     from Q_n, reading store and fd as adg_step_keep wrote them; the
+ *     result equals adg_step_adjoint's (the same iterates, not recomputed).
+ * Conforming meshes only (EUNSUPPORTED otherwise). */
+int adg_keep_bytes(const adg_mesh* m, size_t* store_bytes, size_t* fd_bytes);
+int adg_step_keep(adg_mesh* m, double* store, double* fd, void* stream);
+int adg_step_adjoint_kept(adg_mesh* m, const double* Q_n, const double* store, const double* fd,
+                          const double* lam_np1, double* lam_n, void* adj_ws, void* stream);
+
 /* Bound Q <- initial state of the nodal perturbation theta_prime (device
  * [C][n][n]): hydrostatic background of constant potential temperature,
  * theta = theta_bg + theta' at fixed pressure, at rest (paper, Section 4.2).

@@ -27,6 +27,7 @@ EXPORTED = [
     "adg_batch_step_graph", "adg_batch_autotune", "adg_batch_set_launch", "adg_get_leaves",
     "adg_regrid_plan", "adg_regrid_apply", "adg_adjoint_workspace_bytes", "adg_step_adjoint",
     "adg_ic_theta", "adg_ic_theta_adjoint", "adg_loss_theta", "adg_loss_theta_adjoint",
+    "adg_keep_bytes", "adg_step_keep", "adg_step_adjoint_kept",
     "adg3_init_mesh", "adg3_destroy", "adg3_mesh_info", "adg3_workspace_bytes", "adg3_set_state",
     "adg3_init_state", "adg3_compute_dt", "adg3_predictor", "adg3_corrector", "adg3_step",
     "adg3_check_health",
@@ -126,6 +127,9 @@ def lib():
         L.adg_ic_theta_adjoint.argtypes = [vp, vp, vp, vp, vp]
         L.adg_loss_theta.argtypes = [vp, vp, vp, vp]
         L.adg_loss_theta_adjoint.argtypes = [vp, vp, vp, vp, vp]
+        L.adg_keep_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+        L.adg_step_keep.argtypes = [vp, vp, vp, vp]
+        L.adg_step_adjoint_kept.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.adg3_init_mesh.argtypes = [ctypes.POINTER(adg_params), ctypes.POINTER(adg3_mesh_desc), ctypes.POINTER(vp)]
         L.adg3_destroy.argtypes = [vp]
         L.adg3_mesh_info.argtypes = [vp, ip, ip]
@@ -308,6 +312,23 @@ class Mesh:
         _check(lib().adg_step_adjoint(self.h, ctypes.c_void_p(Q_n.data_ptr()), ctypes.c_void_p(lam_np1.data_ptr()),
                                       ctypes.c_void_p(lam_n.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                                       _stream_ptr(stream)))
+
+    def keep_bytes(self):
+        """(store bytes, face-data bytes) of one kept step."""
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().adg_keep_bytes(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def step_keep(self, store, fd, stream=None):
+        _check(lib().adg_step_keep(self.h, ctypes.c_void_p(store.data_ptr()), ctypes.c_void_p(fd.data_ptr()),
+                                   _stream_ptr(stream)))
+
+    def step_adjoint_kept(self, Q_n, store, fd, lam_np1, lam_n, stream=None):
+        ws = self.adjoint_workspace()
+        _check(lib().adg_step_adjoint_kept(self.h, ctypes.c_void_p(Q_n.data_ptr()), ctypes.c_void_p(store.data_ptr()),
+                                           ctypes.c_void_p(fd.data_ptr()), ctypes.c_void_p(lam_np1.data_ptr()),
+                                           ctypes.c_void_p(lam_n.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                           _stream_ptr(stream)))
 
     def ic_theta(self, theta_prime, stream=None):
         _check(lib().adg_ic_theta(self.h, ctypes.c_void_p(theta_prime.data_ptr()), _stream_ptr(stream)))

@@ -6,9 +6,12 @@ Forward: theta' -> initial state (hydrostatic background perturbed in theta
 at fixed pressure) -> K ADER-DG steps with a frozen time step, each step's
 start state kept as a checkpoint in device memory -> loss
 L = ||theta - theta_bg||_{L2}.  Backward: the loss adjoint, then the step
-adjoints from the last step to the first (each recomputes its predictor from
-its checkpoint), then the adjoint of the initial-state map.  All arithmetic
-runs in the library's kernels.
+adjoints from the last step to the first, then the adjoint of the
+initial-state map.  With keep=True every forward step also keeps its Picard
+iterates and face data in device memory (adg_step_keep) and the backward
+pass uses them (adg_step_adjoint_kept); otherwise each step adjoint
+recomputes its predictor from its checkpoint.  Both give the same gradient.
+All arithmetic runs in the library's kernels.
 """
 from __future__ import annotations
 
@@ -19,18 +22,27 @@ from . import adg
 
 class ThetaRollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, theta_prime, mesh: "adg.Mesh", steps: int, dt: float, t0: float = 0.0):
+    def forward(ctx, theta_prime, mesh: "adg.Mesh", steps: int, dt: float, t0: float = 0.0, keep: bool = False):
         m = mesh
         th = theta_prime.detach().contiguous()
         m.ic_theta(th)
         ck = torch.empty((steps,) + tuple(m.Q.shape), dtype=torch.float64, device=m.device)
         m.clock[0], m.clock[1] = float(t0), float(dt)
+        stores = fds = None
+        if keep:
+            sb, fb = m.keep_bytes()
+            stores = torch.empty((steps, sb // 8), dtype=torch.float64, device=m.device)
+            fds = torch.empty((steps, fb // 8), dtype=torch.float64, device=m.device)
         for k in range(steps):
             ck[k].copy_(m.Q)
-            m.step()
+            if keep:
+                m.step_keep(stores[k], fds[k])
+            else:
+                m.step()
         loss = torch.zeros(1, dtype=torch.float64, device=m.device)
         m.loss_theta(loss)
         ctx.mesh, ctx.steps, ctx.dt, ctx.t0 = m, steps, float(dt), float(t0)
+        ctx.kept = (stores, fds) if keep else None
         ctx.save_for_backward(th, ck, loss)
         return loss[0].clone()
 
@@ -45,12 +57,16 @@ class ThetaRollout(torch.autograd.Function):
         m.loss_theta_adjoint(loss, g, lam)
         for k in range(ctx.steps - 1, -1, -1):
             m.clock[0], m.clock[1] = ctx.t0 + k * ctx.dt, ctx.dt
-            m.step_adjoint(ck[k], lam, lam2)
+            if ctx.kept is not None:
+                m.step_adjoint_kept(ck[k], ctx.kept[0][k], ctx.kept[1][k], lam, lam2)
+            else:
+                m.step_adjoint(ck[k], lam, lam2)
             lam, lam2 = lam2, lam
         grad = torch.empty_like(th)
         m.ic_theta_adjoint(th, lam, grad)
-        return grad, None, None, None, None
+        ctx.kept = None
+        return grad, None, None, None, None, None
 
 
-def theta_rollout(theta_prime, mesh, steps, dt, t0=0.0):
-    return ThetaRollout.apply(theta_prime, mesh, steps, dt, t0)
+def theta_rollout(theta_prime, mesh, steps, dt, t0=0.0, keep=False):
+    return ThetaRollout.apply(theta_prime, mesh, steps, dt, t0, keep)

@@ -661,14 +661,17 @@ static int adj_n(const Group& g, AdjArgs a, hipStream_t s) {
 }
 
 int launch_step_adjoint(const Group& g, const double* Qn, const double* lam_in, double* lam_out, double* store,
-                        double* lamG, double* lamFD, hipStream_t s) {
-  // forward predictor from the checkpoint, keeping the iterates
-  Group gf = g;
-  gf.Q = const_cast<double*>(Qn);
-  int rc = launch_predictor_store(gf, store, s);
-  if (rc) return rc;
+                        const double* fd, bool recompute, double* lamG, double* lamFD, hipStream_t s) {
+  if (recompute) {
+    // forward predictor from the checkpoint, keeping the iterates and the face data
+    Group gf = g;
+    gf.Q = const_cast<double*>(Qn);
+    gf.FD = const_cast<double*>(fd);
+    int rc = launch_predictor_store(gf, store, s);
+    if (rc) return rc;
+  }
   AdjArgs a;
-  a.Qn = Qn; a.lam_in = lam_in; a.lam_out = lam_out; a.FD = g.FD; a.store = store; a.lamG = lamG;
+  a.Qn = Qn; a.lam_in = lam_in; a.lam_out = lam_out; a.FD = fd; a.store = store; a.lamG = lamG;
   a.lamFD = lamFD; a.clock = g.clock; a.geom = g.d_geom; a.nbr = g.d_nbr; a.gtab = g.d_gtab;
   a.C = g.C; a.iters = g.iters;
   switch (g.n) {

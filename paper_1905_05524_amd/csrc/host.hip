@@ -23,7 +23,8 @@ int launch_health(const Group& g, int* flag, hipStream_t s);
 int launch_regrid(int n, int C, const int* ops, const double* Qold, double* Qnew, const double* gtab,
                   hipStream_t s);
 int launch_step_adjoint(const Group& g, const double* Qn, const double* lam_in, double* lam_out, double* store,
-                        double* lamG, double* lamFD, hipStream_t s);
+                        const double* fd, bool recompute, double* lamG, double* lamFD, hipStream_t s);
+int launch_predictor_store(const Group& g, double* store, hipStream_t s);
 int launch_ic_theta(const Group& g, const double* thp, hipStream_t s);
 int launch_ic_theta_adj(const Group& g, const double* thp, const double* lam, double* grad, hipStream_t s);
 int launch_loss(const Group& g, double* part, double* out, hipStream_t s);
@@ -728,7 +729,46 @@ int adg_step_adjoint(adg_mesh* m, const double* Q_n, const double* lam_np1, doub
   size_t os, og, ofd, op, tot;
   adj_layout(m, &os, &og, &ofd, &op, &tot);
   char* w = static_cast<char*>(adj_ws);
-  return launch_step_adjoint(m->g, Q_n, lam_np1, lam_n, reinterpret_cast<double*>(w + os),
+  return launch_step_adjoint(m->g, Q_n, lam_np1, lam_n, reinterpret_cast<double*>(w + os), m->g.FD, true,
+                             reinterpret_cast<double*>(w + og), reinterpret_cast<double*>(w + ofd),
+                             (hipStream_t)stream);
+}
+
+int adg_keep_bytes(const adg_mesh* m, size_t* store_bytes, size_t* fd_bytes) {
+  if (!m) return fail(ADG_EINVAL, "null handle");
+  const size_t C = (size_t)m->g.C, n = (size_t)m->g.n, I = (size_t)m->g.iters;
+  if (store_bytes) *store_bytes = sizeof(double) * C * I * n * 4 * n * n;
+  if (fd_bytes) *fd_bytes = sizeof(double) * C * 32 * n;
+  return ADG_OK;
+}
+
+int adg_step_keep(adg_mesh* m, double* store, double* fd, void* stream) {
+  int rc = need_state(m);
+  if (!rc) rc = adjoint_supported(m);
+  if (rc) return rc;
+  if (!store || !fd) return fail(ADG_EINVAL, "null buffer");
+  hipStream_t s = (hipStream_t)stream;
+  Group gf = m->g;
+  gf.FD = fd;   // the corrector reads the kept face data
+  rc = launch_predictor_store(gf, store, s);
+  if (rc) return rc;
+  rc = launch_corrector(gf, s);
+  if (rc) return rc;
+  return launch_clock(m->clock, gf.dtc, nullptr, nullptr, 1, gf.C, 1, gf.ph.fixed_dt ? 0 : 1, s);
+}
+
+int adg_step_adjoint_kept(adg_mesh* m, const double* Q_n, const double* store, const double* fd,
+                          const double* lam_np1, double* lam_n, void* adj_ws, void* stream) {
+  int rc = need_state(m);
+  if (!rc) rc = adjoint_supported(m);
+  if (rc) return rc;
+  if (!Q_n || !store || !fd || !lam_np1 || !lam_n || !adj_ws) return fail(ADG_EINVAL, "null buffer");
+  if (lam_n == lam_np1) return fail(ADG_EINVAL, "lam_n must not alias lam_np1");
+  if (((uintptr_t)adj_ws & 255) != 0) return fail(ADG_EINVAL, "adjoint workspace must be 256-byte aligned");
+  size_t os, og, ofd, op, tot;
+  adj_layout(m, &os, &og, &ofd, &op, &tot);
+  char* w = static_cast<char*>(adj_ws);
+  return launch_step_adjoint(m->g, Q_n, lam_np1, lam_n, const_cast<double*>(store), fd, false,
                              reinterpret_cast<double*>(w + og), reinterpret_cast<double*>(w + ofd),
                              (hipStream_t)stream);
 }

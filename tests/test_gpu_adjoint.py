@@ -151,3 +151,25 @@ def test_rollout_gradient_bubble27_fd_and_oracle():
     for d in D[:2]:
         _, dL = O.rollout_jvp(w["phys"], w["mesh"], th0, d, 0.0, dt, K)
         assert abs(float(np.sum(g * d)) - dL) <= 1e-8 * abs(dL)
+
+
+def test_kept_iterates_give_the_recomputed_gradient():
+    """Keeping every step's Picard iterates and face data (adg_step_keep /
+    adg_step_adjoint_kept) gives bit for bit the gradient of the path that
+    recomputes them from the checkpoints, and the same loss."""
+    w = I.bubble(9, 4)
+    m = adg.Mesh(w["phys"], w["mesh"], fixed_dt=True)
+    m.init_state("bubbles", w["bubbles"])
+    m.compute_dt()
+    dt = m.dt
+    C, n = m.C, 5
+    rng = np.random.default_rng(8)
+    th0 = dev(0.1 + 0.05 * rng.standard_normal((C, n, n)))
+    res = {}
+    for keep in (False, True):
+        th = th0.clone().requires_grad_(True)
+        L = theta_rollout(th, m, 6, dt, keep=keep)
+        L.backward()
+        res[keep] = (float(L), th.grad.detach().clone())
+    assert res[True][0] == res[False][0]
+    assert torch.equal(res[True][1], res[False][1])
