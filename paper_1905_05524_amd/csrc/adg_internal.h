@@ -15,6 +15,9 @@
 namespace adg {
 
 constexpr int kMaxN = 8;          // nodes per direction supported (order 7)
+// the predictor runs a wavefront per time level while that puts at most this
+// many wavefronts on the chip (three per SIMD): cells * n <= kLevelsWaves
+constexpr int kLevelsWaves = 3072;
 constexpr int kWave = 64;         // CDNA wavefront size
 
 // Basis tables for n nodes, passed by value as a kernel argument so that every
@@ -94,6 +97,9 @@ struct Group {
   double* clock = nullptr;    // [S][4]
   // launch shape: cells per wavefront, wavefronts per workgroup
   int cpw = 1, wpb = 1;
+  // predictor kernel: -1 automatic (one wavefront per time level while
+  // cells * n <= kLevelsWaves), 0 one wavefront per cell, 1 one per time level
+  int lv = -1;
   int nc = 0;                 // the mesh has 1:3 non-conforming faces
 };
 

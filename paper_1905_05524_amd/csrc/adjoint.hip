@@ -649,7 +649,7 @@ __global__ __launch_bounds__(kWave) void k_loss_adj(Phys ph, const double* Q, co
 }
 
 // --------------------------------------------------------------- launchers
-int launch_predictor_store(const Group& g, double* store, hipStream_t s);
+int launch_predictor_any(const Group& g, double* store, hipStream_t s);
 int launch_corrector(const Group& g, hipStream_t s);
 
 template <int n>
@@ -667,7 +667,7 @@ int launch_step_adjoint(const Group& g, const double* Qn, const double* lam_in, 
     Group gf = g;
     gf.Q = const_cast<double*>(Qn);
     gf.FD = const_cast<double*>(fd);
-    int rc = launch_predictor_store(gf, store, s);
+    int rc = launch_predictor_any(gf, store, s);
     if (rc) return rc;
   }
   AdjArgs a;

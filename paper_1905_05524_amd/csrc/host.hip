@@ -25,6 +25,7 @@ int launch_regrid(int n, int C, const int* ops, const double* Qold, double* Qnew
 int launch_step_adjoint(const Group& g, const double* Qn, const double* lam_in, double* lam_out, double* store,
                         const double* fd, bool recompute, double* lamG, double* lamFD, hipStream_t s);
 int launch_predictor_store(const Group& g, double* store, hipStream_t s);
+int launch_predictor_levels(const Group& g, double* store, hipStream_t s);
 int launch_ic_theta(const Group& g, const double* thp, hipStream_t s);
 int launch_ic_theta_adj(const Group& g, const double* thp, const double* lam, double* grad, hipStream_t s);
 int launch_loss(const Group& g, double* part, double* out, hipStream_t s);
@@ -34,6 +35,16 @@ int regrid_plan(const std::vector<int>& lev, const std::vector<int>& ci, const s
                 std::vector<int>& nci, std::vector<int>& ncj, std::vector<int>& ops);
 
 static thread_local std::string g_err;
+
+// Predictor of a group with the kernel its launch mode selects: one
+// wavefront per time level (lv = 1, or automatic while cells * n <= kLevelsWaves),
+// else one wavefront per cell with the group's launch shape; with a store,
+// the Picard iterates are kept (adjoint).
+int launch_predictor_any(const Group& g, double* store, hipStream_t s) {
+  const bool levels = g.lv == 1 || (g.lv < 0 && (long)g.C * g.n <= kLevelsWaves);
+  if (levels) return launch_predictor_levels(g, store, s);
+  return store ? launch_predictor_store(g, store, s) : launch_predictor(g, s);
+}
 
 void set_error(const std::string& msg) { g_err = msg; }
 int fail(int code, const std::string& msg) { g_err = msg; return code; }
@@ -432,36 +443,37 @@ static int autotune_group(Group& g, hipStream_t s, int reps, float* best_ms) {
   if (g.C == 0) return ADG_OK;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(ADG_EHIP, "event");
+  // candidates: (lv, cpw, wpb); lv = 1 is the one-wavefront-per-time-level
+  // predictor (its corrector shape is the default one)
   const int cpws[3] = {1, 2, 4}, wpbs[3] = {1, 2, 4};
-  int bc = g.cpw, bw = g.wpb;
+  int bl = g.lv, bc = g.cpw, bw = g.wpb;
   float best = 1e30f;
-  double* Qsave = g.Q;
-  for (int ci = 0; ci < 3; ++ci) {
-    if (cpws[ci] > max_cpw(g.n)) continue;
-    for (int wi = 0; wi < 3; ++wi) {
-      Group t = g;
-      t.cpw = cpws[ci]; t.wpb = wpbs[wi];
-      Group tc = t;
-      tc.Q = t.Qs;   // corrector reads Q*, writes in place: state untouched
-      (void)Qsave;
-      int rc = launch_predictor(t, s);   // warm-up
-      if (!rc) rc = launch_corrector(tc, s);
-      if (rc) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return rc; }
-      (void)hipEventRecord(e0, s);
-      for (int r = 0; r < reps; ++r) {
-        launch_predictor(t, s);
-        launch_corrector(tc, s);
-      }
-      (void)hipEventRecord(e1, s);
-      (void)hipEventSynchronize(e1);
-      float ms = 0.0f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best) { best = ms; bc = t.cpw; bw = t.wpb; }
+  for (int k = -1; k < 9; ++k) {
+    Group t = g;
+    if (k < 0) { t.lv = 1; t.cpw = 1; t.wpb = 1; }
+    else {
+      t.lv = 0; t.cpw = cpws[k / 3]; t.wpb = wpbs[k % 3];
+      if (t.cpw > max_cpw(g.n)) continue;
     }
+    Group tc = t;
+    tc.Q = t.Qs;   // corrector reads Q*, writes in place: state untouched
+    int rc = launch_predictor_any(t, nullptr, s);   // warm-up
+    if (!rc) rc = launch_corrector(tc, s);
+    if (rc) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return rc; }
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps; ++r) {
+      launch_predictor_any(t, nullptr, s);
+      launch_corrector(tc, s);
+    }
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) { best = ms; bl = t.lv; bc = t.cpw; bw = t.wpb; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  g.cpw = bc; g.wpb = bw;
+  g.lv = bl; g.cpw = bc; g.wpb = bw;
   if (best_ms) *best_ms = best / reps;
   return check_launch("autotune");
 }
@@ -568,7 +580,7 @@ int adg_compute_dt(adg_mesh* m, void* stream) {
 int adg_predictor(adg_mesh* m, void* stream) {
   int rc = need_state(m);
   if (rc) return rc;
-  return launch_predictor(m->g, (hipStream_t)stream);
+  return launch_predictor_any(m->g, nullptr, (hipStream_t)stream);
 }
 
 int adg_corrector(adg_mesh* m, void* stream) {
@@ -750,7 +762,7 @@ int adg_step_keep(adg_mesh* m, double* store, double* fd, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   Group gf = m->g;
   gf.FD = fd;   // the corrector reads the kept face data
-  rc = launch_predictor_store(gf, store, s);
+  rc = launch_predictor_any(gf, store, s);
   if (rc) return rc;
   rc = launch_corrector(gf, s);
   if (rc) return rc;
@@ -807,11 +819,16 @@ int adg_loss_theta_adjoint(adg_mesh* m, const double* loss, const double* grad_l
 
 int adg_set_launch(adg_mesh* m, int cells_per_wave, int waves_per_block) {
   if (!m) return fail(ADG_EINVAL, "null handle");
+  if (cells_per_wave == 0) {   // predictor with one wavefront per time level
+    if (waves_per_block != 1) return fail(ADG_EINVAL, "waves_per_block must be 1 with cells_per_wave 0");
+    m->g.lv = 1; m->g.cpw = 1; m->g.wpb = 1;
+    return ADG_OK;
+  }
   if ((cells_per_wave != 1 && cells_per_wave != 2 && cells_per_wave != 4) || cells_per_wave > max_cpw(m->g.n))
-    return fail(ADG_EINVAL, "cells_per_wave must be 1, 2 or 4 with cells_per_wave * n^2 <= 64");
+    return fail(ADG_EINVAL, "cells_per_wave must be 0, 1, 2 or 4 with cells_per_wave * n^2 <= 64");
   if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
     return fail(ADG_EINVAL, "waves_per_block must be 1, 2 or 4");
-  m->g.cpw = cells_per_wave; m->g.wpb = waves_per_block;
+  m->g.lv = 0; m->g.cpw = cells_per_wave; m->g.wpb = waves_per_block;
   return ADG_OK;
 }
 
@@ -821,7 +838,7 @@ int adg_autotune(adg_mesh* m, int reps, void* stream, int* cells_per_wave, int* 
   if (reps < 1) return fail(ADG_EINVAL, "reps < 1");
   rc = autotune_group(m->g, (hipStream_t)stream, reps, nullptr);
   if (rc) return rc;
-  if (cells_per_wave) *cells_per_wave = m->g.cpw;
+  if (cells_per_wave) *cells_per_wave = m->g.lv == 1 ? 0 : m->g.cpw;
   if (waves_per_block) *waves_per_block = m->g.wpb;
   return ADG_OK;
 }
@@ -884,7 +901,7 @@ static int batch_enqueue_step(adg_batch* b, hipStream_t s) {
   for (int g = 0; g < G; ++g) {
     hipStream_t gs = b->streams[g];
     if (hipStreamWaitEvent(gs, b->events[0], 0) != hipSuccess) return fail(ADG_EHIP, "stream wait");
-    int rc = launch_predictor(b->groups[g], gs);
+    int rc = launch_predictor_any(b->groups[g], nullptr, gs);
     if (!rc) rc = launch_corrector(b->groups[g], gs);
     if (rc) return rc;
     if (hipEventRecord(b->events[1 + g], gs) != hipSuccess) return fail(ADG_EHIP, "event record");
@@ -1116,7 +1133,7 @@ int adg_batch_autotune(adg_batch* b, int reps, void* stream, int* cells_per_wave
   for (size_t gi = 0; gi < b->groups.size(); ++gi) {
     rc = autotune_group(b->groups[gi], (hipStream_t)stream, reps, nullptr);
     if (rc) return rc;
-    if (cells_per_wave) cells_per_wave[gi] = b->groups[gi].cpw;
+    if (cells_per_wave) cells_per_wave[gi] = b->groups[gi].lv == 1 ? 0 : b->groups[gi].cpw;
     if (waves_per_block) waves_per_block[gi] = b->groups[gi].wpb;
   }
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
@@ -1128,11 +1145,16 @@ int adg_batch_set_launch(adg_batch* b, int group, int cells_per_wave, int waves_
   if (!b) return fail(ADG_EINVAL, "null batch");
   if (group < 0 || group >= (int)b->groups.size()) return fail(ADG_EINVAL, "group out of range");
   Group& g = b->groups[group];
-  if ((cells_per_wave != 1 && cells_per_wave != 2 && cells_per_wave != 4) || cells_per_wave > max_cpw(g.n))
-    return fail(ADG_EINVAL, "cells_per_wave must be 1, 2 or 4 with cells_per_wave * n^2 <= 64");
-  if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
-    return fail(ADG_EINVAL, "waves_per_block must be 1, 2 or 4");
-  g.cpw = cells_per_wave; g.wpb = waves_per_block;
+  if (cells_per_wave == 0) {   // predictor with one wavefront per time level
+    if (waves_per_block != 1) return fail(ADG_EINVAL, "waves_per_block must be 1 with cells_per_wave 0");
+    g.lv = 1; g.cpw = 1; g.wpb = 1;
+  } else {
+    if ((cells_per_wave != 1 && cells_per_wave != 2 && cells_per_wave != 4) || cells_per_wave > max_cpw(g.n))
+      return fail(ADG_EINVAL, "cells_per_wave must be 0, 1, 2 or 4 with cells_per_wave * n^2 <= 64");
+    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+      return fail(ADG_EINVAL, "waves_per_block must be 1, 2 or 4");
+    g.lv = 0; g.cpw = cells_per_wave; g.wpb = waves_per_block;
+  }
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   return ADG_OK;

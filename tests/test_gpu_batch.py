@@ -41,10 +41,14 @@ def _run(w, Q, dt, shape=None, steps=2):
 
 @pytest.mark.parametrize("N", [1, 2, 3, 4, 6])
 def test_launch_shapes_are_bitwise_equal(N):
+    """Every packing of the one-wavefront-per-cell predictor gives the same
+    bits; the predictor with one wavefront per time level (shape (0, 1), the
+    default on small meshes) sums the levels in another order and agrees to
+    rounding, and with the oracle."""
     w = I.bubble(7, N)      # 49 cells: ragged for every packing
     Q = I.perturb(O.ic(w["phys"], w["mesh"], "bubbles", w["bubbles"]), seed=N)
     dt = 0.5 * O.dt(w["phys"], w["mesh"], Q)
-    base = _run(w, Q, dt)
+    base = _run(w, Q, dt, (1, 1))
     n = N + 1
     for cpw in (1, 2, 4):
         if cpw * n * n > 64:
@@ -52,6 +56,11 @@ def test_launch_shapes_are_bitwise_equal(N):
         for wpb in (1, 2, 4):
             got = _run(w, Q, dt, (cpw, wpb))
             assert torch.equal(got, base), (cpw, wpb)
+    lv = _run(w, Q, dt, (0, 1))
+    assert torch.equal(lv, _run(w, Q, dt))
+    ref = O.step(w["phys"], w["mesh"], O.step(w["phys"], w["mesh"], Q, 0.0, dt), dt, dt)
+    assert np.all(relerr(lv.cpu().numpy(), ref) <= 1e-11)
+    assert np.all(relerr(base.cpu().numpy(), ref) <= 1e-11)
 
 
 def test_invalid_launch_shape_rejected():
@@ -71,9 +80,10 @@ def test_autotune_keeps_state_and_results():
     Q0, c0 = m.Q.clone(), m.clock.clone()
     cpw, wpb = m.autotune(reps=2)
     assert torch.equal(m.Q, Q0) and torch.equal(m.clock, c0)
-    assert cpw in (1, 2, 4) and wpb in (1, 2, 4)
+    assert cpw in (0, 1, 2, 4) and wpb in (1, 2, 4)
     m.step()
     ref = adg.Mesh(w["phys"], w["mesh"])
+    ref.set_launch(cpw, wpb)
     ref.set_state(Q0)
     ref.clock.copy_(c0)
     ref.step()
@@ -138,6 +148,8 @@ def test_batch_autotune_then_step_unchanged():
         bb.compute_dt()
     cpw, wpb = b.autotune(reps=2)
     assert len(cpw) == b.n_groups
+    for g in range(b.n_groups):
+        a.set_launch(g, cpw[g], wpb[g])
     a.step()
     b.step()
     torch.cuda.synchronize()
