@@ -83,7 +83,7 @@ int adg_fv_workspace_bytes(const adg_fv* m, size_t* bytes);
  * double[4].  Workspace layout (offsets rounded up to 256 bytes): evolved
  * face values [4 faces (west, east, south, north)][4 vars][C], half-step
  * density increments [C], one time-step bound per workgroup of the
- * corrector, a health flag. */
+ * corrector or tile of adg_fv_step, a health flag. */
 int adg_fv_set_state(adg_fv* m, double* Q, void* workspace, double* clock);
 
 /* Initial cell values at the centres.  kind 0: the hydrostatic background
@@ -108,10 +108,14 @@ int adg_fv_predictor(adg_fv* m, void* stream);
 int adg_fv_corrector(adg_fv* m, void* stream);
 
 /* One full step with the arithmetic of adg_fv_predictor + adg_fv_corrector
- * (and the same clock update), fused into one kernel on tiles of 32 x 8
- * cells whose face values stay in on-chip memory, plus a copy-back kernel;
- * the workspace's face-value area holds the new values in between (its
- * contents afterwards are not the evolved face values). */
+ * (and the same clock update), fused into one kernel on tiles of 16 x 16
+ * cells whose face values stay in on-chip memory and whose face fluxes are
+ * evaluated once per face, plus a copy-back kernel that also advances the
+ * clock.  Interior cells of a tile are updated in place; the two outer
+ * layers of every tile pass through the workspace's face-value area (its
+ * contents afterwards are not the evolved face values).  The horizontal
+ * faces inside a tile take their height from the row above the face, so a
+ * result may differ from the split path in the last bits. */
 int adg_fv_step(adg_fv* m, void* stream);
 
 /* Synchronises the stream, then ESTATE if any value of the bound Q is

@@ -4,26 +4,33 @@
 //
 // One thread per cell, x fastest so that a wavefront reads consecutive cells
 // (32 B each) and the x neighbours come from the same cache lines.
-// The step (adg_fv_step) is one fused kernel on tiles of 32 x 8 cells:
+// The step (adg_fv_step) is one fused kernel on tiles of 16 x 16 cells:
 //   k_fv_fused    each thread predicts its cell (slopes, Hancock half step),
-//                 the first 80 threads also the ring of cells around the tile
+//                 the first threads also the ring of cells around the tile
 //                 (only the face value the tile needs); the evolved face
-//                 values meet in LDS; each thread solves its four faces and
-//                 writes the new value to a second buffer (neighbouring
-//                 tiles still read the old one);
-//   k_fv_commit   copies the new values into Q and reduces the time-step
-//                 bound of each workgroup.
-// HBM traffic is the state read (plus the halo) and written twice.  The
-// split entry points keep the two halves apart, with the evolved face
-// values in the workspace (structure-of-arrays, one coalesced segment per
-// face, variable and wavefront):
+//                 values meet in LDS; every face of the tile gets its
+//                 Rusanov flux once (one job per face, 2.25 per cell); each
+//                 thread then updates its cell and writes the new value: in
+//                 place for the tile's interior cells, to a second buffer
+//                 for its two outer layers (the only cells neighbouring tiles
+//                 read: their ring cells and the ring cells' neighbours); and
+//                 the tile's time-step bound of the new values;
+//   k_fv_commit   copies the outer layers' new values into Q; its first
+//                 workgroup reduces the tile bounds and advances the clock.
+// HBM traffic is the state read (plus the halo) and written once, plus the
+// outer layers (44 % of the cells) written and copied again.  The split
+// entry points keep the two halves apart, with the evolved face values in
+// the workspace (structure-of-arrays, one coalesced segment per face,
+// variable and wavefront):
 //   k_fv_predict  slopes and half step of every cell;
 //   k_fv_correct  face fluxes and update in place (a thread reads no other
 //                 cell's Q), and the workgroup's time-step bound.
-// Both paths share the per-cell device functions.
+// Both paths share the per-cell predictor; the face loop of the split path
+// and the face jobs of the fused one take the same arithmetic.
 // The background density and pressure of every row (centre, horizontal
 // faces, wall ghost centres) come from a host-built table, so no kernel
 // evaluates pow().
+#include <algorithm>
 #include <cmath>
 #include <new>
 
@@ -109,45 +116,66 @@ __device__ inline void load4(const double* p, double q[4]) {
 }
 
 // Steps 1-2 of the scheme for cell (i, j) inside the domain: the evolved
-// face values fv[W, E, S, N][var] and the half-step density increment.
+// face values fv[W, E, S, N][var] and the half-step density increment.  One
+// direction at a time (its two neighbours, then its two face fluxes), so few
+// values are live at once.
 __device__ inline void fv_predict_cell(const Phys& ph, const FvArgs& a, int i, int j, double dt, double fv[4][4],
                                        double& inc0) {
   const int c = j * a.nx + i;
   const double* bg = a.bg + 15 * j;
-  const double h = a.h;
-  double q[4], nb[4][4];   // neighbours W, E, S, N
+  double q[4];
   load4(a.Q + 4 * (size_t)c, q);
-  if (i > 0) load4(a.Q + 4 * (size_t)(c - 1), nb[0]);
-  else if (a.wall & 1) fv_ghost(ph, q, bg[3 * kBgC], bg[3 * kBgC + 1], bg[3 * kBgC + 2], nb[0]);
-  else load4(a.Q + 4 * (size_t)(c + a.nx - 1), nb[0]);
-  if (i < a.nx - 1) load4(a.Q + 4 * (size_t)(c + 1), nb[1]);
-  else if (a.wall & 2) fv_ghost(ph, q, bg[3 * kBgC], bg[3 * kBgC + 1], bg[3 * kBgC + 2], nb[1]);
-  else load4(a.Q + 4 * (size_t)(c - a.nx + 1), nb[1]);
-  if (j > 0) load4(a.Q + 4 * (size_t)(c - a.nx), nb[2]);
-  else if (a.wall & 4) fv_ghost(ph, q, bg[3 * kBgGS], bg[3 * kBgGS + 1], bg[3 * kBgGS + 2], nb[2]);
-  else load4(a.Q + 4 * ((size_t)(a.nz - 1) * a.nx + i), nb[2]);
-  if (j < a.nz - 1) load4(a.Q + 4 * (size_t)(c + a.nx), nb[3]);
-  else if (a.wall & 8) fv_ghost(ph, q, bg[3 * kBgGN], bg[3 * kBgGN + 1], bg[3 * kBgGN + 2], nb[3]);
-  else load4(a.Q + 4 * (size_t)i, nb[3]);
+  {  // x: west and east neighbours (wall ghost or periodic image at the domain edge)
+    double nw[4], ne[4];
+    if (i > 0) load4(a.Q + 4 * (size_t)(c - 1), nw);
+    else if (a.wall & 1) fv_ghost(ph, q, bg[3 * kBgC], bg[3 * kBgC + 1], bg[3 * kBgC + 2], nw);
+    else load4(a.Q + 4 * (size_t)(c + a.nx - 1), nw);
+    if (i < a.nx - 1) load4(a.Q + 4 * (size_t)(c + 1), ne);
+    else if (a.wall & 2) fv_ghost(ph, q, bg[3 * kBgC], bg[3 * kBgC + 1], bg[3 * kBgC + 2], ne);
+    else load4(a.Q + 4 * (size_t)(c - a.nx + 1), ne);
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const double sx = van_albada(q[v] - nb[0][v], nb[1][v] - q[v]);
-    const double sz = van_albada(q[v] - nb[2][v], nb[3][v] - q[v]);
-    fv[0][v] = q[v] - 0.5 * sx;
-    fv[1][v] = q[v] + 0.5 * sx;
-    fv[2][v] = q[v] - 0.5 * sz;
-    fv[3][v] = q[v] + 0.5 * sz;
+    for (int v = 0; v < 4; ++v) {
+      const double sx = van_albada(q[v] - nw[v], ne[v] - q[v]);
+      fv[0][v] = q[v] - 0.5 * sx;
+      fv[1][v] = q[v] + 0.5 * sx;
+    }
   }
-  double F[4][4];
-  fv_flux(ph, fv[0], bg[3 * kBgC], bg[3 * kBgC + 2], 0, F[0]);
-  fv_flux(ph, fv[1], bg[3 * kBgC], bg[3 * kBgC + 2], 0, F[1]);
-  fv_flux(ph, fv[2], bg[3 * kBgS], bg[3 * kBgS + 2], 1, F[2]);
-  fv_flux(ph, fv[3], bg[3 * kBgN], bg[3 * kBgN + 2], 1, F[3]);
+  {  // z: south and north neighbours
+    double ns[4], nn[4];
+    if (j > 0) load4(a.Q + 4 * (size_t)(c - a.nx), ns);
+    else if (a.wall & 4) fv_ghost(ph, q, bg[3 * kBgGS], bg[3 * kBgGS + 1], bg[3 * kBgGS + 2], ns);
+    else load4(a.Q + 4 * ((size_t)(a.nz - 1) * a.nx + i), ns);
+    if (j < a.nz - 1) load4(a.Q + 4 * (size_t)(c + a.nx), nn);
+    else if (a.wall & 8) fv_ghost(ph, q, bg[3 * kBgGN], bg[3 * kBgGN + 1], bg[3 * kBgGN + 2], nn);
+    else load4(a.Q + 4 * (size_t)i, nn);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double sz = van_albada(q[v] - ns[v], nn[v] - q[v]);
+      fv[2][v] = q[v] - 0.5 * sz;
+      fv[3][v] = q[v] + 0.5 * sz;
+    }
+  }
+  // flux differences across the cell: (F_W - F_E) + (F_S - F_N)
+  double d[4];
+  {
+    double Fa[4], Fb[4];
+    fv_flux(ph, fv[0], bg[3 * kBgC], bg[3 * kBgC + 2], 0, Fa);
+    fv_flux(ph, fv[1], bg[3 * kBgC], bg[3 * kBgC + 2], 0, Fb);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) d[v] = Fa[v] - Fb[v];
+  }
+  {
+    double Fa[4], Fb[4];
+    fv_flux(ph, fv[2], bg[3 * kBgS], bg[3 * kBgS + 2], 1, Fa);
+    fv_flux(ph, fv[3], bg[3 * kBgN], bg[3 * kBgN + 2], 1, Fb);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) d[v] = d[v] + (Fa[v] - Fb[v]);
+  }
   const double Sw = -ph.geff * (q[0] - bg[3 * kBgC + 1]);
   const double k = 0.5 * dt * a.ih;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    double inc = k * ((F[0][v] - F[1][v]) + (F[2][v] - F[3][v]));
+    double inc = k * d[v];
     if (v == 2) inc += 0.5 * dt * Sw;
     if (v == 0) inc0 = inc;
 #pragma unroll
@@ -163,10 +191,12 @@ template <class Fetch>
 __device__ inline void fv_update_cell(const Phys& ph, const FvArgs& a, int i, int j, double dt, Fetch fetch,
                                       double inc0, double out[4]) {
   const double* bg = a.bg + 15 * j;
-  const bool wall[4] = {i == 0 && (a.wall & 1), i == a.nx - 1 && (a.wall & 2), j == 0 && (a.wall & 4),
-                        j == a.nz - 1 && (a.wall & 8)};
-  double dx[4], dz[4];   // G_east - G_west, G_north - G_south
-#pragma unroll
+  const int wall = (i == 0 ? a.wall & 1 : 0) | (i == a.nx - 1 ? a.wall & 2 : 0) | (j == 0 ? a.wall & 4 : 0) |
+                   (j == a.nz - 1 ? a.wall & 8 : 0);
+  double dx[4] = {0, 0, 0, 0}, dz[4] = {0, 0, 0, 0};   // G_east - G_west, G_north - G_south
+  // a rolled loop: one face's values live at a time (the face index is
+  // uniform, so its branches are scalar)
+#pragma unroll 1
   for (int f = 0; f < 4; ++f) {
     const int d = f >> 1, hi = f & 1;
     const int row = d == 0 ? kBgC : (hi ? kBgN : kBgS);
@@ -174,7 +204,7 @@ __device__ inline void fv_update_cell(const Phys& ph, const FvArgs& a, int i, in
     double own[4], Qn[4], Fo[4], Fn[4], G[4], sn;
     fetch(f, own, Qn);
     const double so = fv_flux(ph, own, zf, pbf, d, Fo);
-    if (wall[f]) {
+    if ((wall >> f) & 1) {
       fv_ghost(ph, own, zf, rbf, pbf, Qn);
       Fn[0] = -Fo[0]; Fn[1] = Fo[1]; Fn[2] = Fo[2]; Fn[3] = -Fo[3];
       const double pg = fv_pressure(ph, Qn, zf), irg = recip(Qn[0]);
@@ -185,9 +215,13 @@ __device__ inline void fv_update_cell(const Phys& ph, const FvArgs& a, int i, in
     const double sp = fmax(so, sn);
     if (hi) rusanov_fv(sp, own, Fo, Qn, Fn, G);
     else rusanov_fv(sp, Qn, Fn, own, Fo, G);
-    double* acc = d == 0 ? dx : dz;
+    if (d == 0) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[v] = hi ? G[v] + acc[v] : -G[v];
+      for (int v = 0; v < 4; ++v) dx[v] = hi ? G[v] + dx[v] : -G[v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dz[v] = hi ? G[v] + dz[v] : -G[v];
+    }
   }
   double q[4];
   load4(a.Q + 4 * ((size_t)j * a.nx + i), q);
@@ -207,14 +241,15 @@ __device__ inline double fv_lambda(const Phys& ph, const double q[4], double z) 
 }
 
 // workgroup maximum of lam -> time-step bound dtb[blockIdx]
+template <int NT = kFvThreads>
 __device__ inline void fv_block_bound(const Phys& ph, const FvArgs& a, double lam, int block) {
-  __shared__ double smax[kFvThreads / kWave];
+  __shared__ double smax[NT / kWave];
   lam = wave_max(lam);
   if ((threadIdx.x & (kWave - 1)) == 0) smax[threadIdx.x / kWave] = lam;
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = smax[0];
-    for (int w = 1; w < kFvThreads / kWave; ++w) m = fmax(m, smax[w]);
+    for (int w = 1; w < NT / kWave; ++w) m = fmax(m, smax[w]);
     a.dtb[block] = ph.cfl * a.h / (2.0 * m);
   }
 }
@@ -261,17 +296,63 @@ __global__ __launch_bounds__(kFvThreads) void k_fv_correct(Phys ph, FvArgs a) {
   fv_block_bound(ph, a, lam, blockIdx.x);
 }
 
+// Rusanov flux of one face along d (0: x, 1: z) at height zf from the
+// evolved values lo and hi on its low (west or south) and high side; d may
+// differ between lanes (selects, no branches).  out = 1: the low side is a
+// wall, its value is the wall ghost of hi; out = 2: the high side is a wall.
+// The same arithmetic as the face loop of fv_update_cell.
+__device__ inline double fv_flux_sel(const Phys& ph, const double q[4], double z, double pb, int d, double F[4]) {
+  const double ir = recip(q[0]);
+  const double u = q[1] * ir, w = q[2] * ir;
+  const double p = ph.gm1 * (q[3] - 0.5 * (q[1] * u + q[2] * w) - q[0] * (ph.geff * z));
+  const double pm = p - pb;
+  const double un = d ? w : u;
+  F[0] = d ? q[2] : q[1];
+  F[1] = q[1] * un + (d == 0 ? pm : 0.0);
+  F[2] = q[2] * un + (d == 1 ? pm : 0.0);
+  F[3] = un * (q[3] + p);
+  return fabs(un) + sqrt(ph.gamma * p * ir);
+}
+
+__device__ inline void fv_face(const Phys& ph, int d, double zf, double rbf, double pbf, int out, const double lo[4],
+                               const double hi[4], double G[4]) {
+  if (out == 0) {
+    double Fl[4], Fh[4];
+    const double sl = fv_flux_sel(ph, lo, zf, pbf, d, Fl);
+    const double sh = fv_flux_sel(ph, hi, zf, pbf, d, Fh);
+    rusanov_fv(fmax(sl, sh), lo, Fl, hi, Fh, G);
+  } else {
+    const double* in = out == 1 ? hi : lo;
+    double qi[4], Fo[4], g[4], Fg[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) qi[v] = in[v];
+    const double so = fv_flux_sel(ph, qi, zf, pbf, d, Fo);
+    fv_ghost(ph, qi, zf, rbf, pbf, g);
+    Fg[0] = -Fo[0]; Fg[1] = Fo[1]; Fg[2] = Fo[2]; Fg[3] = -Fo[3];
+    const double pg = fv_pressure(ph, g, zf), irg = recip(g[0]);
+    const double sg = fabs((d ? g[2] : g[1]) * irg) + sqrt(ph.gamma * pg * irg);
+    const double sp = fmax(so, sg);
+    if (out == 1) rusanov_fv(sp, g, Fg, qi, Fo, G);
+    else rusanov_fv(sp, qi, Fo, g, Fg, G);
+  }
+}
+
 // One step fused into one kernel on tiles of kTX x kTZ cells: every thread
 // predicts its cell, the first threads also the ring of cells around the
 // tile (each only for the face value the tile needs); the evolved face
-// values meet in LDS; the update goes to Qn (other tiles still read Q).
-constexpr int kTX = 32, kTZ = 8;
-static_assert(kTX * kTZ == kFvThreads, "one thread per tile cell");
+// values meet in LDS; the update goes to Qn (other tiles still read Q), and
+// the workgroup's time-step bound of the new values goes to dtb[tile].
+constexpr int kTX = 16, kTZ = 16, kFT = kTX * kTZ;   // tile and workgroup size (one thread per tile cell)
+static_assert(kFT % kWave == 0 && 2 * (kTX + kTZ) <= kFT, "one thread per tile cell, the ring fits");
 
-__global__ __launch_bounds__(kFvThreads) void k_fv_fused(Phys ph, FvArgs a, double* Qn) {
-  // face values by face (W, E, S, N), variable, local row and column with a
-  // one-cell border for the ring: [4][4][kTZ + 2][kTX + 2]
-  __shared__ double sF[4][4][kTZ + 2][kTX + 2];
+__global__ __launch_bounds__(kFT) void k_fv_fused(Phys ph, FvArgs a, double* Qn) {
+  // evolved face values by face type, variable, row, column; each array is
+  // padded by one in the direction of the neighbour that reads it:
+  // west values of columns 0..kTX (kTX: east ring), east values of columns
+  // -1..kTX-1 (stored at column + 1), south values of rows 0..kTZ (kTZ:
+  // north ring), north values of rows -1..kTZ-1 (stored at row + 1)
+  __shared__ double sWv[4][kTZ][kTX + 1], sEv[4][kTZ][kTX + 1];
+  __shared__ double sSv[4][kTZ + 1][kTX], sNv[4][kTZ + 1][kTX];
   const int t = threadIdx.x, tx = t % kTX, tz = t / kTX;
   const int x0 = blockIdx.x * kTX, z0 = blockIdx.y * kTZ;
   const int ew = min(kTX, a.nx - x0), eh = min(kTZ, a.nz - z0);   // extent of the tile inside the domain
@@ -295,8 +376,10 @@ __global__ __launch_bounds__(kFvThreads) void k_fv_fused(Phys ph, FvArgs a, doub
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         // f is known only at run time: select with constant indices so rv stays in registers
-        const double val = f == 0 ? rv[0][v] : (f == 1 ? rv[1][v] : (f == 2 ? rv[2][v] : rv[3][v]));
-        sF[f][v][rz + 1][rx + 1] = val;
+        if (f == 1) sEv[v][rz][0] = rv[1][v];
+        else if (f == 0) sWv[v][rz][ew] = rv[0][v];
+        else if (f == 3) sNv[v][0][rx] = rv[3][v];
+        else sSv[v][eh][rx] = rv[2][v];
       }
     }
   }
@@ -305,44 +388,118 @@ __global__ __launch_bounds__(kFvThreads) void k_fv_fused(Phys ph, FvArgs a, doub
     double fv[4][4];
     fv_predict_cell(ph, a, x0 + tx, z0 + tz, dt, fv, inc0);
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) sF[f][v][tz + 1][tx + 1] = fv[f][v];
+    for (int v = 0; v < 4; ++v) {
+      sWv[v][tz][tx] = fv[0][v];
+      sEv[v][tz][tx + 1] = fv[1][v];
+      sSv[v][tz][tx] = fv[2][v];
+      sNv[v][tz + 1][tx] = fv[3][v];
+    }
   }
   __syncthreads();
-  if (inside) {
-    // face values from LDS, one face at a time: the cell's own (not held
-    // across the barrier) and the facing value of the neighbour (west
-    // neighbour's east value, east neighbour's west value, ...)
-    const int nzz[4] = {tz + 1, tz + 1, tz, tz + 2}, nxx[4] = {tx, tx + 2, tx + 1, tx + 1};
-    auto fetch = [&](int f, double own[4], double nb[4]) {
+  // every face of the tile once: z faces (rows 0..eh, the south face of each
+  // row of cells and the tile's top), then x faces (columns 0..ew); a job's
+  // flux replaces the low side's value, which only this job reads
+  constexpr int kZJobs = (kTZ + 1) * kTX, kXJobs = kTZ * (kTX + 1);
+  constexpr int zvs = (kTZ + 1) * kTX, xvs = kTZ * (kTX + 1);   // variable strides of the two array shapes
+  for (int k = t; k < kZJobs + kXJobs; k += kFT) {
+    const bool zj = k < kZJobs;
+    const int kk = zj ? k : k - kZJobs;
+    const int r = zj ? kk / kTX : kk / (kTX + 1), col = zj ? kk % kTX : kk % (kTX + 1);
+    if (!(zj ? (r <= eh && col < ew) : (r < eh && col <= ew))) continue;
+    const int d = zj ? 1 : 0, vs = zj ? zvs : xvs;
+    double* plo = zj ? &sNv[0][r][col] : &sEv[0][r][col];
+    const double* phi = zj ? &sSv[0][r][col] : &sWv[0][r][col];
+    const int gj = z0 + r;
+    // face height: x faces at the row centre; z faces at the south face of
+    // row gj, the tile's top face at the north face of the row below it
+    const double* bf = !zj ? a.bg + 15 * gj + 3 * kBgC
+                           : (r < eh ? a.bg + 15 * gj + 3 * kBgS : a.bg + 15 * (gj - 1) + 3 * kBgN);
+    int out = 0;
+    if (zj) {
+      if (r == 0 && z0 == 0 && (a.wall & 4)) out = 1;
+      else if (r == eh && z0 + eh == a.nz && (a.wall & 8)) out = 2;
+    } else {
+      if (col == 0 && x0 == 0 && (a.wall & 1)) out = 1;
+      else if (col == ew && x0 + ew == a.nx && (a.wall & 2)) out = 2;
+    }
+    double lo[4], hi[4], G[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        own[v] = sF[f][v][tz + 1][tx + 1];
-        nb[v] = sF[f ^ 1][v][nzz[f]][nxx[f]];
-      }
-    };
-    double out[4];
-    fv_update_cell(ph, a, x0 + tx, z0 + tz, dt, fetch, inc0, out);
-    double2* o = reinterpret_cast<double2*>(Qn + 4 * ((size_t)(z0 + tz) * a.nx + x0 + tx));
+    for (int v = 0; v < 4; ++v) { lo[v] = plo[v * vs]; hi[v] = phi[v * vs]; }
+    fv_face(ph, d, bf[0], bf[1], bf[2], out, lo, hi, G);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) plo[v * vs] = G[v];
+  }
+  __syncthreads();
+  double lam = 0.0;
+  if (inside) {
+    const int i = x0 + tx, j = z0 + tz;
+    double q[4], out[4];
+    load4(a.Q + 4 * ((size_t)j * a.nx + i), q);
+    const double Sh = -ph.geff * ((q[0] + inc0) - a.bg[15 * j + 3 * kBgC + 1]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double dx = sEv[v][tz][tx + 1] - sEv[v][tz][tx];   // G_east - G_west
+      const double dz = sNv[v][tz + 1][tx] - sNv[v][tz][tx];   // G_north - G_south
+      out[v] = q[v] - dt * a.ih * (dx + dz);
+      if (v == 2) out[v] += dt * Sh;
+    }
+    // other tiles read only the two outer layers of this tile (their ring
+    // cells and the ring cells' neighbours): interior cells take the new
+    // value in place, the outer layers go through Qn and the copy-back
+    const bool edge = tx <= 1 || tx >= ew - 2 || tz <= 1 || tz >= eh - 2;
+    double2* o = reinterpret_cast<double2*>((edge ? Qn : a.Q) + 4 * ((size_t)j * a.nx + i));
     o[0] = make_double2(out[0], out[1]);
     o[1] = make_double2(out[2], out[3]);
+    lam = fv_lambda(ph, out, a.bg[15 * j]);
   }
+  fv_block_bound<kFT>(ph, a, lam, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
-// Q <- Qn, and the workgroup's time-step bound of the new values.
-__global__ __launch_bounds__(kFvThreads) void k_fv_commit(Phys ph, FvArgs a, const double* Qn) {
-  const int c = blockIdx.x * kFvThreads + threadIdx.x;
-  double lam = 0.0;
-  if (c < a.C) {
-    double q[4];
-    load4(Qn + 4 * (size_t)c, q);
-    double2* o = reinterpret_cast<double2*>(a.Q + 4 * (size_t)c);
-    o[0] = make_double2(q[0], q[1]);
-    o[1] = make_double2(q[2], q[3]);
-    lam = fv_lambda(ph, q, a.bg[15 * (c / a.nx)]);
+// Q <- Qn on the two outer layers of every tile of the fused step (workgroup
+// b >= 1: tile b - 1, one thread per cell); workgroup 0 instead reduces the
+// tiles' time-step bounds and advances the clock (t += dt, steps += 1, then
+// dt <- the minimum unless update is 0), the work of k_clock, beside the copy.
+__global__ __launch_bounds__(kFT) void k_fv_commit(const double* __restrict__ Qn, double* __restrict__ Q,
+                                                          int nx, int nz, double* clock, const double* dtb, int nb,
+                                                          int update) {
+  const int t = threadIdx.x;
+  if (blockIdx.x == 0) {
+    __shared__ double sm[kFT / kWave];
+    double m = __builtin_inf();
+    if (update) {
+      // four independent loads in flight per thread
+      int k = t;
+      for (; k + 3 * kFT < nb; k += 4 * kFT) {
+        const double a0 = dtb[k], a1 = dtb[k + kFT], a2 = dtb[k + 2 * kFT], a3 = dtb[k + 3 * kFT];
+        m = fmin(m, fmin(fmin(a0, a1), fmin(a2, a3)));
+      }
+      for (; k < nb; k += kFT) m = fmin(m, dtb[k]);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmin(m, __shfl_xor(m, o, kWave));
+    if ((t & (kWave - 1)) == 0) sm[t / kWave] = m;
+    __syncthreads();
+    if (t == 0) {
+      double r = sm[0];
+      for (int k = 1; k < kFT / kWave; ++k) r = fmin(r, sm[k]);
+      clock[0] += clock[1];
+      clock[3] += 1.0;
+      if (update) clock[1] = r;
+    }
+    return;
   }
-  fv_block_bound(ph, a, lam, blockIdx.x);
+  const int tiles_x = (nx + kTX - 1) / kTX, b = blockIdx.x - 1;
+  const int x0 = (b % tiles_x) * kTX, z0 = (b / tiles_x) * kTZ;
+  const int ew = min(kTX, nx - x0), eh = min(kTZ, nz - z0);
+  const int tx = t % kTX, tz = t / kTX;
+  if (tx >= ew || tz >= eh) return;
+  if (!(tx <= 1 || tx >= ew - 2 || tz <= 1 || tz >= eh - 2)) return;
+  const size_t c = (size_t)(z0 + tz) * nx + x0 + tx;
+  const double2* src = reinterpret_cast<const double2*>(Qn + 4 * c);
+  double2* dst = reinterpret_cast<double2*>(Q + 4 * c);
+  const double2 v0 = src[0], v1 = src[1];
+  dst[0] = v0;
+  dst[1] = v1;
 }
 
 // time-step bound of every workgroup of cells from the current Q
@@ -408,7 +565,7 @@ struct adg_fv {
   adg_params prm{};
   adg_fv_desc desc{};
   Phys ph{};
-  int C = 0, blocks = 0;
+  int C = 0, blocks = 0, tiles = 0;   // cell workgroups, tiles of the fused step
   double* d_bg = nullptr;
   double* Q = nullptr;
   void* ws = nullptr;
@@ -482,6 +639,7 @@ int adg_fv_init(const adg_params* prm, const adg_fv_desc* mesh, adg_fv** out) {
   m->desc = *mesh;
   m->C = mesh->nx * mesh->nz;
   m->blocks = (m->C + kFvThreads - 1) / kFvThreads;
+  m->tiles = ((mesh->nx + kTX - 1) / kTX) * ((mesh->nz + kTZ - 1) / kTZ);
   adg_params p1 = *prm;
   p1.order = 1;   // make_phys reads the order only for the DG time-step rule
   m->ph = make_phys(p1);
@@ -513,7 +671,7 @@ int adg_fv_init(const adg_params* prm, const adg_fv_desc* mesh, adg_fv** out) {
   size_t off = 0;
   m->off_e = off; off = align256_fv(off + sizeof(double) * 16 * C);
   m->off_inc = off; off = align256_fv(off + sizeof(double) * C);
-  m->off_dtb = off; off = align256_fv(off + sizeof(double) * m->blocks);
+  m->off_dtb = off; off = align256_fv(off + sizeof(double) * std::max(m->blocks, m->tiles));
   m->off_h = off; off = align256_fv(off + sizeof(int));
   m->ws_bytes = off;
   *out = m;
@@ -605,13 +763,13 @@ int adg_fv_step(adg_fv* m, void* stream) {
   const FvArgs a = fv_args(m);
   double* Qn = a.E;   // the fused step keeps its new values in the face-value area
   const dim3 tiles((m->desc.nx + kTX - 1) / kTX, (m->desc.nz + kTZ - 1) / kTZ);
-  hipLaunchKernelGGL(k_fv_fused, tiles, dim3(kFvThreads), 0, s, m->ph, a, Qn);
+  hipLaunchKernelGGL(k_fv_fused, tiles, dim3(kFT), 0, s, m->ph, a, Qn);
   rc = check_launch("fv_fused");
   if (rc) return rc;
-  hipLaunchKernelGGL(k_fv_commit, dim3(m->blocks), dim3(kFvThreads), 0, s, m->ph, a, (const double*)Qn);
-  rc = check_launch("fv_commit");
-  if (rc) return rc;
-  return launch_clock(m->clock, a.dtb, nullptr, nullptr, 1, m->blocks, 1, m->prm.fixed_dt ? 0 : 1, s);
+  // copy-back of the tiles' edge cells plus one workgroup for the clock
+  hipLaunchKernelGGL(k_fv_commit, dim3(m->tiles + 1), dim3(kFT), 0, s, (const double*)Qn, m->Q,
+                     m->desc.nx, m->desc.nz, m->clock, (const double*)a.dtb, m->tiles, m->prm.fixed_dt ? 0 : 1);
+  return check_launch("fv_commit");
 }
 
 int adg_fv_check_health(adg_fv* m, void* stream) {
