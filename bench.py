@@ -58,12 +58,19 @@ def measured_traffic(kernel):
     return d[kernel]["traffic_bytes"]
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """Oracle (as it stands) on the same workload: whole steps of the 81x81
-    grid on all host threads until about budget_s seconds of CPU work."""
-    from oracle import oracle as O
-    from paper_1905_05524_amd import model
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(O, model, w, threads, budget_s):
+    """Whole oracle steps of workload w on the given number of threads until
+    about budget_s seconds; returns (DOF-updates/s, steps, seconds, threads used)."""
     used = O.set_threads(threads)
     Q = O.ic(w["phys"], w["mesh"], "bubbles", w["bubbles"])
     dt = O.dt(w["phys"], w["mesh"], Q)
@@ -71,20 +78,33 @@ def cpu_baseline(w, budget_s=15.0):
     Q, _ = O.run(w["phys"], w["mesh"], Q, 0.0, 1, dt)
     one = time.perf_counter() - t0
     steps = 1
-    extra = max(0, int(budget_s / max(one, 1e-9)) - 1)
-    extra = min(extra, 400)
+    extra = min(max(0, int(budget_s / max(one, 1e-9)) - 1), 400)
+    total = one
     if extra:
         t1 = time.perf_counter()
         O.run(w["phys"], w["mesh"], Q, dt, extra, dt)
         steps += extra
         total = one + (time.perf_counter() - t1)
-    else:
-        total = one
     C = w["mesh"]["nx"] * w["mesh"]["nz"]
-    rate = model.dofs(C, w["phys"]["N"]) * steps / total
+    return model.dofs(C, w["phys"]["N"]) * steps / total, steps, total, used
+
+
+def cpu_baseline(w, budget_s=15.0, one_thread_budget_s=4.0):
+    """Oracle (as it stands) on the same workload: whole steps of the 81x81
+    grid on all host threads until about budget_s seconds of CPU work, and a
+    shorter sample on one thread."""
+    from oracle import oracle as O
+    from paper_1905_05524_amd import model
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    rate, steps, total, used = _oracle_rate(O, model, w, threads, budget_s)
+    r1, s1, t1, _ = _oracle_rate(O, model, w, 1, one_thread_budget_s)
+    O.set_threads(threads)
     return {"value": rate, "unit": "DOF-updates/s", "cores": used, "kind": "oracle",
             "sample": f"{steps} full step(s) of the 81x81 N=6 bubble workload, {total:.1f} s, "
-                      f"OpenMP threads={used}"}
+                      f"OpenMP threads={used}",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "one_thread": {"value": r1, "unit": "DOF-updates/s",
+                           "sample": f"{s1} full step(s), {t1:.1f} s, one thread"}}
 
 
 def batched_leg(steps=20, warmup=3):
@@ -549,6 +569,8 @@ def main():
                   "sim_time_s": m.t, "dt_s": m.dt},
     }
     if not args.no_batch:
+        out["extra"]["peaks"] = adg.measure_peaks(copy_mib=1024)
+        out["extra"]["peaks"]["predictor_frac_of_measured_fp64"] = achieved / out["extra"]["peaks"]["fp64_vector_tflops"]
         out["extra"]["batched"] = batched_leg()
         out["extra"]["adaptive"] = amr_leg("amr27")
         out["extra"]["adaptive_two_levels"] = amr_leg("amr9")

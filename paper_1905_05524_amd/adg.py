@@ -34,6 +34,7 @@ EXPORTED = [
     "adg_fv_init", "adg_fv_destroy", "adg_fv_info", "adg_fv_workspace_bytes", "adg_fv_set_state",
     "adg_fv_init_state", "adg_fv_compute_dt", "adg_fv_predictor", "adg_fv_corrector", "adg_fv_step",
     "adg_fv_check_health",
+    "adg_peaks_sink_bytes", "adg_measure_peaks",
 ]
 
 
@@ -147,6 +148,8 @@ def lib():
         for name in ("adg_fv_compute_dt", "adg_fv_predictor", "adg_fv_corrector", "adg_fv_step",
                      "adg_fv_check_health"):
             getattr(L, name).argtypes = [vp, vp]
+        L.adg_peaks_sink_bytes.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
+        L.adg_measure_peaks.argtypes = [vp, vp, vp, ctypes.c_size_t, dp, vp]
         _lib = L
     return _lib
 
@@ -643,6 +646,26 @@ class Batch:
 
     def set_launch(self, group: int, cells_per_wave: int, waves_per_block: int):
         _check(lib().adg_batch_set_launch(self.h, int(group), int(cells_per_wave), int(waves_per_block)))
+
+
+def measure_peaks(copy_mib: int = 1024, stream=None) -> dict:
+    """Measured FP64 vector and matrix-core rates and copy bandwidth of the
+    current device (``include/adg_peaks.h``), beside the published figures."""
+    import torch
+    nb = ctypes.c_size_t()
+    _check(lib().adg_peaks_sink_bytes(ctypes.byref(nb)))
+    sink = torch.empty(nb.value // 8, dtype=torch.float64, device="cuda")
+    n = (copy_mib << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    out = (ctypes.c_double * 3)()
+    _check(lib().adg_measure_peaks(ctypes.c_void_p(sink.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                   ctypes.c_void_p(dst.data_ptr()), n * 8, out, _stream_ptr(stream)))
+    if not torch.equal(src[:1024], dst[:1024]) or not torch.equal(src[-1024:], dst[-1024:]):
+        raise AdgError(ADG_ESTATE, "peak copy produced wrong data")
+    return {"fp64_vector_tflops": out[0], "fp64_vector_tflops_spec": 78.6,
+            "fp64_mfma_tflops": out[1], "fp64_mfma_tflops_spec": 78.6,
+            "copy_GBps": out[2], "hbm_GBps_spec": 8000.0, "copy_bytes": n * 8}
 
 
 def _align256(x):

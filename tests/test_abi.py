@@ -147,3 +147,17 @@ def test_null_arguments_rejected_fv():
     assert L.adg_fv_step(None, None) == adg.ADG_EINVAL
     assert L.adg_fv_destroy(None) == adg.ADG_EINVAL
     assert L.adg_fv_init(None, None, None) == adg.ADG_EINVAL
+
+
+def test_peaks_arguments_checked_before_any_device_work():
+    L = adg.lib()
+    nb = ctypes.c_size_t()
+    assert L.adg_peaks_sink_bytes(ctypes.byref(nb)) == adg.ADG_OK and nb.value > 0
+    assert L.adg_peaks_sink_bytes(None) == adg.ADG_EINVAL
+    out = (ctypes.c_double * 3)()
+    assert L.adg_measure_peaks(None, None, None, 0, out, None) == adg.ADG_EINVAL
+    assert L.adg_measure_peaks(ctypes.c_void_p(16), None, None, 0, None, None) == adg.ADG_EINVAL
+    # a copy size with null buffers, and a size that is not a multiple of 16
+    assert L.adg_measure_peaks(ctypes.c_void_p(16), None, None, 64, out, None) == adg.ADG_EINVAL
+    assert L.adg_measure_peaks(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(32), 40, out,
+                               None) == adg.ADG_EINVAL
