@@ -235,6 +235,13 @@ __global__ __launch_bounds__(kThreads3) void k_pred3(Phys ph, Tab<n> tb, Args3 a
   for (int it = 0; it < a.iters; ++it) {
 #pragma unroll
     for (int b = 0; b < n; ++b) {
+      if (b > 0 && it == 0) {
+        // the first sweep starts from Q^n at every time level: all levels
+        // share level 0's residual (bit for bit)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) R[b][v] = R[0][v];
+        continue;
+      }
 #pragma unroll
       for (int v = 0; v < 5; ++v) sq[v * nd + r] = X[b][v];
       sync3<WL>();
@@ -426,6 +433,13 @@ __global__ __launch_bounds__(kThreads3, 3) void k_pred3_w64(Phys ph, Tab<4> tb, 
   for (int it = 0; it < a.iters; ++it) {
 #pragma unroll
     for (int b = 0; b < n; ++b) {
+      if (b > 0 && it == 0) {
+        // the first sweep starts from Q^n at every time level: all levels
+        // share level 0's residual (bit for bit)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) X[b][v] = X[0][v];
+        continue;
+      }
       double F[3][5], Sw;
       grad_flux(X[b], F, Sw);
 #pragma unroll

@@ -9,6 +9,9 @@ predictor, per sweep and time slice (n*n spatial nodes, 4 variables):
     divergence  16 n^3, residual assembly 10 per node
     time solve  4 vars * n targets * n^2 nodes MACs         = 8 n^3
   per sweep: n * (40 n^3 + (FLUX_FLOPS + 18) n^2) + 8 n^3 (q = Q + dt acc)
+  first sweep: every time slice starts from Q^n, so one slice's residual
+    serves all n: 32 n^3 + (FLUX_FLOPS + 18) n^2, plus the time solve
+    n * 8 n^3 + 8 n^3
   final pass: n * (16 n^3 + (FLUX_FLOPS + 8 + 28) n^2)  (28: averages)
   epilogue:   16 n^3 (volume contraction) + 64 n^2 (face values) + 16 n^2
 corrector: per face node 2 eigen bounds (~14 each) + flux (4 * 4), plus the
@@ -26,10 +29,13 @@ def predictor_flops(N: int, iters: int = 0) -> int:
     n = N + 1
     I = iters or n
     c = FLUX_FLOPS
-    sweep = n * (40 * n ** 3 + (c + 18) * n ** 2) + 8 * n ** 3
+    slice_ = 32 * n ** 3 + (c + 18) * n ** 2     # residual of one time slice
+    solve = n * 8 * n ** 3 + 8 * n ** 3           # time solve of one sweep
+    sweep = n * slice_ + solve
+    first = slice_ + solve                        # all slices equal Q^n
     final = n * (16 * n ** 3 + (c + 36) * n ** 2)
     epi = 16 * n ** 3 + 80 * n ** 2
-    return I * sweep + final + epi
+    return (first + (I - 1) * sweep if I > 0 else 0) + final + epi
 
 
 VJP_FLOPS = 260   # reverse of the flux/source function (forward recomputation included)
@@ -86,6 +92,8 @@ def dofs(cells: int, N: int) -> int:
 #     divergence  30 n^4
 #   per sweep: n * (60 n^4 + (FLUX3_FLOPS + 6) n^3) + 10 n^5 + 5 n^3
 #     (time matrix: 5 vars * n targets * n slices MACs per node, plus Q)
+#   first sweep: one slice's residual serves all n (every slice starts from
+#     Q^n): 60 n^4 + (FLUX3_FLOPS + 6) n^3 + 10 n^5 + 5 n^3
 #   final pass: n * (30 n^4 + (FLUX3_FLOPS + 42) n^3)   (42: 21 averages)
 #   epilogue:   30 n^4 (volume term) + 15 n^3 (Q*) + 120 n^3 (60 n^2 face
 #               values of n MACs)
@@ -100,10 +108,13 @@ def predictor3_flops(N: int, iters: int = 0) -> int:
     n = N + 1
     I = iters or n
     c = FLUX3_FLOPS
-    sweep = n * (60 * n ** 4 + (c + 6) * n ** 3) + 10 * n ** 5 + 5 * n ** 3
+    slice_ = 60 * n ** 4 + (c + 6) * n ** 3
+    solve = 10 * n ** 5 + 5 * n ** 3
+    sweep = n * slice_ + solve
+    first = slice_ + solve
     final = n * (30 * n ** 4 + (c + 42) * n ** 3)
     epi = 30 * n ** 4 + 135 * n ** 3
-    return I * sweep + final + epi
+    return (first + (I - 1) * sweep if I > 0 else 0) + final + epi
 
 
 def predictor3_bytes(N: int) -> int:
