@@ -156,6 +156,7 @@ __device__ inline double node_flux(const Phys& ph, const double q[4], double* sf
   return Sw;
 }
 
+// Up to n = 7 the kernel is held to 168 VGPRs, three wavefronts per SIMD.
 // Per cell: lane l < n*n owns spatial node l = (j, i) and holds, in
 // registers, the Picard iterate at all n time nodes, X[b][v] (the time-node
 // loop is unrolled so the array is statically indexed).  Per sweep and time
@@ -166,7 +167,7 @@ __device__ inline double node_flux(const Phys& ph, const double q[4], double* sf
 // X[a] = Q^n + dt sum_b P[a][b] R(b) runs per node in registers.  Then time
 // averages, the volume term and the face data.
 template <int n, int CPW, int WPB>
-__global__ __launch_bounds__(kWave * WPB) void k_predictor(Phys ph, StepArgs a) {
+__global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phys ph, StepArgs a) {
   using L = Lay<n, CPW>;
   constexpr int nn = L::nn, sl = L::sl, T = L::T, F0 = L::F0;
   extern __shared__ double lds[];
@@ -345,11 +346,10 @@ __global__ __launch_bounds__(kWave * WPB) void k_predictor(Phys ph, StepArgs a) 
     for (int v = 0; v < 4; ++v) sm[v * nn + l] = Qb[v];
     sm[4 * nn + l] = SbE;
   }
-  // flux averages accumulate in LDS (own node only), in the layouts the
-  // line jobs of the volume term read: x fluxes in the first, z fluxes in
-  // the transposed one
-  double* sa = sq + F0 + 2 * sl;
-  double Sbw = 0.0;
+  // flux averages accumulate in registers; they go to LDS once, in the
+  // layouts the line jobs of the volume term read: x fluxes in the first, z
+  // fluxes in the transposed one
+  double Sbw = 0.0, Fxa[4], Fza[4];
 #pragma unroll
   for (int b = 0; b < n; ++b) {
     put_slice(X[b]);
@@ -362,13 +362,8 @@ __global__ __launch_bounds__(kWave * WPB) void k_predictor(Phys ph, StepArgs a) 
       const double wb = gt[GTab::W * n + b];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        if (b == 0) {
-          sa[v * nn + l] = wb * Fx[v];
-          sa[T + v * nn + tl] = wb * Fz[v];
-        } else {
-          sa[v * nn + l] = fma(wb, Fx[v], sa[v * nn + l]);
-          sa[T + v * nn + tl] = fma(wb, Fz[v], sa[T + v * nn + tl]);
-        }
+        Fxa[v] = b == 0 ? wb * Fx[v] : fma(wb, Fx[v], Fxa[v]);
+        Fza[v] = b == 0 ? wb * Fz[v] : fma(wb, Fz[v], Fza[v]);
       }
       Sbw = fma(wb, Sw, Sbw);
     }
@@ -387,7 +382,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_predictor(Phys ph, StepArgs a) 
     SbE = sm[4 * nn + l];
     put_slice(Qb);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) { sf[v * nn + l] = sa[v * nn + l]; sf[T + v * nn + tl] = sa[T + v * nn + tl]; }
+    for (int v = 0; v < 4; ++v) { sf[v * nn + l] = Fxa[v]; sf[T + v * nn + tl] = Fza[v]; }
   }
   wave_sync();
   {
