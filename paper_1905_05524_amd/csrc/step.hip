@@ -423,6 +423,199 @@ __global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phy
   }
 }
 
+// ------------------------------------------- predictor, a wavefront per level
+// For meshes too small to fill the chip with one wavefront per cell: one
+// workgroup of n wavefronts per cell, wavefront b owning time node b.  Each
+// wavefront runs the slice machinery of k_predictor (line jobs on both LDS
+// layouts, even-odd contractions) on its own time node, in its own LDS
+// region of 4 slices.  Within a Picard sweep the n residuals are independent;
+// they meet in LDS, where the time matrix mixes them: X_b = Q + dt sum_a
+// P[b][a] R_a.  The first sweep evaluates one residual (every node starts
+// from Q^n).  In the final pass every wavefront leaves its node's weighted
+// state, fluxes and sources in its region; the first wavefront sums them in
+// a fixed order and runs the epilogue of k_predictor (volume term, Q*, face
+// data).  Same arithmetic as k_predictor up to the order of the sums.
+template <int n>
+__global__ __launch_bounds__(kWave * n) void k_predictor_lv(Phys ph, StepArgs a) {
+  using L = Lay<n, 1>;
+  constexpr int nn = L::nn, sl = L::sl, T = L::T, F0 = L::F0, WR = 4 * sl;
+  extern __shared__ double lds[];                 // n regions of WR doubles
+  const int c = blockIdx.x, b = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  double* wl = lds + (size_t)b * WR;
+  const bool node = lane < nn;
+  const int l = node ? lane : 0;
+  const int jz = l / n, ix = l % n, tl = ix * n + jz;
+  double* sq = wl;          // slice, both layouts; later the residual (offset T)
+  double* sf = wl + F0;     // gradients / fluxes, both layouts
+  const double* gt = a.gtab;
+  const int s = a.scen ? a.scen[c] : 0;
+  const double t0 = a.clock[4 * s + 0], dt = a.clock[4 * s + 1];
+  const double x0 = a.geom[4 * c + 0], z0 = a.geom[4 * c + 1], h = a.geom[4 * c + 2];
+  const double ih = 1.0 / h, mu_h = ph.mu * ih, kappa_h = ph.kappa * ih, gh = ph.geff * h;
+  const double sdt = -dt * ih;   // R = -R' / h
+  const double z = z0 + h * gt[GTab::XI * n + jz];
+  double rb, pb;
+  background(ph, z, rb, pb);
+  EOTab<n> Dt;
+  load_eo<n>(gt + GTab::eo_d(n), Dt);
+  const double* Qc = a.Qin + (size_t)c * sl + l;
+  double X[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) X[v] = Qc[v * nn];
+  // manufactured energy source at this node's time (it does not depend on the state)
+  const double SE = (ph.mms && node) ? mms_source(ph, x0 + h * gt[GTab::XI * n + ix], z,
+                                                  t0 + gt[GTab::XI * n + b] * dt) : 0.0;
+
+  const LineJob<n> J(lane, 1);
+  auto lines = [&](int src_off, int dst_off) {
+    if (J.active) line_eo<n>(Dt, J.base, wl + src_off, wl + dst_off);
+  };
+  auto put_slice = [&](const double q[4]) {
+    if (node) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { sq[v * nn + l] = q[v]; sq[T + v * nn + tl] = q[v]; }
+    }
+  };
+  // scaled residual R' = div F - h S of the slice q (without the manufactured source)
+  auto residual = [&](const double q[4], double R[4]) {
+    put_slice(q);
+    wave_sync();
+    lines(0, F0);
+    wave_sync();
+    double Sw = 0.0;
+    if (node) {
+      double Fx[4], Fz[4];
+      Sw = node_flux<n>(ph, q, sf, l, tl, mu_h, kappa_h, gh, z, rb, pb, Fx, Fz, true);
+    }
+    wave_sync();
+    lines(F0, F0);
+    wave_sync();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) R[v] = node ? sf[v * nn + l] + sf[T + v * nn + tl] : 0.0;
+    R[2] = fma(-h, Sw, R[2]);
+  };
+
+#pragma unroll 1
+  for (int it = 0; it < a.iters; ++it) {
+    double R[4];
+    if (it == 0) {
+      // every node starts from Q^n: the first wavefront's residual serves all
+      if (b == 0) {
+        residual(X, R);
+        if (node)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) sq[v * nn + l] = R[v];
+      }
+      __syncthreads();
+      if (node)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) R[v] = lds[v * nn + l];
+    } else {
+      residual(X, R);
+    }
+    if (node) {
+      if (ph.mms) R[3] = fma(-h, SE, R[3]);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sq[T + v * nn + l] = R[v];
+    }
+    __syncthreads();   // every node's residual in LDS
+    if (node) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a2 = 0; a2 < n; ++a2) acc = fma(gt[GTab::pt(n) + a2 * n + b], lds[(size_t)a2 * WR + T + v * nn + l], acc);
+        X[v] = fma(sdt, acc, Qc[v * nn]);
+      }
+      if (a.iter_store) {
+        double* st = a.iter_store + (((size_t)c * a.iters + it) * n + b) * sl;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) st[v * nn + l] = X[v];
+      }
+    }
+    __syncthreads();   // every residual read before the next sweep overwrites them
+  }
+
+  // final pass: this node's flux and sources at the last iterate, weighted,
+  // to its region as [state | x flux | z flux | gravity source | energy source]
+  put_slice(X);
+  wave_sync();
+  lines(0, F0);
+  wave_sync();
+  {
+    double Fx[4], Fz[4], Sw = 0.0;
+    if (node) Sw = node_flux<n>(ph, X, sf, l, tl, mu_h, kappa_h, gh, z, rb, pb, Fx, Fz, false);
+    wave_sync();
+    const double wb = gt[GTab::W * n + b];
+    if (node) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        wl[v * nn + l] = wb * X[v];
+        wl[(4 + v) * nn + l] = wb * Fx[v];
+        wl[(8 + v) * nn + l] = wb * Fz[v];
+      }
+      wl[12 * nn + l] = wb * Sw;
+      wl[13 * nn + l] = wb * SE;
+    }
+  }
+  __syncthreads();
+  if (b != 0) return;
+
+  // level sums in a fixed order, then the epilogue of k_predictor
+  double Qb[4] = {0, 0, 0, 0}, Fbx[4] = {0, 0, 0, 0}, Fbz[4] = {0, 0, 0, 0}, Sbw = 0.0, SbE = 0.0;
+  if (node) {
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      const double* r = lds + (size_t)k * WR;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        Qb[v] += r[v * nn + l];
+        Fbx[v] += r[(4 + v) * nn + l];
+        Fbz[v] += r[(8 + v) * nn + l];
+      }
+      Sbw += r[12 * nn + l];
+      SbE += r[13 * nn + l];
+    }
+  }
+  wave_sync();
+  if (node) {
+    put_slice(Qb);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { sf[v * nn + l] = Fbx[v]; sf[T + v * nn + tl] = Fbz[v]; }
+  }
+  wave_sync();
+  {
+    EOTab<n> Wt;
+    load_eo<n>(gt + GTab::eo_dw(n), Wt);
+    if (J.active) {
+      double q0 = 0, q1 = 0, f0 = 0, f1 = 0;
+#pragma unroll
+      for (int m = 0; m < n; ++m) {
+        const double e0 = gt[GTab::E0 * n + m], e1 = gt[GTab::E1 * n + m];
+        const double iq = wl[J.base + m], iF = wl[F0 + J.base + m];
+        q0 = fma(e0, iq, q0); q1 = fma(e1, iq, q1);
+        f0 = fma(e0, iF, f0); f1 = fma(e1, iF, f1);
+      }
+      line_eo<n>(Wt, J.base, wl + F0, wl + F0);
+      double* fd = a.FD + (size_t)c * 32 * n;
+      const int fl0 = 2 * J.dir, fu = 2 * J.dir + 1;
+      fd[((fl0 * 2 + 0) * 4 + J.v) * n + J.line] = q0;
+      fd[((fl0 * 2 + 1) * 4 + J.v) * n + J.line] = f0;
+      fd[((fu * 2 + 0) * 4 + J.v) * n + J.line] = q1;
+      fd[((fu * 2 + 1) * 4 + J.v) * n + J.line] = f1;
+    }
+  }
+  wave_sync();
+  if (node) {
+    double* qs = a.Qs + (size_t)c * sl;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double S = (v == 2) ? Sbw : (v == 3 ? SbE : 0.0);
+      qs[v * nn + l] = Qc[v * nn] + dt * ((sf[v * nn + l] + sf[T + v * nn + tl]) * ih + S);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ corrector
 // Ghost state and flux at a no-slip wall: mirrored velocity, background
 // density and pressure (interior ones without gravity), mass flux mirrored,
@@ -803,6 +996,29 @@ static int dt_n(const Group& g, hipStream_t s) {
   }
 
 int launch_predictor(const Group& g, hipStream_t s) { ADG_DISPATCH_N(pred_n, g, s); }
+
+template <int n>
+static int pred_lv_n(const Group& g, double* store, hipStream_t s) {
+  using L = Lay<n, 1>;
+  if (g.C == 0) return ADG_OK;
+  StepArgs a = make_args(g);
+  a.iter_store = store;
+  const size_t lds = sizeof(double) * (size_t)n * 4 * L::sl;
+  hipLaunchKernelGGL(k_predictor_lv<n>, dim3(g.C), dim3(kWave * n), lds, s, g.ph, a);
+  return check_launch("predictor (levels)");
+}
+int launch_predictor_levels(const Group& g, double* store, hipStream_t s) {
+  switch (g.n) {
+    case 2: return pred_lv_n<2>(g, store, s);
+    case 3: return pred_lv_n<3>(g, store, s);
+    case 4: return pred_lv_n<4>(g, store, s);
+    case 5: return pred_lv_n<5>(g, store, s);
+    case 6: return pred_lv_n<6>(g, store, s);
+    case 7: return pred_lv_n<7>(g, store, s);
+    case 8: return pred_lv_n<8>(g, store, s);
+    default: return fail(ADG_EUNSUPPORTED, "order not supported");
+  }
+}
 
 template <int n>
 static int pred_store_n(const Group& g, double* store, hipStream_t s) {
