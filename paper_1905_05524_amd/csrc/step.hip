@@ -696,6 +696,18 @@ __global__ __launch_bounds__(kWave * WPB) void k_corrector(Phys ph, StepArgs a) 
   const double* gt = a.gtab;
   const double eta0 = (2.0 * ph.N + 1.0) / 1.2533141373155002512;   // (2N+1)/sqrt(pi/2)
 
+  // Q* of this lane's node, loaded first so that its latency overlaps the
+  // face phase
+  const int slot = lane / nn, l = lane % nn;
+  const int c = cell0 + slot;
+  const bool valid = slot < CPW && c < a.C;
+  double qsv[4] = {0.0, 0.0, 0.0, 0.0};
+  if (valid) {
+    const double* qs = a.Qs + (size_t)c * sl;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) qsv[v] = qs[v * nn + l];
+  }
+
   // face role
   const int fslot = lane / (4 * n);
   const int f = (lane % (4 * n)) / n, k = lane % n;
@@ -788,9 +800,6 @@ __global__ __launch_bounds__(kWave * WPB) void k_corrector(Phys ph, StepArgs a) 
   wave_sync();
 
   // node role: lifting and the next CFL candidate
-  const int slot = lane / nn, l = lane % nn;
-  const int c = cell0 + slot;
-  const bool valid = slot < CPW && c < a.C;
   const double* sGc = wl + (slot < CPW ? slot : 0) * L::corr_cell;
   double lam_n = 0.0, lv_n = 0.0;
   if (valid) {
@@ -800,7 +809,6 @@ __global__ __launch_bounds__(kWave * WPB) void k_corrector(Phys ph, StepArgs a) 
     const double z0 = a.geom[4 * c + 1], h = a.geom[4 * c + 2];
     const double L0i = gt[GTab::L0 * n + ix], L1i = gt[GTab::L1 * n + ix];
     const double L0j = gt[GTab::L0 * n + jz], L1j = gt[GTab::L1 * n + jz];
-    const double* qs = a.Qs + (size_t)c * sl;
     double* qo = a.Qout + (size_t)c * sl;
     const double scl = dt / h;
     double q[4];
@@ -808,7 +816,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_corrector(Phys ph, StepArgs a) 
     for (int v = 0; v < 4; ++v) {
       const double sx = L1i * sGc[(1 * 4 + v) * n + jz] - L0i * sGc[(0 * 4 + v) * n + jz];
       const double sz = L1j * sGc[(3 * 4 + v) * n + ix] - L0j * sGc[(2 * 4 + v) * n + ix];
-      q[v] = qs[v * nn + l] - scl * (sx + sz);
+      q[v] = qsv[v] - scl * (sx + sz);
       qo[v * nn + l] = q[v];
     }
     if (!ph.fixed_dt) {
