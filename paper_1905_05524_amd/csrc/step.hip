@@ -889,6 +889,9 @@ __global__ __launch_bounds__(kReduceThreads) void k_clock(double* clock, const d
   __shared__ double sm[kReduceThreads / kWave];
   const int s = blockIdx.x, t = threadIdx.x;
   const int b0 = beg ? beg[s] : 0, b1 = end ? end[s] : C;
+  // the clock is read before the reduction so that its latency overlaps it
+  double t_old = 0.0, dt_old = 0.0, n_old = 0.0;
+  if (t == 0) { t_old = clock[4 * s + 0]; dt_old = clock[4 * s + 1]; n_old = clock[4 * s + 3]; }
   double m = __builtin_inf();
   if (update) {
     // four independent loads in flight per thread
@@ -907,7 +910,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_clock(double* clock, const d
   if (t == 0) {
     double r = sm[0];
     for (int k = 1; k < kReduceThreads / kWave; ++k) r = fmin(r, sm[k]);
-    if (advance) { clock[4 * s + 0] += clock[4 * s + 1]; clock[4 * s + 3] += 1.0; }
+    if (advance) { clock[4 * s + 0] = t_old + dt_old; clock[4 * s + 3] = n_old + 1.0; }
     if (update) clock[4 * s + 1] = r;
   }
 }
