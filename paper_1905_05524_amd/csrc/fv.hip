@@ -6,7 +6,7 @@
 // (32 B each) and the x neighbours come from the same cache lines.
 // The step (adg_fv_step) is one fused kernel on tiles of 16 x 16 cells:
 //   k_fv_fused    each thread predicts its cell (slopes, Hancock half step),
-//                 the first threads also the ring of cells around the tile
+//                 a fifth wavefront the ring of cells around the tile
 //                 (only the face value the tile needs); the evolved face
 //                 values meet in LDS; every face of the tile gets its
 //                 Rusanov flux once (one job per face, 2.25 per cell); each
@@ -342,10 +342,11 @@ __device__ inline void fv_face(const Phys& ph, int d, double zf, double rbf, dou
 // tile (each only for the face value the tile needs); the evolved face
 // values meet in LDS; the update goes to Qn (other tiles still read Q), and
 // the workgroup's time-step bound of the new values goes to dtb[tile].
-constexpr int kTX = 16, kTZ = 16, kFT = kTX * kTZ;   // tile and workgroup size (one thread per tile cell)
-static_assert(kFT % kWave == 0 && 2 * (kTX + kTZ) <= kFT, "one thread per tile cell, the ring fits");
+constexpr int kTX = 16, kTZ = 16, kFT = kTX * kTZ;   // tile (one thread per tile cell)
+constexpr int kRing = 2 * (kTX + kTZ), kFTR = kFT + kRing;   // workgroup: tile cells, then the ring
+static_assert(kFT % kWave == 0 && kRing % kWave == 0, "tile and ring fill whole wavefronts");
 
-__global__ __launch_bounds__(kFT) void k_fv_fused(Phys ph, FvArgs a, double* Qn) {
+__global__ __launch_bounds__(kFTR) void k_fv_fused(Phys ph, FvArgs a, double* Qn) {
   // evolved face values by face type, variable, row, column; each array is
   // padded by one in the direction of the neighbour that reads it:
   // west values of columns 0..kTX (kTX: east ring), east values of columns
@@ -357,14 +358,16 @@ __global__ __launch_bounds__(kFT) void k_fv_fused(Phys ph, FvArgs a, double* Qn)
   const int x0 = blockIdx.x * kTX, z0 = blockIdx.y * kTZ;
   const int ew = min(kTX, a.nx - x0), eh = min(kTZ, a.nz - z0);   // extent of the tile inside the domain
   const double dt = a.clock[1];
-  const bool inside = tx < ew && tz < eh;
-  // ring: left and right columns (the face towards the tile), bottom and top rows
-  if (t < 2 * kTZ + 2 * kTX) {
+  const bool inside = t < kFT && tx < ew && tz < eh;
+  // ring (threads kFT..kFTR-1, wavefronts of their own): left and right
+  // columns (the face towards the tile), bottom and top rows
+  if (t >= kFT) {
+    const int q = t - kFT;
     int rx, rz, f;
-    if (t < kTZ) { rx = -1; rz = t; f = 1; }
-    else if (t < 2 * kTZ) { rx = ew; rz = t - kTZ; f = 0; }
-    else if (t < 2 * kTZ + kTX) { rx = t - 2 * kTZ; rz = -1; f = 3; }
-    else { rx = t - 2 * kTZ - kTX; rz = eh; f = 2; }
+    if (q < kTZ) { rx = -1; rz = q; f = 1; }
+    else if (q < 2 * kTZ) { rx = ew; rz = q - kTZ; f = 0; }
+    else if (q < 2 * kTZ + kTX) { rx = q - 2 * kTZ; rz = -1; f = 3; }
+    else { rx = q - 2 * kTZ - kTX; rz = eh; f = 2; }
     const bool used = (f < 2) ? rz < eh : rx < ew;
     int gi = x0 + rx, gj = z0 + rz;
     bool ok = used;
@@ -401,7 +404,7 @@ __global__ __launch_bounds__(kFT) void k_fv_fused(Phys ph, FvArgs a, double* Qn)
   // flux replaces the low side's value, which only this job reads
   constexpr int kZJobs = (kTZ + 1) * kTX, kXJobs = kTZ * (kTX + 1);
   constexpr int zvs = (kTZ + 1) * kTX, xvs = kTZ * (kTX + 1);   // variable strides of the two array shapes
-  for (int k = t; k < kZJobs + kXJobs; k += kFT) {
+  for (int k = t; k < kZJobs + kXJobs; k += kFTR) {
     const bool zj = k < kZJobs;
     const int kk = zj ? k : k - kZJobs;
     const int r = zj ? kk / kTX : kk / (kTX + 1), col = zj ? kk % kTX : kk % (kTX + 1);
@@ -452,7 +455,7 @@ __global__ __launch_bounds__(kFT) void k_fv_fused(Phys ph, FvArgs a, double* Qn)
     o[1] = make_double2(out[2], out[3]);
     lam = fv_lambda(ph, out, a.bg[15 * j]);
   }
-  fv_block_bound<kFT>(ph, a, lam, blockIdx.y * gridDim.x + blockIdx.x);
+  fv_block_bound<kFTR>(ph, a, lam, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // Q <- Qn on the two outer layers of every tile of the fused step (workgroup
@@ -763,7 +766,7 @@ int adg_fv_step(adg_fv* m, void* stream) {
   const FvArgs a = fv_args(m);
   double* Qn = a.E;   // the fused step keeps its new values in the face-value area
   const dim3 tiles((m->desc.nx + kTX - 1) / kTX, (m->desc.nz + kTZ - 1) / kTZ);
-  hipLaunchKernelGGL(k_fv_fused, tiles, dim3(kFT), 0, s, m->ph, a, Qn);
+  hipLaunchKernelGGL(k_fv_fused, tiles, dim3(kFTR), 0, s, m->ph, a, Qn);
   rc = check_launch("fv_fused");
   if (rc) return rc;
   // copy-back of the tiles' edge cells plus one workgroup for the clock
