@@ -53,8 +53,15 @@ def increment_err(got, ref, Q0):
     return relerr(dgot, dref, scale=sc)
 
 
-def mesh_of(w, **kw):
+# predictor kernels: one wavefront per cell, one wavefront per time level
+# (small meshes take the second by default, so both are named explicitly)
+KERNELS = {"cell": (1, 1), "level": (0, 1)}
+
+
+def mesh_of(w, kernel=None, **kw):
     m = adg.Mesh(w["phys"], w["mesh"], **kw)
+    if kernel is not None:
+        m.set_launch(*KERNELS[kernel])
     return m
 
 
@@ -125,13 +132,14 @@ def _case(kind, nx, N):
     raise ValueError(kind)
 
 
+@pytest.mark.parametrize("kernel", list(KERNELS))
 @pytest.mark.parametrize("kind,nx,N", CASES)
-def test_predictor_matches_oracle(kind, nx, N):
+def test_predictor_matches_oracle(kind, nx, N, kernel):
     w = _case(kind, nx, N)
     Q = _state(w, seed=1000 + 10 * N + nx)
     dt = 0.5 * O.dt(w["phys"], w["mesh"], Q)
     t = 0.37
-    m = mesh_of(w, fixed_dt=True)
+    m = mesh_of(w, kernel, fixed_dt=True)
     m.set_state(Q, t=t, dt=dt)
     m.predictor()
     torch.cuda.synchronize()
@@ -147,12 +155,13 @@ def test_predictor_matches_oracle(kind, nx, N):
         assert np.all(relerr(a, b) <= TOL), (k, relerr(a, b))
 
 
+@pytest.mark.parametrize("kernel", list(KERNELS))
 @pytest.mark.parametrize("kind,nx,N", CASES)
-def test_step_matches_oracle(kind, nx, N):
+def test_step_matches_oracle(kind, nx, N, kernel):
     w = _case(kind, nx, N)
     Q = _state(w, seed=2000 + 10 * N + nx)
     dt = 0.5 * O.dt(w["phys"], w["mesh"], Q)
-    m = mesh_of(w, fixed_dt=True)
+    m = mesh_of(w, kernel, fixed_dt=True)
     m.set_state(Q, t=0.1, dt=dt)
     m.step()
     ref = O.step(w["phys"], w["mesh"], Q, 0.1, dt)
@@ -175,12 +184,13 @@ def test_cfl_dt_matches_oracle():
         assert abs(m.dt - ref) <= 1e-14 * ref
 
 
-def test_mms_ten_steps_per_step_parity():
+@pytest.mark.parametrize("kernel", list(KERNELS))
+def test_mms_ten_steps_per_step_parity(kernel):
     """The manufactured-solution workload (9x9 periodic, N=2): 10 steps with
     the CFL rule on the GPU; each step is compared with the oracle fed the
     GPU's previous state and time step."""
     w = I.mms_small()
-    m = mesh_of(w)
+    m = mesh_of(w, kernel)
     m.init_state("mms")
     m.compute_dt()
     for s in range(w["steps"]):
