@@ -663,9 +663,14 @@ def measure_peaks(copy_mib: int = 1024, stream=None) -> dict:
                                    ctypes.c_void_p(dst.data_ptr()), n * 8, out, _stream_ptr(stream)))
     if not torch.equal(src[:1024], dst[:1024]) or not torch.equal(src[-1024:], dst[-1024:]):
         raise AdgError(ADG_ESTATE, "peak copy produced wrong data")
+    pr = torch.cuda.get_device_properties(torch.cuda.current_device())
     return {"fp64_vector_tflops": out[0], "fp64_vector_tflops_spec": 78.6,
             "fp64_mfma_tflops": out[1], "fp64_mfma_tflops_spec": 78.6,
-            "copy_GBps": out[2], "hbm_GBps_spec": 8000.0, "copy_bytes": n * 8}
+            "copy_GBps": out[2], "hbm_GBps_spec": 8000.0, "copy_bytes": n * 8,
+            "device": {"name": pr.name, "arch": getattr(pr, "gcnArchName", ""),
+                       "compute_units": pr.multi_processor_count, "memory_bytes": pr.total_memory,
+                       "lds_per_block_bytes": pr.shared_memory_per_block, "wavefront": pr.warp_size,
+                       "l2_bytes": getattr(pr, "L2_cache_size", None)}}
 
 
 def _align256(x):
