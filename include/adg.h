@@ -184,8 +184,10 @@ int adg_regrid_plan(adg_mesh* m, const int8_t* flags_host, int* n_cells_new, siz
 /* Regrid, step 2: transfer the bound state into Q_new (caller-owned,
  * n_cells_new*4*n*n doubles, must not alias Q): copy for kept leaves, exact
  * interpolation of the parent polynomial for new children, L2 projection of
- * the nine children for a new parent; then rebuild the face tables and bind
- * (Q_new, workspace_new, clock).  Synchronises the stream.  The old Q and
+ * the nine children for a new parent; then install the face tables the plan
+ * built (in the handle's device buffers, which grow when the mesh does) and
+ * bind (Q_new, workspace_new, clock).  Synchronises the device (every kernel
+ * that reads the old tables, on any stream, has finished).  The old Q and
  * workspace are the caller's to free. */
 int adg_regrid_apply(adg_mesh* m, double* Q_new, void* workspace_new, double* clock, void* stream);
 

@@ -8,6 +8,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "adg.h"
@@ -109,6 +110,59 @@ struct HostBasis {
   std::vector<double> xi, w, D, P, Dw, e0, e1, gtab;
 };
 
+// Leaves by (level, i, j) on a mesh of nx x nz coarse cells with levels
+// 0..L: one dense table per level while the boxes of all levels number at
+// most kDenseBoxes (16 MB of ints), else a hash map.  Lookups outside the
+// grid of their level find nothing.
+struct LeafIndex {
+  static constexpr long long kDenseBoxes = 1LL << 22;
+  int nx, nz, L;
+  bool dense = false;
+  std::vector<long long> off;   // per level: start of its table
+  std::vector<int> tab;
+  std::unordered_map<long long, int> map;
+  LeafIndex(int nx_, int nz_, int L_, size_t n_leaves) : nx(nx_), nz(nz_), L(L_), off(L_ + 1, 0) {
+    long long total = 0, s = 1;
+    for (int l = 0; l <= L && total <= kDenseBoxes; ++l, s *= 3) {
+      off[l] = total;
+      total += (long long)nx * s * nz * s;
+    }
+    dense = total <= kDenseBoxes;
+    if (dense) tab.assign((size_t)total, -1);
+    else map.reserve(n_leaves * 2);
+  }
+  static long long key(int l, int i, int j) { return ((long long)l << 52) ^ ((long long)i << 26) ^ (long long)j; }
+  bool in_grid(int l, int i, int j) const {
+    if (l < 0 || l > L || i < 0 || j < 0) return false;
+    long long s = 1;
+    for (int k = 0; k < l; ++k) s *= 3;
+    return i < nx * s && j < nz * s;
+  }
+  long long slot(int l, int i, int j) const {
+    long long s = 1;
+    for (int k = 0; k < l; ++k) s *= 3;
+    return off[l] + (long long)j * nx * s + i;
+  }
+  // records leaf c at (l, i, j); false if the box is outside the grid or
+  // holds a leaf already
+  bool insert(int l, int i, int j, int c) {
+    if (!in_grid(l, i, j)) return false;
+    if (!dense) return map.emplace(key(l, i, j), c).second;
+    int& t = tab[(size_t)slot(l, i, j)];
+    if (t >= 0) return false;
+    t = c;
+    return true;
+  }
+  int find(int l, int i, int j) const {
+    if (!in_grid(l, i, j)) return -1;
+    if (!dense) {
+      auto it = map.find(key(l, i, j));
+      return it == map.end() ? -1 : it->second;
+    }
+    return tab[(size_t)slot(l, i, j)];
+  }
+};
+
 // Host mesh: leaves, geometry and face table.
 struct HostMesh {
   int C = 0;
@@ -131,9 +185,19 @@ struct adg_mesh {
   double* clock = nullptr;
   // workspace partition (byte offsets)
   size_t off_qs = 0, off_fd = 0, off_dtc = 0, off_health = 0, ws_bytes = 0;
-  // pending regrid (from adg_regrid_plan)
+  // pending regrid (from adg_regrid_plan): new leaves, transfer operations
+  // and the new mesh tables
   bool plan_ready = false;
   std::vector<int> plan_lev, plan_ci, plan_cj, plan_ops;
+  adg::HostMesh plan_mesh;
+  // grow-only device buffers of the regrid: transfer operations (ints) and
+  // the capacity, in cells, of the geometry and neighbour tables
+  int* d_ops = nullptr;
+  size_t ops_cap = 0;
+  int cells_cap = 0;
+  // pinned host staging of the regrid's uploads (grow-only, bytes)
+  void* h_stage = nullptr;
+  size_t stage_cap = 0;
 };
 
 namespace adg {

@@ -115,22 +115,18 @@ static long long fkey(int l, int i, int j) { return ((long long)l << 52) ^ ((lon
 namespace {
 
 struct LeafMap {
-  std::unordered_map<long long, int> idx;
+  LeafIndex idx;
   const std::vector<int>& lev;
   const std::vector<int>& ci;
   const std::vector<int>& cj;
   int nx, nz;
   const int* bc;
   LeafMap(const std::vector<int>& l, const std::vector<int>& i, const std::vector<int>& j, int nx_, int nz_,
-          const int* bc_)
-      : lev(l), ci(i), cj(j), nx(nx_), nz(nz_), bc(bc_) {
-    idx.reserve(l.size() * 2);
-    for (size_t c = 0; c < l.size(); ++c) idx[fkey(l[c], i[c], j[c])] = (int)c;
+          const int* bc_, int L)
+      : idx(nx_, nz_, L, l.size()), lev(l), ci(i), cj(j), nx(nx_), nz(nz_), bc(bc_) {
+    for (size_t c = 0; c < l.size(); ++c) idx.insert(l[c], i[c], j[c], (int)c);
   }
-  int find(int l, int i, int j) const {
-    auto it = idx.find(fkey(l, i, j));
-    return it == idx.end() ? -1 : it->second;
-  }
+  int find(int l, int i, int j) const { return idx.find(l, i, j); }
 };
 
 int pow3i(int e) { int r = 1; while (e-- > 0) r *= 3; return r; }
@@ -185,7 +181,7 @@ int regrid_plan(const std::vector<int>& lev, const std::vector<int>& ci, const s
     if (f == -1 && lev[c] == 0) f = 0;
     eff[c] = f;
   }
-  const LeafMap M(lev, ci, cj, nx, nz, bc);
+  const LeafMap M(lev, ci, cj, nx, nz, bc, L);
   // new level: +1 refine, -1 accepted coarsening (coded 2 below)
   std::vector<int> coarsen(C, 0);
   auto nl = [&](int c) { return lev[c] + (eff[c] == 1 ? 1 : 0) - coarsen[c]; };

@@ -231,7 +231,6 @@ void build_basis(int n, HostBasis& B) {
 }
 
 // ------------------------------------------------------------------- mesh
-static long long key3(int l, int i, int j) { return ((long long)l << 52) ^ ((long long)i << 26) ^ (long long)j; }
 static int pow3(int e) { int r = 1; while (e-- > 0) r *= 3; return r; }
 
 static int build_mesh(const adg_mesh_desc& d, HostMesh& H) {
@@ -248,12 +247,11 @@ static int build_mesh(const adg_mesh_desc& d, HostMesh& H) {
     if (H.ci[c] < 0 || H.ci[c] >= d.nx * s || H.cj[c] < 0 || H.cj[c] >= d.nz * s)
       return fail(ADG_EINVAL, "leaf index out of range");
   }
-  std::unordered_map<long long, int> idx;
-  idx.reserve((size_t)C * 2);
-  long long area = 0;
   const int L = d.max_level;
+  LeafIndex idx(d.nx, d.nz, L, (size_t)C);
+  long long area = 0;
   for (int c = 0; c < C; ++c) {
-    if (!idx.emplace(key3(H.lev[c], H.ci[c], H.cj[c]), c).second) return fail(ADG_EINVAL, "duplicate leaf");
+    if (!idx.insert(H.lev[c], H.ci[c], H.cj[c], c)) return fail(ADG_EINVAL, "duplicate leaf");
     const long long s = pow3(L - H.lev[c]);
     area += s * s;
   }
@@ -263,7 +261,7 @@ static int build_mesh(const adg_mesh_desc& d, HostMesh& H) {
     int l = H.lev[c], i = H.ci[c], j = H.cj[c];
     while (l > 0) {
       l -= 1; i /= 3; j /= 3;
-      if (idx.count(key3(l, i, j))) return fail(ADG_EINVAL, "leaf overlaps an ancestor");
+      if (idx.find(l, i, j) >= 0) return fail(ADG_EINVAL, "leaf overlaps an ancestor");
     }
   }
   const double hc = d.Lx / d.nx;
@@ -287,12 +285,12 @@ static int build_mesh(const adg_mesh_desc& d, HostMesh& H) {
         if (d.bc[f] == ADG_BC_WALL) { nb[0] = kWall; continue; }
         i = (i + NX) % NX; j = (j + NZ) % NZ;
       }
-      auto it = idx.find(key3(l, i, j));
-      if (it != idx.end()) { nb[0] = kConforming; nb[1] = it->second; continue; }
+      const int same = idx.find(l, i, j);
+      if (same >= 0) { nb[0] = kConforming; nb[1] = same; continue; }
       if (l > 0) {
-        auto pc = idx.find(key3(l - 1, i / 3, j / 3));
-        if (pc != idx.end()) {
-          nb[0] = kFineSide; nb[1] = pc->second;
+        const int pc = idx.find(l - 1, i / 3, j / 3);
+        if (pc >= 0) {
+          nb[0] = kFineSide; nb[1] = pc;
           nb[2] = (f < 2) ? (H.cj[c] % 3) : (H.ci[c] % 3);
           continue;
         }
@@ -304,9 +302,9 @@ static int build_mesh(const adg_mesh_desc& d, HostMesh& H) {
           // children of (l, i, j) touching face f of this cell, in tangential order
           int ci2 = (f == 0) ? 3 * i + 2 : (f == 1) ? 3 * i : 3 * i + s;
           int cj2 = (f == 2) ? 3 * j + 2 : (f == 3) ? 3 * j : 3 * j + s;
-          auto kc = idx.find(key3(l + 1, ci2, cj2));
-          if (kc == idx.end()) { ok = false; break; }
-          kids[s] = kc->second;
+          const int kc = idx.find(l + 1, ci2, cj2);
+          if (kc < 0) { ok = false; break; }
+          kids[s] = kc;
         }
         if (ok) { nb[0] = kCoarseSide; nb[1] = kids[0]; nb[2] = kids[1]; nb[3] = kids[2]; continue; }
       }
@@ -521,6 +519,7 @@ int adg_init_mesh(const adg_params* prm, const adg_mesh_desc* mesh, adg_mesh** o
   g.C = m->hm.C; g.ph = make_phys(*prm);
   rc = upload_group(g, m->hm.geom, m->hm.nbr, m->basis.gtab, nullptr);
   if (rc) { delete m; return rc; }
+  m->cells_cap = g.C;
   layout_workspace(m);
   *out = m;
   return ADG_OK;
@@ -529,6 +528,8 @@ int adg_init_mesh(const adg_params* prm, const adg_mesh_desc* mesh, adg_mesh** o
 int adg_destroy(adg_mesh* m) {
   if (!m) return fail(ADG_EINVAL, "null handle");
   free_group(m->g);
+  if (m->d_ops) (void)hipFree(m->d_ops);
+  if (m->h_stage) (void)hipHostFree(m->h_stage);
   delete m;
   return ADG_OK;
 }
@@ -655,8 +656,7 @@ int adg_regrid_plan(adg_mesh* m, const int8_t* flags_host, int* n_cells_new, siz
   adg_mesh_desc d = m->desc;
   d.n_leaves = (int)m->plan_lev.size();
   d.leaf_level = m->plan_lev.data(); d.leaf_i = m->plan_ci.data(); d.leaf_j = m->plan_cj.data();
-  HostMesh probe;
-  rc = build_mesh(d, probe);
+  rc = build_mesh(d, m->plan_mesh);   // kept for adg_regrid_apply
   if (rc) return fail(ADG_EUNSUPPORTED, std::string("regrid result is not a valid mesh: ") + g_err);
   size_t a, b, c, e;
   if (n_cells_new) *n_cells_new = d.n_leaves;
@@ -673,31 +673,82 @@ int adg_regrid_apply(adg_mesh* m, double* Q_new, void* workspace_new, double* cl
   if (Q_new == m->Q) return fail(ADG_EINVAL, "Q_new must not alias the current state");
   hipStream_t s = (hipStream_t)stream;
   const int Cn = (int)m->plan_lev.size();
-  int* d_ops = nullptr;
-  if (hipMalloc(&d_ops, sizeof(int) * m->plan_ops.size()) != hipSuccess) return fail(ADG_ENOMEM, "alloc ops");
-  if (hipMemcpy(d_ops, m->plan_ops.data(), sizeof(int) * m->plan_ops.size(), hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(d_ops);
-    return fail(ADG_EHIP, "upload ops");
+  const size_t nops = m->plan_ops.size();
+  HostMesh& H = m->plan_mesh;
+  Group& g = m->g;
+  // transfer operations through a grow-only device buffer
+  if (nops > m->ops_cap) {
+    if (m->d_ops) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(m->d_ops);
+      m->d_ops = nullptr;
+      m->ops_cap = 0;
+    }
+    if (hipMalloc(&m->d_ops, sizeof(int) * nops) != hipSuccess) {
+      m->d_ops = nullptr;
+      return fail(ADG_ENOMEM, "alloc ops");
+    }
+    m->ops_cap = nops;
   }
-  rc = launch_regrid(m->g.n, Cn, d_ops, m->Q, Q_new, m->g.d_gtab, s);
-  (void)hipStreamSynchronize(s);
-  (void)hipFree(d_ops);
+  // the uploads go through a grow-only pinned staging buffer: operations,
+  // geometry, neighbours (an apply ends with a stream synchronisation, so no
+  // earlier copy from it is in flight)
+  const size_t b_ops = sizeof(int) * nops, b_geom = sizeof(double) * 4 * (size_t)H.C,
+               b_nbr = sizeof(int) * 16 * (size_t)H.C;
+  const size_t o_geom = align256(b_ops), o_nbr = o_geom + align256(b_geom), need = o_nbr + align256(b_nbr);
+  if (need > m->stage_cap) {
+    if (m->h_stage) {
+      (void)hipDeviceSynchronize();   // no copy from the old buffer is in flight
+      (void)hipHostFree(m->h_stage);
+    }
+    m->h_stage = nullptr;
+    m->stage_cap = 0;
+    if (hipHostMalloc(&m->h_stage, need + need / 4) != hipSuccess) {
+      m->h_stage = nullptr;
+      return fail(ADG_ENOMEM, "pinned staging allocation failed");
+    }
+    m->stage_cap = need + need / 4;
+  }
+  char* st = static_cast<char*>(m->h_stage);
+  if (nops) {
+    std::memcpy(st, m->plan_ops.data(), b_ops);
+    if (hipMemcpyAsync(m->d_ops, st, b_ops, hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(ADG_EHIP, "upload ops");
+  }
+  rc = launch_regrid(m->g.n, Cn, m->d_ops, m->Q, Q_new, m->g.d_gtab, s);
   if (rc) return rc;
-  // rebuild the mesh tables for the new leaves
-  adg_mesh_desc d = m->desc;
-  d.n_leaves = Cn;
-  d.leaf_level = m->plan_lev.data(); d.leaf_i = m->plan_ci.data(); d.leaf_j = m->plan_cj.data();
-  HostMesh H;
-  rc = build_mesh(d, H);
-  if (rc) return rc;
-  Group g = m->g;
-  g.d_geom = nullptr; g.d_nbr = nullptr; g.d_gtab = nullptr; g.d_scen = nullptr;
+  std::memcpy(st + o_geom, H.geom.data(), b_geom);   // staged while the transfer kernel runs
+  std::memcpy(st + o_nbr, H.nbr.data(), b_nbr);
+  // every kernel that reads the old tables (on any stream) is done before
+  // they are overwritten or freed
+  if (hipDeviceSynchronize() != hipSuccess) return fail(ADG_EHIP, "synchronize failed");
+  // the new geometry and neighbour tables (built by the plan): in place when
+  // they fit, else in new buffers with some headroom; the basis table stays
+  if (H.C > m->cells_cap) {
+    if (g.d_geom) (void)hipFree(g.d_geom);
+    if (g.d_nbr) (void)hipFree(g.d_nbr);
+    g.d_geom = nullptr; g.d_nbr = nullptr; m->cells_cap = 0;
+    const int cap = H.C + H.C / 4 + 16;
+    if (hipMalloc(&g.d_geom, sizeof(double) * 4 * (size_t)cap) != hipSuccess ||
+        hipMalloc(&g.d_nbr, sizeof(int) * 16 * (size_t)cap) != hipSuccess) {
+      if (g.d_geom) (void)hipFree(g.d_geom);
+      g.d_geom = nullptr; g.C = 0;
+      return fail(ADG_ENOMEM, "device allocation failed");
+    }
+    m->cells_cap = cap;
+  }
+  if (H.C && (hipMemcpyAsync(g.d_geom, st + o_geom, b_geom, hipMemcpyHostToDevice, s) != hipSuccess ||
+              hipMemcpyAsync(g.d_nbr, st + o_nbr, b_nbr, hipMemcpyHostToDevice, s) != hipSuccess ||
+              hipStreamSynchronize(s) != hipSuccess)) {
+    g.C = 0;
+    return fail(ADG_EHIP, "upload failed");
+  }
   g.C = H.C;
-  rc = upload_group(g, H.geom, H.nbr, m->basis.gtab, nullptr);
-  if (rc) return rc;
-  free_group(m->g);
-  m->g = g;
+  g.nc = 0;
+  for (size_t k = 0; k < 4 * (size_t)H.C; ++k)
+    if (H.nbr[4 * k] == kFineSide || H.nbr[4 * k] == kCoarseSide) { g.nc = 1; break; }
   m->hm = std::move(H);
+  m->plan_mesh = HostMesh();
   m->plan_ready = false;
   layout_workspace(m);
   return adg_set_state(m, Q_new, workspace_new, clock);
