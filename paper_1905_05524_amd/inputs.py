@@ -117,6 +117,15 @@ def amr9():
     return w
 
 
+def paper_grid():
+    """The grid of the paper's performance runs: the colliding bubbles (the
+    warm plateau and cold bubbles of ``amr9``) on a uniform 729 x 729 grid
+    of 1.37 m cells, N = 6 (531,441 cells, 104,162,436 DOF), 20 steps."""
+    w = bubble(729, 6, bubbles=[warm_plateau_bubble(), cold_bubble()], steps=20)
+    w["name"] = "colliding729x729_N6"
+    return w
+
+
 def uniform_leaves(nx: int, nz: int, level: int = 0):
     """Leaf list (level, i, j) of a uniform grid in cell order c = j*nx + i."""
     return [(level, i, j) for j in range(nz) for i in range(nx)]
