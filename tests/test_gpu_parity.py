@@ -225,6 +225,36 @@ def test_bubble81_full_size_step(perturbed):
     assert np.all(increment_err(got, ref, Q0) <= TOL_INC), increment_err(got, ref, Q0)
 
 
+def test_paper_grid_step_on_sampled_cells():
+    """The grid of the paper's performance runs (colliding bubbles, 729x729
+    cells, N=6, 104 M DOF), perturbed: one GPU step with the oracle's time
+    step, sampled cells (corners, edges, interior, random) against the
+    oracle stepping the 3 x 3 block around each (a cell's update depends
+    only on its face neighbours; every boundary of this grid is a wall)."""
+    w = I.paper_grid()
+    phys, mesh = w["phys"], w["mesh"]
+    nx, nz, n = mesh["nx"], mesh["nz"], phys["N"] + 1
+    Q = I.perturb(O.ic(phys, mesh, "bubbles", w["bubbles"]), seed=729)
+    dt = O.dt(phys, mesh, Q)
+    m = mesh_of(w, fixed_dt=True)
+    m.set_state(Q, t=0.0, dt=dt)
+    m.step()
+    torch.cuda.synchronize()
+    h = mesh["Lx"] / nx
+    rng = np.random.default_rng(7)
+    cells = [(0, 0), (nx - 1, nz - 1), (0, nz - 1), (nx - 1, 0), (nx // 2, 0), (364, 364)]
+    cells += [tuple(int(v) for v in rng.integers(0, 729, 2)) for _ in range(4)]
+    for (i, j) in cells:
+        i0, i1, j0, j1 = max(0, i - 1), min(nx, i + 2), max(0, j - 1), min(nz, j + 2)
+        sub = dict(mesh, nx=i1 - i0, nz=j1 - j0, x0=mesh["x0"] + i0 * h, z0=mesh["z0"] + j0 * h,
+                   Lx=(i1 - i0) * h, Lz=(j1 - j0) * h, bc=[I.BC_WALL] * 4, max_level=0)
+        blk = np.ascontiguousarray(Q.reshape(nz, nx, 4, n, n)[j0:j1, i0:i1].reshape(-1, 4, n, n))
+        ref = O.step(phys, sub, blk, 0.0, dt)[(j - j0) * (i1 - i0) + (i - i0)][None]
+        got = m.Q[j * nx + i].cpu().numpy()[None]
+        e = relerr(got, ref, _scales(Q))
+        assert np.all(e <= TOL), ((i, j), e)
+
+
 def _tv_compare(w, Q, var, Tr, Tc):
     m = mesh_of(w)
     m.set_state(Q)
