@@ -188,7 +188,9 @@ int adg_regrid_plan(adg_mesh* m, const int8_t* flags_host, int* n_cells_new, siz
  * built (in the handle's device buffers, which grow when the mesh does) and
  * bind (Q_new, workspace_new, clock).  Synchronises the device (every kernel
  * that reads the old tables, on any stream, has finished).  The old Q and
- * workspace are the caller's to free. */
+ * workspace are the caller's to free.  ENOMEM or EHIP after the transfer
+ * leaves the handle without a usable mesh (its cell count reads 0): destroy
+ * it and create a new one. */
 int adg_regrid_apply(adg_mesh* m, double* Q_new, void* workspace_new, double* clock, void* stream);
 
 /* Launch shape of the predictor and corrector: cells per wavefront (1, 2 or
