@@ -134,7 +134,7 @@ def test_rollout_gradient_bubble27_fd_and_oracle():
     g = th.grad.cpu().numpy()
     D = I.fd_directions(16, th0.size, seed=4).reshape((16,) + th0.shape)
     nrm = np.linalg.norm(th0)
-    Lv = float(L)
+    Lv = float(L.detach())
     def central(d, eps):
         with torch.no_grad():
             Lp = float(theta_rollout(dev(th0 + eps * d), m, K, dt))
