@@ -372,7 +372,14 @@ def convergence_leg(T=0.05, grids=(9, 18, 36), orders=(1, 2, 3, 4, 5, 6)):
     e1.record(s)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / 10
-    out["mms9x9_N2"] = {"ms_per_step": ms, "dof_updates_per_s": model.dofs(81, 2) / (ms / 1e3)}
+    # the N = 2 workload sits at the ridge of the roofline: both fractions (81
+    # cells are far too few to load the chip, so both are small)
+    flops = model.step_flops(2) * 81
+    bytes_ = (model.predictor_bytes(2) + model.corrector_bytes(2)) * 81
+    out["mms9x9_N2"] = {"ms_per_step": ms, "dof_updates_per_s": model.dofs(81, 2) / (ms / 1e3),
+                        "fp64_frac": flops / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+                        "hbm_frac": bytes_ / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                        "flops_per_step": flops, "bytes_per_step": bytes_}
     return out
 
 
