@@ -175,6 +175,6 @@ def test_kept_iterates_give_the_recomputed_gradient():
         th = th0.clone().requires_grad_(True)
         L = theta_rollout(th, m, 6, dt, keep=keep)
         L.backward()
-        res[keep] = (float(L), th.grad.detach().clone())
+        res[keep] = (float(L.detach()), th.grad.detach().clone())
     assert res[True][0] == res[False][0]
     assert torch.equal(res[True][1], res[False][1])
