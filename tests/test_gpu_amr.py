@@ -56,6 +56,40 @@ def test_regrid_matches_oracle(N):
     assert np.all(relerr(got, ref) <= 1e-11)
 
 
+
+def test_large_mesh_uses_the_hashed_leaf_index():
+    """700 x 700 coarse cells with one refinement level: 4.9 M boxes, past
+    the dense per-level tables, so the host builds the face table and the
+    regrid plan through the hash map.  One step on the initial mesh, the
+    regrid of 3,000 scattered cells and one step on the new mesh match the
+    oracle (N = 1)."""
+    w = I.bubble(700, 1)
+    leaves = I.uniform_leaves(700, 700)
+    mesh = dict(w["mesh"], max_level=1, leaves=leaves)
+    Q = I.perturb(O.ic(w["phys"], mesh, "bubbles", w["bubbles"]), seed=3)
+    m = adg.Mesh(w["phys"], mesh)
+    m.set_state(Q)
+    dt = 0.5 * O.dt(w["phys"], mesh, Q)
+    m.clock[0], m.clock[1] = 0.0, dt
+    m.step()
+    ref = O.step(w["phys"], mesh, Q, 0.0, dt)
+    assert np.all(relerr(m.Q.cpu().numpy(), ref) <= 1e-11)
+    rng = np.random.default_rng(11)
+    flags = np.zeros(len(leaves), np.int8)
+    flags[rng.choice(len(leaves), 3000, replace=False)] = 1
+    Q1 = m.Q.cpu().numpy().copy()
+    C = m.regrid(flags)
+    ref_leaves, ref_Q = O.regrid(w["phys"], mesh, Q1, flags)
+    assert C == len(ref_leaves) and leaves_of(m) == ref_leaves
+    assert np.all(relerr(m.Q.cpu().numpy(), ref_Q) <= 1e-13)
+    new_mesh = dict(mesh, leaves=ref_leaves)
+    dt = 0.5 * O.dt(w["phys"], new_mesh, ref_Q)
+    m.clock[0], m.clock[1] = 0.0, dt
+    Q2 = m.Q.cpu().numpy().copy()
+    m.step()
+    ref = O.step(w["phys"], new_mesh, Q2, 0.0, dt)
+    assert np.all(relerr(m.Q.cpu().numpy(), ref) <= 1e-11)
+
 def _tv(m, var, Tr, Tc):
     tv = torch.zeros(m.C, dtype=torch.float64, device="cuda")
     fl = torch.zeros(m.C, dtype=torch.int8, device="cuda")
