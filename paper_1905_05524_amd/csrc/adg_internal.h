@@ -112,8 +112,9 @@ struct HostBasis {
 
 // Leaves by (level, i, j) on a mesh of nx x nz coarse cells with levels
 // 0..L: one dense table per level while the boxes of all levels number at
-// most kDenseBoxes (16 MB of ints), else a hash map.  Lookups outside the
-// grid of their level find nothing.
+// most kDenseBoxes (16 MB of ints), else a hash map keyed by the same box
+// number (unique: nx * nz <= 2^26 coarse cells and L <= 8 give fewer than
+// 2^62 boxes).  Lookups outside the grid of their level find nothing.
 struct LeafIndex {
   static constexpr long long kDenseBoxes = 1LL << 22;
   int nx, nz, L;
@@ -123,7 +124,7 @@ struct LeafIndex {
   std::unordered_map<long long, int> map;
   LeafIndex(int nx_, int nz_, int L_, size_t n_leaves) : nx(nx_), nz(nz_), L(L_), off(L_ + 1, 0) {
     long long total = 0, s = 1;
-    for (int l = 0; l <= L && total <= kDenseBoxes; ++l, s *= 3) {
+    for (int l = 0; l <= L; ++l, s *= 3) {
       off[l] = total;
       total += (long long)nx * s * nz * s;
     }
@@ -131,7 +132,6 @@ struct LeafIndex {
     if (dense) tab.assign((size_t)total, -1);
     else map.reserve(n_leaves * 2);
   }
-  static long long key(int l, int i, int j) { return ((long long)l << 52) ^ ((long long)i << 26) ^ (long long)j; }
   bool in_grid(int l, int i, int j) const {
     if (l < 0 || l > L || i < 0 || j < 0) return false;
     long long s = 1;
@@ -147,7 +147,7 @@ struct LeafIndex {
   // holds a leaf already
   bool insert(int l, int i, int j, int c) {
     if (!in_grid(l, i, j)) return false;
-    if (!dense) return map.emplace(key(l, i, j), c).second;
+    if (!dense) return map.emplace(slot(l, i, j), c).second;
     int& t = tab[(size_t)slot(l, i, j)];
     if (t >= 0) return false;
     t = c;
@@ -156,7 +156,7 @@ struct LeafIndex {
   int find(int l, int i, int j) const {
     if (!in_grid(l, i, j)) return -1;
     if (!dense) {
-      auto it = map.find(key(l, i, j));
+      auto it = map.find(slot(l, i, j));
       return it == map.end() ? -1 : it->second;
     }
     return tab[(size_t)slot(l, i, j)];

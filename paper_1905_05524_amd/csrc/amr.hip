@@ -12,6 +12,8 @@
 // Transfer: copy; prolongation to a child by exact interpolation of the
 // parent polynomial; restriction of nine children by L2 projection.
 #include <algorithm>
+#include <map>
+#include <set>
 #include <tuple>
 #include <unordered_map>
 
@@ -97,7 +99,7 @@ int launch_regrid(int n, int C, const int* ops, const double* Qold, double* Qnew
   }
 }
 
-static long long fkey(int l, int i, int j) { return ((long long)l << 52) ^ ((long long)i << 26) ^ (long long)j; }
+using Box = std::tuple<int, int, int>;   // level, i, j
 
 // Regrid decisions with 2:1 balance, so that neighbouring leaves differ by
 // at most one level after the regrid (the 1:3 face coupling needs it):
@@ -199,30 +201,28 @@ int regrid_plan(const std::vector<int>& lev, const std::vector<int>& ci, const s
     }
   }
   // coarsening candidates: families whose nine children are leaves flagged coarsen
-  std::unordered_map<long long, int> cnt;
+  // (parents in (level, i, j) order)
+  std::map<Box, int> cnt;
   for (int c = 0; c < C; ++c)
-    if (lev[c] > 0 && eff[c] == -1) cnt[fkey(lev[c] - 1, ci[c] / 3, cj[c] / 3)] += 1;
-  std::vector<long long> fams;
+    if (lev[c] > 0 && eff[c] == -1) cnt[Box(lev[c] - 1, ci[c] / 3, cj[c] / 3)] += 1;
+  std::vector<Box> fams;
   for (const auto& kv : cnt)
     if (kv.second == 9) fams.push_back(kv.first);
-  std::sort(fams.begin(), fams.end());
-  auto family = [&](long long pk, int* out) {
-    // the nine children (row by row) of parent key pk, as leaf indices
-    const int pl = (int)(pk >> 52);
-    const long long rest = pk ^ ((long long)pl << 52);
-    const int pi = (int)(rest >> 26), pj = (int)(rest & ((1LL << 26) - 1));
+  auto family = [&](const Box& pk, int* out) {
+    // the nine children (row by row) of parent box pk, as leaf indices
+    const auto [pl, pi, pj] = pk;
     for (int b = 0; b < 3; ++b)
       for (int a = 0; a < 3; ++a) out[3 * b + a] = M.find(pl + 1, 3 * pi + a, 3 * pj + b);
-    return std::make_tuple(pl, pi, pj);
+    return pk;
   };
-  for (long long pk : fams) {
+  for (const Box& pk : fams) {
     int kids[9];
     family(pk, kids);
     for (int k = 0; k < 9; ++k) coarsen[kids[k]] = 1;
   }
   for (bool changed = true; changed;) {
     changed = false;
-    for (long long pk : fams) {
+    for (const Box& pk : fams) {
       int kids[9];
       auto [pl, pi, pj] = family(pk, kids);
       if (!coarsen[kids[0]]) continue;
@@ -235,7 +235,7 @@ int regrid_plan(const std::vector<int>& lev, const std::vector<int>& ci, const s
       }
     }
   }
-  std::unordered_map<long long, int> emitted;
+  std::set<Box> emitted;
   nlev.clear(); nci.clear(); ncj.clear(); ops.clear();
   auto emit = [&](int l, int i, int j, int op, int a, int b, const int* src, int ns) {
     nlev.push_back(l); nci.push_back(i); ncj.push_back(j);
@@ -246,9 +246,8 @@ int regrid_plan(const std::vector<int>& lev, const std::vector<int>& ci, const s
   for (int c = 0; c < C; ++c) {
     const int l = lev[c], i = ci[c], j = cj[c];
     if (coarsen[c]) {
-      const long long pk = fkey(l - 1, i / 3, j / 3);
-      if (emitted.count(pk)) continue;
-      emitted[pk] = 1;
+      const Box pk(l - 1, i / 3, j / 3);
+      if (!emitted.insert(pk).second) continue;
       int src[9];
       family(pk, src);
       emit(l - 1, i / 3, j / 3, kRestrict, 0, 0, src, 9);
