@@ -60,6 +60,9 @@ CASES = [
     ("atmo_walls", lambda: atmo_case(27, 27, 4)),
     ("atmo_ragged", lambda: atmo_case(31, 19, 5)),
     ("one_row", lambda: cfd_case(40, 1, [WALL, WALL, PER, PER], 6)),
+    # trailing tiles one and two cells wide (16 x 16 tiles)
+    ("thin_tiles_mixed", lambda: cfd_case(17, 18, [PER, PER, WALL, WALL], 9)),
+    ("thin_tiles_wall", lambda: cfd_case(33, 34, [WALL] * 4, 10)),
     ("single_cell_per", lambda: cfd_case(1, 1, [PER] * 4, 7)),
     ("single_cell_wall", lambda: cfd_case(1, 1, [WALL] * 4, 8)),
 ]
