@@ -172,6 +172,23 @@ def test_step_matches_oracle(kind, nx, N, kernel):
     assert clk[0] == 0.1 + dt and clk[1] == dt and clk[3] == 1.0
 
 
+
+@pytest.mark.parametrize("nx,nz", [(73, 6), (439, 1)])
+def test_automatic_kernel_choice_at_its_threshold(nx, nz):
+    """N = 6 with the default launch mode: 438 cells (438 x 7 = 3066
+    wavefronts) take the time-level predictor, 439 cells the one-wavefront-
+    per-cell predictor; both match the oracle over one step."""
+    w = cfd_periodic(nx, nz, 6)
+    Q = _state(w, seed=3000 + nx)
+    dt = 0.5 * O.dt(w["phys"], w["mesh"], Q)
+    m = mesh_of(w, None, fixed_dt=True)
+    m.set_state(Q, t=0.2, dt=dt)
+    m.step()
+    ref = O.step(w["phys"], w["mesh"], Q, 0.2, dt)
+    got = m.Q.cpu().numpy()
+    assert np.all(relerr(got, ref) <= TOL), relerr(got, ref)
+    assert np.all(increment_err(got, ref, Q) <= TOL_INC), increment_err(got, ref, Q)
+
 def test_cfl_dt_matches_oracle():
     for w in (I.bubble(9, 6), I.mms_small(N=2)):
         m = mesh_of(w)
