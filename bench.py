@@ -222,7 +222,7 @@ def amr_leg(workload="amr27", steps=200, repeats=3):
                       "Gaussian bubble, regrid every 10 steps (TV of theta, T_refine 0, T_coarsen -0.4)",
              "amr9": "amr9x9_L2_N6: colliding bubbles, 9x9 coarse cells of 111.1 m, two 3-way levels "
                      "(37.04 m, 12.35 m), 3 initial refinement passes, regrid every 10 steps "
-                     "(TV of theta, T_refine 1.0, T_coarsen -0.5)"}
+                     "(TV of theta, T_refine 2.5, T_coarsen -0.5)"}
     return {"workload": names[workload],
             "steps": steps, "initial_leaves": c0, "leaves_min": min(cells + [c0]), "leaves_max": max(cells + [c0]),
             "leaves_final": m.C, "leaves_per_level_final": levels.tolist(),

@@ -146,7 +146,12 @@ int adg_corrector(adg_mesh* m, void* stream);
 /* One full step: adg_predictor + adg_corrector. */
 int adg_step(adg_mesh* m, void* stream);
 
-/* TV indicator (eq. tv) of theta (ADG_VAR_THETA) or rho per cell, the
+/* TV indicator (eq. tv) of theta (ADG_VAR_THETA) or rho per cell, read as
+ * the l1 norm of the physical gradient integrated by GL quadrature with the
+ * reference element's weights (which sum to one), i.e. the mean of
+ * |df/dx| + |df/dz| over the cell:
+ *   TV = (1/h) sum_ji w_i w_j (|sum_m D_im f_jm| + |sum_m D_jm f_mi|),
+ * so a cell's TV does not scale with its size; the
  * population mean/std of TV over all cells merged with the pairwise updates of
  * Chan, Golub and LeVeque, and the flags of eq. refinement-criterion:
  * +1 refine if TV >= mu + T_refine sigma, -1 coarsen if TV < mu + T_coarsen

@@ -738,9 +738,13 @@ T theta_of(const Params& P, const T q[4], double z) {
   return Tm * pow(P.p0 / p, P.R / P.cp);
 }
 
-// TV of f over a cell (paper eq. tv): integral of the l1 norm of grad f,
-// by GL quadrature on the collocated nodes, derivatives by D on the cell:
-//   TV = h sum_ji w_i w_j (|sum_m D_im f_jm| + |sum_m D_jm f_mi|)
+// TV of f over a cell (paper eq. tv): the l1 norm of grad f integrated by
+// GL quadrature on the collocated nodes with the weights of the reference
+// element (they sum to one), physical derivatives (1/h) D; that is the mean
+// of |df/dx| + |df/dz| over the cell:
+//   TV = (1/h) sum_ji w_i w_j (|sum_m D_im f_jm| + |sum_m D_jm f_mi|)
+// (reading: a cell-size-independent indicator; with the h^2 Jacobian of the
+// physical cell, children would carry a ninth of their parent's TV)
 template <class T>
 T cell_tv(const Params& P, const Basis& B, const Cell& c, const T* Qc, int var) {
   const int n = P.n;
@@ -761,7 +765,7 @@ T cell_tv(const Params& P, const Basis& B, const Cell& c, const T* Qc, int var) 
       }
       tv += B.w[i] * B.w[j] * (fabs(dx) + fabs(dz));
     }
-  return c.h * tv;
+  return tv / c.h;
 }
 
 // Initial state from a nodal potential-temperature perturbation theta' at

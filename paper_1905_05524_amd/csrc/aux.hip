@@ -48,8 +48,11 @@ __global__ void k_init_state(Phys ph, int n, int C, const double* geom, const do
 }
 
 // ------------------------------------------------------------- TV per cell
-// TV = h sum_ji w_i w_j (|sum_m D_im f_jm| + |sum_m D_jm f_mi|), f = theta or
-// rho at the nodes.  One wavefront per cell; lanes < 2n run the line jobs.
+// TV = (1/h) sum_ji w_i w_j (|sum_m D_im f_jm| + |sum_m D_jm f_mi|), f =
+// theta or rho at the nodes: the mean of |df/dx| + |df/dz| over the cell
+// (eq. tv by GL quadrature with the reference element's weights, which sum
+// to one, of the physical gradient).  One wavefront per cell; lanes < 2n run
+// the line jobs.
 template <int n>
 __global__ __launch_bounds__(kWave) void k_tv(Tab<n> T, Phys ph, const double* Q, const double* geom,
                                                 const double* gtab, int var, double* tv) {
@@ -89,7 +92,7 @@ __global__ __launch_bounds__(kWave) void k_tv(Tab<n> T, Phys ph, const double* Q
     part *= gtab[GTab::W * n + line];
   }
   part = wave_sum(part);
-  if (lane == 0) tv[c] = h * part;
+  if (lane == 0) tv[c] = part / h;
 }
 
 // ---------------------------------------------------- statistics and flags

@@ -104,15 +104,14 @@ def amr9():
     A = 0.5 K, a = 150 m, s = 50 m at (500, 300) m and cold bubble
     A = -0.15 K, s = 50 m at (560, 640) m; 9x9 coarse cells of 111.1 m with
     two 3-way refinement levels (37.04 m, 12.35 m), N=6, mu = 1e-3 (the
-    paper's AMR run).  T_coarsen = -0.5 as in the paper; T_refine = 1.0
-    instead of its 2.5, which with the TV integrated over the physical cell
-    never refines past the first level on this state.  The initial mesh is
-    refined from the analytic state in three passes; regrid every 10 steps."""
+    paper's AMR run) with the paper's thresholds T_refine = 2.5,
+    T_coarsen = -0.5.  The initial mesh is refined from the analytic state in
+    three passes; regrid every 10 steps."""
     w = bubble(9, 6, bubbles=[warm_plateau_bubble(), cold_bubble()], steps=200)
     w["mesh"]["max_level"] = 2
     w["mesh"]["leaves"] = uniform_leaves(9, 9)
     w["name"] = "amr9x9_L2_N6"
-    w["T_refine"], w["T_coarsen"], w["regrid_every"] = 1.0, -0.5, 10
+    w["T_refine"], w["T_coarsen"], w["regrid_every"] = 2.5, -0.5, 10
     w["initial_passes"] = 3
     return w
 

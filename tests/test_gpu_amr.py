@@ -194,8 +194,9 @@ def test_two_level_regrids_match_oracle(seed):
 def test_colliding_bubbles_initial_refinement_matches_oracle():
     """The paper's colliding bubbles on 9x9 coarse cells with two levels:
     three passes of indicator -> flags -> regrid -> analytic state, each
-    compared with the oracle fed the GPU's state; the mesh reaches level 2
-    (905 leaves)."""
+    compared with the oracle fed the GPU's state; with the paper's
+    thresholds (2.5, -0.5) the mesh reaches level 2 (209 leaves: 71, 84 and
+    54 on levels 0-2)."""
     w = I.amr9()
     m = adg.Mesh(w["phys"], w["mesh"])
     m.init_state("bubbles", w["bubbles"])
@@ -209,7 +210,7 @@ def test_colliding_bubbles_initial_refinement_matches_oracle():
         ref_leaves, _ = O.regrid(w["phys"], cur, Q, fl)
         assert leaves_of(m) == ref_leaves, p
         m.init_state("bubbles", w["bubbles"])
-    assert m.C == 905
+    assert m.C == 209
     assert max(l for l, _, _ in leaves_of(m)) == 2
     m.compute_dt()
     Q0 = m.Q.cpu().numpy().copy()

@@ -284,12 +284,12 @@ def _tv_compare(w, Q, var, Tr, Tc):
     rtv, rfl, rst = O.tv(w["phys"], w["mesh"], Q, var, Tr, Tc)
     tv, fl, st = tv.cpu().numpy(), fl.cpu().numpy(), st.cpu().numpy()
     # rounding bound: relative 1e-13 of the largest TV, plus the noise floor of
-    # a constant field, h * ||D||_inf * (few ulp of max |f|) per derivative
+    # a constant field, ||D||_inf / h * (few ulp of max |f|) per derivative
     N = w["phys"]["N"]
     Dinf = np.max(np.sum(np.abs(O.basis(N)["D"]), axis=1))
     h = w["mesh"]["Lx"] / w["mesh"]["nx"]
     fmax = 400.0 if var == adg.ADG_VAR_THETA else np.max(np.abs(Q[:, 0]))
-    bound = 1e-13 * np.max(np.abs(rtv)) + 2 * 8 * h * Dinf * 2.3e-16 * fmax
+    bound = 1e-13 * np.max(np.abs(rtv)) + 2 * 8 * Dinf / h * 2.3e-16 * fmax
     assert np.max(np.abs(tv - rtv)) <= bound, (np.max(np.abs(tv - rtv)), bound)
     assert st[0] == rst[0]
     dmu, dsig = abs(st[1] - rst[1]), abs(st[2] - rst[2])

@@ -299,3 +299,35 @@ def test_random_two_level_regrids_stay_balanced(seed):
                 assert all(flags[leaves.index(s)] == -1 for s in fam)
         leaves = new
         mesh = dict(mesh, leaves=leaves)
+
+
+def _levels(leaves, L):
+    c = [0] * (L + 1)
+    for (l, _, _) in leaves:
+        c[l] += 1
+    return c
+
+
+def test_paper_thresholds_track_the_colliding_bubbles():
+    """The paper's AMR run (stratified-flow section: colliding bubbles, 9x9
+    coarse cells, two levels, T_refine = 2.5, T_coarsen = -0.5) shows cells of
+    all three sizes.  With the indicator read as the mean gradient norm over
+    the cell, three initial passes reach level 2, and the mesh then stays
+    unchanged over regrids every 10 steps (no refine/coarsen cycle: a refined
+    family carries its parent's TV)."""
+    w = I.amr9()
+    phys, mesh = w["phys"], dict(w["mesh"])
+    Q = O.ic(phys, mesh, "bubbles", w["bubbles"])
+    for _ in range(w["initial_passes"]):
+        _, fl, _ = O.tv(phys, mesh, Q, O.VAR_THETA, w["T_refine"], w["T_coarsen"])
+        leaves, _ = O.regrid(phys, mesh, Q, fl)
+        mesh["leaves"] = leaves
+        Q = O.ic(phys, mesh, "bubbles", w["bubbles"])
+    lv = _levels(mesh["leaves"], 2)
+    assert lv == [71, 84, 54], lv
+    t = 0.0
+    for _ in range(2):
+        Q, t = O.run(phys, mesh, Q, t, 10)
+        _, fl, _ = O.tv(phys, mesh, Q, O.VAR_THETA, w["T_refine"], w["T_coarsen"])
+        leaves, Q = O.regrid(phys, mesh, Q, fl)
+        assert leaves == mesh["leaves"]

@@ -21,7 +21,9 @@ def periodic(nx):
 def brute_tv_rho(Q, N, nx):
     """TV of rho per cell: derivative of the interpolating polynomial from
     numpy's polyfit (not the derivative matrix), Gauss quadrature with numpy's
-    Gauss-Legendre rule, h^2 Jacobian and 1/h derivative scaling."""
+    Gauss-Legendre rule on the reference element (weights summing to one) of
+    the physical gradient (1/h derivative scaling): the mean of
+    |df/dx| + |df/dz| over the cell."""
     n = N + 1
     x, w = np.polynomial.legendre.leggauss(n)
     xi, w = (x + 1) / 2, w / 2
@@ -38,7 +40,7 @@ def brute_tv_rho(Q, N, nx):
             pc = np.polynomial.polynomial.polyfit(xi, f[:, i], N)
             dz[:, i] = np.polynomial.polynomial.polyval(xi, np.polynomial.polynomial.polyder(pc))
         integrand = (np.abs(dx) + np.abs(dz)) / h
-        out.append(h * h * np.sum(np.outer(w, w) * integrand))
+        out.append(np.sum(np.outer(w, w) * integrand))
     return np.array(out)
 
 
@@ -88,7 +90,7 @@ def test_tv_brute_force_and_exact_flags(N):
 
 
 def test_tv_of_linear_field():
-    """f = a x + b z: TV = h^2 (|a| + |b|) on every cell."""
+    """f = a x + b z: TV = |a| + |b| on every cell, whatever its size."""
     N, nx = 3, 4
     n = N + 1
     b = O.basis(N)
@@ -102,9 +104,31 @@ def test_tv_of_linear_field():
         Q[c, 0] = 2.0 + a * X[None, :] + bb * Z[:, None]
         Q[c, 3] = 2.5
     tv, flags, st = O.tv(dict(I.CFD, N=N, mu=0.0, mms=0), periodic(nx), Q, O.VAR_RHO, 1.0, -1.0)
-    assert np.max(np.abs(tv - h * h * (abs(a) + abs(bb)))) <= 1e-15
-    # identical TVs: sigma ~ 0 within rounding; flags must not mark everything
-    assert st[2] <= 1e-15
+    assert np.max(np.abs(tv - (abs(a) + abs(bb)))) <= 1e-14
+    # identical TVs: sigma ~ 0 within rounding of the TV (|a| + |b| = 1)
+    assert st[2] <= 1e-14 * (abs(a) + abs(bb))
+
+
+def test_tv_of_linear_field_on_a_refined_mesh():
+    """Cell-size independence of the indicator: on a mesh with coarse cells
+    and 3x3 children, a linear field f = a x + b z has TV = |a| + |b| on
+    every leaf, so a refined family carries its parent's TV (the indicator
+    compares gradients, not cell sizes)."""
+    N, nx = 2, 3
+    n = N + 1
+    b = O.basis(N)
+    a, bb = 0.4, -1.1
+    leaves = I.refined_leaves(nx, nx, [(1, 1), (0, 2)])
+    mesh = dict(periodic(nx), max_level=1, leaves=leaves)
+    Q = np.zeros((len(leaves), 4, n, n))
+    for c, (l, i, j) in enumerate(leaves):
+        h = 1.0 / (nx * 3 ** l)
+        X = i * h + h * b["xi"]
+        Z = j * h + h * b["xi"]
+        Q[c, 0] = 2.0 + a * X[None, :] + bb * Z[:, None]
+        Q[c, 3] = 2.5
+    tv, _, _ = O.tv(dict(I.CFD, N=N, mu=0.0, mms=0), mesh, Q, O.VAR_RHO, 1.0, -1.0)
+    assert np.max(np.abs(tv - (abs(a) + abs(bb)))) <= 1e-13
 
 
 def test_constant_tv_keeps_everything():
@@ -123,7 +147,8 @@ def test_theta_tv_vanishes_on_background():
     w = I.bubble(9, 4, bubbles=[])
     Q = O.ic(w["phys"], w["mesh"], "bubbles", [])
     tv, _, _ = O.tv(w["phys"], w["mesh"], Q, O.VAR_THETA, 1.5, -0.5)
-    assert np.max(tv) <= 1e-9 * 300.0 * (1000.0 / 9)
+    # mean gradient of theta on 111 m cells: rounding of theta (300 K) / h
+    assert np.max(tv) <= 1e-9 * 300.0 / (1000.0 / 9)
 
 
 @pytest.mark.parametrize("seed", range(6))
