@@ -70,7 +70,8 @@ enum {
 struct Params {
   int N, n, iters;
   double gamma, Pr, R, cp, mu, g, p0, theta_bg;
-  bool gravity, mms;
+  bool gravity;
+  int mms;   // manufactured source: 0 none, 1 advected density wave, 2 the paper's wave
   double mms_amp, mms_u, mms_w, mms_kx, mms_kz, mms_p;
   double cfl;
   double kappa;
@@ -82,7 +83,7 @@ Params read_params(const double* p) {
   P.iters = (int)p[P_PICARD]; if (P.iters <= 0) P.iters = P.N + 1;
   P.gamma = p[P_GAMMA]; P.Pr = p[P_PR]; P.R = p[P_R]; P.cp = p[P_CP];
   P.mu = p[P_MU]; P.g = p[P_G]; P.p0 = p[P_P0]; P.theta_bg = p[P_THETA];
-  P.gravity = p[P_GRAVITY] != 0.0; P.mms = p[P_MMS] != 0.0;
+  P.gravity = p[P_GRAVITY] != 0.0; P.mms = (int)p[P_MMS];
   P.mms_amp = p[P_MMS_AMP]; P.mms_u = p[P_MMS_U]; P.mms_w = p[P_MMS_W];
   P.mms_kx = p[P_MMS_KX]; P.mms_kz = p[P_MMS_KZ]; P.mms_p = p[P_MMS_P];
   P.cfl = p[P_CFL];
@@ -240,6 +241,55 @@ double mms_source_E(const Params& P, double x, double z, double t) {
   return -P.kappa * lapT;
 }
 
+// Manufactured solution of the convergence test (paper, CFD scenarios, eq.
+// manufactured-solution, with the CFD constants gamma = 1.4, Pr = 0.7,
+// c_v = 1): every field depends on xi = k (x + z) - 2 pi t, k = pi/5,
+//   p = 1/gamma + (1/10) cos xi,  rho = 1 + (1/2) sin xi,
+//   (u, w) = (1/4, 1/4) sin xi,   E = p/(gamma-1) + rho (u^2 + w^2)/2,
+// on the periodic square [0,10]^2 (one period along each axis).
+void paper_mms_state(const Params& P, double x, double z, double t, double q[4]) {
+  const double PI = 3.14159265358979323846;
+  const double xi = (PI / 5.0) * (x + z) - 2.0 * PI * t;
+  const double sn = std::sin(xi), cs = std::cos(xi);
+  const double p = 1.0 / P.gamma + 0.1 * cs, rho = 1.0 + 0.5 * sn, u = 0.25 * sn;
+  q[0] = rho; q[1] = rho * u; q[2] = rho * u;
+  q[3] = p / (P.gamma - 1.0) + rho * u * u;
+}
+
+// Its source S = dQ/dt + div F(Q, grad Q) of the equation set without
+// gravity (eq. equation-set with the stress tensor and the heat flux),
+// worked out along xi: d/dx = d/dz = k d/dxi, d/dt = -omega d/dxi
+// (omega = 2 pi), primes are d/dxi, s = sin xi, c = cos xi, a = 1/4:
+//   rho' = c/2, p' = -s/10, u' = w' = a c, div v = 2 k a c,
+//   sigma_xx = sigma_zz = -(2/3) mu k a c, sigma_xz = -2 mu k a c,
+//   S_rho = -omega rho' + 2 k (rho u)'
+//   S_mx = S_mz = -omega (rho u)' + k (2 (rho u^2)' + p') + (8/3) mu k^2 a s
+//   S_E  = -omega E' + 2 k (u (E + p))' - (16/3) mu k^2 a^2 (c^2 - s^2)
+//          - 2 kappa k^2 (p/rho)'' / R
+// with (rho u)' = a c (1 + s), (rho u^2)' = a^2 c (2 s + 3 s^2 / 2).
+void paper_mms_source(const Params& P, double x, double z, double t, double S[4]) {
+  const double PI = 3.14159265358979323846;
+  const double k = PI / 5.0, om = 2.0 * PI, a = 0.25, gm1 = P.gamma - 1.0;
+  const double xi = k * (x + z) - om * t;
+  const double sn = std::sin(xi), cs = std::cos(xi);
+  const double rho = 1.0 + 0.5 * sn, p = 1.0 / P.gamma + 0.1 * cs, u = a * sn;
+  const double E = p / gm1 + rho * u * u;
+  const double d_rho = 0.5 * cs, dd_rho = -0.5 * sn;
+  const double d_p = -0.1 * sn, dd_p = -0.1 * cs;
+  const double d_ru = a * cs * (1.0 + sn);
+  const double d_ruu = a * a * cs * (2.0 * sn + 1.5 * sn * sn);
+  const double d_E = d_p / gm1 + d_ruu;
+  const double d_uEp = a * cs * (E + p) + u * (d_E + d_p);
+  // (p/rho)'' by the quotient rule
+  const double f2 = dd_p / rho - 2.0 * d_p * d_rho / (rho * rho) - p * dd_rho / (rho * rho) +
+                    2.0 * p * d_rho * d_rho / (rho * rho * rho);
+  S[0] = -om * d_rho + 2.0 * k * d_ru;
+  S[1] = -om * d_ru + k * (2.0 * d_ruu + d_p) + (8.0 / 3.0) * P.mu * k * k * a * sn;
+  S[2] = S[1];
+  S[3] = -om * d_E + 2.0 * k * d_uEp - (16.0 / 3.0) * P.mu * k * k * a * a * (cs * cs - sn * sn) -
+         2.0 * P.kappa * k * k * f2 / P.R;
+}
+
 // ----------------------------------------------------------- pointwise physics
 // Flux F = F^h(Q) + F^v(Q, grad Q) in x and z and source S at one point
 // (paper eq. equation-set, eos, temperature, stress-tensor,
@@ -286,7 +336,12 @@ void pointwise(const Params& P, const T q[4], const T gx[4], const T gz[4],
   Fz[3] = w * (E + p) + (u * sxz + w * szz) - P.kappa * dTz;
   S[0] = T(0.0); S[1] = T(0.0);
   S[2] = P.gravity ? -P.g * (rho - rho_b) : T(0.0);
-  S[3] = P.mms ? T(mms_source_E(P, x, z, t)) : T(0.0);
+  S[3] = P.mms == 1 ? T(mms_source_E(P, x, z, t)) : T(0.0);
+  if (P.mms == 2) {
+    double Sm[4];
+    paper_mms_source(P, x, z, t, Sm);
+    for (int v = 0; v < 4; ++v) S[v] = S[v] + Sm[v];
+  }
 }
 
 // pressure and eigenvalue bounds at a state (used by the face flux and dt)
@@ -810,6 +865,24 @@ T loss_theta(const Params& P, const Basis& B, const Mesh& M, const T* Q) {
   return sqrt(acc);
 }
 
+// Potential-temperature perturbation of a list of bubbles at (x, z) (paper,
+// stratified flows: eqs. cos-pertubation, read with cos(pi r / a) so that it
+// vanishes at r = a, and bubbles-pertubation), r = |(x, z) - (xc, zc)|_2;
+// bubbles[b] = (shape, A, a, s, xc, zc): shape 0 = cosine
+// A/2 (1 + cos(pi r / a)) for r <= a, else 0; shape 1 = plateau A for r <= a
+// and A exp(-(r - a)^2 / s^2) beyond.  Perturbations of several bubbles add.
+double bubble_theta(int nb, const double* bubbles, double x, double z) {
+  const double PI = 3.14159265358979323846;
+  double th = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    const double* bb = bubbles + 6 * b;
+    double r = std::sqrt((x - bb[4]) * (x - bb[4]) + (z - bb[5]) * (z - bb[5]));
+    if ((int)bb[0] == 0) { if (r <= bb[2]) th += 0.5 * bb[1] * (1.0 + std::cos(PI * r / bb[2])); }
+    else th += (r <= bb[2]) ? bb[1] : bb[1] * std::exp(-(r - bb[2]) * (r - bb[2]) / (bb[3] * bb[3]));
+  }
+  return th;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -914,6 +987,35 @@ int oracle_dt(const double* prm, const int* mi, const double* md, const int* lev
   return 0;
 }
 
+// Perturbation theta' of a bubble list at one point (the routine the
+// initial state interpolates at the nodes).
+int oracle_bubble_theta(int nb, const double* bubbles, double x, double z, double* th) {
+  *th = bubble_theta(nb, bubbles, x, z);
+  return 0;
+}
+
+// Numerical flux across one face along direction d (0 = x, 1 = z) of cells
+// of size h from the two sides' face data (time-averaged state and normal
+// flux at the n face nodes, [4][n] each, L the lower-coordinate side), the
+// face nodes at heights zf[n]; G [4][n].
+int oracle_face_flux(const double* prm, int d, double h, const double* zf, const double* QL, const double* FL,
+                     const double* QR, const double* FR, double* G) {
+  Params P = read_params(prm);
+  rusanov<double>(P, d, h, zf, QL, FL, QR, FR, G);
+  return 0;
+}
+
+// Potential-temperature loss of a state.
+int oracle_loss_theta(const double* prm, const int* mi, const double* md, const int* lev, const int* ci,
+                      const int* cj, const double* Q, double* L) {
+  Params P = read_params(prm);
+  Basis B = make_basis(P.N);
+  Mesh M = build_mesh(mi, md, lev, ci, cj);
+  if (!M.ok) return -1;
+  *L = loss_theta<double>(P, B, M, Q);
+  return 0;
+}
+
 // TV per cell, mean/std over cells merged pairwise with the update formulas of
 // Chan, Golub & LeVeque (paper, refinement criterion), and flags
 //   +1 refine if TV >= mu + Tr sigma, -1 coarsen if TV < mu + Tc sigma, else 0;
@@ -957,6 +1059,7 @@ int oracle_tv(const double* prm, const int* mi, const double* md, const int* lev
 //   A exp(-(r-a)^2/s^2) beyond; theta' of several bubbles add; the pressure
 //   stays the background one, rho = p/(R T), T = theta * Exner, at rest.
 // kind 1: the advected density wave of the manufactured solution at time t0.
+// kind 2: the paper's manufactured solution at time t0.
 int oracle_ic(const double* prm, const int* mi, const double* md, const int* lev, const int* ci,
               const int* cj, int kind, int nb, const double* bubbles, double t0, double* Q) {
   Params P = read_params(prm);
@@ -964,26 +1067,21 @@ int oracle_ic(const double* prm, const int* mi, const double* md, const int* lev
   Mesh M = build_mesh(mi, md, lev, ci, cj);
   if (!M.ok) return -1;
   const int n = P.n, sl = 4 * n * n;
-  const double PI = 3.14159265358979323846;
   for (size_t c = 0; c < M.cells.size(); ++c) {
     const Cell& cc = M.cells[c];
     for (int j = 0; j < n; ++j)
       for (int i = 0; i < n; ++i) {
         double x = cc.x0 + cc.h * B.xi[i], z = cc.z0 + cc.h * B.xi[j];
         double q[4];
-        if (kind == 1) {
+        if (kind == 2) {
+          paper_mms_state(P, x, z, t0, q);
+        } else if (kind == 1) {
           double X = x - P.mms_u * t0, Z = z - P.mms_w * t0;
           double rho = 1.0 + P.mms_amp * std::sin(P.mms_kx * X) * std::sin(P.mms_kz * Z);
           q[0] = rho; q[1] = rho * P.mms_u; q[2] = rho * P.mms_w;
           q[3] = P.mms_p / (P.gamma - 1.0) + 0.5 * rho * (P.mms_u * P.mms_u + P.mms_w * P.mms_w);
         } else {
-          double th = 0.0;
-          for (int b = 0; b < nb; ++b) {
-            const double* bb = bubbles + 6 * b;
-            double r = std::sqrt((x - bb[4]) * (x - bb[4]) + (z - bb[5]) * (z - bb[5]));
-            if ((int)bb[0] == 0) { if (r <= bb[2]) th += 0.5 * bb[1] * (1.0 + std::cos(PI * r / bb[2])); }
-            else th += (r <= bb[2]) ? bb[1] : bb[1] * std::exp(-(r - bb[2]) * (r - bb[2]) / (bb[3] * bb[3]));
-          }
+          double th = bubble_theta(nb, bubbles, x, z);
           double pi = 1.0 - P.g * z / (P.cp * P.theta_bg);
           double pb = P.p0 * std::pow(pi, P.cp / P.R);
           double T = (P.theta_bg + th) * pi;
@@ -1702,7 +1800,7 @@ FVMesh read_fv_mesh(const int* mi, const double* md) {
 Params fv_params(const double* prm) {
   Params P = read_params(prm);
   P.N = 0; P.n = 1; P.iters = 1;
-  P.mu = 0.0; P.kappa = 0.0; P.mms = false;
+  P.mu = 0.0; P.kappa = 0.0; P.mms = 0;
   return P;
 }
 

@@ -64,6 +64,9 @@ def lib():
                                               dp, i8p, dp]
         L.oracle_ic.argtypes = [dp] + mesh + [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, dp]
         L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_bubble_theta.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_double, dp]
+        L.oracle_face_flux.argtypes = [dp, ctypes.c_int, ctypes.c_double, dp, dp, dp, dp, dp, dp]
+        L.oracle_loss_theta.argtypes = [dp] + mesh + [dp, dp]
         L.oracle_regrid.argtypes = [dp] + mesh + [dp, i8p, ip, ip, ip, dp, ip]
         L.oracle_step_jvp.argtypes = [dp] + mesh + [dp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
         L.oracle_rollout_jvp.argtypes = [dp] + mesh + [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -223,13 +226,42 @@ def tv(phys: dict, mesh: dict, Q: np.ndarray, var: int, Tr: float, Tc: float):
     return tvv, fl, st
 
 
+def bubble_theta(bubbles, x: float, z: float) -> float:
+    """Perturbation theta' of a bubble list at one point."""
+    bb = np.ascontiguousarray(np.asarray(bubbles, dtype=np.float64).reshape(-1, 6))
+    out = np.zeros(1)
+    _check(lib().oracle_bubble_theta(bb.shape[0], _dp(bb), float(x), float(z), _dp(out)), "bubble_theta")
+    return float(out[0])
+
+
+def face_flux(phys: dict, d: int, h: float, zf, QL, FL, QR, FR) -> np.ndarray:
+    """Numerical flux G [4][n] across one face (direction d) from both sides'
+    face data [4][n] (L = lower side) at face-node heights zf [n]."""
+    p = params(phys)
+    arr = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in (zf, QL, FL, QR, FR)]
+    G = np.zeros_like(arr[1])
+    _check(lib().oracle_face_flux(_dp(p), int(d), float(h), *[_dp(a) for a in arr], _dp(G)), "face_flux")
+    return G
+
+
+def loss_theta(phys: dict, mesh: dict, Q: np.ndarray) -> float:
+    """Potential-temperature loss sqrt(sum_c h^2 sum_ji w_i w_j (theta - theta_bg)^2)."""
+    p, m = params(phys), _Mesh(mesh)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    out = np.zeros(1)
+    _check(lib().oracle_loss_theta(_dp(p), *m.args, _dp(Q), _dp(out)), "loss_theta")
+    return float(out[0])
+
+
 def ic(phys: dict, mesh: dict, kind: str = "bubbles", bubbles=(), t0: float = 0.0) -> np.ndarray:
-    """Initial state by nodal interpolation; kind 'bubbles' or 'mms'."""
+    """Initial state by nodal interpolation; kind 'bubbles', 'mms' (the
+    advected density wave) or 'paper_mms' (the paper's manufactured
+    solution)."""
     p, m = params(phys), _Mesh(mesh)
     n = int(phys["N"]) + 1
     Q = np.zeros((m.C, 4, n, n))
     bb = np.ascontiguousarray(np.asarray(bubbles, dtype=np.float64).reshape(-1, 6))
-    k = 1 if kind == "mms" else 0
+    k = {"bubbles": 0, "mms": 1, "paper_mms": 2}[kind]
     _check(lib().oracle_ic(_dp(p), *m.args, k, bb.shape[0], _dp(bb), float(t0), _dp(Q)), "ic")
     return Q
 

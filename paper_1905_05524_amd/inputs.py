@@ -10,6 +10,8 @@ Workloads follow the paper's scenarios (Krenz, Rannabauer, Bader 2019):
   * ``mms_small``   periodic unit square 9x9, N=2, advected density wave with
                     its manufactured heat-flux source (CFD constants gamma=1.4,
                     Pr=0.7, c_v=1 of the convergence section)
+  * ``paper_mms``   the paper's manufactured solution: periodic [0,10]^2,
+                    mu = 0.1, to t = 0.5, orders 1..6
   * ``bubble81``    2D cosine warm bubble (stratified-flow section) on 81x81
                     cells of 12.35 m, N=6, no-slip walls, Courant factor 0.4
   * ``amr27``       the same box on 27x27 coarse cells with one 3-way
@@ -47,6 +49,22 @@ def mms_small(N: int = 2, nx: int = 9, mu: float = 0.01):
                 mms_kx=2.0 * math.pi, mms_kz=2.0 * math.pi, mms_p=1.0, cfl=0.5)
     mesh = dict(nx=nx, nz=nx, max_level=0, x0=0.0, z0=0.0, Lx=1.0, Lz=1.0, bc=[BC_PERIODIC] * 4)
     return dict(name=f"mms{nx}x{nx}_N{N}", phys=phys, mesh=mesh, ic="mms", bubbles=[], steps=10)
+
+
+def paper_mms(N: int, nx: int, mu: float = 0.1, t_end: float = 0.5):
+    """The paper's manufactured-solution run (CFD scenarios): periodic
+    [0,10]^2 on nx x nx cells, CFD constants, mu = 0.1, to t = 0.5; the
+    fields and their source are fixed by the paper (kind 'paper_mms')."""
+    phys = dict(CFD, N=N, picard_iters=0, mu=mu, mms=2, cfl=0.5)
+    mesh = dict(nx=nx, nz=nx, max_level=0, x0=0.0, z0=0.0, Lx=10.0, Lz=10.0, bc=[BC_PERIODIC] * 4)
+    return dict(name=f"paper_mms{nx}x{nx}_N{N}", phys=phys, mesh=mesh, ic="paper_mms", bubbles=[],
+                t_end=t_end)
+
+
+# Grids of the convergence study on the paper's manufactured solution, per
+# order (three or four grids each, coarse enough for the CPU oracle)
+PAPER_MMS_GRIDS = {1: (4, 8, 16, 32), 2: (4, 8, 16, 32), 3: (4, 8, 16, 32),
+                   4: (2, 4, 8, 16), 5: (2, 4, 8, 16), 6: (2, 4, 8, 16)}
 
 
 def cosine_bubble(A=0.5, a=250.0, xc=500.0, zc=350.0):

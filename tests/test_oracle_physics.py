@@ -120,3 +120,61 @@ def test_mms_source_solves_pde():
         _, _, S = O.pointwise(phys, q, np.zeros(4), np.zeros(4), xv, zv, tv)
         assert abs(S[3] - expect) <= 1e-12 * max(1.0, abs(expect))
         assert S[0] == 0 and S[1] == 0 and S[2] == 0
+
+
+def paper_mms_fields():
+    """The paper's manufactured solution (CFD scenarios, eq.
+    manufactured-solution) as sympy expressions: p, rho, v = v0 sin(k.x - 2 pi t)
+    with v0 = (1/4, 1/4) and k = pi/5 (1, 1)."""
+    x, z, t = sp.symbols("x z t", real=True)
+    arg = sp.pi / 5 * x + sp.pi / 5 * z - 2 * sp.pi * t
+    gam = sp.Rational(7, 5)
+    p = sp.cos(arg) / 10 + 1 / gam
+    rho = sp.sin(arg) / 2 + 1
+    u = sp.sin(arg) / 4
+    w = sp.sin(arg) / 4
+    return (x, z, t), gam, p, rho, u, w
+
+
+def test_paper_mms_source_solves_pde():
+    """The paper's manufactured solution with the oracle's source solves the
+    full equation set (no gravity): dQ/dt + div F(Q, grad Q) = S for all four
+    conserved variables, F transcribed from the paper's equation set,
+    stress tensor and heat flux and differentiated by sympy, at random
+    space-time points.  CFD constants gamma = 1.4, Pr = 0.7, c_v = 1,
+    mu = 0.1 (the paper's values for this test)."""
+    (x, z, t), gam, p, rho, u, w = paper_mms_fields()
+    R, cp, Pr, mu = sp.Rational(2, 5), sp.Rational(7, 5), sp.Rational(7, 10), sp.Rational(1, 10)
+    E = p / (gam - 1) + rho * (u * u + w * w) / 2
+    T = p / (rho * R)
+    kappa = mu * cp / Pr
+    X, v = (x, z), (u, w)
+    div = sp.diff(u, x) + sp.diff(w, z)
+    sig = [[mu * (sp.Rational(2, 3) * div * (1 if a == b else 0) - (sp.diff(v[b], X[a]) + sp.diff(v[a], X[b])))
+            for b in range(2)] for a in range(2)]
+    m = (rho * u, rho * w)
+    F = []
+    for a in range(2):
+        Fa = [m[a]] + [v[a] * m[b] + (p if a == b else 0) + sig[a][b] for b in range(2)]
+        Fa.append(v[a] * (E + p) + sum(v[b] * sig[b][a] for b in range(2)) - kappa * sp.diff(T, X[a]))
+        F.append(Fa)
+    Q = [rho, m[0], m[1], E]
+    res = [sp.diff(Q[k], t) + sp.diff(F[0][k], x) + sp.diff(F[1][k], z) for k in range(4)]
+    phys = dict(I.CFD, N=2, mu=0.1, mms=2)
+    rng = np.random.default_rng(5)
+    for _ in range(6):
+        xv, zv = rng.uniform(0, 10, 2)
+        tv = rng.uniform(0, 0.5)
+        sub = {x: xv, z: zv, t: tv}
+        expect = np.array([float(sp.N(r.subs(sub), 30)) for r in res])
+        q = np.array([float(sp.N(e.subs(sub), 30)) for e in Q])
+        _, _, S = O.pointwise(phys, q, np.zeros(4), np.zeros(4), xv, zv, tv)
+        assert np.all(np.abs(S - expect) <= 1e-13 * max(1.0, np.max(np.abs(expect)))), (S, expect)
+    # the state the oracle interpolates is the paper's field
+    mesh = dict(nx=2, nz=2, max_level=0, x0=0.0, z0=0.0, Lx=10.0, Lz=10.0, bc=[I.BC_PERIODIC] * 4)
+    Qo = O.ic(phys, mesh, "paper_mms", t0=0.3)
+    xi = O.basis(2)["xi"]
+    c, jz, ix = 3, 1, 2                       # cell (1, 1), node (z = 1, x = 2)
+    sub = {x: 5.0 + 5.0 * xi[ix], z: 5.0 + 5.0 * xi[jz], t: 0.3}
+    ref = np.array([float(sp.N(e.subs(sub), 30)) for e in Q])
+    assert np.all(np.abs(Qo[c, :, jz, ix] - ref) <= 1e-14 * np.abs(ref).max())
