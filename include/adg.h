@@ -66,9 +66,14 @@ enum { ADG_SHAPE_COSINE = 0, ADG_SHAPE_PLATEAU_GAUSS = 1 };
  *     vertical momentum (eq. momentum-equation-split); the background is the
  *     hydrostatic atmosphere of constant potential temperature theta_bg
  *     (eq. hydrostatic-balance) with reference pressure p0;
- *   mms != 0: adds the energy source of the manufactured advected density
+ *   mms = 1: adds the energy source of the manufactured advected density
  *     wave rho = 1 + mms_amp sin(mms_kx (x - mms_u t)) sin(mms_kz (z - mms_w t)),
  *     velocity (mms_u, mms_w), pressure mms_p (for convergence checks);
+ *   mms = 2: adds the source of the paper's manufactured solution (CFD
+ *     scenarios, eq. manufactured-solution): with xi = (pi/5)(x + z) - 2 pi t,
+ *     p = 1/gamma + cos(xi)/10, rho = 1 + sin(xi)/2, u = w = sin(xi)/4, on
+ *     every conserved variable (EINVAL with gravity; the mms_* fields are
+ *     not used);
  *   cfl: Courant number of the time-step rule;
  *   fixed_dt != 0: keep clock[1] unchanged (no CFL update after a step). */
 typedef struct {
@@ -122,7 +127,8 @@ int adg_set_state(adg_mesh* m, double* Q, void* workspace, double* clock);
  * pressure; cosine bubble eq. cos-pertubation read with cos(pi r / a);
  * bubbles of eq. bubbles-pertubation).  bubbles: host array [n_bubbles][6] =
  * (shape, A, a, s, xc, zc); perturbations add.  kind 0 = bubbles, 1 = the
- * manufactured wave at time t0.  Writes the bound Q. */
+ * manufactured density wave at time t0, 2 = the paper's manufactured
+ * solution at time t0.  Writes the bound Q. */
 int adg_init_state(adg_mesh* m, int kind, int n_bubbles, const double* bubbles, double t0,
                    void* stream);
 

@@ -84,6 +84,10 @@ class adg_fv_desc(ctypes.Structure):
 _lib = None
 
 
+# kinds of adg_init_state: the bubble states, the manufactured advected
+# density wave, the paper's manufactured solution
+INIT_KINDS = {"bubbles": 0, "mms": 1, "paper_mms": 2}
+
 def lib():
     """Load libadg.so (raises if it has not been built)."""
     global _lib
@@ -242,7 +246,7 @@ class Mesh:
     # -- calls with the C names --------------------------------------------
     def init_state(self, kind="bubbles", bubbles=(), t0=0.0, stream=None):
         bb = np.ascontiguousarray(np.asarray(bubbles, dtype=np.float64).reshape(-1, 6))
-        k = 1 if kind == "mms" else 0
+        k = INIT_KINDS[kind]
         _check(lib().adg_init_state(self.h, k, bb.shape[0],
                                     bb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(t0),
                                     _stream_ptr(stream)))
@@ -625,7 +629,7 @@ class Batch:
 
     def init_state(self, s, kind="bubbles", bubbles=(), t0=0.0, stream=None):
         bb = np.ascontiguousarray(np.asarray(bubbles, dtype=np.float64).reshape(-1, 6))
-        _check(lib().adg_batch_init_state(self.h, int(s), 1 if kind == "mms" else 0, bb.shape[0],
+        _check(lib().adg_batch_init_state(self.h, int(s), INIT_KINDS[kind], bb.shape[0],
                                           bb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(t0),
                                           _stream_ptr(stream)))
 

@@ -265,6 +265,47 @@ __device__ inline double mms_source(const Phys& ph, double x, double z, double t
   return -ph.kappa * lapT;
 }
 
+// The paper's manufactured solution (CFD scenarios, eq.
+// manufactured-solution): with phase xi = k (x + z) - om t, k = pi/5,
+// om = 2 pi, the fields rho = 1 + sin(xi)/2, p = 1/gamma + cos(xi)/10,
+// u = w = sin(xi)/4 depend on xi alone; d/dx = d/dz = k d/dxi and
+// d/dt = -om d/dxi.
+constexpr double kWaveK = 0.62831853071795864769;   // pi / 5
+constexpr double kWaveOm = 6.28318530717958647693;  // 2 pi
+__device__ inline void paper_wave_state(const Phys& ph, double x, double z, double t, double q[4]) {
+  double sn, cs;
+  sincos(kWaveK * (x + z) - kWaveOm * t, &sn, &cs);
+  const double rho = 1.0 + 0.5 * sn, p = 1.0 / ph.gamma + 0.1 * cs, u = 0.25 * sn;
+  q[0] = rho; q[1] = rho * u; q[2] = rho * u;
+  q[3] = p / ph.gm1 + rho * u * u;
+}
+// Source that makes the wave solve the equation set without gravity,
+// S = dQ/dt + div F, from the derivatives of the fields along xi (primes):
+// the stress tensor gives sigma_xx = sigma_zz = -(2/3) mu k u',
+// sigma_xz = -2 mu k u'; the heat flux -kappa k T' with T = p/(R rho), whose
+// second derivative follows from differentiating R rho T = p twice.
+__device__ inline void paper_wave_source(const Phys& ph, double x, double z, double t, double S[4]) {
+  constexpr double k = kWaveK, om = kWaveOm;
+  double sn, cs;
+  sincos(k * (x + z) - om * t, &sn, &cs);
+  const double rho = 1.0 + 0.5 * sn, r1 = 0.5 * cs, r2 = -0.5 * sn;
+  const double p = 1.0 / ph.gamma + 0.1 * cs, p1 = -0.1 * sn, p2 = -0.1 * cs;
+  const double u = 0.25 * sn, u1 = 0.25 * cs, u2 = -0.25 * sn;
+  const double ir = 1.0 / rho;
+  const double m1 = r1 * u + rho * u1;                 // (rho u)'
+  const double mu1 = u * (r1 * u + 2.0 * rho * u1);    // (rho u^2)'
+  const double E = p / ph.gm1 + rho * u * u, E1 = p1 / ph.gm1 + mu1;
+  const double H1 = u1 * (E + p) + u * (E1 + p1);      // (u (E + p))'
+  const double T = p * ir * ph.iR;
+  const double T1 = (p1 * ph.iR - r1 * T) * ir;
+  const double T2 = (p2 * ph.iR - r2 * T - 2.0 * r1 * T1) * ir;
+  const double kk = k * k;
+  S[0] = 2.0 * k * m1 - om * r1;
+  S[1] = k * (2.0 * mu1 + p1) - om * m1 - (8.0 / 3.0) * ph.mu * kk * u2;
+  S[2] = S[1];
+  S[3] = 2.0 * k * H1 - om * E1 - (16.0 / 3.0) * ph.mu * kk * (u1 * u1 + u * u2) - 2.0 * ph.kappa * kk * T2;
+}
+
 // Reciprocal of a positive normal double: the hardware estimate refined by
 // two Newton steps r <- r + r (1 - x r) (quadratic convergence; the result
 // is within an ulp or so of 1/x, not necessarily correctly rounded).

@@ -7,7 +7,8 @@ namespace adg {
 // --------------------------------------------------------- initial state
 // One thread per node.  kind 0: hydrostatic background of constant potential
 // temperature perturbed in theta at fixed pressure (rho from p = rho R T,
-// T = theta * Exner, at rest); kind 1: the manufactured density wave at t0.
+// T = theta * Exner, at rest); kind 1: the manufactured density wave at t0;
+// kind 2: the paper's manufactured solution at t0.
 __global__ void k_init_state(Phys ph, int n, int C, const double* geom, const double* gtab, int kind,
                              int nbub, const double* bub, double t0, double* Q) {
   // geom and Q point at the first cell of the range
@@ -20,7 +21,9 @@ __global__ void k_init_state(Phys ph, int n, int C, const double* geom, const do
   const double x = geom[4 * c + 0] + h * gtab[GTab::XI * n + ix];
   const double z = geom[4 * c + 1] + h * gtab[GTab::XI * n + jz];
   double q[4];
-  if (kind == 1) {
+  if (kind == 2) {
+    paper_wave_state(ph, x, z, t0, q);
+  } else if (kind == 1) {
     const double rho = 1.0 + ph.mms_amp * sin(ph.mms_kx * (x - ph.mms_u * t0)) * sin(ph.mms_kz * (z - ph.mms_w * t0));
     q[0] = rho; q[1] = rho * ph.mms_u; q[2] = rho * ph.mms_w;
     q[3] = ph.mms_p / ph.gm1 + 0.5 * rho * (ph.mms_u * ph.mms_u + ph.mms_w * ph.mms_w);

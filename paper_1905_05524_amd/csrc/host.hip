@@ -325,6 +325,9 @@ int validate_params(const adg_params* p) {
   if (p->gravity && (!(p->theta_bg > 0.0) || !(p->p0 > 0.0) || !(p->g >= 0.0)))
     return fail(ADG_EINVAL, "invalid background atmosphere");
   if (!(p->cfl > 0.0)) return fail(ADG_EINVAL, "cfl must be > 0");
+  if (p->mms < 0 || p->mms > 2) return fail(ADG_EINVAL, "mms must be 0, 1 or 2");
+  if (p->mms == 2 && p->gravity)
+    return fail(ADG_EINVAL, "the paper's manufactured solution solves the equations without gravity");
   return ADG_OK;
 }
 
@@ -358,7 +361,7 @@ Phys make_phys(const adg_params& p) {
   ph.lv_coef = std::max(4.0 * p.mu / 3.0, p.gamma * p.mu / p.Pr);
   ph.mms_amp = p.mms_amp; ph.mms_u = p.mms_u; ph.mms_w = p.mms_w;
   ph.mms_kx = p.mms_kx; ph.mms_kz = p.mms_kz; ph.mms_p = p.mms_p;
-  ph.cfl = p.cfl; ph.geff = p.gravity ? p.g : 0.0; ph.gravity = p.gravity ? 1 : 0; ph.mms = p.mms ? 1 : 0; ph.fixed_dt = p.fixed_dt ? 1 : 0;
+  ph.cfl = p.cfl; ph.geff = p.gravity ? p.g : 0.0; ph.gravity = p.gravity ? 1 : 0; ph.mms = p.mms; ph.fixed_dt = p.fixed_dt ? 1 : 0;
   ph.N = p.order;
   return ph;
 }
@@ -403,7 +406,8 @@ static int need_state(adg_mesh* m) {
 }
 
 static int check_bubbles(int kind, int gravity, int n_bubbles, const double* bubbles) {
-  if (kind != 0 && kind != 1) return fail(ADG_EINVAL, "kind must be 0 (bubbles) or 1 (manufactured)");
+  if (kind < 0 || kind > 2)
+    return fail(ADG_EINVAL, "kind must be 0 (bubbles), 1 (manufactured density wave) or 2 (the paper's wave)");
   if (kind == 0 && !gravity) return fail(ADG_EINVAL, "bubble states need gravity (background)");
   if (n_bubbles < 0 || n_bubbles > 16 || (n_bubbles > 0 && !bubbles)) return fail(ADG_EINVAL, "bad bubble list");
   for (int b = 0; b < n_bubbles; ++b) {

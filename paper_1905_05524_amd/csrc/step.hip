@@ -165,8 +165,11 @@ __device__ inline double node_flux(const Phys& ph, const double q[4], double* sf
 // jobs in place, and the residual R(b) replaces X[b] (the old iterate at b is
 // no longer needed).  At the end of the sweep the time solve
 // X[a] = Q^n + dt sum_b P[a][b] R(b) runs per node in registers.  Then time
-// averages, the volume term and the face data.
-template <int n, int CPW, int WPB>
+// averages, the volume term and the face data.  PW: the variant with the
+// source of the paper's manufactured solution (a separate instantiation, so
+// that the source's temporaries do not add to the register pressure of the
+// other workloads).
+template <int n, int CPW, int WPB, bool PW = false>
 __global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phys ph, StepArgs a) {
   using L = Lay<n, CPW>;
   constexpr int nn = L::nn, sl = L::sl, T = L::T, F0 = L::F0;
@@ -214,9 +217,9 @@ __global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phy
     for (int b = 0; b < n; ++b) X[b][v] = q;
   }
 
-  // manufactured energy source at the n time nodes (it does not depend on
-  // the state), evaluated once
-  if (ph.mms && node) {
+  // manufactured energy source of the density wave at the n time nodes (it
+  // does not depend on the state), evaluated once
+  if ((!PW && ph.mms) && node) {
     const double x = x0 + h * gt[GTab::XI * n + ix];
 #pragma unroll 1
     for (int b = 0; b < n; ++b) sm[b * nn + l] = mms_source(ph, x, z, t0 + gt[GTab::XI * n + b] * dt);
@@ -242,11 +245,12 @@ __global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phy
   for (int it = 0; it < a.iters; ++it) {
 #pragma unroll
     for (int b = 0; b < n; ++b) {
-      if (b > 0 && it == 0) {
+      if (b > 0 && it == 0 && !PW) {
         // the first sweep starts from Q^n at every time node, so every node
         // has the residual of node 0 (bit for bit); only the manufactured
         // source depends on the time node: node 0's divergence of the energy
-        // flux is still in LDS
+        // flux is still in LDS.  (With the paper's wave, whose source acts
+        // on every variable, the first sweep evaluates every time node.)
         if (node) {
           X[b][0] = X[0][0];
           X[b][1] = X[0][1];
@@ -271,7 +275,13 @@ __global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phy
 #pragma unroll
         for (int v = 0; v < 4; ++v) X[b][v] = sf[v * nn + l] + sf[T + v * nn + tl];
         X[b][2] = fma(-h, Sw, X[b][2]);
-        if (ph.mms) X[b][3] = fma(-h, sm[b * nn + l], X[b][3]);
+        if ((!PW && ph.mms)) X[b][3] = fma(-h, sm[b * nn + l], X[b][3]);
+        if constexpr (PW) {
+          double Sm[4];
+          paper_wave_source(ph, x0 + h * gt[GTab::XI * n + ix], z, t0 + gt[GTab::XI * n + b] * dt, Sm);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) X[b][v] = fma(-h, Sm[v], X[b][v]);
+        }
       }
     }
     // time solve per node, in place: X[a] = Q^n + dt (K1^{-1} W R)[a] by
@@ -331,7 +341,7 @@ __global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phy
   // registers through the final pass.
   if (node) {
     double SbE = 0.0;
-    if (ph.mms) {
+    if ((!PW && ph.mms)) {
 #pragma unroll
       for (int b = 0; b < n; ++b) SbE = fma(gt[GTab::W * n + b], sm[b * nn + l], SbE);
     }
@@ -415,10 +425,29 @@ __global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phy
   wave_sync();
   if (valid) {
     double* qs = a.Qs + (size_t)c * sl;
+    if constexpr (PW) {
+      // time average of the paper's manufactured source (state-independent)
+      double Sp[4] = {0.0, 0.0, 0.0, 0.0};
+      const double xn = x0 + h * gt[GTab::XI * n + ix];
+#pragma unroll 1
+      for (int b = 0; b < n; ++b) {
+        double Sm[4];
+        paper_wave_source(ph, xn, z, t0 + gt[GTab::XI * n + b] * dt, Sm);
+        const double wb = gt[GTab::W * n + b];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const double S = (v == 2) ? Sbw : (v == 3 ? SbE : 0.0);
-      qs[v * nn + l] = Qc[v * nn] + dt * ((sf[v * nn + l] + sf[T + v * nn + tl]) * ih + S);
+        for (int v = 0; v < 4; ++v) Sp[v] = fma(wb, Sm[v], Sp[v]);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double S = ((v == 2) ? Sbw : (v == 3 ? SbE : 0.0)) + Sp[v];
+        qs[v * nn + l] = Qc[v * nn] + dt * ((sf[v * nn + l] + sf[T + v * nn + tl]) * ih + S);
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double S = (v == 2) ? Sbw : (v == 3 ? SbE : 0.0);
+        qs[v * nn + l] = Qc[v * nn] + dt * ((sf[v * nn + l] + sf[T + v * nn + tl]) * ih + S);
+      }
     }
   }
 }
@@ -435,7 +464,7 @@ __global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phy
 // state, fluxes and sources in its region; the first wavefront sums them in
 // a fixed order and runs the epilogue of k_predictor (volume term, Q*, face
 // data).  Same arithmetic as k_predictor up to the order of the sums.
-template <int n>
+template <int n, bool PW = false>
 __global__ __launch_bounds__(kWave * n) void k_predictor_lv(Phys ph, StepArgs a) {
   using L = Lay<n, 1>;
   constexpr int nn = L::nn, sl = L::sl, T = L::T, F0 = L::F0, WR = 4 * sl;
@@ -462,9 +491,15 @@ __global__ __launch_bounds__(kWave * n) void k_predictor_lv(Phys ph, StepArgs a)
   double X[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) X[v] = Qc[v * nn];
-  // manufactured energy source at this node's time (it does not depend on the state)
-  const double SE = (ph.mms && node) ? mms_source(ph, x0 + h * gt[GTab::XI * n + ix], z,
-                                                  t0 + gt[GTab::XI * n + b] * dt) : 0.0;
+  // manufactured source at this node and level's time (it does not depend on
+  // the state): the density wave's energy source, or the paper's wave's
+  // source of every variable
+  const double SE = (!PW && ph.mms && node) ? mms_source(ph, x0 + h * gt[GTab::XI * n + ix], z,
+                                                            t0 + gt[GTab::XI * n + b] * dt) : 0.0;
+  double Sm[4] = {0.0, 0.0, 0.0, 0.0};
+  if constexpr (PW) {
+    if (node) paper_wave_source(ph, x0 + h * gt[GTab::XI * n + ix], z, t0 + gt[GTab::XI * n + b] * dt, Sm);
+  }
 
   const LineJob<n> J(lane, 1);
   auto lines = [&](int src_off, int dst_off) {
@@ -514,7 +549,11 @@ __global__ __launch_bounds__(kWave * n) void k_predictor_lv(Phys ph, StepArgs a)
       residual(X, R);
     }
     if (node) {
-      if (ph.mms) R[3] = fma(-h, SE, R[3]);
+      if (!PW && ph.mms) R[3] = fma(-h, SE, R[3]);
+      if constexpr (PW) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) R[v] = fma(-h, Sm[v], R[v]);
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) sq[T + v * nn + l] = R[v];
     }
@@ -537,7 +576,8 @@ __global__ __launch_bounds__(kWave * n) void k_predictor_lv(Phys ph, StepArgs a)
   }
 
   // final pass: this node's flux and sources at the last iterate, weighted,
-  // to its region as [state | x flux | z flux | gravity source | energy source]
+  // to its region as [state | x flux | z flux | vertical-momentum source |
+  // energy source | mass source | horizontal-momentum source]
   put_slice(X);
   wave_sync();
   lines(0, F0);
@@ -554,8 +594,15 @@ __global__ __launch_bounds__(kWave * n) void k_predictor_lv(Phys ph, StepArgs a)
         wl[(4 + v) * nn + l] = wb * Fx[v];
         wl[(8 + v) * nn + l] = wb * Fz[v];
       }
-      wl[12 * nn + l] = wb * Sw;
-      wl[13 * nn + l] = wb * SE;
+      if constexpr (PW) {
+        wl[12 * nn + l] = wb * (Sw + Sm[2]);
+        wl[13 * nn + l] = wb * Sm[3];
+        wl[14 * nn + l] = wb * Sm[0];
+        wl[15 * nn + l] = wb * Sm[1];
+      } else {
+        wl[12 * nn + l] = wb * Sw;
+        wl[13 * nn + l] = wb * SE;
+      }
     }
   }
   __syncthreads();
@@ -563,6 +610,7 @@ __global__ __launch_bounds__(kWave * n) void k_predictor_lv(Phys ph, StepArgs a)
 
   // level sums in a fixed order, then the epilogue of k_predictor
   double Qb[4] = {0, 0, 0, 0}, Fbx[4] = {0, 0, 0, 0}, Fbz[4] = {0, 0, 0, 0}, Sbw = 0.0, SbE = 0.0;
+  double Sb0 = 0.0, Sb1 = 0.0;   // paper's wave only
   if (node) {
 #pragma unroll
     for (int k = 0; k < n; ++k) {
@@ -575,6 +623,10 @@ __global__ __launch_bounds__(kWave * n) void k_predictor_lv(Phys ph, StepArgs a)
       }
       Sbw += r[12 * nn + l];
       SbE += r[13 * nn + l];
+      if constexpr (PW) {
+        Sb0 += r[14 * nn + l];
+        Sb1 += r[15 * nn + l];
+      }
     }
   }
   wave_sync();
@@ -610,7 +662,7 @@ __global__ __launch_bounds__(kWave * n) void k_predictor_lv(Phys ph, StepArgs a)
     double* qs = a.Qs + (size_t)c * sl;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const double S = (v == 2) ? Sbw : (v == 3 ? SbE : 0.0);
+      const double S = (v == 2) ? Sbw : (v == 3 ? SbE : (v == 0 ? Sb0 : Sb1));
       qs[v * nn + l] = Qc[v * nn] + dt * ((sf[v * nn + l] + sf[T + v * nn + tl]) * ih + S);
     }
   }
@@ -925,14 +977,15 @@ StepArgs make_args(const Group& g) {
   return a;
 }
 
-template <int n, int CPW, int WPB>
+template <int n, int CPW, int WPB, bool PW = false>
 static int launch_pred_t(const Group& g, hipStream_t s) {
   using L = Lay<n, CPW>;
   const size_t lds = sizeof(double) * (size_t)WPB * CPW * L::pred_cell;
   const int per_block = CPW * WPB;
   const int blocks = (g.C + per_block - 1) / per_block;
   if (blocks == 0) return ADG_OK;
-  hipLaunchKernelGGL((k_predictor<n, CPW, WPB>), dim3(blocks), dim3(kWave * WPB), lds, s, g.ph, make_args(g));
+  hipLaunchKernelGGL((k_predictor<n, CPW, WPB, PW>), dim3(blocks), dim3(kWave * WPB), lds, s, g.ph,
+                     make_args(g));
   return check_launch("predictor");
 }
 template <int n, int CPW, int WPB>
@@ -974,6 +1027,9 @@ static int corr_w(const Group& g, hipStream_t s) {
 template <int n>
 static int pred_n(const Group& g, hipStream_t s) {
   constexpr int nn = n * n;
+  // the paper's manufactured solution runs one cell per wavefront (the
+  // launch shape does not change results)
+  if (g.ph.mms == 2) return launch_pred_t<n, 1, 1, true>(g, s);
   if (g.cpw == 1) return pred_w<n, 1>(g, s);
   if constexpr (2 * nn <= kWave) { if (g.cpw == 2) return pred_w<n, 2>(g, s); }
   if constexpr (4 * nn <= kWave) { if (g.cpw == 4) return pred_w<n, 4>(g, s); }
@@ -1015,7 +1071,10 @@ static int pred_lv_n(const Group& g, double* store, hipStream_t s) {
   StepArgs a = make_args(g);
   a.iter_store = store;
   const size_t lds = sizeof(double) * (size_t)n * 4 * L::sl;
-  hipLaunchKernelGGL(k_predictor_lv<n>, dim3(g.C), dim3(kWave * n), lds, s, g.ph, a);
+  if (g.ph.mms == 2)
+    hipLaunchKernelGGL((k_predictor_lv<n, true>), dim3(g.C), dim3(kWave * n), lds, s, g.ph, a);
+  else
+    hipLaunchKernelGGL((k_predictor_lv<n>), dim3(g.C), dim3(kWave * n), lds, s, g.ph, a);
   return check_launch("predictor (levels)");
 }
 int launch_predictor_levels(const Group& g, double* store, hipStream_t s) {
@@ -1038,7 +1097,10 @@ static int pred_store_n(const Group& g, double* store, hipStream_t s) {
   StepArgs a = make_args(g);
   a.iter_store = store;
   const size_t lds = sizeof(double) * (size_t)L::pred_cell;
-  hipLaunchKernelGGL((k_predictor<n, 1, 1>), dim3(g.C), dim3(kWave), lds, s, g.ph, a);
+  if (g.ph.mms == 2)
+    hipLaunchKernelGGL((k_predictor<n, 1, 1, true>), dim3(g.C), dim3(kWave), lds, s, g.ph, a);
+  else
+    hipLaunchKernelGGL((k_predictor<n, 1, 1>), dim3(g.C), dim3(kWave), lds, s, g.ph, a);
   return check_launch("predictor(store)");
 }
 int launch_predictor_store(const Group& g, double* store, hipStream_t s) {
