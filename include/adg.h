@@ -152,6 +152,26 @@ int adg_corrector(adg_mesh* m, void* stream);
 /* One full step: adg_predictor + adg_corrector. */
 int adg_step(adg_mesh* m, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one step
+ * exactly like adg_step, of Q (device [C][4][n][n], updated in place) with
+ * clock (device double[4], as for adg_set_state), whose workspace (the
+ * predictor's partial update, the face data and the per-cell time-step
+ * bounds) lives in a static device buffer of the library of
+ * ADG_STATIC_SCRATCH_BYTES (32 MiB, enough for about 9,900 cells at order
+ * 6), one per GPU, held until the process ends.  Allocates nothing and does
+ * not use the buffers bound by adg_set_state.  Must be called with the
+ * handle's device current.  EINVAL if Q or clock is null or misaligned, if
+ * the mesh's workspace (adg_workspace_bytes) exceeds the buffer, or if the
+ * current device is not the handle's; EHIP if the buffer's device address
+ * could not be looked up when the handle was created.  Every call on one
+ * GPU shares the buffer, which keeps the last call's contents (nothing in
+ * it must start at zero: each step writes every entry it reads): calls that
+ * overlap on one GPU (other streams or threads) race and must be
+ * serialised by the caller. */
+#define ADG_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+int adg_step_static(adg_mesh* m, double* Q, double* clock, void* stream);
+
 /* TV indicator (eq. tv) of theta (ADG_VAR_THETA) or rho per cell, read as
  * the l1 norm of the physical gradient integrated by GL quadrature with the
  * reference element's weights (which sum to one), i.e. the mean of

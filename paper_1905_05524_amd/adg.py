@@ -21,7 +21,7 @@ ADG_VAR_THETA, ADG_VAR_RHO = 0, 1
 EXPORTED = [
     "adg_init_mesh", "adg_destroy", "adg_mesh_info", "adg_workspace_bytes", "adg_set_state",
     "adg_init_state", "adg_compute_dt", "adg_predictor", "adg_corrector", "adg_step",
-    "adg_tv_indicator", "adg_check_health", "adg_last_error", "adg_basis", "adg_set_launch",
+    "adg_tv_indicator", "adg_check_health", "adg_last_error", "adg_basis", "adg_set_launch", "adg_step_static",
     "adg_autotune", "adg_batch_create", "adg_batch_destroy", "adg_batch_info", "adg_batch_scenario",
     "adg_batch_set_state", "adg_batch_init_state", "adg_batch_compute_dt", "adg_batch_step",
     "adg_batch_step_graph", "adg_batch_autotune", "adg_batch_set_launch", "adg_get_leaves",
@@ -106,6 +106,7 @@ def lib():
         for name in ("adg_compute_dt", "adg_predictor", "adg_corrector", "adg_step", "adg_check_health"):
             getattr(L, name).argtypes = [vp, vp]
         L.adg_tv_indicator.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp]
+        L.adg_step_static.argtypes = [vp, vp, vp, vp]
         L.adg_last_error.restype = ctypes.c_char_p
         L.adg_basis.argtypes = [vp, dp, dp, dp, dp]
         ip = ctypes.POINTER(ctypes.c_int)
@@ -271,6 +272,12 @@ class Mesh:
 
     def step(self, stream=None):
         _check(lib().adg_step(self.h, _stream_ptr(stream)))
+
+    def step_static(self, Q, clock, stream=None):
+        """adg_step_static: one step of the caller's Q and clock (device
+        tensors) with the library's static workspace; allocates nothing."""
+        _check(lib().adg_step_static(self.h, ctypes.c_void_p(Q.data_ptr()), ctypes.c_void_p(clock.data_ptr()),
+                                     _stream_ptr(stream)))
 
     def tv_indicator(self, var, T_refine, T_coarsen, tv, flags, stats, stream=None):
         _check(lib().adg_tv_indicator(self.h, int(var), float(T_refine), float(T_coarsen),

@@ -175,6 +175,11 @@ struct HostMesh {
 
 struct adg_mesh {
   adg_params prm;
+  // device the handle's tables live on, and that device's static scratch
+  // (device address, resolved at init; NULL if the lookup failed)
+  int dev = 0;
+  void* static_scratch = nullptr;
+  int static_scratch_rc = 0;
   adg_mesh_desc desc{};
   adg::HostBasis basis;
   adg::HostMesh hm;
@@ -209,6 +214,9 @@ int check_launch(const char* what);
 // Gauss-Legendre basis of n nodes and its device tables (computed in long
 // double, stored in double).
 void build_basis(int n, HostBasis& B);
+// device address of the allocation-free step's static scratch on device dev
+// (the current device); looked up once per device
+int static_scratch_address(int dev, void** ptr);
 // parameter checks shared by the 2D and 3D handles
 int validate_params(const adg_params* p);
 Phys make_phys(const adg_params& p);

@@ -525,6 +525,10 @@ int adg_init_mesh(const adg_params* prm, const adg_mesh_desc* mesh, adg_mesh** o
   if (rc) { delete m; return rc; }
   m->cells_cap = g.C;
   layout_workspace(m);
+  // the allocation-free step's scratch on this device (a failed lookup only
+  // disables adg_step_static, which then reports it)
+  if (hipGetDevice(&m->dev) != hipSuccess) m->static_scratch_rc = fail(ADG_EHIP, "no current device");
+  else m->static_scratch_rc = static_scratch_address(m->dev, &m->static_scratch);
   *out = m;
   return ADG_OK;
 }
