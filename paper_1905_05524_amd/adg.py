@@ -236,6 +236,16 @@ class Mesh:
                                    ctypes.c_void_p(self.ws.data_ptr()),
                                    ctypes.c_void_p(self.clock.data_ptr())))
 
+    def bind_clock(self, clock):
+        """Bind another device clock (double[4] tensor) with the same state
+        and workspace: a host-side pointer change, no device work."""
+        _check(lib().adg_set_state(self.h, ctypes.c_void_p(self.Q.data_ptr()),
+                                   ctypes.c_void_p(self.ws.data_ptr()), ctypes.c_void_p(clock.data_ptr())))
+
+    @property
+    def fixed_dt(self):
+        return bool(self._p.fixed_dt)
+
     def __del__(self):
         try:
             if getattr(self, "h", None):

@@ -24,9 +24,14 @@ class ThetaRollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta_prime, mesh: "adg.Mesh", steps: int, dt: float, t0: float = 0.0, keep: bool = False):
         m = mesh
+        if not m.fixed_dt:
+            # the adjoint differentiates steps of one frozen length
+            raise ValueError("theta_rollout needs a mesh created with fixed_dt=True")
         th = theta_prime.detach().contiguous()
         m.ic_theta(th)
-        ck = torch.empty((steps,) + tuple(m.Q.shape), dtype=torch.float64, device=m.device)
+        # checkpoints Q^0 .. Q^K: the loss adjoint reads the rollout's own end
+        # state, whatever the mesh is used for between forward and backward
+        ck = torch.empty((steps + 1,) + tuple(m.Q.shape), dtype=torch.float64, device=m.device)
         m.clock[0], m.clock[1] = float(t0), float(dt)
         stores = fds = None
         if keep:
@@ -39,6 +44,7 @@ class ThetaRollout(torch.autograd.Function):
                 m.step_keep(stores[k], fds[k])
             else:
                 m.step()
+        ck[steps].copy_(m.Q)
         loss = torch.zeros(1, dtype=torch.float64, device=m.device)
         m.loss_theta(loss)
         ctx.mesh, ctx.steps, ctx.dt, ctx.t0 = m, steps, float(dt), float(t0)
@@ -50,18 +56,29 @@ class ThetaRollout(torch.autograd.Function):
     def backward(ctx, grad_out):
         th, ck, loss = ctx.saved_tensors
         m = ctx.mesh
+        K = ctx.steps
         g = grad_out.reshape(1).to(torch.float64).contiguous()
         lam = torch.empty_like(m.Q)
         lam2 = torch.empty_like(m.Q)
-        # the bound state holds Q^K (forward end state)
+        # the loss adjoint at the rollout's end state Q^K
+        m.Q.copy_(ck[K])
         m.loss_theta_adjoint(loss, g, lam)
-        for k in range(ctx.steps - 1, -1, -1):
-            m.clock[0], m.clock[1] = ctx.t0 + k * ctx.dt, ctx.dt
-            if ctx.kept is not None:
-                m.step_adjoint_kept(ck[k], ctx.kept[0][k], ctx.kept[1][k], lam, lam2)
-            else:
-                m.step_adjoint(ck[k], lam, lam2)
-            lam, lam2 = lam2, lam
+        # each step's clock (start time, frozen dt), built on the device once:
+        # rebinding a row per step is a host-side pointer change, so the loop
+        # enqueues kernels only (no host writes that wait for the device)
+        clocks = torch.zeros((max(K, 1), 4), dtype=torch.float64, device=m.device)
+        clocks[:, 0] = ctx.t0 + ctx.dt * torch.arange(max(K, 1), dtype=torch.float64, device=m.device)
+        clocks[:, 1] = ctx.dt
+        try:
+            for k in range(K - 1, -1, -1):
+                m.bind_clock(clocks[k])
+                if ctx.kept is not None:
+                    m.step_adjoint_kept(ck[k], ctx.kept[0][k], ctx.kept[1][k], lam, lam2)
+                else:
+                    m.step_adjoint(ck[k], lam, lam2)
+                lam, lam2 = lam2, lam
+        finally:
+            m.bind()
         grad = torch.empty_like(th)
         m.ic_theta_adjoint(th, lam, grad)
         ctx.kept = None
@@ -69,4 +86,7 @@ class ThetaRollout(torch.autograd.Function):
 
 
 def theta_rollout(theta_prime, mesh, steps, dt, t0=0.0, keep=False):
+    """Loss after `steps` frozen-dt steps from theta' (differentiable).  The
+    mesh must have been created with fixed_dt=True; its bound state ends at
+    the rollout's final state (forward) and again after backward."""
     return ThetaRollout.apply(theta_prime, mesh, steps, dt, t0, keep)

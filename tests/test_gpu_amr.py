@@ -13,6 +13,8 @@ from oracle import oracle as O
 from paper_1905_05524_amd import adg
 from paper_1905_05524_amd import inputs as I
 
+import parity as P
+
 pytestmark = pytest.mark.gpu
 
 
@@ -52,8 +54,7 @@ def test_regrid_matches_oracle(N):
     m.clock[0], m.clock[1] = 0.0, dt
     m.step()
     ref = O.step(w["phys"], new_mesh, Qg, 0.0, dt)
-    got = m.Q.cpu().numpy()
-    assert np.all(relerr(got, ref) <= 1e-11)
+    P.assert_step(m.Q.cpu().numpy(), ref, Qg)
 
 
 
@@ -73,7 +74,7 @@ def test_large_mesh_uses_the_hashed_leaf_index():
     m.clock[0], m.clock[1] = 0.0, dt
     m.step()
     ref = O.step(w["phys"], mesh, Q, 0.0, dt)
-    assert np.all(relerr(m.Q.cpu().numpy(), ref) <= 1e-11)
+    P.assert_step(m.Q.cpu().numpy(), ref, Q)
     rng = np.random.default_rng(11)
     flags = np.zeros(len(leaves), np.int8)
     flags[rng.choice(len(leaves), 3000, replace=False)] = 1
@@ -88,7 +89,7 @@ def test_large_mesh_uses_the_hashed_leaf_index():
     Q2 = m.Q.cpu().numpy().copy()
     m.step()
     ref = O.step(w["phys"], new_mesh, Q2, 0.0, dt)
-    assert np.all(relerr(m.Q.cpu().numpy(), ref) <= 1e-11)
+    P.assert_step(m.Q.cpu().numpy(), ref, Q2)
 
 def _tv(m, var, Tr, Tc):
     tv = torch.zeros(m.C, dtype=torch.float64, device="cuda")
@@ -129,7 +130,7 @@ def test_refinement_cycle_matches_oracle():
             t, dt = m.t, m.dt
             m.step()
             ref = O.step(w["phys"], cur, Q0, t, dt)
-            assert np.all(relerr(m.Q.cpu().numpy(), ref) <= 1e-11), (cycle, s)
+            P.assert_step(m.Q.cpu().numpy(), ref, Q0, what=(cycle, s))
     assert m.C != 81
 
 
@@ -153,7 +154,7 @@ def test_adaptive_workload_initial_refinement():
     m.step()
     cur = dict(w["mesh"], leaves=ref_leaves)
     ref = O.step(w["phys"], cur, Q0, t, dt)
-    assert np.all(relerr(m.Q.cpu().numpy(), ref) <= 1e-11)
+    P.assert_step(m.Q.cpu().numpy(), ref, Q0)
 
 
 def _two_level_random(seed):
@@ -187,7 +188,7 @@ def test_two_level_regrids_match_oracle(seed):
         m.clock[0], m.clock[1] = 0.0, dt
         m.step()
         ref = O.step(phys, new_mesh, Qg, 0.0, dt)
-        assert np.all(relerr(m.Q.cpu().numpy(), ref) <= 1e-11), rnd
+        P.assert_step(m.Q.cpu().numpy(), ref, Qg, what=rnd)
     assert max(l for l, _, _ in leaves_of(m)) == 2
 
 
@@ -217,4 +218,4 @@ def test_colliding_bubbles_initial_refinement_matches_oracle():
     t, dt = m.t, m.dt
     m.step()
     ref = O.step(w["phys"], dict(w["mesh"], leaves=leaves_of(m)), Q0, t, dt)
-    assert np.all(relerr(m.Q.cpu().numpy(), ref) <= 1e-11)
+    P.assert_step(m.Q.cpu().numpy(), ref, Q0)

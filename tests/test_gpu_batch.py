@@ -1,8 +1,9 @@
 """GPU tests of the launch shapes, the multi-scenario batch (eager and HIP
 graph) and adaptive meshes with 1:3 non-conforming faces, all through the C
 ABI.  Launch shapes and batching must not change results: they are compared
-bitwise with the single-mesh default shape; adaptive meshes are compared with
-the oracle."""
+bitwise with the single-mesh default shape; batched scenarios (sampled from
+the 64-scenario workload, and a batch holding a 1:3 adaptive scenario) and
+adaptive meshes are compared with the oracle, state and increment."""
 import math
 
 import numpy as np
@@ -13,6 +14,8 @@ torch = pytest.importorskip("torch")
 from oracle import oracle as O
 from paper_1905_05524_amd import adg
 from paper_1905_05524_amd import inputs as I
+
+import parity as P
 
 pytestmark = pytest.mark.gpu
 
@@ -59,8 +62,8 @@ def test_launch_shapes_are_bitwise_equal(N):
     lv = _run(w, Q, dt, (0, 1))
     assert torch.equal(lv, _run(w, Q, dt))
     ref = O.step(w["phys"], w["mesh"], O.step(w["phys"], w["mesh"], Q, 0.0, dt), dt, dt)
-    assert np.all(relerr(lv.cpu().numpy(), ref) <= 1e-11)
-    assert np.all(relerr(base.cpu().numpy(), ref) <= 1e-11)
+    P.assert_step(lv.cpu().numpy(), ref, Q, what="level kernel")
+    P.assert_step(base.cpu().numpy(), ref, Q, what="cell kernel")
 
 
 def test_invalid_launch_shape_rejected():
@@ -117,6 +120,67 @@ def test_batch_matches_single_runs_bitwise():
         torch.cuda.synchronize()
         assert torch.equal(b.state(s), m.Q), s
         assert torch.equal(b.clock[s], m.clock), s
+
+
+def _oracle_steps(w, Q, t, dts):
+    """The oracle's state after steps of the given lengths from (Q, t)."""
+    for dt in dts:
+        Q = O.step(w["phys"], w["mesh"], Q, t, dt)
+        t += dt
+    return Q
+
+
+def _batch_vs_oracle(ws, sample, steps=2, graph=False):
+    """Step a batch (eagerly or as graph replays), then compare the sampled
+    scenarios with the oracle run on the same inputs and the same time-step
+    sequence (each scenario's own CFL step, read from its clock)."""
+    b = adg.Batch(ws)
+    for s, w in enumerate(ws):
+        if w["ic"] == "bubbles":
+            b.init_state(s, "bubbles", w["bubbles"])
+    b.compute_dt()
+    torch.cuda.synchronize()
+    start = {s: (b.state(s).cpu().numpy().copy(), float(b.clock[s][0])) for s in sample}
+    dts = {s: [] for s in sample}
+    stream = torch.cuda.Stream() if graph else None
+    for _ in range(steps):
+        for s in sample:
+            dts[s].append(float(b.clock[s][1]))
+        if graph:
+            with torch.cuda.stream(stream):
+                b.step_graph(stream)
+            stream.synchronize()
+        else:
+            b.step()
+        torch.cuda.synchronize()
+    for s in sample:
+        Q0, t0 = start[s]
+        print(f"batch scenario {s} ({ws[s]['name']}) vs oracle", flush=True)
+        ref = _oracle_steps(ws[s], Q0, t0, dts[s])
+        P.assert_step(b.state(s).cpu().numpy(), ref, Q0, what=ws[s]["name"])
+        assert float(b.clock[s][0]) == pytest.approx(t0 + sum(dts[s]), rel=1e-14)
+
+
+def test_full_batch_sampled_scenarios_match_oracle():
+    """The 64-scenario batch (134,577 cells, orders 3-6, grids 9..81) as
+    graph replays: two steps; the smallest and largest scenario of each
+    order against the oracle."""
+    ws = I.batch_scenarios()
+    by_order = {}
+    for s, w in enumerate(ws):
+        by_order.setdefault(w["phys"]["N"], []).append((w["mesh"]["nx"], s))
+    sample = sorted({min(v)[1] for v in by_order.values()} | {max(v)[1] for v in by_order.values()})
+    _batch_vs_oracle(ws, sample, steps=2, graph=True)
+
+
+def test_batch_with_adaptive_scenario_matches_oracle():
+    """A batch of three scenarios of two orders, one of them on a mesh with
+    1:3 non-conforming faces (the wall-bounded two-bubble case): every
+    scenario against the oracle after three eager steps."""
+    ws = [I.bubble(5, 3), I.bubble(6, 4, bubbles=[I.cosine_bubble(), I.cold_bubble()]), I.bubble(4, 4)]
+    ws[1]["mesh"] = dict(ws[1]["mesh"], max_level=1,
+                         leaves=I.refined_leaves(6, 6, [(2, 1), (3, 1), (2, 2), (0, 5), (5, 0)]))
+    _batch_vs_oracle(ws, [0, 1, 2], steps=3)
 
 
 def test_batch_graph_replay_equals_eager():
@@ -185,8 +249,7 @@ def test_adaptive_step_matches_oracle(kind, N):
     m.set_state(Q, t=0.2, dt=dt)
     m.step()
     ref = O.step(phys, mesh, Q, 0.2, dt)
-    got = m.Q.cpu().numpy()
-    assert np.all(relerr(got, ref) <= TOL), relerr(got, ref)
+    P.assert_step(m.Q.cpu().numpy(), ref, Q)
 
 
 def test_adaptive_periodic_conservation_on_gpu():

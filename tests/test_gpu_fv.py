@@ -18,6 +18,8 @@ from oracle import oracle as O
 from paper_1905_05524_amd import adg
 from paper_1905_05524_amd import inputs as I
 
+import parity as P
+
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-11
@@ -94,8 +96,7 @@ def test_step_and_time_step_match_oracle(case):
     g.set_state(Q, t=0.0, dt=dt)
     g.step()
     torch.cuda.synchronize()
-    e = relerr(g.Q.cpu().numpy(), ref)
-    assert np.all(e <= TOL), e
+    P.assert_step(g.Q.cpu().numpy(), ref, Q)
     clock = g.clock.cpu().numpy()
     assert clock[0] == dt and clock[3] == 1.0
     assert abs(clock[1] - O.fv_dt(phys, m, ref)) <= 1e-13 * clock[1]
@@ -112,7 +113,7 @@ def test_split_step_matches_oracle(case):
     g.predictor()
     g.corrector()
     torch.cuda.synchronize()
-    assert np.all(relerr(g.Q.cpu().numpy(), ref) <= TOL)
+    P.assert_step(g.Q.cpu().numpy(), ref, Q)
     assert abs(g.dt - O.fv_dt(phys, m, ref)) <= 1e-13 * g.dt
 
 
@@ -150,8 +151,7 @@ def test_twenty_steps_with_the_courant_rule():
         g.step()
     torch.cuda.synchronize()
     assert abs(g.t - t) <= 1e-12 * t
-    e = relerr(g.Q.cpu().numpy(), Qo)
-    assert np.all(e <= 10 * TOL), e
+    P.assert_step(g.Q.cpu().numpy(), Qo, Q, tol=10 * TOL, tol_inc=10 * P.TOL_INC)
 
 
 def test_full_size_colliding_bubbles():
@@ -169,13 +169,13 @@ def test_full_size_colliding_bubbles():
     g.set_state(Q, t=0.0, dt=dt)
     g.step()
     torch.cuda.synchronize()
-    assert np.all(relerr(g.Q.cpu().numpy(), ref) <= TOL)
+    P.assert_step(g.Q.cpu().numpy(), ref, Q)
     Qo, t = O.fv_run(phys, m, ref, dt, 10)
     for _ in range(10):
         g.step()
     torch.cuda.synchronize()
     assert abs(g.t - t) <= 1e-12 * t
-    assert np.all(relerr(g.Q.cpu().numpy(), Qo) <= 10 * TOL)
+    P.assert_step(g.Q.cpu().numpy(), Qo, ref, tol=10 * TOL, tol_inc=10 * P.TOL_INC)
     g.check_health()
 
 
@@ -194,4 +194,4 @@ def test_large_grid_step():
     g.set_state(Q, t=0.0, dt=dt)
     g.step()
     torch.cuda.synchronize()
-    assert np.all(relerr(g.Q.cpu().numpy(), ref) <= TOL)
+    P.assert_step(g.Q.cpu().numpy(), ref, Q)

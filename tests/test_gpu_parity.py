@@ -42,14 +42,14 @@ def relerr(a, b, scale=None):
     return np.array([np.max(np.abs(a[:, v] - b[:, v])) / (sc[v] if sc[v] > 0 else 1.0) for v in range(4)])
 
 
-def increment_err(got, ref, Q0):
+def increment_err(got, ref, Q0, state_scale=None):
     """Normwise error of the increment Q^{n+1} - Q^n, each variable scaled by
     max |increment| floored at 1e-6 of the state scale (the hydrostatic
     cancellation p - p_bar limits the increment's own precision)."""
     dref = np.asarray(ref) - np.asarray(Q0)
     dgot = np.asarray(got) - np.asarray(Q0)
     inc = np.array([np.max(np.abs(dref.reshape(dref.shape[0], 4, -1)[:, v])) for v in range(4)])
-    sc = np.maximum(inc, 1e-6 * _scales(ref))
+    sc = np.maximum(inc, 1e-6 * (_scales(ref) if state_scale is None else state_scale))
     return relerr(dgot, dref, scale=sc)
 
 
@@ -270,6 +270,8 @@ def test_paper_grid_step_on_sampled_cells():
         got = m.Q[j * nx + i].cpu().numpy()[None]
         e = relerr(got, ref, _scales(Q))
         assert np.all(e <= TOL), ((i, j), e)
+        ei = increment_err(got, ref, Q[j * nx + i][None], state_scale=_scales(Q))
+        assert np.all(ei <= TOL_INC), ((i, j), ei)
 
 
 def _tv_compare(w, Q, var, Tr, Tc):
