@@ -349,6 +349,13 @@ static int validate_mesh(const adg_mesh_desc* d) {
   if (!all && d->max_level != 0) return fail(ADG_EINVAL, "uniform grid requires max_level 0");
   long long cells = all ? d->n_leaves : (long long)d->nx * d->nz;
   if (cells > (1LL << 26)) return fail(ADG_EINVAL, "too many cells");
+  // the coarse grid, and each direction of the finest level, must index in
+  // 32-bit ints (leaf indices, box products in the face search and regrid)
+  if ((long long)d->nx * d->nz > (1LL << 26)) return fail(ADG_EINVAL, "too many coarse cells");
+  long long s = 1;
+  for (int l = 0; l < d->max_level; ++l) s *= 3;
+  if ((long long)d->nx * s > INT32_MAX || (long long)d->nz * s > INT32_MAX)
+    return fail(ADG_EINVAL, "finest level exceeds 32-bit indices (nx or nz times 3^max_level)");
   return ADG_OK;
 }
 

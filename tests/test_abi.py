@@ -65,6 +65,35 @@ def test_invalid_mesh_rejected(change, msg):
     assert rc == adg.ADG_EINVAL and msg in err
 
 
+def _init_leaves(nx, nz, max_level, n_leaves=1):
+    """adg_init_mesh with a leaf-list mesh of the given coarse grid (the leaf
+    arrays are never read: validation fails first)."""
+    w = I.bubble81()
+    p = adg.make_params(w["phys"])
+    d = adg.adg_mesh_desc()
+    d.Lx, d.Lz, d.nx, d.nz, d.max_level = 1.0 * nx, 1.0 * nz, nx, nz, max_level
+    for k in range(4):
+        d.bc[k] = adg.ADG_BC_WALL
+    one = (ctypes.c_int32 * 1)(0)
+    d.n_leaves = n_leaves
+    d.leaf_level = d.leaf_i = d.leaf_j = ctypes.cast(one, ctypes.POINTER(ctypes.c_int32))
+    h = ctypes.c_void_p()
+    rc = adg.lib().adg_init_mesh(ctypes.byref(p), ctypes.byref(d), ctypes.byref(h))
+    return rc, adg.lib().adg_last_error().decode()
+
+
+def test_meshes_beyond_32_bit_indices_rejected():
+    """A wide coarse grid at a deep level would overflow 32-bit leaf and box
+    indices: nx * 3^max_level and nz * 3^max_level must stay below 2^31, and
+    a leaf-list mesh's coarse grid below 2^26 cells."""
+    rc, err = _init_leaves(1 << 26, 1, 8)
+    assert rc == adg.ADG_EINVAL and "coarse" not in err and "32-bit" in err
+    rc, err = _init_leaves(1, 400000, 8)          # 400000 * 6561 > 2^31
+    assert rc == adg.ADG_EINVAL and "32-bit" in err
+    rc, err = _init_leaves(1 << 14, 1 << 13, 1)   # 2^27 coarse cells
+    assert rc == adg.ADG_EINVAL and "coarse" in err
+
+
 def test_null_arguments_rejected():
     L = adg.lib()
     assert L.adg_step(None, None) == adg.ADG_EINVAL
