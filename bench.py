@@ -110,7 +110,8 @@ def cpu_baseline(w, budget_s=15.0, one_thread_budget_s=4.0):
 def batched_leg(steps=20, warmup=3):
     """64 independent bubble scenarios (grids 9..81, N in 3..6): one HIP-graph
     launch per step of the whole batch (autotuned launch shapes), against the
-    same 64 scenarios run one after another with plain adg_step calls."""
+    same 64 scenarios run one after another with plain adg_step calls; and
+    the same graph step with the persistent work-counter predictor."""
     import torch
     from paper_1905_05524_amd import adg, model
     from paper_1905_05524_amd import inputs as I
@@ -135,6 +136,23 @@ def batched_leg(steps=20, warmup=3):
         e1.record(st)
     torch.cuda.synchronize()
     t_batch = e0.elapsed_time(e1) / 1e3
+    # the persistent work-counter predictor (one resident grid per order,
+    # items from a device counter), same graph step otherwise
+    bp = adg.Batch(ws)
+    for s_, w in enumerate(ws):
+        bp.init_state(s_, "bubbles", w["bubbles"])
+    bp.compute_dt()
+    bp.set_mode(adg.ADG_BATCH_PERSISTENT)
+    with torch.cuda.stream(st):
+        for _ in range(warmup):
+            bp.step_graph(st)
+        e0.record(st)
+        for _ in range(steps):
+            bp.step_graph(st)
+        e1.record(st)
+    torch.cuda.synchronize()
+    t_pers = e0.elapsed_time(e1) / 1e3
+    del bp
     # sequential plain runs, same kernels, default launch shape
     meshes = []
     for w in ws:
@@ -164,7 +182,11 @@ def batched_leg(steps=20, warmup=3):
             "speedup_batched_vs_sequential": t_seq / t_batch,
             "batched_dof_updates_per_s": dof * steps / t_batch,
             "batched_fp64_frac": flops * steps / t_batch / 1e12 / FP64_PEAK_TFLOPS,
-            "autotuned_cells_per_wave": cpw, "autotuned_waves_per_block": wpb}
+            "autotuned_cells_per_wave": cpw, "autotuned_waves_per_block": wpb,
+            "persistent_graph_s_per_step": t_pers / steps,
+            "persistent_fp64_frac": flops * steps / t_pers / 1e12 / FP64_PEAK_TFLOPS,
+            "kept": "per-order launches (faster than the persistent work-counter predictor)"
+                    if t_batch <= t_pers else "persistent"}
 
 
 def amr_leg(workload="amr27", steps=200, repeats=3):

@@ -325,6 +325,18 @@ int adg_batch_step_graph(adg_batch* b, void* stream);
  * n_groups entries, may be NULL).  Drops a captured graph.  Synchronises. */
 int adg_batch_autotune(adg_batch* b, int reps, void* stream, int* cells_per_wave, int* waves_per_block);
 int adg_batch_set_launch(adg_batch* b, int group, int cells_per_wave, int waves_per_block);
+/* Predictor of a batch step: ADG_BATCH_PER_ORDER (default) launches one
+ * predictor grid per order group over its cells, on the group's forked
+ * stream; ADG_BATCH_PERSISTENT launches, per order group, a persistent grid
+ * of resident wavefronts that take work items (one wavefront's cells) from
+ * a device counter (reset by the grid's last wavefront), each order's grid
+ * sized by its share of the modelled predictor work (cells x (N+1)^4).
+ * Results are identical; the persistent mode measured slower (its loop
+ * around the order-6 body spills registers) and exists for comparison.
+ * Drops a captured graph; EUNSUPPORTED for the paper's manufactured
+ * solution in persistent mode. */
+enum { ADG_BATCH_PER_ORDER = 0, ADG_BATCH_PERSISTENT = 1 };
+int adg_batch_set_mode(adg_batch* b, int mode);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,7 @@ EXPORTED = [
     "adg_tv_indicator", "adg_check_health", "adg_last_error", "adg_basis", "adg_set_launch", "adg_step_static",
     "adg_autotune", "adg_batch_create", "adg_batch_destroy", "adg_batch_info", "adg_batch_scenario",
     "adg_batch_set_state", "adg_batch_init_state", "adg_batch_compute_dt", "adg_batch_step",
-    "adg_batch_step_graph", "adg_batch_autotune", "adg_batch_set_launch", "adg_get_leaves",
+    "adg_batch_step_graph", "adg_batch_autotune", "adg_batch_set_launch", "adg_batch_set_mode", "adg_get_leaves",
     "adg_regrid_plan", "adg_regrid_apply", "adg_adjoint_workspace_bytes", "adg_step_adjoint",
     "adg_ic_theta", "adg_ic_theta_adjoint", "adg_loss_theta", "adg_loss_theta_adjoint",
     "adg_keep_bytes", "adg_step_keep", "adg_step_adjoint_kept",
@@ -123,6 +123,7 @@ def lib():
             getattr(L, name).argtypes = [vp, vp]
         L.adg_batch_autotune.argtypes = [vp, ctypes.c_int, vp, ip, ip]
         L.adg_batch_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.adg_batch_set_mode.argtypes = [vp, ctypes.c_int]
         i32p = ctypes.POINTER(ctypes.c_int32)
         L.adg_get_leaves.argtypes = [vp, i32p, i32p, i32p]
         L.adg_regrid_plan.argtypes = [vp, vp, ip, ctypes.POINTER(ctypes.c_size_t)]
@@ -667,6 +668,10 @@ class Batch:
 
     def set_launch(self, group: int, cells_per_wave: int, waves_per_block: int):
         _check(lib().adg_batch_set_launch(self.h, int(group), int(cells_per_wave), int(waves_per_block)))
+
+    def set_mode(self, mode: int):
+        """ADG_BATCH_PER_ORDER (0) or ADG_BATCH_PERSISTENT (1) predictor."""
+        _check(lib().adg_batch_set_mode(self.h, int(mode)))
 
 
 def measure_peaks(copy_mib: int = 1024, stream=None) -> dict:

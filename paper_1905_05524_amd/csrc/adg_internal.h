@@ -214,6 +214,11 @@ int check_launch(const char* what);
 // Gauss-Legendre basis of n nodes and its device tables (computed in long
 // double, stored in double).
 void build_basis(int n, HostBasis& B);
+// persistent predictor of one order group (k_predictor's body on work items
+// from counter [2], nwaves resident wavefronts), and its resident
+// wavefronts per CU
+int launch_predictor_queue(const Group& g, unsigned* counter, int nwaves, hipStream_t s);
+int predictor_queue_occupancy(int n, int* per_cu);
 // device address of the allocation-free step's static scratch on device dev
 // (the current device); looked up once per device
 int static_scratch_address(int dev, void** ptr);

@@ -937,6 +937,11 @@ struct adg_batch {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   hipStream_t graph_stream = nullptr;
+  // predictor mode: 0 one launch per order group, 1 one persistent launch per
+  // order group on a work counter, resident grids sized by modelled work
+  int mode = 0;
+  unsigned* d_queue = nullptr;           // [2 per group]
+  std::vector<int> queue_waves;          // resident wavefronts per group
 };
 
 namespace adg {
@@ -948,6 +953,8 @@ static void batch_free(adg_batch* b) {
   for (auto s : b->streams) (void)hipStreamDestroy(s);
   for (auto e : b->events) (void)hipEventDestroy(e);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->d_queue) (void)hipFree(b->d_queue);
+  b->d_queue = nullptr;
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->streams.clear(); b->events.clear();
   b->exec = nullptr; b->graph = nullptr;
@@ -967,7 +974,8 @@ static int batch_enqueue_step(adg_batch* b, hipStream_t s) {
   for (int g = 0; g < G; ++g) {
     hipStream_t gs = b->streams[g];
     if (hipStreamWaitEvent(gs, b->events[0], 0) != hipSuccess) return fail(ADG_EHIP, "stream wait");
-    int rc = launch_predictor_any(b->groups[g], nullptr, gs);
+    int rc = b->mode == 1 ? launch_predictor_queue(b->groups[g], b->d_queue + 2 * g, b->queue_waves[g], gs)
+                          : launch_predictor_any(b->groups[g], nullptr, gs);
     if (!rc) rc = launch_corrector(b->groups[g], gs);
     if (rc) return rc;
     if (hipEventRecord(b->events[1 + g], gs) != hipSuccess) return fail(ADG_EHIP, "event record");
@@ -1202,6 +1210,43 @@ int adg_batch_autotune(adg_batch* b, int reps, void* stream, int* cells_per_wave
     if (cells_per_wave) cells_per_wave[gi] = b->groups[gi].lv == 1 ? 0 : b->groups[gi].cpw;
     if (waves_per_block) waves_per_block[gi] = b->groups[gi].wpb;
   }
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  return ADG_OK;
+}
+
+int adg_batch_set_mode(adg_batch* b, int mode) {
+  if (!b) return fail(ADG_EINVAL, "null batch");
+  if (mode != 0 && mode != 1) return fail(ADG_EINVAL, "mode must be 0 (launch per order) or 1 (persistent)");
+  if (mode == 1 && b->prm0.mms == 2)
+    return fail(ADG_EUNSUPPORTED, "the persistent batch predictor has no manufactured-solution source");
+  if (mode == 1 && !b->d_queue) {
+    const int G = (int)b->groups.size();
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      return fail(ADG_EHIP, "device query failed");
+    // resident wavefronts: every group's share of the chip, by modelled
+    // predictor work (cells x (N+1)^4), of the slots its own occupancy allows
+    double tot = 0.0;
+    std::vector<double> w(G);
+    for (int g = 0; g < G; ++g) {
+      const double n = b->groups[g].n;
+      w[g] = b->groups[g].C * n * n * n * n;
+      tot += w[g];
+    }
+    b->queue_waves.assign(G, 1);
+    for (int g = 0; g < G; ++g) {
+      int per_cu = 0;
+      int rc = predictor_queue_occupancy(b->groups[g].n, &per_cu);
+      if (rc) return rc;
+      b->queue_waves[g] = std::max(1, (int)(cus * per_cu * (w[g] / tot) + 0.5));
+    }
+    if (hipMalloc(&b->d_queue, sizeof(unsigned) * 2 * (size_t)G) != hipSuccess ||
+        hipMemset(b->d_queue, 0, sizeof(unsigned) * 2 * (size_t)G) != hipSuccess)
+      return fail(ADG_ENOMEM, "work counter allocation failed");
+  }
+  b->mode = mode;
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   return ADG_OK;

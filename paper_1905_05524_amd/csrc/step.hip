@@ -35,6 +35,9 @@ struct Lay {
   static constexpr int corr_cell = 16 * n + 24 * n + 48 * n;  // sG, sL/sV, sGs
 };
 
+// most cells per wavefront for n nodes per direction (at most four)
+constexpr int max_cpw_c(int n) { return (4 * n * n <= kWave) ? 4 : ((2 * n * n <= kWave) ? 2 : 1); }
+
 // Line job of one lane in one round: direction, variable, line, cell slot and
 // the offset of its first value within a region (x lines in the first
 // layout, z lines in the transposed one; unit stride in both).
@@ -169,14 +172,18 @@ __device__ inline double node_flux(const Phys& ph, const double q[4], double* sf
 // source of the paper's manufactured solution (a separate instantiation, so
 // that the source's temporaries do not add to the register pressure of the
 // other workloads).
-template <int n, int CPW, int WPB, bool PW = false>
-__global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phys ph, StepArgs a) {
+//
+// predictor_wave is the work of wavefront `wave` of a workgroup on CPW cells
+// starting at cell0, in that wavefront's LDS region; k_predictor runs it on
+// consecutive cells, the persistent batch predictor on cells handed out by a
+// work counter.
+template <int n, int CPW, bool PW>
+__device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, int cell0) {
   using L = Lay<n, CPW>;
   constexpr int nn = L::nn, sl = L::sl, T = L::T, F0 = L::F0;
   extern __shared__ double lds[];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int lane = threadIdx.x % kWave;
   double* wl = lds + (size_t)wave * CPW * L::pred_cell;
-  const int cell0 = (blockIdx.x * WPB + wave) * CPW;
 
   // node role
   const int slot = lane / nn, l = lane % nn;
@@ -450,6 +457,12 @@ __global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phy
       }
     }
   }
+}
+
+template <int n, int CPW, int WPB, bool PW = false>
+__global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phys ph, StepArgs a) {
+  const int wave = threadIdx.x / kWave;
+  predictor_wave<n, CPW, PW>(ph, a, wave, (blockIdx.x * WPB + wave) * CPW);
 }
 
 // ------------------------------------------- predictor, a wavefront per level
@@ -977,6 +990,87 @@ StepArgs make_args(const Group& g) {
   return a;
 }
 
+// ------------------------------------------------- persistent batch predictor
+// One persistent launch per order group: a grid of resident wavefronts that
+// take work items (one wavefront's cells) from the group's device counter
+// until none are left, each running the per-wavefront body of k_predictor.
+// The last wavefront to finish resets the counter pair for the next launch
+// (every wavefront of the grid reaches that point: the loop ends when the
+// counter passes the last item).  The batch sizes each order's grid by its
+// share of the modelled work, so that the orders, launched side by side,
+// finish together.
+template <int n, int CPW>
+__global__ __launch_bounds__(kWave, (n <= 7 ? 3 : 1)) void k_predictor_queue(Phys ph, StepArgs a, unsigned* counter,
+                                                                              unsigned nwaves) {
+  const unsigned items = (unsigned)((a.C + CPW - 1) / CPW);
+  for (;;) {
+    unsigned item = 0;
+    if (threadIdx.x == 0) item = atomicAdd(&counter[0], 1u);
+    item = __builtin_amdgcn_readfirstlane(item);
+    if (item >= items) break;
+    // an opaque copy of the buffer pointers per item, so that the body's
+    // table and state loads stay inside the loop (hoisted, they would stay
+    // live across the whole body)
+    StepArgs ai = a;
+    asm volatile("" : "+s"(ai.gtab), "+s"(ai.geom), "+s"(ai.Qin), "+s"(ai.clock));
+    predictor_wave<n, CPW, false>(ph, ai, 0, (int)item * CPW);
+  }
+  if (threadIdx.x == 0) {
+    const unsigned done = atomicAdd(&counter[1], 1u);
+    if (done + 1 == nwaves) {
+      atomicExch(&counter[0], 0u);
+      atomicExch(&counter[1], 0u);
+    }
+  }
+}
+
+template <int n>
+static int queue_n(const Group& g, unsigned* counter, int nwaves, hipStream_t s) {
+  constexpr int CPW = max_cpw_c(n);
+  using L = Lay<n, CPW>;
+  const size_t lds = sizeof(double) * (size_t)CPW * L::pred_cell;
+  hipLaunchKernelGGL((k_predictor_queue<n, CPW>), dim3(nwaves), dim3(kWave), lds, s, g.ph, make_args(g), counter,
+                     (unsigned)nwaves);
+  return check_launch("persistent predictor");
+}
+
+int launch_predictor_queue(const Group& g, unsigned* counter, int nwaves, hipStream_t s) {
+  if (g.C == 0 || nwaves < 1) return ADG_OK;
+  if (g.ph.mms == 2) return fail(ADG_EUNSUPPORTED, "the persistent batch predictor has no manufactured-solution source");
+  switch (g.n) {
+    case 2: return queue_n<2>(g, counter, nwaves, s);
+    case 3: return queue_n<3>(g, counter, nwaves, s);
+    case 4: return queue_n<4>(g, counter, nwaves, s);
+    case 5: return queue_n<5>(g, counter, nwaves, s);
+    case 6: return queue_n<6>(g, counter, nwaves, s);
+    case 7: return queue_n<7>(g, counter, nwaves, s);
+    case 8: return queue_n<8>(g, counter, nwaves, s);
+    default: return fail(ADG_EUNSUPPORTED, "order not supported");
+  }
+}
+
+// resident wavefronts per CU of the persistent predictor of order n-1
+template <int n>
+static int queue_occ(int* per_cu) {
+  constexpr int CPW = max_cpw_c(n);
+  const size_t lds = sizeof(double) * (size_t)CPW * Lay<n, CPW>::pred_cell;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_predictor_queue<n, CPW>, kWave, lds) == hipSuccess
+             ? ADG_OK
+             : fail(ADG_EHIP, "occupancy query failed");
+}
+int predictor_queue_occupancy(int n, int* per_cu) {
+  switch (n) {
+    case 2: return queue_occ<2>(per_cu);
+    case 3: return queue_occ<3>(per_cu);
+    case 4: return queue_occ<4>(per_cu);
+    case 5: return queue_occ<5>(per_cu);
+    case 6: return queue_occ<6>(per_cu);
+    case 7: return queue_occ<7>(per_cu);
+    case 8: return queue_occ<8>(per_cu);
+    default: return fail(ADG_EUNSUPPORTED, "order not supported");
+  }
+}
+
 template <int n, int CPW, int WPB, bool PW = false>
 static int launch_pred_t(const Group& g, hipStream_t s) {
   using L = Lay<n, CPW>;
@@ -1125,6 +1219,6 @@ int launch_clock(double* clock, const double* dtc, const int* beg, const int* en
   return check_launch("clock");
 }
 
-int max_cpw(int n) { return (4 * n * n <= kWave) ? 4 : ((2 * n * n <= kWave) ? 2 : 1); }
+int max_cpw(int n) { return max_cpw_c(n); }
 
 }  // namespace adg

@@ -203,6 +203,37 @@ def test_batch_graph_replay_equals_eager():
         assert torch.equal(eager.clock, graph.clock), k
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_persistent_mode_equals_per_order_launches(mixed):
+    """The persistent work-counter predictor (one resident grid per order,
+    items from a device counter) gives the bits of the per-order launches,
+    over several graph replays (the counters reset themselves between
+    launches), also with a scenario on a 1:3 mesh."""
+    ws = _small_batch()
+    if mixed:
+        ws[1]["mesh"] = dict(I.bubble(6, ws[1]["phys"]["N"])["mesh"], max_level=1,
+                             leaves=I.refined_leaves(6, 6, [(2, 1), (3, 1), (0, 5)]))
+    a, b = adg.Batch(ws), adg.Batch(ws)
+    for bb in (a, b):
+        for s, w in enumerate(ws):
+            bb.init_state(s, "bubbles", w["bubbles"])
+        bb.compute_dt()
+    b.set_mode(adg.ADG_BATCH_PERSISTENT)
+    stream = torch.cuda.Stream()
+    for k in range(4):
+        with torch.cuda.stream(stream):
+            a.step_graph(stream)
+            b.step_graph(stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        assert torch.equal(a.Q, b.Q), k
+        assert torch.equal(a.clock, b.clock), k
+    b.step()                      # eager launch after the replays
+    a.step()
+    torch.cuda.synchronize()
+    assert torch.equal(a.Q, b.Q)
+
+
 def test_batch_autotune_then_step_unchanged():
     ws = _small_batch()
     a, b = adg.Batch(ws), adg.Batch(ws)
