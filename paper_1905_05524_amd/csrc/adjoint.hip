@@ -407,22 +407,26 @@ __global__ __launch_bounds__(kWave) void k_face_adj(Phys ph, AdjArgs a) {
 }
 
 // ------------------------------------------------------- reverse predictor
-// One workgroup of n wavefronts per cell: wavefront b owns time level b.
-// The reverse of every time level of a sweep (and of the final pass) is
-// independent of the others once the sweep's residual adjoints are known, so
-// the n levels run side by side; the workgroup synchronises only where the
-// levels meet (the time matrix mixes them).  Each wavefront has its own LDS
-// slice buffers; the iterate adjoints Lq and the residual adjoints sR are
-// shared.
+// One workgroup of NW wavefronts per cell; wavefront w owns the time levels
+// b = w, w + NW, ... (NW = min(n, 4): at order 6, three cells' workgroups
+// share a CU, so a 27x27 mesh runs in one round).  The reverse of every time
+// level of a sweep (and of the final pass) is independent of the others once
+// the sweep's residual adjoints are known, so the levels run side by side;
+// the workgroup synchronises only where the levels meet (the time matrix
+// mixes them).  Each wavefront has its own LDS slice buffers; the iterate
+// adjoints Lq and the residual adjoints sR are shared.
 template <int n>
-__global__ __launch_bounds__(kWave * n) void k_pred_adj(Phys ph, AdjArgs a) {
-  constexpr int nn = n * n, sl = 4 * nn;
+constexpr int adj_waves() { return n < 4 ? n : 4; }
+
+template <int n>
+__global__ __launch_bounds__(kWave * adj_waves<n>()) void k_pred_adj(Phys ph, AdjArgs a) {
+  constexpr int nn = n * n, sl = 4 * nn, NW = adj_waves<n>();
   __shared__ double Lq[n * sl];        // adjoint of the iterate at every time node
   __shared__ double sR[n * sl];        // residual adjoints of one reverse sweep
-  __shared__ double sW[n][3 * sl];     // per wavefront: state slice, then gradients / adjoint work
-  const int c = blockIdx.x, b = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  double* sq = sW[b];
-  double* sg = sW[b] + sl;             // [2][sl]: gradients along x and z, reused for the adjoint work
+  __shared__ double sW[NW][3 * sl];    // per wavefront: state slice, then gradients / adjoint work
+  const int c = blockIdx.x, w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  double* sq = sW[w];
+  double* sg = sW[w] + sl;             // [2][sl]: gradients along x and z, reused for the adjoint work
   const bool node = lane < nn;
   const int l = node ? lane : 0;
   const int jz = l / n, ix = l % n;
@@ -450,7 +454,7 @@ __global__ __launch_bounds__(kWave * n) void k_pred_adj(Phys ph, AdjArgs a) {
   double aQn[4], aQb[4], aFbx[4], aFbz[4], aSb = 0.0;
   double lq[4];
   for (int v = 0; v < 4; ++v) lq[v] = node ? lin[v * nn + l] : 0.0;
-  for (int v = 0; v < 4; ++v) aQn[v] = b == 0 ? lq[v] : 0.0;   // direct part, counted once
+  for (int v = 0; v < 4; ++v) aQn[v] = w == 0 ? lq[v] : 0.0;   // direct part, counted once
   aSb = dt * lq[2];
   if (node)
     for (int v = 0; v < 4; ++v) sq[v * nn + l] = lq[v];
@@ -477,10 +481,10 @@ __global__ __launch_bounds__(kWave * n) void k_pred_adj(Phys ph, AdjArgs a) {
   }
   wave_sync_a();
 
-  // reverse of "flux/source at this wavefront's time level": given aF (x, z)
-  // and aSw per node, the state adjoint (direct + through the gradients)
-  // plus add[] becomes Lq[b]
-  auto slice_vjp = [&](const double* qsrc, const double aFx[4], const double aFz[4], double aSw,
+  // reverse of "flux/source at time level b": given aF (x, z) and aSw per
+  // node, the state adjoint (direct + through the gradients) plus add[]
+  // becomes Lq[b]
+  auto slice_vjp = [&](int b, const double* qsrc, const double aFx[4], const double aFz[4], double aSw,
                        const double add[4]) {
     if (node)
       for (int v = 0; v < 4; ++v) sq[v * nn + l] = qsrc[v * nn + l];
@@ -504,48 +508,57 @@ __global__ __launch_bounds__(kWave * n) void k_pred_adj(Phys ph, AdjArgs a) {
   };
 
   // (b) final pass: F, S and q at the last iterate, averaged with w_b
-  {
+  for (int b = w; b < n; b += NW) {
     const double wb = gt[GTab::W * n + b];
     double aFx[4], aFz[4], add[4];
     for (int v = 0; v < 4; ++v) { aFx[v] = wb * aFbx[v]; aFz[v] = wb * aFbz[v]; add[v] = wb * aQb[v]; }
-    slice_vjp(store + ((size_t)(I - 1) * n + b) * sl, aFx, aFz, wb * aSb, add);
+    slice_vjp(b, store + ((size_t)(I - 1) * n + b) * sl, aFx, aFz, wb * aSb, add);
   }
   __syncthreads();
 
   // (c) Picard sweeps in reverse: q^{k+1}[a] = Q^n + dt sum_b P[a][b] R(q^k[b])
-  const double* prow = gt + GTab::pt(n) + b * n;   // P[a][b] over a
   for (int it = I - 1; it >= 0; --it) {
-    if (node)
-      for (int v = 0; v < 4; ++v) {
-        aQn[v] += Lq[b * sl + v * nn + l];
-        double s = 0.0;
-        for (int a2 = 0; a2 < n; ++a2) s = fma(prow[a2], Lq[a2 * sl + v * nn + l], s);
-        sR[b * sl + v * nn + l] = dt * s;
-      }
-    __syncthreads();   // every level's Lq read before any is overwritten
-    // R = S - (1/h)(Dx Fx + Dz Fz): lambda_F = -(1/h) D^T lambda_R, lambda_Sw = lambda_R[2]
-    if (job) line_MT<n>(Dv, jbase, jstride, sR + b * sl, sg + dir * sl, -ih);
-    wave_sync_a();
-    double aFx[4], aFz[4];
-    for (int v = 0; v < 4; ++v) {
-      aFx[v] = node ? sg[v * nn + l] : 0.0;
-      aFz[v] = node ? sg[sl + v * nn + l] : 0.0;
+    for (int b = w; b < n; b += NW) {
+      const double* prow = gt + GTab::pt(n) + b * n;   // P[a][b] over a
+      if (node)
+        for (int v = 0; v < 4; ++v) {
+          aQn[v] += Lq[b * sl + v * nn + l];
+          double s = 0.0;
+          for (int a2 = 0; a2 < n; ++a2) s = fma(prow[a2], Lq[a2 * sl + v * nn + l], s);
+          sR[b * sl + v * nn + l] = dt * s;
+        }
     }
-    const double aSw = node ? sR[b * sl + 2 * nn + l] : 0.0;
-    wave_sync_a();
-    const double zero[4] = {0, 0, 0, 0};
-    slice_vjp(it > 0 ? store + ((size_t)(it - 1) * n + b) * sl : Qc, aFx, aFz, aSw, zero);
+    __syncthreads();   // every level's Lq read before any is overwritten
+    for (int b = w; b < n; b += NW) {
+      // R = S - (1/h)(Dx Fx + Dz Fz): lambda_F = -(1/h) D^T lambda_R, lambda_Sw = lambda_R[2]
+      if (job) line_MT<n>(Dv, jbase, jstride, sR + b * sl, sg + dir * sl, -ih);
+      wave_sync_a();
+      double aFx[4], aFz[4];
+      for (int v = 0; v < 4; ++v) {
+        aFx[v] = node ? sg[v * nn + l] : 0.0;
+        aFz[v] = node ? sg[sl + v * nn + l] : 0.0;
+      }
+      const double aSw = node ? sR[b * sl + 2 * nn + l] : 0.0;
+      wave_sync_a();
+      const double zero[4] = {0, 0, 0, 0};
+      slice_vjp(b, it > 0 ? store + ((size_t)(it - 1) * n + b) * sl : Qc, aFx, aFz, aSw, zero);
+    }
     __syncthreads();   // every level's Lq written before the next sweep reads them
   }
-  // q^0[b] = Q^n for every b; sum the levels' shares through LDS
+  // q^0[b] = Q^n for every b; each wavefront's share (its accumulator and its
+  // levels' last adjoints) summed through LDS
   if (node)
-    for (int v = 0; v < 4; ++v) sR[b * sl + v * nn + l] = aQn[v] + Lq[b * sl + v * nn + l];
+    for (int v = 0; v < 4; ++v) {
+      double s = aQn[v];
+      for (int b = w; b < n; b += NW) s += Lq[b * sl + v * nn + l];
+      sR[w * sl + v * nn + l] = s;
+    }
   __syncthreads();
-  if (b == 0 && node) {
+  if (w == 0 && node) {
     double* out = a.lam_out + (size_t)c * sl;
     for (int v = 0; v < 4; ++v) {
       double s = 0.0;
-      for (int w = 0; w < n; ++w) s += sR[w * sl + v * nn + l];
+      for (int k = 0; k < NW; ++k) s += sR[k * sl + v * nn + l];
       out[v * nn + l] = s;
     }
   }
@@ -656,7 +669,7 @@ template <int n>
 static int adj_n(const Group& g, AdjArgs a, hipStream_t s) {
   hipLaunchKernelGGL(k_lift_adj<n>, dim3(g.C), dim3(kWave), 0, s, g.ph, a);
   hipLaunchKernelGGL(k_face_adj<n>, dim3(g.C), dim3(kWave), 0, s, g.ph, a);
-  hipLaunchKernelGGL(k_pred_adj<n>, dim3(g.C), dim3(kWave * n), 0, s, g.ph, a);
+  hipLaunchKernelGGL(k_pred_adj<n>, dim3(g.C), dim3(kWave * adj_waves<n>()), 0, s, g.ph, a);
   return check_launch("step adjoint");
 }
 
