@@ -207,7 +207,6 @@ struct AdjArgs {
   double* lam_out;       // dL/dQ^n
   const double* FD;      // forward face data (recomputed)
   const double* store;   // iterates [C][I][n][4][n][n]
-  double* lamG;          // [C][4 faces][4][n] this cell's half of the face-flux adjoint
   double* lamFD;         // [C][4 faces][2][4][n]
   const double* clock;
   const double* geom;
@@ -217,28 +216,23 @@ struct AdjArgs {
 };
 
 // ---------------------------------------------------------- lifting adjoint
+// The corrector's surface term of cell c, -(dt/h) (L1 G_{+} - L0 G_{-}) per
+// row or column, transposed: cell c's half of the adjoint of face f's flux
+// at face node k, variable v (L0 = e0/w, L1 = e1/w).
 template <int n>
-__global__ __launch_bounds__(kWave) void k_lift_adj(Phys ph, AdjArgs a) {
+__device__ inline double lift_adj_half(const AdjArgs& a, int c, int f, int k, int v) {
   constexpr int nn = n * n;
-  const int c = blockIdx.x, lane = threadIdx.x;
-  if (lane >= 4 * n) return;
-  const int f = lane / n, k = lane % n;
-  const double dt = a.clock[1], h = a.geom[4 * c + 2];
-  const double sc = dt / h;
-  const double* lam = a.lam_in + (size_t)c * 4 * nn;
+  const double sc = a.clock[1] / a.geom[4 * c + 2];
+  const double* lam = a.lam_in + (size_t)c * 4 * nn + v * nn;
   const double* Lt = a.gtab + (((f & 1) ? GTab::L1 : GTab::L0) * n);
   const double sgn = (f & 1) ? -sc : sc;   // +face: -(dt/h) L1, -face: +(dt/h) L0
-  double* out = a.lamG + (size_t)c * 16 * n + f * 4 * n;
+  double s = 0.0;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    double s = 0.0;
-#pragma unroll
-    for (int m = 0; m < n; ++m) {
-      const int idx = (f < 2) ? (k * n + m) : (m * n + k);   // x-faces: row k; z-faces: column k
-      s = fma(Lt[m], lam[v * nn + idx], s);
-    }
-    out[v * n + k] = sgn * s;
+  for (int m = 0; m < n; ++m) {
+    const int idx = (f < 2) ? (k * n + m) : (m * n + k);   // x-faces: row k; z-faces: column k
+    s = fma(Lt[m], lam[idx], s);
   }
+  return sgn * s;
 }
 
 // ------------------------------------------------------------ face adjoint
@@ -313,7 +307,8 @@ __device__ inline void ghost_vjp(const Phys& ph, double zf, const double Qi[4], 
 }
 
 // Per cell, lanes (f, k): total flux adjoint of face f at node k (this
-// cell's half plus the neighbour's), then the reverse of the Rusanov flux
+// cell's half plus the neighbour's, both from the lifting adjoint of the
+// incoming adjoint state), then the reverse of the Rusanov flux
 // onto this cell's own face data (and, at walls, through the ghost).
 template <int n>
 __global__ __launch_bounds__(kWave) void k_face_adj(Phys ph, AdjArgs a) {
@@ -331,13 +326,17 @@ __global__ __launch_bounds__(kWave) void k_face_adj(Phys ph, AdjArgs a) {
   const double zf = (d == 0) ? z0 + h * gt[GTab::XI * n + k] : z0 + ((f & 1) ? h : 0.0);
   if (act) {
     const double* fd = a.FD + (size_t)c * 32 * n + f * 8 * n;
-    const double* lg = a.lamG + (size_t)c * 16 * n + f * 4 * n;
-    for (int v = 0; v < 4; ++v) { Qm[v] = fd[v * n + k]; Fm[v] = fd[4 * n + v * n + k]; aG[v] = lg[v * n + k]; }
+    for (int v = 0; v < 4; ++v) {
+      Qm[v] = fd[v * n + k]; Fm[v] = fd[4 * n + v * n + k];
+      aG[v] = lift_adj_half<n>(a, c, f, k, v);
+    }
     if (kind == kConforming) {
       const int o = nb[1];
       const double* fo = a.FD + (size_t)o * 32 * n + (f ^ 1) * 8 * n;
-      const double* lo = a.lamG + (size_t)o * 16 * n + (f ^ 1) * 4 * n;
-      for (int v = 0; v < 4; ++v) { Qo[v] = fo[v * n + k]; Fo[v] = fo[4 * n + v * n + k]; aG[v] += lo[v * n + k]; }
+      for (int v = 0; v < 4; ++v) {
+        Qo[v] = fo[v * n + k]; Fo[v] = fo[4 * n + v * n + k];
+        aG[v] += lift_adj_half<n>(a, o, f ^ 1, k, v);
+      }
     } else {
       ghost_fwd(ph, d, zf, Qm, Fm, Qo, Fo);
     }
@@ -667,14 +666,13 @@ int launch_corrector(const Group& g, hipStream_t s);
 
 template <int n>
 static int adj_n(const Group& g, AdjArgs a, hipStream_t s) {
-  hipLaunchKernelGGL(k_lift_adj<n>, dim3(g.C), dim3(kWave), 0, s, g.ph, a);
   hipLaunchKernelGGL(k_face_adj<n>, dim3(g.C), dim3(kWave), 0, s, g.ph, a);
   hipLaunchKernelGGL(k_pred_adj<n>, dim3(g.C), dim3(kWave * adj_waves<n>()), 0, s, g.ph, a);
   return check_launch("step adjoint");
 }
 
 int launch_step_adjoint(const Group& g, const double* Qn, const double* lam_in, double* lam_out, double* store,
-                        const double* fd, bool recompute, double* lamG, double* lamFD, hipStream_t s) {
+                        const double* fd, bool recompute, double* lamFD, hipStream_t s) {
   if (recompute) {
     // forward predictor from the checkpoint, keeping the iterates and the face data
     Group gf = g;
@@ -684,7 +682,7 @@ int launch_step_adjoint(const Group& g, const double* Qn, const double* lam_in, 
     if (rc) return rc;
   }
   AdjArgs a;
-  a.Qn = Qn; a.lam_in = lam_in; a.lam_out = lam_out; a.FD = fd; a.store = store; a.lamG = lamG;
+  a.Qn = Qn; a.lam_in = lam_in; a.lam_out = lam_out; a.FD = fd; a.store = store;
   a.lamFD = lamFD; a.clock = g.clock; a.geom = g.d_geom; a.nbr = g.d_nbr; a.gtab = g.d_gtab;
   a.C = g.C; a.iters = g.iters;
   switch (g.n) {

@@ -23,7 +23,7 @@ int launch_health(const Group& g, int* flag, hipStream_t s);
 int launch_regrid(int n, int C, const int* ops, const double* Qold, double* Qnew, const double* gtab,
                   hipStream_t s);
 int launch_step_adjoint(const Group& g, const double* Qn, const double* lam_in, double* lam_out, double* store,
-                        const double* fd, bool recompute, double* lamG, double* lamFD, hipStream_t s);
+                        const double* fd, bool recompute, double* lamFD, hipStream_t s);
 int launch_predictor_store(const Group& g, double* store, hipStream_t s);
 int launch_predictor_levels(const Group& g, double* store, hipStream_t s);
 int launch_ic_theta(const Group& g, const double* thp, hipStream_t s);
@@ -769,14 +769,12 @@ int adg_regrid_apply(adg_mesh* m, double* Q_new, void* workspace_new, double* cl
   return adg_set_state(m, Q_new, workspace_new, clock);
 }
 
-// adjoint workspace: iterate store [C][I][n][4][n][n], face-flux adjoint
-// halves [C][4][4][n], face-data adjoints [C][4][2][4][n], loss partials [C]
-static void adj_layout(const adg_mesh* m, size_t* off_store, size_t* off_g, size_t* off_fd, size_t* off_part,
-                       size_t* total) {
+// adjoint workspace: iterate store [C][I][n][4][n][n], face-data adjoints
+// [C][4][2][4][n], loss partials [C]
+static void adj_layout(const adg_mesh* m, size_t* off_store, size_t* off_fd, size_t* off_part, size_t* total) {
   const size_t C = (size_t)m->g.C, n = (size_t)m->g.n, I = (size_t)m->g.iters;
   size_t off = 0;
   *off_store = off; off = align256(off + sizeof(double) * C * I * n * 4 * n * n);
-  *off_g = off; off = align256(off + sizeof(double) * C * 16 * n);
   *off_fd = off; off = align256(off + sizeof(double) * C * 32 * n);
   *off_part = off; off = align256(off + sizeof(double) * C);
   *total = off;
@@ -791,8 +789,8 @@ static int adjoint_supported(const adg_mesh* m) {
 
 int adg_adjoint_workspace_bytes(const adg_mesh* m, size_t* bytes) {
   if (!m || !bytes) return fail(ADG_EINVAL, "null argument");
-  size_t a, b, c, d;
-  adj_layout(m, &a, &b, &c, &d, bytes);
+  size_t a, c, d;
+  adj_layout(m, &a, &c, &d, bytes);
   return ADG_OK;
 }
 
@@ -804,11 +802,11 @@ int adg_step_adjoint(adg_mesh* m, const double* Q_n, const double* lam_np1, doub
   if (!Q_n || !lam_np1 || !lam_n || !adj_ws) return fail(ADG_EINVAL, "null buffer");
   if (lam_n == lam_np1) return fail(ADG_EINVAL, "lam_n must not alias lam_np1");
   if (((uintptr_t)adj_ws & 255) != 0) return fail(ADG_EINVAL, "adjoint workspace must be 256-byte aligned");
-  size_t os, og, ofd, op, tot;
-  adj_layout(m, &os, &og, &ofd, &op, &tot);
+  size_t os, ofd, op, tot;
+  adj_layout(m, &os, &ofd, &op, &tot);
   char* w = static_cast<char*>(adj_ws);
   return launch_step_adjoint(m->g, Q_n, lam_np1, lam_n, reinterpret_cast<double*>(w + os), m->g.FD, true,
-                             reinterpret_cast<double*>(w + og), reinterpret_cast<double*>(w + ofd),
+                             reinterpret_cast<double*>(w + ofd),
                              (hipStream_t)stream);
 }
 
@@ -843,11 +841,11 @@ int adg_step_adjoint_kept(adg_mesh* m, const double* Q_n, const double* store, c
   if (!Q_n || !store || !fd || !lam_np1 || !lam_n || !adj_ws) return fail(ADG_EINVAL, "null buffer");
   if (lam_n == lam_np1) return fail(ADG_EINVAL, "lam_n must not alias lam_np1");
   if (((uintptr_t)adj_ws & 255) != 0) return fail(ADG_EINVAL, "adjoint workspace must be 256-byte aligned");
-  size_t os, og, ofd, op, tot;
-  adj_layout(m, &os, &og, &ofd, &op, &tot);
+  size_t os, ofd, op, tot;
+  adj_layout(m, &os, &ofd, &op, &tot);
   char* w = static_cast<char*>(adj_ws);
   return launch_step_adjoint(m->g, Q_n, lam_np1, lam_n, const_cast<double*>(store), fd, false,
-                             reinterpret_cast<double*>(w + og), reinterpret_cast<double*>(w + ofd),
+                             reinterpret_cast<double*>(w + ofd),
                              (hipStream_t)stream);
 }
 
@@ -871,8 +869,8 @@ int adg_loss_theta(adg_mesh* m, double* loss, void* adj_ws, void* stream) {
   int rc = need_state(m);
   if (rc) return rc;
   if (!loss || !adj_ws) return fail(ADG_EINVAL, "null buffer");
-  size_t os, og, ofd, op, tot;
-  adj_layout(m, &os, &og, &ofd, &op, &tot);
+  size_t os, ofd, op, tot;
+  adj_layout(m, &os, &ofd, &op, &tot);
   return launch_loss(m->g, reinterpret_cast<double*>(static_cast<char*>(adj_ws) + op), loss, (hipStream_t)stream);
 }
 
