@@ -346,39 +346,63 @@ def adjoint_leg(steps=50):
     return out
 
 
-def convergence_leg(T=0.05, grids=(9, 18, 36), orders=(1, 2, 3, 4, 5, 6)):
-    """Convergence study on the manufactured solution (periodic unit square,
-    advected density wave with its heat-flux source): L2 error of rho at
-    t = T against the exact solution, for each order and grid, with the
-    experimental order of convergence between successive grids; plus the
-    step throughput of the 9x9, N=2 workload (10 steps, Courant factor 0.5)."""
+def _l2_rho_error(m, exact_kind, T, nx, L):
+    import torch
+    from paper_1905_05524_amd import adg
+    ex = adg.Mesh(m.phys, m.mesh_desc)
+    ex.init_state(exact_kind, t0=T)
+    wq = torch.as_tensor(m.basis()["w"], dtype=torch.float64, device="cuda")
+    W = torch.outer(wq, wq) * (L / nx) ** 2
+    return float(torch.sqrt(torch.sum(W[None] * (m.Q[:, 0] - ex.Q[:, 0]) ** 2)))
+
+
+def _run_to(w, kind, T):
+    import math
+    from paper_1905_05524_amd import adg
+    m = adg.Mesh(w["phys"], w["mesh"], fixed_dt=True)
+    m.init_state(kind)
+    m.compute_dt()
+    ns = int(math.ceil(T / m.dt))
+    m.set_state(m.Q.clone(), t=0.0, dt=T / ns)
+    for _ in range(ns):
+        m.step()
+    return m, ns
+
+
+def convergence_leg(orders=(1, 2, 3, 4, 5, 6)):
+    """Convergence studies on the GPU path: the paper's manufactured solution
+    (CFD scenarios: periodic [0,10]^2, mu = 0.1, to t = 0.5, L2 error of rho
+    on three or four grids per order), and the advected density wave
+    (periodic unit square, mu = 0.01, Courant factor 0.4, to t = 0.05, grids
+    9, 18, 36), with the experimental orders between successive grids; plus
+    the step throughput of the 9x9, N=2 density-wave workload."""
     import math
     import torch
     from paper_1905_05524_amd import adg, model
     from paper_1905_05524_amd import inputs as I
-    out = {"workload": "mms: periodic [0,1]^2, rho = 1 + 0.1 sin 2pi x sin 2pi z, u = w = 0.5, p = 1, "
-                       "mu = 0.01, Courant factor 0.4 (stable at every order); L2 error of rho at t = 0.05",
-           "orders": {}}
+    out = {"paper_mms": {"workload": "the paper's manufactured solution: periodic [0,10]^2, CFD constants, "
+                                     "mu = 0.1, Courant factor 0.5, L2 error of rho at t = 0.5",
+                         "orders": {}},
+           "density_wave": {"workload": "periodic [0,1]^2, rho = 1 + 0.1 sin 2pi x sin 2pi z, u = w = 0.5, p = 1, "
+                                        "mu = 0.01, Courant factor 0.4; L2 error of rho at t = 0.05",
+                            "orders": {}}}
     for N in orders:
         errs = []
-        for nx in grids:
+        for nx in I.PAPER_MMS_GRIDS[N]:
+            w = I.paper_mms(N, nx)
+            m, ns = _run_to(w, "paper_mms", w["t_end"])
+            errs.append({"nx": nx, "steps": ns, "l2_rho": _l2_rho_error(m, "paper_mms", w["t_end"], nx, 10.0)})
+        eoc = [math.log2(errs[k]["l2_rho"] / errs[k + 1]["l2_rho"]) for k in range(len(errs) - 1)]
+        out["paper_mms"]["orders"][str(N)] = {"errors": errs, "eoc": eoc}
+    for N in orders:
+        errs = []
+        for nx in (9, 18, 36):
             w = I.mms_small(N=N, nx=nx)
             w["phys"]["cfl"] = 0.4
-            m = adg.Mesh(w["phys"], w["mesh"], fixed_dt=True)
-            m.init_state("mms")
-            m.compute_dt()
-            ns = int(math.ceil(T / m.dt))
-            m.set_state(m.Q.clone(), t=0.0, dt=T / ns)
-            for _ in range(ns):
-                m.step()
-            ex = adg.Mesh(w["phys"], w["mesh"])
-            ex.init_state("mms", t0=T)
-            wq = torch.as_tensor(m.basis()["w"], dtype=torch.float64, device="cuda")
-            W = torch.outer(wq, wq) / nx ** 2
-            e = float(torch.sqrt(torch.sum(W[None] * (m.Q[:, 0] - ex.Q[:, 0]) ** 2)))
-            errs.append({"nx": nx, "steps": ns, "l2_rho": e})
+            m, ns = _run_to(w, "mms", 0.05)
+            errs.append({"nx": nx, "steps": ns, "l2_rho": _l2_rho_error(m, "mms", 0.05, nx, 1.0)})
         eoc = [math.log2(errs[k]["l2_rho"] / errs[k + 1]["l2_rho"]) for k in range(len(errs) - 1)]
-        out["orders"][str(N)] = {"errors": errs, "eoc": eoc}
+        out["density_wave"]["orders"][str(N)] = {"errors": errs, "eoc": eoc}
     # throughput of the small workload: 9x9 cells, N = 2, 10 steps
     w = I.mms_small(N=2, nx=9)
     m = adg.Mesh(w["phys"], w["mesh"])

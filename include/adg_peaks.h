@@ -33,6 +33,15 @@ int adg_peaks_sink_bytes(size_t* bytes);
  * Synchronises the stream.  EINVAL on null or misaligned arguments. */
 int adg_measure_peaks(void* sink, const void* src, void* dst, size_t copy_bytes, double* out, void* stream);
 
+/* Whether FP64 matrix cores add to the FP64 vector rate: chains of
+ * v_mfma_f64_4x4x4 (512 flops each) on every wave; chains of vector FMAs on
+ * every wave; then half the waves of each workgroup on each.  out (host,
+ * 5 doubles) = (MFMA TFLOP/s alone, FMA TFLOP/s alone, combined TFLOP/s of
+ * the half-and-half run, its MFMA part, its FMA part): a combined rate near
+ * the larger single rate means the two share the FP64 units, near their sum
+ * that they add.  sink as for adg_measure_peaks.  Synchronises the stream. */
+int adg_measure_fp64_sharing(void* sink, double* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

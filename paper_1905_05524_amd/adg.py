@@ -34,7 +34,7 @@ EXPORTED = [
     "adg_fv_init", "adg_fv_destroy", "adg_fv_info", "adg_fv_workspace_bytes", "adg_fv_set_state",
     "adg_fv_init_state", "adg_fv_compute_dt", "adg_fv_predictor", "adg_fv_corrector", "adg_fv_step",
     "adg_fv_check_health",
-    "adg_peaks_sink_bytes", "adg_measure_peaks",
+    "adg_peaks_sink_bytes", "adg_measure_peaks", "adg_measure_fp64_sharing",
 ]
 
 
@@ -156,6 +156,7 @@ def lib():
             getattr(L, name).argtypes = [vp, vp]
         L.adg_peaks_sink_bytes.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
         L.adg_measure_peaks.argtypes = [vp, vp, vp, ctypes.c_size_t, dp, vp]
+        L.adg_measure_fp64_sharing.argtypes = [vp, dp, vp]
         _lib = L
     return _lib
 
@@ -689,8 +690,12 @@ def measure_peaks(copy_mib: int = 1024, stream=None) -> dict:
                                    ctypes.c_void_p(dst.data_ptr()), n * 8, out, _stream_ptr(stream)))
     if not torch.equal(src[:1024], dst[:1024]) or not torch.equal(src[-1024:], dst[-1024:]):
         raise AdgError(ADG_ESTATE, "peak copy produced wrong data")
+    sh = (ctypes.c_double * 5)()
+    _check(lib().adg_measure_fp64_sharing(ctypes.c_void_p(sink.data_ptr()), sh, _stream_ptr(stream)))
     pr = torch.cuda.get_device_properties(torch.cuda.current_device())
-    return {"fp64_vector_tflops": out[0], "fp64_vector_tflops_spec": 78.6,
+    return {"fp64_sharing": {"mfma_4x4x4_tflops": sh[0], "fma_tflops": sh[1], "half_and_half_tflops": sh[2],
+                             "half_and_half_mfma_part": sh[3], "half_and_half_fma_part": sh[4]},
+            "fp64_vector_tflops": out[0], "fp64_vector_tflops_spec": 78.6,
             "fp64_mfma_tflops": out[1], "fp64_mfma_tflops_spec": 78.6,
             "copy_GBps": out[2], "hbm_GBps_spec": 8000.0, "copy_bytes": n * 8,
             "device": {"name": pr.name, "arch": getattr(pr, "gcnArchName", ""),

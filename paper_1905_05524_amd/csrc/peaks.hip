@@ -45,6 +45,38 @@ __global__ __launch_bounds__(kPeakThreads) void k_peak_mfma(double* sink, double
   sink[(size_t)blockIdx.x * kPeakThreads + threadIdx.x] = s;
 }
 
+// FP64 matrix cores beside the FP64 vector units: the waves of a workgroup
+// below mfma_waves run chains of v_mfma_f64_4x4x4 (512 flops each), the
+// others chains of vector FMAs, each side sized to take about as long alone
+// (four MFMA chains of kMfmaIters steps; eight FMA chains of 4 kMfmaIters).
+__global__ __launch_bounds__(kPeakThreads) void k_peak_share(double* sink, double a, double b, int mfma_waves) {
+  const int wave = threadIdx.x / kWave;
+  double s = 0.0;
+  if (wave < mfma_waves) {
+    double acc[kMfmaChains];
+#pragma unroll
+    for (int c = 0; c < kMfmaChains; ++c) acc[c] = 0.0;
+    const double av = a * (1 + threadIdx.x % 4), bv = b * (1 + threadIdx.x % 3);
+    for (int i = 0; i < kMfmaIters; ++i) {
+#pragma unroll
+      for (int c = 0; c < kMfmaChains; ++c) acc[c] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, bv, acc[c], 0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < kMfmaChains; ++c) s += acc[c];
+  } else {
+    double x[kFmaChains];
+#pragma unroll
+    for (int c = 0; c < kFmaChains; ++c) x[c] = a * (c + 1 + threadIdx.x % 7);
+    for (int i = 0; i < 4 * kMfmaIters; ++i) {
+#pragma unroll
+      for (int c = 0; c < kFmaChains; ++c) x[c] = fma(x[c], 0.999999, b);
+    }
+#pragma unroll
+    for (int c = 0; c < kFmaChains; ++c) s += x[c];
+  }
+  sink[(size_t)blockIdx.x * kPeakThreads + threadIdx.x] = s;
+}
+
 // dst <- src, 16-byte words, four per thread and round with the loads issued together
 __global__ __launch_bounds__(kPeakThreads) void k_peak_copy(const double2* __restrict__ src, double2* __restrict__ dst,
                                                             size_t n2) {
@@ -98,6 +130,32 @@ extern "C" {
 int adg_peaks_sink_bytes(size_t* bytes) {
   if (!bytes) return fail(ADG_EINVAL, "null argument");
   *bytes = sizeof(double) * (size_t)kPeakBlocks * kPeakThreads;
+  return ADG_OK;
+}
+
+int adg_measure_fp64_sharing(void* sink, double* out, void* stream) {
+  if (!sink || !out) return fail(ADG_EINVAL, "null argument");
+  if (((uintptr_t)sink & 7) != 0) return fail(ADG_EINVAL, "misaligned sink");
+  hipStream_t s = (hipStream_t)stream;
+  double* sk = static_cast<double*>(sink);
+  const int waves_per_block = kPeakThreads / kWave;
+  const double blocks = kPeakBlocks;
+  const double mfma_flops = 512.0 * kMfmaChains * kMfmaIters;                   // per wave
+  const double fma_flops = 2.0 * kFmaChains * 4.0 * kMfmaIters * kWave;         // per wave
+  double ms = 0.0;
+  // MFMA on every wave, then FMA on every wave, then half and half
+  const int split[3] = {waves_per_block, 0, waves_per_block / 2};
+  for (int k = 0; k < 3; ++k) {
+    int rc = best_ms(s, [&] {
+      hipLaunchKernelGGL(k_peak_share, dim3(kPeakBlocks), dim3(kPeakThreads), 0, s, sk, 1e-3, 2e-3, split[k]);
+    }, ms);
+    if (rc) return rc;
+    const double mw = blocks * split[k], vw = blocks * (waves_per_block - split[k]);
+    const double secs = ms * 1e-3;
+    if (k == 0) out[0] = mfma_flops * mw / secs / 1e12;
+    if (k == 1) out[1] = fma_flops * vw / secs / 1e12;
+    if (k == 2) { out[3] = mfma_flops * mw / secs / 1e12; out[4] = fma_flops * vw / secs / 1e12; out[2] = out[3] + out[4]; }
+  }
   return ADG_OK;
 }
 

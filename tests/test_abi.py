@@ -18,7 +18,7 @@ def header_functions():
         if h.endswith(".h"):
             src = open(os.path.join(ROOT, "include", h)).read()
             src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-            names |= set(re.findall(r"\b(adg3?_[a-z_]+)\s*\(", src))
+            names |= set(re.findall(r"\b(adg3?_[a-z0-9_]+)\s*\(", src))
     return sorted(names)
 
 
