@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_PKG, "libadg.so")
 ADG_OK, ADG_EINVAL, ADG_ENOMEM, ADG_EHIP, ADG_ESTATE, ADG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 ADG_BC_PERIODIC, ADG_BC_WALL = 0, 1
 ADG_VAR_THETA, ADG_VAR_RHO = 0, 1
+ADG_BATCH_PER_ORDER, ADG_BATCH_PERSISTENT = 0, 1
 
 EXPORTED = [
     "adg_init_mesh", "adg_destroy", "adg_mesh_info", "adg_workspace_bytes", "adg_set_state",

@@ -31,6 +31,23 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(adg.EXPORTED)
 
 
+def test_binding_constants_match_header_enums():
+    """Every enumerator of include/*.h has the binding's value (inputs.py for
+    the bubble shapes), so a constant dropped from the binding fails here."""
+    found = {}
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", h)).read(), flags=re.S)
+            for body in re.findall(r"enum\s*\{(.*?)\}", src, flags=re.S):
+                for name, val in re.findall(r"(ADG\w+)\s*=\s*(-?\d+)", body):
+                    found[name] = int(val)
+    assert len(found) >= 13
+    for name, val in found.items():
+        src = I if name.startswith("ADG_SHAPE_") else adg
+        attr = name[len("ADG_"):] if src is I else name
+        assert getattr(src, attr) == val, name
+
+
 def _init(phys, mesh):
     p = adg.make_params(phys)
     d = adg.adg_mesh_desc()
