@@ -331,7 +331,11 @@ int adg_batch_set_launch(adg_batch* b, int group, int cells_per_wave, int waves_
  * of resident wavefronts that take work items (one wavefront's cells) from
  * a device counter (reset by the grid's last wavefront), each order's grid
  * sized by its share of the modelled predictor work (cells x (N+1)^4).
- * Results are identical; the persistent mode measured slower (its loop
+ * Its bits are those of the per-order mode with one wavefront per cell
+ * (adg_batch_set_launch with cells_per_wave >= 1); a group that the
+ * per-order mode runs with one wavefront per time level (small groups, by
+ * default) sums the levels in another order and agrees to rounding.  The
+ * persistent mode measured slower (its loop
  * around the order-6 body spills registers) and exists for comparison.
  * Drops a captured graph; EUNSUPPORTED for the paper's manufactured
  * solution in persistent mode. */

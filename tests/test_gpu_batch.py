@@ -206,9 +206,11 @@ def test_batch_graph_replay_equals_eager():
 @pytest.mark.parametrize("mixed", [False, True])
 def test_persistent_mode_equals_per_order_launches(mixed):
     """The persistent work-counter predictor (one resident grid per order,
-    items from a device counter) gives the bits of the per-order launches,
-    over several graph replays (the counters reset themselves between
-    launches), also with a scenario on a 1:3 mesh."""
+    items from a device counter) gives the bits of the per-order launches
+    with one wavefront per cell, over several graph replays (the counters
+    reset themselves between launches), also with a scenario on a 1:3 mesh.
+    (The small groups here default to one wavefront per time level, which
+    sums in another order: the per-order side is set to per-cell launches.)"""
     ws = _small_batch()
     if mixed:
         ws[1]["mesh"] = dict(I.bubble(6, ws[1]["phys"]["N"])["mesh"], max_level=1,
@@ -218,6 +220,8 @@ def test_persistent_mode_equals_per_order_launches(mixed):
         for s, w in enumerate(ws):
             bb.init_state(s, "bubbles", w["bubbles"])
         bb.compute_dt()
+    for g in range(a.n_groups):
+        a.set_launch(g, 1, 1)
     b.set_mode(adg.ADG_BATCH_PERSISTENT)
     stream = torch.cuda.Stream()
     for k in range(4):
