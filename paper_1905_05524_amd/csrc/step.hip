@@ -405,10 +405,14 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
   {
     EOTab<n> Wt;
     load_eo<n>(gt + GTab::eo_dw(n), Wt);
+    // the line-job roles are derived again from the lane (hidden from the
+    // compiler) instead of being held in registers through the sweeps
+    int lane_r = lane;
+    asm volatile("" : "+v"(lane_r));
 #pragma unroll
     for (int r = 0; r < L::rounds; ++r) {
-      const LineJob<n>& J = r == 0 ? J0 : J1;
-      double* jl = r == 0 ? jl0 : jl1;
+      const LineJob<n> J(lane_r + r * kWave, CPW);
+      double* jl = wl + (J.active ? J.slot : 0) * L::pred_cell;
       if (!J.active) continue;
       const int cj = cell0 + J.slot;
       double q0 = 0, q1 = 0, f0 = 0, f1 = 0;
@@ -461,7 +465,9 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
 
 template <int n, int CPW, int WPB, bool PW = false>
 __global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phys ph, StepArgs a) {
-  const int wave = threadIdx.x / kWave;
+  // with several wavefronts per workgroup the index is made wave-uniform
+  // (scalar), which keeps the cell-level values out of vector registers
+  const int wave = WPB == 1 ? (int)(threadIdx.x / kWave) : __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   predictor_wave<n, CPW, PW>(ph, a, wave, (blockIdx.x * WPB + wave) * CPW);
 }
 
