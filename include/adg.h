@@ -226,13 +226,17 @@ int adg_regrid_apply(adg_mesh* m, double* Q_new, void* workspace_new, double* cl
 
 /* Launch shape of the predictor and corrector: cells per wavefront (1, 2 or
  * 4, with cells_per_wave * n^2 <= 64) and wavefronts per workgroup (1, 2 or
- * 4); cells_per_wave 0 (with waves_per_block 1) selects the predictor that
- * runs one workgroup of n wavefronts per cell, one per time level of the
- * Picard sweeps, for meshes too small to fill the GPU with one wavefront per
- * cell.  Results do not depend on the shape (up to the order of sums).
+ * 4); cells_per_wave 0 selects the time-level predictor, for meshes too
+ * small to fill the GPU with one wavefront per cell: one workgroup per cell
+ * whose wavefronts share the time levels of the Picard sweeps, one
+ * wavefront per level (waves_per_block 1) or the levels spread over 2 or 4
+ * wavefronts (waves_per_block 2 or 4; with n or fewer levels the same as 1).
+ * Results do not depend on the shape (up to the order of sums).
  * Default: one wavefront per time level while n_cells * (order + 1) <= 3072
- * (about three wavefronts per SIMD), else 1, 1.
- * adg_autotune reports the time-level predictor as cells_per_wave 0. */
+ * (about three wavefronts per SIMD), else (order >= 4) the levels over four
+ * wavefronts while n_cells * 4 <= 3072, else 1, 1.
+ * adg_autotune reports the time-level predictor as cells_per_wave 0 with its
+ * waves_per_block as above. */
 int adg_set_launch(adg_mesh* m, int cells_per_wave, int waves_per_block);
 
 /* Time every launch shape on the bound state (reps predictor + corrector

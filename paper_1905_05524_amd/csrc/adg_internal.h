@@ -98,11 +98,18 @@ struct Group {
   double* clock = nullptr;    // [S][4]
   // launch shape: cells per wavefront, wavefronts per workgroup
   int cpw = 1, wpb = 1;
-  // predictor kernel: -1 automatic (one wavefront per time level while
-  // cells * n <= kLevelsWaves), 0 one wavefront per cell, 1 one per time level
+  // predictor kernel: -1 automatic (the time-level predictor while cells * n
+  // <= kLevelsWaves, or over four wavefronts per cell while cells * 4 <=
+  // kLevelsWaves), 0 one wavefront per cell, 1 the time-level predictor
   int lv = -1;
+  // wavefronts per cell of the time-level predictor: 2 or 4 spread the n
+  // time nodes over that many wavefronts (when fewer than n), else n
+  int lw = 0;
   int nc = 0;                 // the mesh has 1:3 non-conforming faces
 };
+
+// wavefronts per cell the time-level predictor of g launches
+inline int level_waves(const Group& g) { return (g.lw == 2 || g.lw == 4) && g.lw < g.n ? g.lw : g.n; }
 
 // Host copies of the basis of one order.
 struct HostBasis {

@@ -36,13 +36,22 @@ int regrid_plan(const std::vector<int>& lev, const std::vector<int>& ci, const s
 
 static thread_local std::string g_err;
 
-// Predictor of a group with the kernel its launch mode selects: one
-// wavefront per time level (lv = 1, or automatic while cells * n <= kLevelsWaves),
-// else one wavefront per cell with the group's launch shape; with a store,
-// the Picard iterates are kept (adjoint).
+// Predictor of a group with the kernel its launch mode selects: the
+// time-level predictor (lv = 1 with the group's wavefronts per cell), or
+// automatically one wavefront per time level while cells * n <= kLevelsWaves,
+// the levels over four wavefronts per cell while cells * 4 <= kLevelsWaves
+// (n > 4), else one wavefront per cell with the group's launch shape; with a
+// store, the Picard iterates are kept (adjoint).
 int launch_predictor_any(const Group& g, double* store, hipStream_t s) {
-  const bool levels = g.lv == 1 || (g.lv < 0 && (long)g.C * g.n <= kLevelsWaves);
-  if (levels) return launch_predictor_levels(g, store, s);
+  if (g.lv == 1) return launch_predictor_levels(g, store, s);
+  if (g.lv < 0) {
+    const long cn = (long)g.C * g.n;
+    if (cn <= kLevelsWaves || (g.n > 4 && 4L * g.C <= kLevelsWaves)) {
+      Group t = g;
+      t.lw = cn <= kLevelsWaves ? 0 : 4;
+      return launch_predictor_levels(t, store, s);
+    }
+  }
   return store ? launch_predictor_store(g, store, s) : launch_predictor(g, s);
 }
 
@@ -452,15 +461,17 @@ static int autotune_group(Group& g, hipStream_t s, int reps, float* best_ms) {
   if (g.C == 0) return ADG_OK;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(ADG_EHIP, "event");
-  // candidates: (lv, cpw, wpb); lv = 1 is the one-wavefront-per-time-level
-  // predictor (its corrector shape is the default one)
-  const int cpws[3] = {1, 2, 4}, wpbs[3] = {1, 2, 4};
-  int bl = g.lv, bc = g.cpw, bw = g.wpb;
+  // candidates: (lv, lw, cpw, wpb); lv = 1 is the time-level predictor with
+  // lw = n, 2 or 4 wavefronts per cell (its corrector shape is the default one)
+  const int cpws[3] = {1, 2, 4}, wpbs[3] = {1, 2, 4}, lws[3] = {0, 2, 4};
+  int bl = g.lv, blw = g.lw, bc = g.cpw, bw = g.wpb;
   float best = 1e30f;
-  for (int k = -1; k < 9; ++k) {
+  for (int k = -3; k < 9; ++k) {
     Group t = g;
-    if (k < 0) { t.lv = 1; t.cpw = 1; t.wpb = 1; }
-    else {
+    if (k < 0) {
+      t.lv = 1; t.lw = lws[k + 3]; t.cpw = 1; t.wpb = 1;
+      if (t.lw && t.lw >= g.n) continue;   // the same kernel as lw = n
+    } else {
       t.lv = 0; t.cpw = cpws[k / 3]; t.wpb = wpbs[k % 3];
       if (t.cpw > max_cpw(g.n)) continue;
     }
@@ -478,11 +489,11 @@ static int autotune_group(Group& g, hipStream_t s, int reps, float* best_ms) {
     (void)hipEventSynchronize(e1);
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best) { best = ms; bl = t.lv; bc = t.cpw; bw = t.wpb; }
+    if (ms < best) { best = ms; bl = t.lv; blw = t.lw; bc = t.cpw; bw = t.wpb; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  g.lv = bl; g.cpw = bc; g.wpb = bw;
+  g.lv = bl; g.lw = blw; g.cpw = bc; g.wpb = bw;
   if (best_ms) *best_ms = best / reps;
   return check_launch("autotune");
 }
@@ -883,9 +894,10 @@ int adg_loss_theta_adjoint(adg_mesh* m, const double* loss, const double* grad_l
 
 int adg_set_launch(adg_mesh* m, int cells_per_wave, int waves_per_block) {
   if (!m) return fail(ADG_EINVAL, "null handle");
-  if (cells_per_wave == 0) {   // predictor with one wavefront per time level
-    if (waves_per_block != 1) return fail(ADG_EINVAL, "waves_per_block must be 1 with cells_per_wave 0");
-    m->g.lv = 1; m->g.cpw = 1; m->g.wpb = 1;
+  if (cells_per_wave == 0) {   // time-level predictor: n (1), 2 or 4 wavefronts per cell
+    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+      return fail(ADG_EINVAL, "waves_per_block must be 1, 2 or 4 with cells_per_wave 0");
+    m->g.lv = 1; m->g.lw = waves_per_block == 1 ? 0 : waves_per_block; m->g.cpw = 1; m->g.wpb = 1;
     return ADG_OK;
   }
   if ((cells_per_wave != 1 && cells_per_wave != 2 && cells_per_wave != 4) || cells_per_wave > max_cpw(m->g.n))
@@ -903,7 +915,7 @@ int adg_autotune(adg_mesh* m, int reps, void* stream, int* cells_per_wave, int* 
   rc = autotune_group(m->g, (hipStream_t)stream, reps, nullptr);
   if (rc) return rc;
   if (cells_per_wave) *cells_per_wave = m->g.lv == 1 ? 0 : m->g.cpw;
-  if (waves_per_block) *waves_per_block = m->g.wpb;
+  if (waves_per_block) *waves_per_block = m->g.lv == 1 ? (level_waves(m->g) == m->g.n ? 1 : m->g.lw) : m->g.wpb;
   return ADG_OK;
 }
 
@@ -1206,7 +1218,10 @@ int adg_batch_autotune(adg_batch* b, int reps, void* stream, int* cells_per_wave
     rc = autotune_group(b->groups[gi], (hipStream_t)stream, reps, nullptr);
     if (rc) return rc;
     if (cells_per_wave) cells_per_wave[gi] = b->groups[gi].lv == 1 ? 0 : b->groups[gi].cpw;
-    if (waves_per_block) waves_per_block[gi] = b->groups[gi].wpb;
+    if (waves_per_block) {
+      const Group& gg = b->groups[gi];
+      waves_per_block[gi] = gg.lv == 1 ? (level_waves(gg) == gg.n ? 1 : gg.lw) : gg.wpb;
+    }
   }
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
@@ -1254,9 +1269,10 @@ int adg_batch_set_launch(adg_batch* b, int group, int cells_per_wave, int waves_
   if (!b) return fail(ADG_EINVAL, "null batch");
   if (group < 0 || group >= (int)b->groups.size()) return fail(ADG_EINVAL, "group out of range");
   Group& g = b->groups[group];
-  if (cells_per_wave == 0) {   // predictor with one wavefront per time level
-    if (waves_per_block != 1) return fail(ADG_EINVAL, "waves_per_block must be 1 with cells_per_wave 0");
-    g.lv = 1; g.cpw = 1; g.wpb = 1;
+  if (cells_per_wave == 0) {   // time-level predictor: n (1), 2 or 4 wavefronts per cell
+    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+      return fail(ADG_EINVAL, "waves_per_block must be 1, 2 or 4 with cells_per_wave 0");
+    g.lv = 1; g.lw = waves_per_block == 1 ? 0 : waves_per_block; g.cpw = 1; g.wpb = 1;
   } else {
     if ((cells_per_wave != 1 && cells_per_wave != 2 && cells_per_wave != 4) || cells_per_wave > max_cpw(g.n))
       return fail(ADG_EINVAL, "cells_per_wave must be 0, 1, 2 or 4 with cells_per_wave * n^2 <= 64");

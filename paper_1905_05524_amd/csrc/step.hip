@@ -471,29 +471,37 @@ __global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phy
   predictor_wave<n, CPW, PW>(ph, a, wave, (blockIdx.x * WPB + wave) * CPW);
 }
 
-// ------------------------------------------- predictor, a wavefront per level
+// ------------------------------------------- predictor, wavefronts per level
 // For meshes too small to fill the chip with one wavefront per cell: one
-// workgroup of n wavefronts per cell, wavefront b owning time node b.  Each
-// wavefront runs the slice machinery of k_predictor (line jobs on both LDS
-// layouts, even-odd contractions) on its own time node, in its own LDS
-// region of 4 slices.  Within a Picard sweep the n residuals are independent;
-// they meet in LDS, where the time matrix mixes them: X_b = Q + dt sum_a
-// P[b][a] R_a.  The first sweep evaluates one residual (every node starts
-// from Q^n).  In the final pass every wavefront leaves its node's weighted
-// state, fluxes and sources in its region; the first wavefront sums them in
-// a fixed order and runs the epilogue of k_predictor (volume term, Q*, face
-// data).  Same arithmetic as k_predictor up to the order of the sums.
-template <int n, bool PW = false>
-__global__ __launch_bounds__(kWave * n) void k_predictor_lv(Phys ph, StepArgs a) {
+// workgroup of W wavefronts per cell, wavefront w owning the time nodes
+// w, w + W, ... (W = n: one wavefront per time node).  Each wavefront runs
+// the slice machinery of k_predictor (line jobs on both LDS layouts,
+// even-odd contractions) on its time nodes one after the other, in its own
+// LDS region of 4 slices.  Within a Picard sweep the n residuals are
+// independent; they meet in a shared LDS area, where the time matrix mixes
+// them: X_b = Q + dt sum_a P[b][a] R_a (with one wavefront per node each
+// residual sits in its wavefront's region, else in an area of its own).  The
+// first sweep evaluates one residual (every node starts from Q^n).  In the
+// final pass every wavefront
+// leaves the weighted sum of its nodes' state, fluxes and sources in its
+// region; the first wavefront sums the W regions in order and runs the
+// epilogue of k_predictor (volume term, Q*, face data).  Same arithmetic as
+// k_predictor up to the order of the sums.
+template <int n, int W, bool PW>
+__device__ __forceinline__ void predictor_levels(Phys ph, StepArgs a, int c) {
   using L = Lay<n, 1>;
   constexpr int nn = L::nn, sl = L::sl, T = L::T, F0 = L::F0, WR = 4 * sl;
-  extern __shared__ double lds[];                 // n regions of WR doubles
-  const int c = blockIdx.x, b = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  double* wl = lds + (size_t)b * WR;
+  constexpr int NL = (n + W - 1) / W;             // time nodes per wavefront (the last may own fewer)
+  extern __shared__ double lds[];                 // W regions of WR doubles, then (W < n) the residuals [n][sl]
+  // the wavefront index is wave-uniform: scalar, so are its time-node tables
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+  double* wl = lds + (size_t)w * WR;
+  // residual of time node b: the transposed slice of its region (W = n), or [b][sl] after the regions
+  auto res = [&](int b) { return W == n ? lds + (size_t)b * WR + T : lds + (size_t)W * WR + (size_t)b * sl; };
   const bool node = lane < nn;
   const int l = node ? lane : 0;
   const int jz = l / n, ix = l % n, tl = ix * n + jz;
-  double* sq = wl;          // slice, both layouts; later the residual (offset T)
+  double* sq = wl;          // slice, both layouts
   double* sf = wl + F0;     // gradients / fluxes, both layouts
   const double* gt = a.gtab;
   const int s = a.scen ? a.scen[c] : 0;
@@ -507,17 +515,27 @@ __global__ __launch_bounds__(kWave * n) void k_predictor_lv(Phys ph, StepArgs a)
   EOTab<n> Dt;
   load_eo<n>(gt + GTab::eo_d(n), Dt);
   const double* Qc = a.Qin + (size_t)c * sl + l;
-  double X[4];
+  double X[NL][4];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) X[v] = Qc[v * nn];
-  // manufactured source at this node and level's time (it does not depend on
-  // the state): the density wave's energy source, or the paper's wave's
-  // source of every variable
-  const double SE = (!PW && ph.mms && node) ? mms_source(ph, x0 + h * gt[GTab::XI * n + ix], z,
-                                                            t0 + gt[GTab::XI * n + b] * dt) : 0.0;
-  double Sm[4] = {0.0, 0.0, 0.0, 0.0};
-  if constexpr (PW) {
-    if (node) paper_wave_source(ph, x0 + h * gt[GTab::XI * n + ix], z, t0 + gt[GTab::XI * n + b] * dt, Sm);
+  for (int v = 0; v < 4; ++v) {
+    const double q = Qc[v * nn];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) X[k][v] = q;
+  }
+  // manufactured source at this node and each owned level's time (it does
+  // not depend on the state): the density wave's energy source, or the
+  // paper's wave's source of every variable
+  double SE[NL], Sm[NL][4];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int b = w + k * W;
+    SE[k] = (!PW && ph.mms && node && b < n) ? mms_source(ph, x0 + h * gt[GTab::XI * n + ix], z,
+                                                          t0 + gt[GTab::XI * n + b] * dt) : 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Sm[k][v] = 0.0;
+    if constexpr (PW) {
+      if (node && b < n) paper_wave_source(ph, x0 + h * gt[GTab::XI * n + ix], z, t0 + gt[GTab::XI * n + b] * dt, Sm[k]);
+    }
   }
 
   const LineJob<n> J(lane, 1);
@@ -548,91 +566,127 @@ __global__ __launch_bounds__(kWave * n) void k_predictor_lv(Phys ph, StepArgs a)
     for (int v = 0; v < 4; ++v) R[v] = node ? sf[v * nn + l] + sf[T + v * nn + tl] : 0.0;
     R[2] = fma(-h, Sw, R[2]);
   };
+  // the manufactured source of owned level k added, to the shared area
+  auto put_residual = [&](int k, double R[4]) {
+    const int b = w + k * W;
+    if (node) {
+      if (!PW && ph.mms) R[3] = fma(-h, SE[k], R[3]);
+      if constexpr (PW) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) R[v] = fma(-h, Sm[k][v], R[v]);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) res(b)[v * nn + l] = R[v];
+    }
+  };
 
 #pragma unroll 1
   for (int it = 0; it < a.iters; ++it) {
-    double R[4];
     if (it == 0) {
       // every node starts from Q^n: the first wavefront's residual serves all
-      if (b == 0) {
-        residual(X, R);
+      if (w == 0) {
+        double R[4];
+        residual(X[0], R);
         if (node)
 #pragma unroll
           for (int v = 0; v < 4; ++v) sq[v * nn + l] = R[v];
       }
       __syncthreads();
-      if (node)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) R[v] = lds[v * nn + l];
-    } else {
-      residual(X, R);
-    }
-    if (node) {
-      if (!PW && ph.mms) R[3] = fma(-h, SE, R[3]);
-      if constexpr (PW) {
+      for (int k = 0; k < NL; ++k) {
+        if (w + k * W >= n) break;
+        double R[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) R[v] = fma(-h, Sm[v], R[v]);
+        for (int v = 0; v < 4; ++v) R[v] = node ? lds[v * nn + l] : 0.0;
+        put_residual(k, R);
       }
+    } else {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) sq[T + v * nn + l] = R[v];
+      for (int k = 0; k < NL; ++k) {
+        if (w + k * W >= n) break;
+        double R[4];
+        residual(X[k], R);
+        put_residual(k, R);
+        wave_sync();
+      }
     }
     __syncthreads();   // every node's residual in LDS
     if (node) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        double acc = 0.0;
+      for (int k = 0; k < NL; ++k) {
+        const int b = w + k * W;
+        if (b >= n) break;
 #pragma unroll
-        for (int a2 = 0; a2 < n; ++a2) acc = fma(gt[GTab::pt(n) + a2 * n + b], lds[(size_t)a2 * WR + T + v * nn + l], acc);
-        X[v] = fma(sdt, acc, Qc[v * nn]);
-      }
-      if (a.iter_store) {
-        double* st = a.iter_store + (((size_t)c * a.iters + it) * n + b) * sl;
+        for (int v = 0; v < 4; ++v) {
+          double acc = 0.0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) st[v * nn + l] = X[v];
+          for (int a2 = 0; a2 < n; ++a2) acc = fma(gt[GTab::pt(n) + a2 * n + b], res(a2)[v * nn + l], acc);
+          X[k][v] = fma(sdt, acc, Qc[v * nn]);
+        }
+        if (a.iter_store) {
+          double* st = a.iter_store + (((size_t)c * a.iters + it) * n + b) * sl;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) st[v * nn + l] = X[k][v];
+        }
       }
     }
-    __syncthreads();   // every residual read before the next sweep overwrites them
+    __syncthreads();   // every residual read (and the first sweep's shared one) before the next sweep
   }
 
-  // final pass: this node's flux and sources at the last iterate, weighted,
-  // to its region as [state | x flux | z flux | vertical-momentum source |
-  // energy source | mass source | horizontal-momentum source]
-  put_slice(X);
-  wave_sync();
-  lines(0, F0);
-  wave_sync();
-  {
+  // final pass: the owned nodes' fluxes and sources at the last iterate,
+  // weighted and summed, to this wavefront's region as [state | x flux |
+  // z flux | vertical-momentum source | energy source | mass source |
+  // horizontal-momentum source]
+  double Qw[4], Fxw[4], Fzw[4], Sww = 0.0, SEw = 0.0, S0w = 0.0, S1w = 0.0;
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int b = w + k * W;
+    if (b >= n) break;
+    put_slice(X[k]);
+    wave_sync();
+    lines(0, F0);
+    wave_sync();
     double Fx[4], Fz[4], Sw = 0.0;
-    if (node) Sw = node_flux<n>(ph, X, sf, l, tl, mu_h, kappa_h, gh, z, rb, pb, Fx, Fz, false);
+    if (node) Sw = node_flux<n>(ph, X[k], sf, l, tl, mu_h, kappa_h, gh, z, rb, pb, Fx, Fz, false);
     wave_sync();
     const double wb = gt[GTab::W * n + b];
-    if (node) {
+    const double s2 = PW ? Sw + Sm[k][2] : Sw, s3 = PW ? Sm[k][3] : SE[k];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        wl[v * nn + l] = wb * X[v];
-        wl[(4 + v) * nn + l] = wb * Fx[v];
-        wl[(8 + v) * nn + l] = wb * Fz[v];
-      }
-      if constexpr (PW) {
-        wl[12 * nn + l] = wb * (Sw + Sm[2]);
-        wl[13 * nn + l] = wb * Sm[3];
-        wl[14 * nn + l] = wb * Sm[0];
-        wl[15 * nn + l] = wb * Sm[1];
-      } else {
-        wl[12 * nn + l] = wb * Sw;
-        wl[13 * nn + l] = wb * SE;
-      }
+    for (int v = 0; v < 4; ++v) {
+      Qw[v] = k == 0 ? wb * X[k][v] : fma(wb, X[k][v], Qw[v]);
+      Fxw[v] = k == 0 ? wb * Fx[v] : fma(wb, Fx[v], Fxw[v]);
+      Fzw[v] = k == 0 ? wb * Fz[v] : fma(wb, Fz[v], Fzw[v]);
+    }
+    Sww = k == 0 ? wb * s2 : fma(wb, s2, Sww);
+    SEw = k == 0 ? wb * s3 : fma(wb, s3, SEw);
+    if constexpr (PW) {
+      S0w = k == 0 ? wb * Sm[k][0] : fma(wb, Sm[k][0], S0w);
+      S1w = k == 0 ? wb * Sm[k][1] : fma(wb, Sm[k][1], S1w);
+    }
+  }
+  if (node) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      wl[v * nn + l] = Qw[v];
+      wl[(4 + v) * nn + l] = Fxw[v];
+      wl[(8 + v) * nn + l] = Fzw[v];
+    }
+    wl[12 * nn + l] = Sww;
+    wl[13 * nn + l] = SEw;
+    if constexpr (PW) {
+      wl[14 * nn + l] = S0w;
+      wl[15 * nn + l] = S1w;
     }
   }
   __syncthreads();
-  if (b != 0) return;
+  if (w != 0) return;
 
-  // level sums in a fixed order, then the epilogue of k_predictor
+  // sums over the wavefronts in a fixed order, then the epilogue of k_predictor
   double Qb[4] = {0, 0, 0, 0}, Fbx[4] = {0, 0, 0, 0}, Fbz[4] = {0, 0, 0, 0}, Sbw = 0.0, SbE = 0.0;
   double Sb0 = 0.0, Sb1 = 0.0;   // paper's wave only
   if (node) {
 #pragma unroll
-    for (int k = 0; k < n; ++k) {
+    for (int k = 0; k < W; ++k) {
       const double* r = lds + (size_t)k * WR;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -685,6 +739,11 @@ __global__ __launch_bounds__(kWave * n) void k_predictor_lv(Phys ph, StepArgs a)
       qs[v * nn + l] = Qc[v * nn] + dt * ((sf[v * nn + l] + sf[T + v * nn + tl]) * ih + S);
     }
   }
+}
+
+template <int n, int W, bool PW = false>
+__global__ __launch_bounds__(kWave * W, (W < n && n <= 7 ? 3 : 1)) void k_predictor_lv(Phys ph, StepArgs a) {
+  predictor_levels<n, W, PW>(ph, a, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ corrector
@@ -1164,17 +1223,24 @@ static int dt_n(const Group& g, hipStream_t s) {
 
 int launch_predictor(const Group& g, hipStream_t s) { ADG_DISPATCH_N(pred_n, g, s); }
 
+template <int n, int W>
+static void pred_lv_w(const Group& g, const StepArgs& a, hipStream_t s) {
+  using L = Lay<n, 1>;
+  const size_t lds = sizeof(double) * ((size_t)W * 4 * L::sl + (W < n ? (size_t)n * L::sl : 0));
+  if (g.ph.mms == 2)
+    hipLaunchKernelGGL((k_predictor_lv<n, W, true>), dim3(g.C), dim3(kWave * W), lds, s, g.ph, a);
+  else
+    hipLaunchKernelGGL((k_predictor_lv<n, W>), dim3(g.C), dim3(kWave * W), lds, s, g.ph, a);
+}
 template <int n>
 static int pred_lv_n(const Group& g, double* store, hipStream_t s) {
-  using L = Lay<n, 1>;
   if (g.C == 0) return ADG_OK;
   StepArgs a = make_args(g);
   a.iter_store = store;
-  const size_t lds = sizeof(double) * (size_t)n * 4 * L::sl;
-  if (g.ph.mms == 2)
-    hipLaunchKernelGGL((k_predictor_lv<n, true>), dim3(g.C), dim3(kWave * n), lds, s, g.ph, a);
-  else
-    hipLaunchKernelGGL((k_predictor_lv<n>), dim3(g.C), dim3(kWave * n), lds, s, g.ph, a);
+  const int W = level_waves(g);
+  if constexpr (n > 2) { if (W == 2) { pred_lv_w<n, 2>(g, a, s); return check_launch("predictor (levels)"); } }
+  if constexpr (n > 4) { if (W == 4) { pred_lv_w<n, 4>(g, a, s); return check_launch("predictor (levels)"); } }
+  pred_lv_w<n, n>(g, a, s);
   return check_launch("predictor (levels)");
 }
 int launch_predictor_levels(const Group& g, double* store, hipStream_t s) {

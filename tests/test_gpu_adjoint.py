@@ -41,13 +41,14 @@ def _case(kind, N):
     return phys, mesh, I.random_state_cfd(9, N, seed=20 + N)
 
 
-@pytest.mark.parametrize("kernel", [(1, 1), (0, 1)], ids=["cell", "level"])
+@pytest.mark.parametrize("kernel", [(1, 1), (0, 1), (0, 2), (0, 4)], ids=["cell", "level", "level2", "level4"])
 @pytest.mark.parametrize("kind", ["walls", "periodic"])
 @pytest.mark.parametrize("N", [1, 2, 4, 6])
 def test_step_adjoint_dot_product(kind, N, kernel):
     """<J v, w> = <v, J^T w> against the oracle's forward-mode derivative;
-    the forward predictor with the iterate store runs on either kernel (one
-    wavefront per cell, or per time level, the small meshes' default)."""
+    the forward predictor with the iterate store runs on every kernel (one
+    wavefront per cell; one per time level, the small meshes' default; the
+    levels shared by two or four wavefronts)."""
     phys, mesh, Q = _case(kind, N)
     dt = 0.5 * O.dt(phys, mesh, Q)
     rng = np.random.default_rng(100 + N)

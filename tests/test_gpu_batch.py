@@ -64,6 +64,13 @@ def test_launch_shapes_are_bitwise_equal(N):
     ref = O.step(w["phys"], w["mesh"], O.step(w["phys"], w["mesh"], Q, 0.0, dt), dt, dt)
     P.assert_step(lv.cpu().numpy(), ref, Q, what="level kernel")
     P.assert_step(base.cpu().numpy(), ref, Q, what="cell kernel")
+    # the time levels shared by two or four wavefronts: with as many
+    # wavefronts as levels or more, the one-per-level kernel bit for bit
+    for W in (2, 4):
+        got = _run(w, Q, dt, (0, W))
+        if W >= n:
+            assert torch.equal(got, lv), W
+        P.assert_step(got.cpu().numpy(), ref, Q, what=f"levels over {W} wavefronts")
 
 
 def test_invalid_launch_shape_rejected():
@@ -73,6 +80,8 @@ def test_invalid_launch_shape_rejected():
         m.set_launch(2, 1)    # 2 * 49 > 64
     with pytest.raises(adg.AdgError):
         m.set_launch(1, 3)
+    with pytest.raises(adg.AdgError):
+        m.set_launch(0, 3)
 
 
 def test_autotune_keeps_state_and_results():

@@ -53,9 +53,9 @@ def increment_err(got, ref, Q0, state_scale=None):
     return relerr(dgot, dref, scale=sc)
 
 
-# predictor kernels: one wavefront per cell, one wavefront per time level
-# (small meshes take the second by default, so both are named explicitly)
-KERNELS = {"cell": (1, 1), "level": (0, 1)}
+# predictor kernels: one wavefront per cell; one workgroup per cell whose
+# wavefronts own one time level each, or share them two or four ways
+KERNELS = {"cell": (1, 1), "level": (0, 1), "level2": (0, 2), "level4": (0, 4)}
 
 
 def mesh_of(w, kernel=None, **kw):
@@ -173,11 +173,13 @@ def test_step_matches_oracle(kind, nx, N, kernel):
 
 
 
-@pytest.mark.parametrize("nx,nz", [(73, 6), (439, 1)])
+@pytest.mark.parametrize("nx,nz", [(73, 6), (439, 1), (768, 1), (769, 1)])
 def test_automatic_kernel_choice_at_its_threshold(nx, nz):
     """N = 6 with the default launch mode: 438 cells (438 x 7 = 3066
-    wavefronts) take the time-level predictor, 439 cells the one-wavefront-
-    per-cell predictor; both match the oracle over one step."""
+    wavefronts) take the predictor with one wavefront per time level, 439
+    and 768 cells (768 x 4 = 3072) the time levels over four wavefronts, 769
+    cells the one-wavefront-per-cell predictor; all match the oracle over
+    one step."""
     w = cfd_periodic(nx, nz, 6)
     Q = _state(w, seed=3000 + nx)
     dt = 0.5 * O.dt(w["phys"], w["mesh"], Q)
