@@ -281,13 +281,25 @@ def paper_grid_leg(steps=20, warmup=2):
     ms = e0.elapsed_time(e1) / steps
     pred_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
     m.check_health(s)
+    # the TV indicator (TV of theta per cell, statistics, flags) on this grid
+    tv = torch.zeros(m.C, dtype=torch.float64, device="cuda")
+    fl = torch.zeros(m.C, dtype=torch.int8, device="cuda")
+    st = torch.zeros(3, dtype=torch.float64, device="cuda")
+    m.tv_indicator(adg.ADG_VAR_THETA, 1.5, -0.5, tv, fl, st, s)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(s)
+    for _ in range(5):
+        m.tv_indicator(adg.ADG_VAR_THETA, 1.5, -0.5, tv, fl, st, s)
+    t1.record(s)
+    torch.cuda.synchronize()
+    tv_ms = t0.elapsed_time(t1) / 5
     dof = model.dofs(m.C, N)
     pt = model.predictor_flops(N) * m.C / (pred_ms / 1e3) / 1e12
     return {"workload": "colliding729x729_N6: warm plateau and cold bubble, 729x729 cells of 1.37 m, N=6, "
                         "no-slip walls, mu=1e-3, Courant factor 0.4 (the grid of the paper's performance runs)",
             "cells": m.C, "dof": dof, "steps": steps, "ms_per_step": ms,
             "dof_updates_per_s": dof / (ms / 1e3), "predictor_ms": pred_ms, "predictor_tflops": pt,
-            "predictor_fp64_frac": pt / FP64_PEAK_TFLOPS,
+            "predictor_fp64_frac": pt / FP64_PEAK_TFLOPS, "tv_indicator_ms": tv_ms,
             "paper_context": "the paper reports 20.2 MDOF/s on half a CPU node and 137.3 MDOF/s on five nodes "
                              "for this grid (other hardware: context, not a target)"}
 
