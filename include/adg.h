@@ -182,7 +182,9 @@ int adg_step_static(adg_mesh* m, double* Q, double* clock, void* stream);
  * Chan, Golub and LeVeque, and the flags of eq. refinement-criterion:
  * +1 refine if TV >= mu + T_refine sigma, -1 coarsen if TV < mu + T_coarsen
  * sigma, else 0 (sigma == 0 keeps all).  tv: device double[C], flags: device
- * int8[C], stats: device double[3] = (count, mean, sigma). */
+ * int8[C], stats: device double[3] = (count, mean, sigma).  Above 65,536
+ * cells the statistics go through per-workgroup partials in a small
+ * handle-owned buffer: calls on one handle that overlap in time race. */
 int adg_tv_indicator(adg_mesh* m, int var, double T_refine, double T_coarsen, double* tv,
                      int8_t* flags, double* stats, void* stream);
 

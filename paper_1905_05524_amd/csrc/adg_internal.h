@@ -105,8 +105,15 @@ struct Group {
   // wavefronts per cell of the time-level predictor: 2 or 4 spread the n
   // time nodes over that many wavefronts (when fewer than n), else n
   int lw = 0;
+  // handle-owned scratch of the TV statistics over many cells: per-workgroup
+  // partials (count, mean, M2) and the thresholds (kTvPartDoubles doubles)
+  double* d_part = nullptr;
   int nc = 0;                 // the mesh has 1:3 non-conforming faces
 };
+
+// TV statistics over many cells: at most kStatParts per-workgroup partials
+constexpr int kStatParts = 512;
+constexpr int kTvPartDoubles = 3 * kStatParts + 3;
 
 // wavefronts per cell the time-level predictor of g launches
 inline int level_waves(const Group& g) { return (g.lw == 2 || g.lw == 4) && g.lw < g.n ? g.lw : g.n; }

@@ -1,5 +1,7 @@
 // Auxiliary kernels for gfx950: initial state, total-variation indicator with
 // Chan-merged statistics and refinement flags, state health check.
+#include <algorithm>
+
 #include "adg_internal.h"
 
 namespace adg {
@@ -54,48 +56,58 @@ __global__ void k_init_state(Phys ph, int n, int C, const double* geom, const do
 // TV = (1/h) sum_ji w_i w_j (|sum_m D_im f_jm| + |sum_m D_jm f_mi|), f =
 // theta or rho at the nodes: the mean of |df/dx| + |df/dz| over the cell
 // (eq. tv by GL quadrature with the reference element's weights, which sum
-// to one, of the physical gradient).  One wavefront per cell; lanes < 2n run
-// the line jobs.
+// to one, of the physical gradient).  A wavefront holds 64 / P cells, P the
+// power of two >= n^2, one lane per node: the lane forms f, then both
+// derivatives at its node from the cell's values in LDS; the cell's P lanes
+// sum the weighted node terms in a butterfly.
+constexpr int kTvThreads = 256;
+constexpr int pow2_at_least(int v) { return v <= 1 ? 1 : 2 * pow2_at_least((v + 1) / 2); }
+// cells per workgroup of k_tv
 template <int n>
-__global__ __launch_bounds__(kWave) void k_tv(Tab<n> T, Phys ph, const double* Q, const double* geom,
-                                                const double* gtab, int var, double* tv) {
-  constexpr int nn = n * n;
-  __shared__ double sfv[nn];
-  const int c = blockIdx.x;
-  const int lane = threadIdx.x;
-  const double z0 = geom[4 * c + 1], h = geom[4 * c + 2];
-  if (lane < nn) {
-    const int jz = lane / n;
+constexpr int tv_cells_per_block() { return (kTvThreads / kWave) * (kWave / pow2_at_least(n * n)); }
+template <int n>
+__global__ __launch_bounds__(kTvThreads) void k_tv(Phys ph, int C, const double* Q, const double* geom,
+                                                    const double* gtab, int var, double* tv) {
+  constexpr int nn = n * n, P = pow2_at_least(nn), K = kWave / P, CB = tv_cells_per_block<n>();
+  __shared__ double sf[CB * nn];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int slot = lane / P, node = lane % P;
+  const int cs = wave * K + slot;                           // cell within the workgroup
+  const int c = blockIdx.x * CB + cs;
+  const bool valid = node < nn && c < C;
+  const int jz = node / n, ix = node % n;
+  double h = 1.0;
+  if (valid) {
+    const double z0 = geom[4 * c + 1];
+    h = geom[4 * c + 2];
     const double* Qc = Q + (size_t)c * 4 * nn;
-    const double rho = Qc[lane];
+    const double rho = Qc[node];
     double f = rho;
     if (var == ADG_VAR_THETA) {
       const double z = z0 + h * gtab[GTab::XI * n + jz];
-      const double p = pressure(ph, rho, Qc[nn + lane], Qc[2 * nn + lane], Qc[3 * nn + lane], z);
+      const double p = pressure(ph, rho, Qc[nn + node], Qc[2 * nn + node], Qc[3 * nn + node], z);
       const double Tm = p / (rho * ph.R);
       f = Tm * pow(ph.p0 / p, ph.R_over_cp);
     }
-    sfv[lane] = f;
+    sf[cs * nn + node] = f;
   }
   __syncthreads();
   double part = 0.0;
-  if (lane < 2 * n) {
-    const int dir = lane / n, line = lane % n;
-    const int base = dir == 0 ? line * n : line, stride = dir == 0 ? 1 : n;
-    double in[n];
+  if (valid) {
+    const double* Di = gtab + GTab::d(n) + ix * n;   // row i of D
+    const double* Dj = gtab + GTab::d(n) + jz * n;   // row j of D
+    const double* fc = sf + cs * nn;
+    double dx = 0.0, dz = 0.0;
 #pragma unroll
-    for (int m = 0; m < n; ++m) in[m] = sfv[base + m * stride];
-#pragma unroll
-    for (int i = 0; i < n; ++i) {
-      double s = 0.0;
-#pragma unroll
-      for (int m = 0; m < n; ++m) s = fma(T.D[i][m], in[m], s);
-      part = fma(T.w[i], fabs(s), part);
+    for (int m = 0; m < n; ++m) {
+      dx = fma(Di[m], fc[jz * n + m], dx);
+      dz = fma(Dj[m], fc[m * n + ix], dz);
     }
-    part *= gtab[GTab::W * n + line];
+    part = gtab[GTab::W * n + ix] * gtab[GTab::W * n + jz] * (fabs(dx) + fabs(dz));
   }
-  part = wave_sum(part);
-  if (lane == 0) tv[c] = part / h;
+#pragma unroll
+  for (int o = 1; o < P; o <<= 1) part += __shfl_xor(part, o, kWave);
+  if (node == 0 && c < C) tv[c] = part / h;
 }
 
 // ---------------------------------------------------- statistics and flags
@@ -169,6 +181,70 @@ __global__ __launch_bounds__(kStatThreads) void k_stats_flags(const double* tv, 
   }
 }
 
+// Many cells: each workgroup folds a contiguous range of cells into (count,
+// mean, M2) as above and writes its partial; one workgroup merges the
+// partials in workgroup order (Chan), writes the statistics and keeps the
+// threshold pair; a grid then writes the flags.  Deterministic for a given C.
+constexpr int kStatSingle = 65536;   // up to this many cells: the single-workgroup kernel
+
+__global__ __launch_bounds__(kStatThreads) void k_stats_part(const double* tv, int C, int per_block, double* part) {
+  constexpr int nw = kStatThreads / kWave;
+  __shared__ double sn[nw], sm[nw], sq[nw];
+  const int t = threadIdx.x;
+  const int beg = blockIdx.x * per_block, end = min(C, beg + per_block);
+  double na = 0.0, ma = 0.0, qa = 0.0;
+  for (int c = beg + t; c < end; c += kStatThreads) {
+    const double x = tv[c];
+    const double nt = na + 1.0;
+    const double d = x - ma;
+    const double r = 1.0 / nt;
+    ma = fma(d, r, ma);
+    qa = fma(d * d, na * r, qa);
+    na = nt;
+  }
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) chan_shfl(na, ma, qa, o);
+  if ((t & (kWave - 1)) == 0) { sn[t / kWave] = na; sm[t / kWave] = ma; sq[t / kWave] = qa; }
+  __syncthreads();
+  if (t == 0) {
+    double cn = sn[0], cm = sm[0], cq = sq[0];
+    for (int w = 1; w < nw; ++w) chan_merge(cn, cm, cq, sn[w], sm[w], sq[w]);
+    part[3 * blockIdx.x + 0] = cn;
+    part[3 * blockIdx.x + 1] = cm;
+    part[3 * blockIdx.x + 2] = cq;
+  }
+}
+
+// merge of the nparts partials (one wavefront: a Chan butterfly over lanes
+// holding parts k, k + 64, ..., folded in order first); stats as above, and
+// (mean + Tr sigma, mean + Tc sigma, sigma) to thr for the flag pass
+__global__ __launch_bounds__(kWave) void k_stats_merge(const double* part, int nparts, double Tr, double Tc,
+                                                      double* stats, double* thr) {
+  const int t = threadIdx.x;
+  double na = 0.0, ma = 0.0, qa = 0.0;
+  for (int k = t; k < nparts; k += kWave) chan_merge(na, ma, qa, part[3 * k], part[3 * k + 1], part[3 * k + 2]);
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) chan_shfl(na, ma, qa, o);
+  if (t == 0) {
+    const double sigma = na > 0.0 ? sqrt(qa / na) : 0.0;
+    stats[0] = na; stats[1] = ma; stats[2] = sigma;
+    thr[0] = ma + Tr * sigma; thr[1] = ma + Tc * sigma; thr[2] = sigma;
+  }
+}
+
+__global__ void k_flags(const double* tv, int C, const double* thr, int8_t* flags) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const double sigma = thr[2];
+  int8_t f = 0;
+  if (sigma != 0.0) {
+    const double v = tv[c];
+    if (v >= thr[0]) f = 1;
+    else if (v < thr[1]) f = -1;
+  }
+  flags[c] = f;
+}
+
 // ------------------------------------------------------------------ health
 __global__ void k_health(Phys ph, int n, int C, const double* Q, const double* geom, const double* gtab,
                          int* flag) {
@@ -197,8 +273,10 @@ int launch_init_state(const Group& g, int c0, int count, int kind, int nbub, con
 }
 
 template <int n>
-static int launch_tv_n(const Group& g, const HostBasis& B, int var, double* tv, hipStream_t s) {
-  hipLaunchKernelGGL(k_tv<n>, dim3(g.C), dim3(kWave), 0, s, tab_of<n>(B), g.ph, g.Q, g.d_geom, g.d_gtab, var, tv);
+static int launch_tv_n(const Group& g, int var, double* tv, hipStream_t s) {
+  constexpr int CB = tv_cells_per_block<n>();
+  hipLaunchKernelGGL(k_tv<n>, dim3((g.C + CB - 1) / CB), dim3(kTvThreads), 0, s, g.ph, g.C, g.Q, g.d_geom, g.d_gtab,
+                     var, tv);
   return check_launch("tv");
 }
 
@@ -207,17 +285,28 @@ int launch_tv(const Group& g, const HostBasis& B, int var, double Tr, double Tc,
   int rc;
   if (g.C == 0) return fail(ADG_EINVAL, "empty mesh");
   switch (g.n) {
-    case 2: rc = launch_tv_n<2>(g, B, var, tv, s); break;
-    case 3: rc = launch_tv_n<3>(g, B, var, tv, s); break;
-    case 4: rc = launch_tv_n<4>(g, B, var, tv, s); break;
-    case 5: rc = launch_tv_n<5>(g, B, var, tv, s); break;
-    case 6: rc = launch_tv_n<6>(g, B, var, tv, s); break;
-    case 7: rc = launch_tv_n<7>(g, B, var, tv, s); break;
-    case 8: rc = launch_tv_n<8>(g, B, var, tv, s); break;
+    case 2: rc = launch_tv_n<2>(g, var, tv, s); break;
+    case 3: rc = launch_tv_n<3>(g, var, tv, s); break;
+    case 4: rc = launch_tv_n<4>(g, var, tv, s); break;
+    case 5: rc = launch_tv_n<5>(g, var, tv, s); break;
+    case 6: rc = launch_tv_n<6>(g, var, tv, s); break;
+    case 7: rc = launch_tv_n<7>(g, var, tv, s); break;
+    case 8: rc = launch_tv_n<8>(g, var, tv, s); break;
     default: return fail(ADG_EUNSUPPORTED, "order not supported");
   }
   if (rc) return rc;
-  hipLaunchKernelGGL(k_stats_flags, dim3(1), dim3(kStatThreads), 0, s, tv, g.C, Tr, Tc, flags, stats);
+  if (g.C <= kStatSingle || !g.d_part) {
+    hipLaunchKernelGGL(k_stats_flags, dim3(1), dim3(kStatThreads), 0, s, tv, g.C, Tr, Tc, flags, stats);
+    return check_launch("stats_flags");
+  }
+  // contiguous ranges of at least kStatThreads cells, at most kStatParts of them
+  const int per = std::max(kStatThreads, (g.C + kStatParts - 1) / kStatParts);
+  const int nparts = (g.C + per - 1) / per;
+  double* part = g.d_part;
+  double* thr = g.d_part + 3 * kStatParts;
+  hipLaunchKernelGGL(k_stats_part, dim3(nparts), dim3(kStatThreads), 0, s, tv, g.C, per, part);
+  hipLaunchKernelGGL(k_stats_merge, dim3(1), dim3(kWave), 0, s, part, nparts, Tr, Tc, stats, thr);
+  hipLaunchKernelGGL(k_flags, dim3((g.C + 255) / 256), dim3(256), 0, s, tv, g.C, thr, flags);
   return check_launch("stats_flags");
 }
 

@@ -387,7 +387,8 @@ static void free_group(Group& g) {
   if (g.d_nbr) (void)hipFree(g.d_nbr);
   if (g.d_gtab) (void)hipFree(g.d_gtab);
   if (g.d_scen) (void)hipFree(g.d_scen);
-  g.d_geom = nullptr; g.d_nbr = nullptr; g.d_gtab = nullptr; g.d_scen = nullptr;
+  if (g.d_part) (void)hipFree(g.d_part);
+  g.d_geom = nullptr; g.d_nbr = nullptr; g.d_gtab = nullptr; g.d_scen = nullptr; g.d_part = nullptr;
 }
 
 // Allocate and upload a group's tables.
@@ -404,6 +405,7 @@ static int upload_group(Group& g, const std::vector<double>& geom, const std::ve
     if (e == hipSuccess && scen) e = hipMalloc(&g.d_scen, sizeof(int) * C);
   }
   if (e == hipSuccess) e = hipMalloc(&g.d_gtab, sizeof(double) * gtab.size());
+  if (e == hipSuccess) e = hipMalloc(&g.d_part, sizeof(double) * kTvPartDoubles);
   if (e != hipSuccess) { free_group(g); return fail(ADG_ENOMEM, "device allocation failed"); }
   if (C) {
     e = hipMemcpy(g.d_geom, geom.data(), sizeof(double) * 4 * C, hipMemcpyHostToDevice);

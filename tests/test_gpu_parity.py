@@ -322,6 +322,16 @@ def test_tv_indicator_matches_oracle(N):
     _tv_compare(wr, I.random_state_cfd(36, N, 9), adg.ADG_VAR_RHO, 0.5, -0.5)
 
 
+def test_tv_indicator_many_cells_matches_oracle():
+    """Above 65,536 cells the statistics run through per-workgroup partials
+    (300 x 300 = 90,000 cells, N = 2), and the TV kernel packs four cells
+    per wavefront: TV, statistics and flags against the oracle."""
+    w = I.bubble(300, 2, bubbles=[I.cosine_bubble(), I.cold_bubble()])
+    Q = O.ic(w["phys"], w["mesh"], "bubbles", w["bubbles"])
+    fl = _tv_compare(w, Q, adg.ADG_VAR_THETA, 1.0, 0.0)
+    assert (fl == 1).sum() > 0 and (fl == -1).sum() > 0
+
+
 def test_tv_constant_field_keeps_all():
     w = cfd_periodic(4, 4, 3)
     n = 4
