@@ -47,8 +47,9 @@ __global__ __launch_bounds__(kPeakThreads) void k_peak_mfma(double* sink, double
 
 // FP64 matrix cores beside the FP64 vector units: the waves of a workgroup
 // below mfma_waves run chains of v_mfma_f64_4x4x4 (512 flops each), the
-// others chains of vector FMAs, each side sized to take about as long alone
-// (four MFMA chains of kMfmaIters steps; eight FMA chains of 4 kMfmaIters).
+// others chains of vector FMAs: four MFMA chains of kMfmaIters steps (2,048
+// flops per wavefront and step), eight FMA chains of 4 kMfmaIters steps
+// (twice the flops of the MFMA side).
 __global__ __launch_bounds__(kPeakThreads) void k_peak_share(double* sink, double a, double b, int mfma_waves) {
   const int wave = threadIdx.x / kWave;
   double s = 0.0;
