@@ -89,6 +89,46 @@ def _oracle_rate(O, model, w, threads, budget_s):
     return model.dofs(C, w["phys"]["N"]) * steps / total, steps, total, used
 
 
+def _timed(fn):
+    t0 = time.perf_counter()
+    fn()
+    return time.perf_counter() - t0
+
+
+def cpu_other_workloads(O, model):
+    """The oracle on the other measured workloads (bounded samples, all host
+    threads): the 9x9, N=2 density wave (10 whole steps); one forward step
+    with its forward-mode derivative along one direction on the 27x27 adjoint
+    workload (the oracle's reference for the adjoint); one step of every
+    eighth scenario of the 64-scenario batch (DOF-updates over the summed
+    times)."""
+    import numpy as np
+    from paper_1905_05524_amd import inputs as I
+    out = {}
+    w = I.mms_small(N=2, nx=9)
+    Q = O.ic(w["phys"], w["mesh"], "mms")
+    dt = O.dt(w["phys"], w["mesh"], Q)
+    sec = _timed(lambda: O.run(w["phys"], w["mesh"], Q, 0.0, 10, dt))
+    out["mms9x9_N2"] = {"dof_updates_per_s": model.dofs(81, 2) * 10 / sec, "sample": f"10 steps, {sec:.3f} s"}
+    w = I.bubble27()
+    Q = O.ic(w["phys"], w["mesh"], "bubbles", w["bubbles"])
+    dt = O.dt(w["phys"], w["mesh"], Q)
+    v = np.random.default_rng(4).standard_normal(Q.shape)
+    sec = _timed(lambda: O.step_jvp(w["phys"], w["mesh"], Q, v, 0.0, dt))
+    out["bubble27_N6_step_and_jvp"] = {"s_per_step_and_direction": sec,
+                                       "sample": f"one step with one tangent direction, {sec:.3f} s"}
+    ws = I.batch_scenarios(64)
+    dofs, tot = 0, 0.0
+    for k in range(0, 64, 8):
+        wk = ws[k]
+        Qk = O.ic(wk["phys"], wk["mesh"], "bubbles", wk["bubbles"])
+        dk = O.dt(wk["phys"], wk["mesh"], Qk)
+        tot += _timed(lambda: O.step(wk["phys"], wk["mesh"], Qk, 0.0, dk))
+        dofs += model.dofs(wk["mesh"]["nx"] * wk["mesh"]["nz"], wk["phys"]["N"])
+    out["batch64_every_8th"] = {"dof_updates_per_s": dofs / tot, "sample": f"8 scenarios, one step each, {tot:.2f} s"}
+    return out
+
+
 def cpu_baseline(w, budget_s=15.0, one_thread_budget_s=4.0):
     """Oracle (as it stands) on the same workload: whole steps of the 81x81
     grid on all host threads until about budget_s seconds of CPU work, and a
@@ -99,7 +139,9 @@ def cpu_baseline(w, budget_s=15.0, one_thread_budget_s=4.0):
     rate, steps, total, used = _oracle_rate(O, model, w, threads, budget_s)
     r1, s1, t1, _ = _oracle_rate(O, model, w, 1, one_thread_budget_s)
     O.set_threads(threads)
+    others = cpu_other_workloads(O, model)
     return {"value": rate, "unit": "DOF-updates/s", "cores": used, "kind": "oracle",
+            "other_workloads": others,
             "sample": f"{steps} full step(s) of the 81x81 N=6 bubble workload, {total:.1f} s, "
                       f"OpenMP threads={used}",
             "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
@@ -651,6 +693,15 @@ def main():
     pred_ms = sum(a.elapsed_time(b) for a, b, _ in ev) / K
     corr_ms = sum(b.elapsed_time(c) for _, b, c in ev) / K
     m.check_health(s)
+    # the TV indicator alone (HBM-bound read of Q, theta per node): 10 calls
+    t0e, t1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0e.record(s)
+    for _ in range(10):
+        m.tv_indicator(adg.ADG_VAR_THETA, 1.5, -0.5, tv, fl, st, s)
+    t1e.record(s)
+    torch.cuda.synchronize()
+    tv_ms = t0e.elapsed_time(t1e) / 10
+    tv_bytes = C * (4 * (N + 1) ** 2 * 8 + 8 + 1)
 
     dof = model.dofs(C, N)
     ms_step = total_ms / K
@@ -682,6 +733,7 @@ def main():
                      "flops_per_launch": pflops},
         "extra": {"corrector_ms": corr_ms,
                   "corrector_GBps": cbytes / (corr_ms / 1e3) / 1e9,
+                  "tv_indicator_ms": tv_ms, "tv_indicator_GBps": tv_bytes / (tv_ms / 1e3) / 1e9,
                   "wall_s_timed_region": t_wall,
                   "sim_time_s": m.t, "dt_s": m.dt},
     }
