@@ -280,6 +280,15 @@ int adg_step_adjoint(adg_mesh* m, const double* Q_n, const double* lam_np1, doub
  * Conforming meshes only (EUNSUPPORTED otherwise). */
 int adg_keep_bytes(const adg_mesh* m, size_t* store_bytes, size_t* fd_bytes);
 int adg_step_keep(adg_mesh* m, double* store, double* fd, void* stream);
+
+/* adg_step (store = fd = NULL) or adg_step_keep (both given) with the new
+ * state Q^{n+1} written to Q_out (device [C][4][n][n], caller-owned; may be
+ * the bound state, which gives the in-place step) instead of the bound state,
+ * which keeps Q^n: a rollout writes each step into the next checkpoint slot
+ * and binds it (adg_set_state) for the next step, with no copy.  The clock
+ * advances as in adg_step.  Keeping iterates: conforming meshes only
+ * (EUNSUPPORTED otherwise); EINVAL when only one of store and fd is given. */
+int adg_step_to(adg_mesh* m, double* Q_out, double* store, double* fd, void* stream);
 int adg_step_adjoint_kept(adg_mesh* m, const double* Q_n, const double* store, const double* fd,
                           const double* lam_np1, double* lam_n, void* adj_ws, void* stream);
 

@@ -35,7 +35,7 @@ EXPORTED = [
     "adg_fv_init", "adg_fv_destroy", "adg_fv_info", "adg_fv_workspace_bytes", "adg_fv_set_state",
     "adg_fv_init_state", "adg_fv_compute_dt", "adg_fv_predictor", "adg_fv_corrector", "adg_fv_step",
     "adg_fv_check_health",
-    "adg_peaks_sink_bytes", "adg_measure_peaks", "adg_measure_fp64_sharing",
+    "adg_peaks_sink_bytes", "adg_measure_peaks", "adg_measure_fp64_sharing", "adg_step_to",
 ]
 
 
@@ -137,6 +137,7 @@ def lib():
         L.adg_loss_theta_adjoint.argtypes = [vp, vp, vp, vp, vp]
         L.adg_keep_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
         L.adg_step_keep.argtypes = [vp, vp, vp, vp]
+        L.adg_step_to.argtypes = [vp, vp, vp, vp, vp]
         L.adg_step_adjoint_kept.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.adg3_init_mesh.argtypes = [ctypes.POINTER(adg_params), ctypes.POINTER(adg3_mesh_desc), ctypes.POINTER(vp)]
         L.adg3_destroy.argtypes = [vp]
@@ -239,6 +240,13 @@ class Mesh:
                                    ctypes.c_void_p(self.ws.data_ptr()),
                                    ctypes.c_void_p(self.clock.data_ptr())))
 
+    def bind_state(self, Q):
+        """Bind another state tensor (same shape) with the same workspace and
+        clock: a host-side pointer change, no device work.  bind() rebinds
+        self.Q."""
+        _check(lib().adg_set_state(self.h, ctypes.c_void_p(Q.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+                                   ctypes.c_void_p(self.clock.data_ptr())))
+
     def bind_clock(self, clock):
         """Bind another device clock (double[4] tensor) with the same state
         and workspace: a host-side pointer change, no device work."""
@@ -285,6 +293,13 @@ class Mesh:
 
     def step(self, stream=None):
         _check(lib().adg_step(self.h, _stream_ptr(stream)))
+
+    def step_to(self, Q_out, store=None, fd=None, stream=None):
+        """adg_step_to: one step from the bound state into Q_out (keeping the
+        iterates in store/fd when given); the bound state is left as it was."""
+        vp = ctypes.c_void_p
+        _check(lib().adg_step_to(self.h, vp(Q_out.data_ptr()), vp(store.data_ptr()) if store is not None else None,
+                                 vp(fd.data_ptr()) if fd is not None else None, _stream_ptr(stream)))
 
     def step_static(self, Q, clock, stream=None):
         """adg_step_static: one step of the caller's Q and clock (device

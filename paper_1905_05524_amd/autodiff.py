@@ -3,12 +3,13 @@ initial perturbation, as a ``torch.autograd.Function`` over the library's
 hand-written adjoint.
 
 Forward: theta' -> initial state (hydrostatic background perturbed in theta
-at fixed pressure) -> K ADER-DG steps with a frozen time step, each step's
-start state kept as a checkpoint in device memory -> loss
+at fixed pressure) -> K ADER-DG steps with a frozen time step, each step
+writing its new state into the next checkpoint slot in device memory -> loss
 L = ||theta - theta_bg||_{L2}.  Backward: the loss adjoint, then the step
 adjoints from the last step to the first, then the adjoint of the
 initial-state map.  With keep=True every forward step also keeps its Picard
-iterates and face data in device memory (adg_step_keep) and the backward
+iterates and face data in device memory (adg_step_to with a store, the step
+of adg_step_keep) and the backward
 pass uses them (adg_step_adjoint_kept); otherwise each step adjoint
 recomputes its predictor from its checkpoint.  Both give the same gradient.
 All arithmetic runs in the library's kernels.
@@ -38,13 +39,18 @@ class ThetaRollout(torch.autograd.Function):
             sb, fb = m.keep_bytes()
             stores = torch.empty((steps, sb // 8), dtype=torch.float64, device=m.device)
             fds = torch.empty((steps, fb // 8), dtype=torch.float64, device=m.device)
-        for k in range(steps):
-            ck[k].copy_(m.Q)
-            if keep:
-                m.step_keep(stores[k], fds[k])
-            else:
-                m.step()
-        ck[steps].copy_(m.Q)
+        # each step reads checkpoint k (bound) and writes checkpoint k + 1
+        ck[0].copy_(m.Q)
+        try:
+            for k in range(steps):
+                m.bind_state(ck[k])
+                if keep:
+                    m.step_to(ck[k + 1], stores[k], fds[k])
+                else:
+                    m.step_to(ck[k + 1])
+        finally:
+            m.bind()
+        m.Q.copy_(ck[steps])
         loss = torch.zeros(1, dtype=torch.float64, device=m.device)
         m.loss_theta(loss)
         ctx.mesh, ctx.steps, ctx.dt, ctx.t0 = m, steps, float(dt), float(t0)

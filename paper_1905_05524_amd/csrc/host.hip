@@ -846,6 +846,28 @@ int adg_step_keep(adg_mesh* m, double* store, double* fd, void* stream) {
   return launch_clock(m->clock, gf.dtc, nullptr, nullptr, 1, gf.C, 1, gf.ph.fixed_dt ? 0 : 1, s);
 }
 
+int adg_step_to(adg_mesh* m, double* Q_out, double* store, double* fd, void* stream) {
+  int rc = need_state(m);
+  if (rc) return rc;
+  if (!Q_out) return fail(ADG_EINVAL, "null buffer");
+  if (((uintptr_t)Q_out & 7) != 0) return fail(ADG_EINVAL, "misaligned buffer");
+  if ((store == nullptr) != (fd == nullptr)) return fail(ADG_EINVAL, "store and fd must both be given or both be NULL");
+  if (store) {
+    rc = adjoint_supported(m);
+    if (rc) return rc;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  Group gp = m->g;
+  if (fd) gp.FD = fd;   // the corrector reads the kept face data
+  rc = launch_predictor_any(gp, store, s);
+  if (rc) return rc;
+  Group gc = gp;
+  gc.Q = Q_out;         // the corrector writes Q^{n+1} here; it reads only Q* and the face data
+  rc = launch_corrector(gc, s);
+  if (rc) return rc;
+  return launch_clock(m->clock, gp.dtc, nullptr, nullptr, 1, gp.C, 1, gp.ph.fixed_dt ? 0 : 1, s);
+}
+
 int adg_step_adjoint_kept(adg_mesh* m, const double* Q_n, const double* store, const double* fd,
                           const double* lam_np1, double* lam_n, void* adj_ws, void* stream) {
   int rc = need_state(m);

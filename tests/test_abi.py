@@ -118,6 +118,7 @@ def test_null_arguments_rejected():
     assert L.adg_set_state(None, None, None, None) == adg.ADG_EINVAL
     assert L.adg_step_static(None, None, None, None) == adg.ADG_EINVAL
     assert L.adg_batch_set_mode(None, 1) == adg.ADG_EINVAL
+    assert L.adg_step_to(None, None, None, None, None) == adg.ADG_EINVAL
 
 
 def _init3(phys, mesh):

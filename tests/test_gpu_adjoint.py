@@ -219,3 +219,40 @@ def test_gradient_unchanged_by_another_rollout_before_backward():
         assert torch.equal(ta.grad, ref), keep
         Lb.backward()
         assert torch.isfinite(tb.grad).all()
+
+
+def test_step_to_equals_the_in_place_step():
+    """adg_step_to writes the step's result into another buffer and leaves
+    the bound state as it was: the same bits as adg_step (without a store)
+    and as adg_step_keep (with one, also the same kept iterates and face
+    data); only one of store and fd is rejected."""
+    w = I.bubble27()
+    ref = adg.Mesh(w["phys"], w["mesh"], fixed_dt=True)
+    ref.init_state("bubbles", w["bubbles"])
+    ref.compute_dt()
+    m = adg.Mesh(w["phys"], w["mesh"], fixed_dt=True)
+    m.set_state(ref.Q.clone(), t=0.0, dt=ref.dt)
+    ref.set_state(ref.Q.clone(), t=0.0, dt=ref.dt)
+    Q0 = m.Q.clone()
+    out = torch.empty_like(m.Q)
+    m.step_to(out)
+    ref.step()
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref.Q)
+    assert torch.equal(m.Q, Q0)
+    assert torch.equal(m.clock, ref.clock)
+    sb, fb = m.keep_bytes()
+    st1 = torch.empty(sb // 8, dtype=torch.float64, device="cuda")
+    fd1 = torch.empty(fb // 8, dtype=torch.float64, device="cuda")
+    st2, fd2 = torch.empty_like(st1), torch.empty_like(fd1)
+    m.bind_state(out)
+    out2 = torch.empty_like(out)
+    m.step_to(out2, st1, fd1)
+    ref.step_keep(st2, fd2)
+    torch.cuda.synchronize()
+    m.bind()
+    assert torch.equal(out2, ref.Q)
+    assert torch.equal(st1, st2) and torch.equal(fd1, fd2)
+    with pytest.raises(adg.AdgError):
+        m.step_to(out2, st1, None)
+
