@@ -247,6 +247,40 @@ def test_persistent_mode_equals_per_order_launches(mixed):
     assert torch.equal(a.Q, b.Q)
 
 
+def test_persistent_mode_at_the_extreme_orders():
+    """The persistent predictor at orders 1, 2 and 7 (four, four and one
+    cells per wavefront; at order 7 one wavefront per SIMD) against the
+    per-order launches with one wavefront per cell, and against the oracle
+    on one scenario of each order."""
+    ws = []
+    for N, nx in ((1, 11), (2, 7), (7, 5), (1, 4)):
+        w = I.bubble(nx, N)
+        ws.append(w)
+    a, b = adg.Batch(ws), adg.Batch(ws)
+    for bb in (a, b):
+        for s, w in enumerate(ws):
+            bb.init_state(s, "bubbles", w["bubbles"])
+        bb.compute_dt()
+    for g in range(a.n_groups):
+        a.set_launch(g, 1, 1)
+    b.set_mode(adg.ADG_BATCH_PERSISTENT)
+    Q0 = [b.state(s).cpu().numpy() for s in range(len(ws))]
+    c0 = b.clock.cpu().numpy()
+    for _ in range(2):
+        a.step()
+        b.step()
+    torch.cuda.synchronize()
+    assert torch.equal(a.Q, b.Q)
+    assert torch.equal(a.clock, b.clock)
+    for s in range(3):
+        w = ws[s]
+        dt0 = c0[s, 1]
+        ref = O.step(w["phys"], w["mesh"], Q0[s], 0.0, dt0)
+        dt1 = O.dt(w["phys"], w["mesh"], ref)
+        ref = O.step(w["phys"], w["mesh"], ref, dt0, dt1)
+        P.assert_step(b.state(s).cpu().numpy(), ref, Q0[s], what=f"persistent N={w['phys']['N']}")
+
+
 def test_batch_autotune_then_step_unchanged():
     ws = _small_batch()
     a, b = adg.Batch(ws), adg.Batch(ws)
