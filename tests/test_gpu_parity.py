@@ -173,6 +173,25 @@ def test_step_matches_oracle(kind, nx, N, kernel):
 
 
 
+@pytest.mark.parametrize("kernel", list(KERNELS))
+@pytest.mark.parametrize("N", [1, 3, 6, 7])
+def test_paper_mms_step_matches_oracle(N, kernel):
+    """The paper's manufactured solution (its source on every variable, a
+    separate instantiation of each predictor kernel) on a 3x3 grid,
+    one step from the exact state at t = 0.2 against the oracle, on every
+    predictor kernel."""
+    w = I.paper_mms(N, 3)
+    Q = O.ic(w["phys"], w["mesh"], "paper_mms", t0=0.2)
+    dt = 0.5 * O.dt(w["phys"], w["mesh"], Q)
+    m = mesh_of(w, kernel, fixed_dt=True)
+    m.set_state(Q, t=0.2, dt=dt)
+    m.step()
+    ref = O.step(w["phys"], w["mesh"], Q, 0.2, dt)
+    got = m.Q.cpu().numpy()
+    assert np.all(relerr(got, ref) <= TOL), relerr(got, ref)
+    assert np.all(increment_err(got, ref, Q) <= TOL_INC), increment_err(got, ref, Q)
+
+
 @pytest.mark.parametrize("nx,nz", [(73, 6), (439, 1), (768, 1), (769, 1)])
 def test_automatic_kernel_choice_at_its_threshold(nx, nz):
     """N = 6 with the default launch mode: 438 cells (438 x 7 = 3066
