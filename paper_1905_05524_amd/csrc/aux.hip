@@ -280,7 +280,7 @@ static int launch_tv_n(const Group& g, int var, double* tv, hipStream_t s) {
   return check_launch("tv");
 }
 
-int launch_tv(const Group& g, const HostBasis& B, int var, double Tr, double Tc, double* tv, int8_t* flags,
+int launch_tv(const Group& g, int var, double Tr, double Tc, double* tv, int8_t* flags,
               double* stats, hipStream_t s) {
   int rc;
   if (g.C == 0) return fail(ADG_EINVAL, "empty mesh");

@@ -17,7 +17,7 @@ int launch_clock(double* clock, const double* dtc, const int* beg, const int* en
 int max_cpw(int n);
 int launch_init_state(const Group& g, int c0, int count, int kind, int nbub, const double* d_bub, double t0,
                       hipStream_t s);
-int launch_tv(const Group& g, const HostBasis& B, int var, double Tr, double Tc, double* tv, int8_t* flags,
+int launch_tv(const Group& g, int var, double Tr, double Tc, double* tv, int8_t* flags,
               double* stats, hipStream_t s);
 int launch_health(const Group& g, int* flag, hipStream_t s);
 int launch_regrid(int n, int C, const int* ops, const double* Qold, double* Qnew, const double* gtab,
@@ -635,7 +635,7 @@ int adg_tv_indicator(adg_mesh* m, int var, double T_refine, double T_coarsen, do
   if (var == ADG_VAR_THETA && !(m->prm.p0 > 0.0)) return fail(ADG_EINVAL, "theta needs p0 > 0");
   if (!tv || !flags || !stats) return fail(ADG_EINVAL, "null output");
   if (!(T_refine > T_coarsen)) return fail(ADG_EINVAL, "T_refine must exceed T_coarsen");
-  return launch_tv(m->g, m->basis, var, T_refine, T_coarsen, tv, flags, stats, (hipStream_t)stream);
+  return launch_tv(m->g, var, T_refine, T_coarsen, tv, flags, stats, (hipStream_t)stream);
 }
 
 int adg_check_health(adg_mesh* m, void* stream) {
