@@ -108,6 +108,9 @@ struct Group {
   // handle-owned scratch of the TV statistics over many cells: per-workgroup
   // partials (count, mean, M2) and the thresholds (kTvPartDoubles doubles)
   double* d_part = nullptr;
+  // corrector launches: a clock the corrector advances itself (frozen time
+  // step, one mesh), or NULL
+  double* advance = nullptr;
   int nc = 0;                 // the mesh has 1:3 non-conforming faces
 };
 

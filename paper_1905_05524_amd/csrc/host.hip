@@ -55,6 +55,19 @@ int launch_predictor_any(const Group& g, double* store, hipStream_t s) {
   return store ? launch_predictor_store(g, store, s) : launch_predictor(g, s);
 }
 
+// Corrector of one mesh, then its clock: with a frozen time step the
+// corrector's first workgroup advances t and the step count itself (no clock
+// kernel); otherwise the clock kernel reduces the per-cell bounds into dt.
+int launch_corrector_clock(Group g, double* clock, hipStream_t s) {
+  if (g.ph.fixed_dt) {
+    g.advance = clock;
+    return launch_corrector(g, s);
+  }
+  int rc = launch_corrector(g, s);
+  if (rc) return rc;
+  return launch_clock(clock, g.dtc, nullptr, nullptr, 1, g.C, 1, 1, s);
+}
+
 void set_error(const std::string& msg) { g_err = msg; }
 int fail(int code, const std::string& msg) { g_err = msg; return code; }
 int check_launch(const char* what) {
@@ -615,10 +628,7 @@ int adg_predictor(adg_mesh* m, void* stream) {
 int adg_corrector(adg_mesh* m, void* stream) {
   int rc = need_state(m);
   if (rc) return rc;
-  hipStream_t s = (hipStream_t)stream;
-  rc = launch_corrector(m->g, s);
-  if (rc) return rc;
-  return launch_clock(m->clock, m->g.dtc, nullptr, nullptr, 1, m->g.C, 1, m->g.ph.fixed_dt ? 0 : 1, s);
+  return launch_corrector_clock(m->g, m->clock, (hipStream_t)stream);
 }
 
 int adg_step(adg_mesh* m, void* stream) {
@@ -841,9 +851,7 @@ int adg_step_keep(adg_mesh* m, double* store, double* fd, void* stream) {
   gf.FD = fd;   // the corrector reads the kept face data
   rc = launch_predictor_any(gf, store, s);
   if (rc) return rc;
-  rc = launch_corrector(gf, s);
-  if (rc) return rc;
-  return launch_clock(m->clock, gf.dtc, nullptr, nullptr, 1, gf.C, 1, gf.ph.fixed_dt ? 0 : 1, s);
+  return launch_corrector_clock(gf, m->clock, s);
 }
 
 int adg_step_to(adg_mesh* m, double* Q_out, double* store, double* fd, void* stream) {
@@ -863,9 +871,7 @@ int adg_step_to(adg_mesh* m, double* Q_out, double* store, double* fd, void* str
   if (rc) return rc;
   Group gc = gp;
   gc.Q = Q_out;         // the corrector writes Q^{n+1} here; it reads only Q* and the face data
-  rc = launch_corrector(gc, s);
-  if (rc) return rc;
-  return launch_clock(m->clock, gp.dtc, nullptr, nullptr, 1, gp.C, 1, gp.ph.fixed_dt ? 0 : 1, s);
+  return launch_corrector_clock(gc, m->clock, s);
 }
 
 int adg_step_adjoint_kept(adg_mesh* m, const double* Q_n, const double* store, const double* fd,

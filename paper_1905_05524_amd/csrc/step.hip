@@ -131,6 +131,7 @@ struct StepArgs {
   const int* nbr;       // [C][4][4]
   const double* gtab;
   double* iter_store;   // optional [C][iters][n][4][n][n]: Picard iterates q^1..q^I (adjoint)
+  double* advance;      // optional clock [4] the corrector advances (t += dt, steps += 1)
   int C, iters;
 };
 
@@ -979,6 +980,12 @@ __global__ __launch_bounds__(kWave * WPB) void k_corrector(Phys ph, StepArgs a) 
       a.dtc[c] = ph.cfl * h / (2.0 * o * (lm + 2.0 * vm * o / h));
     }
   }
+  // a frozen time step: the clock advances here, with no reduction to wait
+  // for (the corrector reads only dt, which does not change)
+  if (a.advance && blockIdx.x == 0 && threadIdx.x == 0) {
+    a.advance[0] += a.advance[1];
+    a.advance[3] += 1.0;
+  }
 }
 
 // per-cell CFL candidate from the current state (no update)
@@ -1052,6 +1059,7 @@ StepArgs make_args(const Group& g) {
   a.clock = g.clock; a.scen = g.d_scen; a.geom = g.d_geom; a.nbr = g.d_nbr; a.gtab = g.d_gtab;
   a.C = g.C; a.iters = g.iters;
   a.iter_store = nullptr;
+  a.advance = g.advance;
   return a;
 }
 

@@ -40,8 +40,7 @@ int static_scratch_address(int dev, void** ptr) {
 
 int launch_predictor_any(const Group& g, double* store, hipStream_t s);
 int launch_corrector(const Group& g, hipStream_t s);
-int launch_clock(double* clock, const double* dtc, const int* beg, const int* end, int nscen, int C, int advance,
-                 int update, hipStream_t s);
+int launch_corrector_clock(Group g, double* clock, hipStream_t s);
 
 }  // namespace adg
 
@@ -72,7 +71,5 @@ extern "C" int adg_step_static(adg_mesh* m, double* Q, double* clock, void* stre
   hipStream_t s = static_cast<hipStream_t>(stream);
   int rc = launch_predictor_any(g, nullptr, s);
   if (rc) return rc;
-  rc = launch_corrector(g, s);
-  if (rc) return rc;
-  return launch_clock(clock, g.dtc, nullptr, nullptr, 1, g.C, 1, g.ph.fixed_dt ? 0 : 1, s);
+  return launch_corrector_clock(g, clock, s);
 }
