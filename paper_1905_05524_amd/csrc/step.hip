@@ -29,7 +29,6 @@ struct Lay {
   static constexpr int nn = n * n, sl = 4 * nn;
   static constexpr int T = sl;                             // transposed copy of a region
   static constexpr int F0 = 2 * sl;                        // gradients / fluxes region
-  static constexpr int pred_cell = 6 * sl + (n > 5 ? n : 5) * nn;   // predictor LDS doubles per cell
   static constexpr int jobs = 8 * n * CPW;                 // line jobs per wavefront
   static constexpr int rounds = (jobs + kWave - 1) / kWave;
   static constexpr int corr_cell = 16 * n + 24 * n + 48 * n;  // sG, sL/sV, sGs
@@ -54,6 +53,65 @@ struct LineJob {
     v = (jj % (4 * n)) / n;
     line = jj % n;
     base = (dir ? 4 * nn : 0) + v * nn + line * n;
+  }
+};
+
+// LDS layout of the per-cell predictor (k_predictor, the persistent batch
+// predictor).  With several cells per wavefront it is Lay's: each slice in
+// both layouts.  With one cell per wavefront the slice is written once, as
+// [4 vars][z][x], and the z line jobs of the gradient pass read it with
+// stride n; the gradients, fluxes and divergences keep their two parts (x
+// part [v][z][x], z part [v][x][z]), so every other line access has unit
+// stride.  Writing the slice once removes a quarter of the LDS writes of a
+// time level.  Jobs are ordered as in LineJob (variable-major), the x jobs
+// from lane 0 and the z jobs from the first 16-lane boundary after them: at
+// n = 7 that measured half the LDS bank-conflict cycles of z jobs packed
+// right after the x jobs, and fewer than variables padded to other strides
+// or line-major job orders.
+template <int n, int CPW>
+struct PLay {
+  static constexpr int nn = n * n;
+  static constexpr bool one = CPW == 1;
+  static constexpr int ST = 4 * nn;                  // transposed slice (several cells per wavefront)
+  static constexpr int GX = one ? 4 * nn : 8 * nn;   // x part of gradients / fluxes
+  static constexpr int GZ = GX + 4 * nn;             // z part
+  static constexpr int SM = GZ + 4 * nn;             // manufactured source, staging of the averages
+  static constexpr int cell = SM + (n > 5 ? n : 5) * nn;   // doubles per cell
+  static constexpr int Z0 = ((4 * n + 15) / 16) * 16;      // first z job's lane (one cell per wavefront)
+  static constexpr int rounds = one ? 1 : Lay<n, CPW>::rounds;
+  static_assert(!one || Z0 + 4 * n <= kWave, "one round of line jobs");
+};
+
+// Line job of one lane in one round of the per-cell predictor: direction,
+// variable, line, cell slot; the gradient pass reads n values from src with
+// stride sst and writes them to dst (unit stride), where the divergence pass
+// and the face extrapolation of the fluxes also work; the face
+// extrapolation of the state reads the src line.
+template <int n, int CPW>
+struct PJob {
+  int dir, slot, v, line, src, sst, dst;
+  bool active;
+  __device__ PJob(int job) {
+    using P = PLay<n, CPW>;
+    constexpr int nn = n * n;
+    if constexpr (P::one) {
+      dir = job >= P::Z0;
+      const int j = dir ? job - P::Z0 : job;
+      active = j < 4 * n;
+      const int jj = active ? j : 0;
+      slot = 0;
+      v = jj / n;
+      line = jj % n;
+      src = dir ? v * nn + line : v * nn + line * n;
+      sst = dir ? n : 1;
+      dst = (dir ? P::GZ : P::GX) + v * nn + line * n;
+    } else {
+      const LineJob<n> J(job, CPW);
+      dir = J.dir; slot = J.slot; v = J.v; line = J.line; active = J.active;
+      src = J.base;
+      sst = 1;
+      dst = P::GX + J.base;
+    }
   }
 };
 
@@ -111,6 +169,37 @@ __device__ inline void line_eo(const EOTab<n>& T, int base, const double* src, d
   }
 }
 
+// d line = T * (n values of s with stride ss); d has unit stride and may
+// equal s (then ss = 1).
+template <int n>
+__device__ inline void line_eo_s(const EOTab<n>& T, const double* s, int ss, double* d) {
+  constexpr int h = n / 2, mid = (n - 1) / 2;
+  // the stride is opaque to the compiler at each call, so that the n read
+  // addresses are formed here rather than hoisted and held in registers
+  asm volatile("" : "+v"(ss));
+  double in[n];
+#pragma unroll
+  for (int m = 0; m < n; ++m) in[m] = s[m * ss];
+  double e[h], o[h];
+#pragma unroll
+  for (int m = 0; m < h; ++m) { e[m] = in[m] + in[n - 1 - m]; o[m] = in[m] - in[n - 1 - m]; }
+#pragma unroll
+  for (int i = 0; i < h; ++i) {
+    double S = T.A[i][0] * o[0], U = T.B[i][0] * e[0];
+#pragma unroll
+    for (int m = 1; m < h; ++m) { S = fma(T.A[i][m], o[m], S); U = fma(T.B[i][m], e[m], U); }
+    if constexpr (n % 2) U = fma(T.C[i], in[mid], U);
+    d[i] = S + U;
+    d[n - 1 - i] = S - U;
+  }
+  if constexpr (n % 2) {
+    double S = T.M[0] * o[0];
+#pragma unroll
+    for (int m = 1; m < h; ++m) S = fma(T.M[m], o[m], S);
+    d[mid] = S;
+  }
+}
+
 // A wave-uniform double moved to scalar registers.
 __device__ inline double uniform(double v) {
   const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
@@ -164,7 +253,7 @@ __device__ inline double node_flux(const Phys& ph, const double q[4], double* sf
 // Per cell: lane l < n*n owns spatial node l = (j, i) and holds, in
 // registers, the Picard iterate at all n time nodes, X[b][v] (the time-node
 // loop is unrolled so the array is statically indexed).  Per sweep and time
-// node b: the slice X[b] goes to LDS (both layouts), gradients by line jobs,
+// node b: the slice X[b] goes to LDS, gradients by line jobs,
 // flux and source per node (fluxes over the gradients), divergence by line
 // jobs in place, and the residual R(b) replaces X[b] (the old iterate at b is
 // no longer needed).  At the end of the sweep the time solve
@@ -180,11 +269,11 @@ __device__ inline double node_flux(const Phys& ph, const double q[4], double* sf
 // work counter.
 template <int n, int CPW, bool PW>
 __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, int cell0) {
-  using L = Lay<n, CPW>;
-  constexpr int nn = L::nn, sl = L::sl, T = L::T, F0 = L::F0;
+  using P = PLay<n, CPW>;
+  constexpr int nn = P::nn, sl = 4 * nn, ZO = 4 * nn;   // z part of gradients / fluxes
   extern __shared__ double lds[];
   const int lane = threadIdx.x % kWave;
-  double* wl = lds + (size_t)wave * CPW * L::pred_cell;
+  double* wl = lds + (size_t)wave * CPW * P::cell;
 
   // node role
   const int slot = lane / nn, l = lane % nn;
@@ -194,9 +283,9 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
   const int cc = valid ? c : 0;
   const int jz = l / n, ix = l % n;
   const int tl = ix * n + jz;                           // node offset in the transposed layout
-  double* sq = wl + (node ? slot : 0) * L::pred_cell;   // slice, both layouts
-  double* sf = sq + F0;                                 // gradients / fluxes, both layouts
-  double* sm = sq + F0 + 4 * sl;                        // [n][n*n] manufactured source (if any)
+  double* sq = wl + (node ? slot : 0) * P::cell;       // slice
+  double* sf = sq + P::GX;                              // gradients / fluxes: x part, z part at ZO
+  double* sm = sq + P::SM;                              // [n][n*n] manufactured source (if any)
   const double* gt = a.gtab;
 
   // cell-level values: with one cell per wavefront they are read through a
@@ -234,18 +323,26 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
   }
 
   // line-job roles (rounds of 64 jobs)
-  const LineJob<n> J0(lane, CPW), J1(lane + kWave, CPW);
-  double* jl0 = wl + (J0.active ? J0.slot : 0) * L::pred_cell;
-  double* jl1 = wl + (J1.active ? J1.slot : 0) * L::pred_cell;
-  // line jobs from region src_off to region dst_off of the cell
-  auto lines = [&](int src_off, int dst_off) {
-    if (J0.active) line_eo<n>(Dt, J0.base, jl0 + src_off, jl0 + dst_off);
-    if (L::rounds > 1 && J1.active) line_eo<n>(Dt, J1.base, jl1 + src_off, jl1 + dst_off);
+  const PJob<n, CPW> J0(lane), J1(lane + kWave);
+  double* jl0 = wl + (J0.active ? J0.slot : 0) * P::cell;
+  double* jl1 = wl + (J1.active ? J1.slot : 0) * P::cell;
+  // the gradient pass (slice to gradients) and the divergence pass (fluxes,
+  // in place)
+  auto grad_lines = [&]() {
+    if (J0.active) line_eo_s<n>(Dt, jl0 + J0.src, J0.sst, jl0 + J0.dst);
+    if (P::rounds > 1 && J1.active) line_eo_s<n>(Dt, jl1 + J1.src, J1.sst, jl1 + J1.dst);
+  };
+  auto div_lines = [&]() {
+    if (J0.active) line_eo_s<n>(Dt, jl0 + J0.dst, 1, jl0 + J0.dst);
+    if (P::rounds > 1 && J1.active) line_eo_s<n>(Dt, jl1 + J1.dst, 1, jl1 + J1.dst);
   };
   auto put_slice = [&](const double q[4]) {
     if (node) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) { sq[v * nn + l] = q[v]; sq[T + v * nn + tl] = q[v]; }
+      for (int v = 0; v < 4; ++v) {
+        sq[v * nn + l] = q[v];
+        if constexpr (!P::one) sq[P::ST + v * nn + tl] = q[v];
+      }
     }
   };
 
@@ -263,13 +360,13 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
           X[b][0] = X[0][0];
           X[b][1] = X[0][1];
           X[b][2] = X[0][2];
-          X[b][3] = ph.mms ? fma(-h, sm[b * nn + l], sf[3 * nn + l] + sf[T + 3 * nn + tl]) : X[0][3];
+          X[b][3] = ph.mms ? fma(-h, sm[b * nn + l], sf[3 * nn + l] + sf[ZO + 3 * nn + tl]) : X[0][3];
         }
         continue;
       }
       put_slice(X[b]);
       wave_sync();
-      lines(0, F0);                          // gradients of time node b
+      grad_lines();                          // gradients of time node b
       wave_sync();
       double Sw = 0.0;
       if (node) {
@@ -277,11 +374,11 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
         Sw = node_flux<n>(ph, X[b], sf, l, tl, mu_h, kappa_h, gh, z, rb, pb, Fx, Fz, true);
       }
       wave_sync();
-      lines(F0, F0);                         // divergence parts, in place
+      div_lines();                           // divergence parts, in place
       wave_sync();
       if (node) {   // scaled residual R' = div F - h S, with R = -R' / h
 #pragma unroll
-        for (int v = 0; v < 4; ++v) X[b][v] = sf[v * nn + l] + sf[T + v * nn + tl];
+        for (int v = 0; v < 4; ++v) X[b][v] = sf[v * nn + l] + sf[ZO + v * nn + tl];
         X[b][2] = fma(-h, Sw, X[b][2]);
         if ((!PW && ph.mms)) X[b][3] = fma(-h, sm[b * nn + l], X[b][3]);
         if constexpr (PW) {
@@ -372,7 +469,7 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
   for (int b = 0; b < n; ++b) {
     put_slice(X[b]);
     wave_sync();
-    lines(0, F0);
+    grad_lines();
     wave_sync();
     if (node) {
       double Fx[4], Fz[4];
@@ -400,7 +497,7 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
     SbE = sm[4 * nn + l];
     put_slice(Qb);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) { sf[v * nn + l] = Fxa[v]; sf[T + v * nn + tl] = Fza[v]; }
+    for (int v = 0; v < 4; ++v) { sf[v * nn + l] = Fxa[v]; sf[ZO + v * nn + tl] = Fza[v]; }
   }
   wave_sync();
   {
@@ -411,20 +508,20 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
     int lane_r = lane;
     asm volatile("" : "+v"(lane_r));
 #pragma unroll
-    for (int r = 0; r < L::rounds; ++r) {
-      const LineJob<n> J(lane_r + r * kWave, CPW);
-      double* jl = wl + (J.active ? J.slot : 0) * L::pred_cell;
+    for (int r = 0; r < P::rounds; ++r) {
+      const PJob<n, CPW> J(lane_r + r * kWave);
+      double* jl = wl + (J.active ? J.slot : 0) * P::cell;
       if (!J.active) continue;
       const int cj = cell0 + J.slot;
       double q0 = 0, q1 = 0, f0 = 0, f1 = 0;
 #pragma unroll
       for (int m = 0; m < n; ++m) {
         const double e0 = gt[GTab::E0 * n + m], e1 = gt[GTab::E1 * n + m];
-        const double iq = jl[J.base + m], iF = jl[F0 + J.base + m];
+        const double iq = jl[J.src + m * J.sst], iF = jl[J.dst + m];
         q0 = fma(e0, iq, q0); q1 = fma(e1, iq, q1);
         f0 = fma(e0, iF, f0); f1 = fma(e1, iF, f1);
       }
-      line_eo<n>(Wt, J.base, jl + F0, jl + F0);
+      line_eo_s<n>(Wt, jl + J.dst, 1, jl + J.dst);
       if (cj >= a.C) continue;
       double* fd = a.FD + (size_t)cj * 32 * n;
       const int fl0 = 2 * J.dir, fu = 2 * J.dir + 1;
@@ -452,13 +549,13 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const double S = ((v == 2) ? Sbw : (v == 3 ? SbE : 0.0)) + Sp[v];
-        qs[v * nn + l] = Qc[v * nn] + dt * ((sf[v * nn + l] + sf[T + v * nn + tl]) * ih + S);
+        qs[v * nn + l] = Qc[v * nn] + dt * ((sf[v * nn + l] + sf[ZO + v * nn + tl]) * ih + S);
       }
     } else {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const double S = (v == 2) ? Sbw : (v == 3 ? SbE : 0.0);
-        qs[v * nn + l] = Qc[v * nn] + dt * ((sf[v * nn + l] + sf[T + v * nn + tl]) * ih + S);
+        qs[v * nn + l] = Qc[v * nn] + dt * ((sf[v * nn + l] + sf[ZO + v * nn + tl]) * ih + S);
       }
     }
   }
@@ -476,9 +573,9 @@ __global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phy
 // For meshes too small to fill the chip with one wavefront per cell: one
 // workgroup of W wavefronts per cell, wavefront w owning the time nodes
 // w, w + W, ... (W = n: one wavefront per time node).  Each wavefront runs
-// the slice machinery of k_predictor (line jobs on both LDS layouts,
-// even-odd contractions) on its time nodes one after the other, in its own
-// LDS region of 4 slices.  Within a Picard sweep the n residuals are
+// the slice machinery of k_predictor with one cell per wavefront (the slice
+// in one LDS layout, line jobs, even-odd contractions) on its time nodes one
+// after the other, in its own LDS region of 4 slices.  Within a Picard sweep the n residuals are
 // independent; they meet in a shared LDS area, where the time matrix mixes
 // them: X_b = Q + dt sum_a P[b][a] R_a (with one wavefront per node each
 // residual sits in its wavefront's region, else in an area of its own).  The
@@ -490,20 +587,21 @@ __global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phy
 // k_predictor up to the order of the sums.
 template <int n, int W, bool PW>
 __device__ __forceinline__ void predictor_levels(Phys ph, StepArgs a, int c) {
-  using L = Lay<n, 1>;
-  constexpr int nn = L::nn, sl = L::sl, T = L::T, F0 = L::F0, WR = 4 * sl;
+  using P = PLay<n, 1>;
+  constexpr int nn = n * n, sl = 4 * nn, ZO = 4 * nn, WR = 4 * sl;
+  static_assert(P::GZ + 4 * nn + sl <= WR, "slice, gradients and a residual fit a region");
   constexpr int NL = (n + W - 1) / W;             // time nodes per wavefront (the last may own fewer)
   extern __shared__ double lds[];                 // W regions of WR doubles, then (W < n) the residuals [n][sl]
   // the wavefront index is wave-uniform: scalar, so are its time-node tables
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
   double* wl = lds + (size_t)w * WR;
-  // residual of time node b: the transposed slice of its region (W = n), or [b][sl] after the regions
-  auto res = [&](int b) { return W == n ? lds + (size_t)b * WR + T : lds + (size_t)W * WR + (size_t)b * sl; };
+  // residual of time node b: the last slice of its region (W = n), or [b][sl] after the regions
+  auto res = [&](int b) { return W == n ? lds + (size_t)b * WR + (WR - sl) : lds + (size_t)W * WR + (size_t)b * sl; };
   const bool node = lane < nn;
   const int l = node ? lane : 0;
   const int jz = l / n, ix = l % n, tl = ix * n + jz;
-  double* sq = wl;          // slice, both layouts
-  double* sf = wl + F0;     // gradients / fluxes, both layouts
+  double* sq = wl;           // slice
+  double* sf = wl + P::GX;   // gradients / fluxes: x part, z part at ZO
   const double* gt = a.gtab;
   const int s = a.scen ? a.scen[c] : 0;
   const double t0 = a.clock[4 * s + 0], dt = a.clock[4 * s + 1];
@@ -539,21 +637,24 @@ __device__ __forceinline__ void predictor_levels(Phys ph, StepArgs a, int c) {
     }
   }
 
-  const LineJob<n> J(lane, 1);
-  auto lines = [&](int src_off, int dst_off) {
-    if (J.active) line_eo<n>(Dt, J.base, wl + src_off, wl + dst_off);
+  const PJob<n, 1> J(lane);
+  auto grad_lines = [&]() {
+    if (J.active) line_eo_s<n>(Dt, wl + J.src, J.sst, wl + J.dst);
+  };
+  auto div_lines = [&]() {
+    if (J.active) line_eo_s<n>(Dt, wl + J.dst, 1, wl + J.dst);
   };
   auto put_slice = [&](const double q[4]) {
     if (node) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) { sq[v * nn + l] = q[v]; sq[T + v * nn + tl] = q[v]; }
+      for (int v = 0; v < 4; ++v) sq[v * nn + l] = q[v];
     }
   };
   // scaled residual R' = div F - h S of the slice q (without the manufactured source)
   auto residual = [&](const double q[4], double R[4]) {
     put_slice(q);
     wave_sync();
-    lines(0, F0);
+    grad_lines();
     wave_sync();
     double Sw = 0.0;
     if (node) {
@@ -561,10 +662,10 @@ __device__ __forceinline__ void predictor_levels(Phys ph, StepArgs a, int c) {
       Sw = node_flux<n>(ph, q, sf, l, tl, mu_h, kappa_h, gh, z, rb, pb, Fx, Fz, true);
     }
     wave_sync();
-    lines(F0, F0);
+    div_lines();
     wave_sync();
 #pragma unroll
-    for (int v = 0; v < 4; ++v) R[v] = node ? sf[v * nn + l] + sf[T + v * nn + tl] : 0.0;
+    for (int v = 0; v < 4; ++v) R[v] = node ? sf[v * nn + l] + sf[ZO + v * nn + tl] : 0.0;
     R[2] = fma(-h, Sw, R[2]);
   };
   // the manufactured source of owned level k added, to the shared area
@@ -645,7 +746,7 @@ __device__ __forceinline__ void predictor_levels(Phys ph, StepArgs a, int c) {
     if (b >= n) break;
     put_slice(X[k]);
     wave_sync();
-    lines(0, F0);
+    grad_lines();
     wave_sync();
     double Fx[4], Fz[4], Sw = 0.0;
     if (node) Sw = node_flux<n>(ph, X[k], sf, l, tl, mu_h, kappa_h, gh, z, rb, pb, Fx, Fz, false);
@@ -707,7 +808,7 @@ __device__ __forceinline__ void predictor_levels(Phys ph, StepArgs a, int c) {
   if (node) {
     put_slice(Qb);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) { sf[v * nn + l] = Fbx[v]; sf[T + v * nn + tl] = Fbz[v]; }
+    for (int v = 0; v < 4; ++v) { sf[v * nn + l] = Fbx[v]; sf[ZO + v * nn + tl] = Fbz[v]; }
   }
   wave_sync();
   {
@@ -718,11 +819,11 @@ __device__ __forceinline__ void predictor_levels(Phys ph, StepArgs a, int c) {
 #pragma unroll
       for (int m = 0; m < n; ++m) {
         const double e0 = gt[GTab::E0 * n + m], e1 = gt[GTab::E1 * n + m];
-        const double iq = wl[J.base + m], iF = wl[F0 + J.base + m];
+        const double iq = wl[J.src + m * J.sst], iF = wl[J.dst + m];
         q0 = fma(e0, iq, q0); q1 = fma(e1, iq, q1);
         f0 = fma(e0, iF, f0); f1 = fma(e1, iF, f1);
       }
-      line_eo<n>(Wt, J.base, wl + F0, wl + F0);
+      line_eo_s<n>(Wt, wl + J.dst, 1, wl + J.dst);
       double* fd = a.FD + (size_t)c * 32 * n;
       const int fl0 = 2 * J.dir, fu = 2 * J.dir + 1;
       fd[((fl0 * 2 + 0) * 4 + J.v) * n + J.line] = q0;
@@ -737,7 +838,7 @@ __device__ __forceinline__ void predictor_levels(Phys ph, StepArgs a, int c) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const double S = (v == 2) ? Sbw : (v == 3 ? SbE : (v == 0 ? Sb0 : Sb1));
-      qs[v * nn + l] = Qc[v * nn] + dt * ((sf[v * nn + l] + sf[T + v * nn + tl]) * ih + S);
+      qs[v * nn + l] = Qc[v * nn] + dt * ((sf[v * nn + l] + sf[ZO + v * nn + tl]) * ih + S);
     }
   }
 }
@@ -1100,8 +1201,7 @@ __global__ __launch_bounds__(kWave, (n <= 7 ? 3 : 1)) void k_predictor_queue(Phy
 template <int n>
 static int queue_n(const Group& g, unsigned* counter, int nwaves, hipStream_t s) {
   constexpr int CPW = max_cpw_c(n);
-  using L = Lay<n, CPW>;
-  const size_t lds = sizeof(double) * (size_t)CPW * L::pred_cell;
+  const size_t lds = sizeof(double) * (size_t)CPW * PLay<n, CPW>::cell;
   hipLaunchKernelGGL((k_predictor_queue<n, CPW>), dim3(nwaves), dim3(kWave), lds, s, g.ph, make_args(g), counter,
                      (unsigned)nwaves);
   return check_launch("persistent predictor");
@@ -1126,7 +1226,7 @@ int launch_predictor_queue(const Group& g, unsigned* counter, int nwaves, hipStr
 template <int n>
 static int queue_occ(int* per_cu) {
   constexpr int CPW = max_cpw_c(n);
-  const size_t lds = sizeof(double) * (size_t)CPW * Lay<n, CPW>::pred_cell;
+  const size_t lds = sizeof(double) * (size_t)CPW * PLay<n, CPW>::cell;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_predictor_queue<n, CPW>, kWave, lds) == hipSuccess
              ? ADG_OK
              : fail(ADG_EHIP, "occupancy query failed");
@@ -1146,8 +1246,7 @@ int predictor_queue_occupancy(int n, int* per_cu) {
 
 template <int n, int CPW, int WPB, bool PW = false>
 static int launch_pred_t(const Group& g, hipStream_t s) {
-  using L = Lay<n, CPW>;
-  const size_t lds = sizeof(double) * (size_t)WPB * CPW * L::pred_cell;
+  const size_t lds = sizeof(double) * (size_t)WPB * CPW * PLay<n, CPW>::cell;
   const int per_block = CPW * WPB;
   const int blocks = (g.C + per_block - 1) / per_block;
   if (blocks == 0) return ADG_OK;
@@ -1266,11 +1365,10 @@ int launch_predictor_levels(const Group& g, double* store, hipStream_t s) {
 
 template <int n>
 static int pred_store_n(const Group& g, double* store, hipStream_t s) {
-  using L = Lay<n, 1>;
   if (g.C == 0) return ADG_OK;
   StepArgs a = make_args(g);
   a.iter_store = store;
-  const size_t lds = sizeof(double) * (size_t)L::pred_cell;
+  const size_t lds = sizeof(double) * (size_t)PLay<n, 1>::cell;
   if (g.ph.mms == 2)
     hipLaunchKernelGGL((k_predictor<n, 1, 1, true>), dim3(g.C), dim3(kWave), lds, s, g.ph, a);
   else
