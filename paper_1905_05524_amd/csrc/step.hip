@@ -84,13 +84,24 @@ struct PLay {
 
 // Line job of one lane in one round of the per-cell predictor: direction,
 // variable, line, cell slot; the gradient pass reads n values from src with
-// stride sst and writes them to dst (unit stride), where the divergence pass
-// and the face extrapolation of the fluxes also work; the face
+// stride sst() and writes them to dst (unit stride), where the divergence
+// pass and the face extrapolation of the fluxes also work; the face
 // extrapolation of the state reads the src line.
 template <int n, int CPW>
 struct PJob {
-  int dir, slot, v, line, src, sst, dst;
+  int dir, slot, v, line, src, dst;
   bool active;
+  // the stride of the src line, from src and dst alone (z jobs: dst - src >
+  // 4 n^2), so that it need not be kept in a register through the sweeps
+  __device__ int sst() const {
+    if constexpr (CPW == 1) {
+      int d = dst;
+      asm volatile("" : "+v"(d));
+      return d - src > 4 * n * n ? n : 1;
+    } else {
+      return 1;
+    }
+  }
   __device__ PJob(int job) {
     using P = PLay<n, CPW>;
     constexpr int nn = n * n;
@@ -103,13 +114,11 @@ struct PJob {
       v = jj / n;
       line = jj % n;
       src = dir ? v * nn + line : v * nn + line * n;
-      sst = dir ? n : 1;
       dst = (dir ? P::GZ : P::GX) + v * nn + line * n;
     } else {
       const LineJob<n> J(job, CPW);
       dir = J.dir; slot = J.slot; v = J.v; line = J.line; active = J.active;
       src = J.base;
-      sst = 1;
       dst = P::GX + J.base;
     }
   }
@@ -278,9 +287,10 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
   // node role
   const int slot = lane / nn, l = lane % nn;
   const bool node = slot < CPW;
-  const int c = cell0 + (node ? slot : 0);
+  // (with one cell per wavefront the cell index is wave-uniform)
+  const int c = CPW == 1 ? cell0 : cell0 + (node ? slot : 0);
   const bool valid = node && c < a.C;
-  const int cc = valid ? c : 0;
+  const int cc = CPW == 1 ? (cell0 < a.C ? cell0 : 0) : (valid ? c : 0);
   const int jz = l / n, ix = l % n;
   const int tl = ix * n + jz;                           // node offset in the transposed layout
   double* sq = wl + (node ? slot : 0) * P::cell;       // slice
@@ -329,8 +339,8 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
   // the gradient pass (slice to gradients) and the divergence pass (fluxes,
   // in place)
   auto grad_lines = [&]() {
-    if (J0.active) line_eo_s<n>(Dt, jl0 + J0.src, J0.sst, jl0 + J0.dst);
-    if (P::rounds > 1 && J1.active) line_eo_s<n>(Dt, jl1 + J1.src, J1.sst, jl1 + J1.dst);
+    if (J0.active) line_eo_s<n>(Dt, jl0 + J0.src, J0.sst(), jl0 + J0.dst);
+    if (P::rounds > 1 && J1.active) line_eo_s<n>(Dt, jl1 + J1.src, J1.sst(), jl1 + J1.dst);
   };
   auto div_lines = [&]() {
     if (J0.active) line_eo_s<n>(Dt, jl0 + J0.dst, 1, jl0 + J0.dst);
@@ -517,7 +527,7 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
 #pragma unroll
       for (int m = 0; m < n; ++m) {
         const double e0 = gt[GTab::E0 * n + m], e1 = gt[GTab::E1 * n + m];
-        const double iq = jl[J.src + m * J.sst], iF = jl[J.dst + m];
+        const double iq = jl[J.src + m * J.sst()], iF = jl[J.dst + m];
         q0 = fma(e0, iq, q0); q1 = fma(e1, iq, q1);
         f0 = fma(e0, iF, f0); f1 = fma(e1, iF, f1);
       }
@@ -639,7 +649,7 @@ __device__ __forceinline__ void predictor_levels(Phys ph, StepArgs a, int c) {
 
   const PJob<n, 1> J(lane);
   auto grad_lines = [&]() {
-    if (J.active) line_eo_s<n>(Dt, wl + J.src, J.sst, wl + J.dst);
+    if (J.active) line_eo_s<n>(Dt, wl + J.src, J.sst(), wl + J.dst);
   };
   auto div_lines = [&]() {
     if (J.active) line_eo_s<n>(Dt, wl + J.dst, 1, wl + J.dst);
@@ -819,7 +829,7 @@ __device__ __forceinline__ void predictor_levels(Phys ph, StepArgs a, int c) {
 #pragma unroll
       for (int m = 0; m < n; ++m) {
         const double e0 = gt[GTab::E0 * n + m], e1 = gt[GTab::E1 * n + m];
-        const double iq = wl[J.src + m * J.sst], iF = wl[J.dst + m];
+        const double iq = wl[J.src + m * J.sst()], iF = wl[J.dst + m];
         q0 = fma(e0, iq, q0); q1 = fma(e1, iq, q1);
         f0 = fma(e0, iF, f0); f1 = fma(e1, iF, f1);
       }
