@@ -178,8 +178,7 @@ __device__ inline void line_eo(const EOTab<n>& T, int base, const double* src, d
   }
 }
 
-// d line = T * (n values of s with stride ss); d has unit stride and may
-// equal s (then ss = 1).
+// d line = T * (n values of s with stride ss); d has unit stride.
 template <int n>
 __device__ inline void line_eo_s(const EOTab<n>& T, const double* s, int ss, double* d) {
   constexpr int h = n / 2, mid = (n - 1) / 2;
@@ -343,8 +342,8 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
     if (P::rounds > 1 && J1.active) line_eo_s<n>(Dt, jl1 + J1.src, J1.sst(), jl1 + J1.dst);
   };
   auto div_lines = [&]() {
-    if (J0.active) line_eo_s<n>(Dt, jl0 + J0.dst, 1, jl0 + J0.dst);
-    if (P::rounds > 1 && J1.active) line_eo_s<n>(Dt, jl1 + J1.dst, 1, jl1 + J1.dst);
+    if (J0.active) line_eo<n>(Dt, J0.dst, jl0, jl0);
+    if (P::rounds > 1 && J1.active) line_eo<n>(Dt, J1.dst, jl1, jl1);
   };
   auto put_slice = [&](const double q[4]) {
     if (node) {
@@ -531,7 +530,7 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
         q0 = fma(e0, iq, q0); q1 = fma(e1, iq, q1);
         f0 = fma(e0, iF, f0); f1 = fma(e1, iF, f1);
       }
-      line_eo_s<n>(Wt, jl + J.dst, 1, jl + J.dst);
+      line_eo<n>(Wt, J.dst, jl, jl);
       if (cj >= a.C) continue;
       double* fd = a.FD + (size_t)cj * 32 * n;
       const int fl0 = 2 * J.dir, fu = 2 * J.dir + 1;
@@ -652,7 +651,7 @@ __device__ __forceinline__ void predictor_levels(Phys ph, StepArgs a, int c) {
     if (J.active) line_eo_s<n>(Dt, wl + J.src, J.sst(), wl + J.dst);
   };
   auto div_lines = [&]() {
-    if (J.active) line_eo_s<n>(Dt, wl + J.dst, 1, wl + J.dst);
+    if (J.active) line_eo<n>(Dt, J.dst, wl, wl);
   };
   auto put_slice = [&](const double q[4]) {
     if (node) {
@@ -833,7 +832,7 @@ __device__ __forceinline__ void predictor_levels(Phys ph, StepArgs a, int c) {
         q0 = fma(e0, iq, q0); q1 = fma(e1, iq, q1);
         f0 = fma(e0, iF, f0); f1 = fma(e1, iF, f1);
       }
-      line_eo_s<n>(Wt, wl + J.dst, 1, wl + J.dst);
+      line_eo<n>(Wt, J.dst, wl, wl);
       double* fd = a.FD + (size_t)c * 32 * n;
       const int fl0 = 2 * J.dir, fu = 2 * J.dir + 1;
       fd[((fl0 * 2 + 0) * 4 + J.v) * n + J.line] = q0;
