@@ -16,14 +16,15 @@ namespace adg {
 template <int n>
 struct Half { static constexpr int nh = (n + 1) / 2; };
 
-// Predictor LDS layout per cell.  Each time slice is kept twice: as
-// [4 vars][z][x] and transposed as [4 vars][x][z], so that every line job
-// (one lane per direction, variable and line: x lines in the first layout, z
-// lines in the second) reads and writes n consecutive values.  Gradients,
-// fluxes and divergences follow the same pairing: the x parts in the first
-// layout, the z parts in the transposed one.  With 64-bit accesses served in
-// four passes of 16 lanes over 32 four-byte banks, lines that start n
-// doubles apart are conflict-free for odd n in the job order used here.
+// Two-layout LDS regions (the predictor with several cells per wavefront;
+// the corrector's sizes).  Each time slice is kept twice: as [4 vars][z][x]
+// and transposed as [4 vars][x][z], so that every line job (one lane per
+// direction, variable and line: x lines in the first layout, z lines in the
+// second) reads and writes n consecutive values.  Gradients, fluxes and
+// divergences follow the same pairing: the x parts in the first layout, the
+// z parts in the transposed one.  Lines that start n doubles apart (n odd)
+// measured no LDS bank conflicts in the job order used here.  With one cell
+// per wavefront the slice is kept once (PLay below).
 template <int n, int CPW>
 struct Lay {
   static constexpr int nn = n * n, sl = 4 * nn;
