@@ -58,29 +58,35 @@ struct LineJob {
 };
 
 // LDS layout of the per-cell predictor (k_predictor, the persistent batch
-// predictor).  With several cells per wavefront it is Lay's: each slice in
-// both layouts.  With one cell per wavefront the slice is written once, as
-// [4 vars][z][x], and the z line jobs of the gradient pass read it with
-// stride n; the gradients, fluxes and divergences keep their two parts (x
-// part [v][z][x], z part [v][x][z]), so every other line access has unit
-// stride.  Writing the slice once removes a quarter of the LDS writes of a
-// time level.  Jobs are ordered as in LineJob (variable-major), the x jobs
-// from lane 0 and the z jobs from the first 16-lane boundary after them: at
-// n = 7 that measured half the LDS bank-conflict cycles of z jobs packed
-// right after the x jobs, and fewer than variables padded to other strides
-// or line-major job orders.
+// predictor).  The slice is written once, as [4 vars][z][x], and the z line
+// jobs of the gradient pass read it with stride n; the gradients, fluxes and
+// divergences keep their two parts (x part [v][z][x], z part [v][x][z]), so
+// every other line access has unit stride.  Writing the slice once removes
+// a quarter of the LDS writes of a time level.  Jobs are variable-major as in
+// LineJob.  With one cell per wavefront the x jobs start at lane 0 and the z
+// jobs at the first 16-lane boundary after them (at n = 7 that measured half
+// the LDS bank-conflict cycles of z jobs packed right after the x jobs, and
+// fewer than variables padded to other strides or line-major job orders).
+// With several cells per wavefront, two rounds of line jobs and odd n, the
+// first round runs every x job and the second every z job, so that each
+// round has one stride (3 % faster at n = 3 and 5; at n = 4 the stride-4 z
+// reads measured 2.5 % slower).  Otherwise, with several cells per
+// wavefront, the slice is kept in both layouts (Lay).
 template <int n, int CPW>
 struct PLay {
   static constexpr int nn = n * n;
   static constexpr bool one = CPW == 1;
-  static constexpr int ST = 4 * nn;                  // transposed slice (several cells per wavefront)
-  static constexpr int GX = one ? 4 * nn : 8 * nn;   // x part of gradients / fluxes
+  static constexpr bool split = CPW > 1 && Lay<n, CPW>::rounds == 2 && n % 2 == 1;   // x round, z round
+  static constexpr bool single = one || split;       // the slice in one layout
+  static constexpr int ST = 4 * nn;                  // transposed slice (two-layout case)
+  static constexpr int GX = single ? 4 * nn : 8 * nn;   // x part of gradients / fluxes
   static constexpr int GZ = GX + 4 * nn;             // z part
   static constexpr int SM = GZ + 4 * nn;             // manufactured source, staging of the averages
   static constexpr int cell = SM + (n > 5 ? n : 5) * nn;   // doubles per cell
   static constexpr int Z0 = ((4 * n + 15) / 16) * 16;      // first z job's lane (one cell per wavefront)
   static constexpr int rounds = one ? 1 : Lay<n, CPW>::rounds;
   static_assert(!one || Z0 + 4 * n <= kWave, "one round of line jobs");
+  static_assert(!split || 4 * n * CPW <= kWave, "the x jobs fit one round");
 };
 
 // Line job of one lane in one round of the per-cell predictor: direction,
@@ -92,13 +98,17 @@ template <int n, int CPW>
 struct PJob {
   int dir, slot, v, line, src, dst;
   bool active;
-  // the stride of the src line, from src and dst alone (z jobs: dst - src >
-  // 4 n^2), so that it need not be kept in a register through the sweeps
+  // the stride of the src line; with one cell per wavefront it is derived
+  // from src and dst alone (z jobs: dst - src > 4 n^2), so that it need not
+  // be kept in a register through the sweeps
   __device__ int sst() const {
-    if constexpr (CPW == 1) {
+    using P = PLay<n, CPW>;
+    if constexpr (P::one) {
       int d = dst;
       asm volatile("" : "+v"(d));
       return d - src > 4 * n * n ? n : 1;
+    } else if constexpr (P::split) {
+      return dir ? n : 1;
     } else {
       return 1;
     }
@@ -106,12 +116,19 @@ struct PJob {
   __device__ PJob(int job) {
     using P = PLay<n, CPW>;
     constexpr int nn = n * n;
-    if constexpr (P::one) {
-      dir = job >= P::Z0;
-      const int j = dir ? job - P::Z0 : job;
-      active = j < 4 * n;
-      const int jj = active ? j : 0;
-      slot = 0;
+    if constexpr (P::one || P::split) {
+      int j;
+      if constexpr (P::one) {
+        dir = job >= P::Z0;
+        j = dir ? job - P::Z0 : job;
+      } else {
+        dir = job >= kWave;
+        j = dir ? job - kWave : job;
+      }
+      slot = j / (4 * n);
+      active = slot < CPW;
+      const int jj = active ? j % (4 * n) : 0;
+      if (!active) slot = 0;
       v = jj / n;
       line = jj % n;
       src = dir ? v * nn + line : v * nn + line * n;
@@ -179,13 +196,15 @@ __device__ inline void line_eo(const EOTab<n>& T, int base, const double* src, d
   }
 }
 
-// d line = T * (n values of s with stride ss); d has unit stride.
-template <int n>
+// d line = T * (n values of s with stride ss); d has unit stride.  SS > 0:
+// the stride is SS, known at compile time (immediate offsets).
+template <int n, int SS = 0>
 __device__ inline void line_eo_s(const EOTab<n>& T, const double* s, int ss, double* d) {
   constexpr int h = n / 2, mid = (n - 1) / 2;
-  // the stride is opaque to the compiler at each call, so that the n read
-  // addresses are formed here rather than hoisted and held in registers
-  asm volatile("" : "+v"(ss));
+  // a run-time stride is opaque to the compiler at each call, so that the n
+  // read addresses are formed here rather than hoisted and held in registers
+  if constexpr (SS > 0) ss = SS;
+  else asm volatile("" : "+v"(ss));
   double in[n];
 #pragma unroll
   for (int m = 0; m < n; ++m) in[m] = s[m * ss];
@@ -339,8 +358,13 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
   // the gradient pass (slice to gradients) and the divergence pass (fluxes,
   // in place)
   auto grad_lines = [&]() {
-    if (J0.active) line_eo_s<n>(Dt, jl0 + J0.src, J0.sst(), jl0 + J0.dst);
-    if (P::rounds > 1 && J1.active) line_eo_s<n>(Dt, jl1 + J1.src, J1.sst(), jl1 + J1.dst);
+    if constexpr (P::split) {   // x jobs in the first round, z jobs in the second
+      if (J0.active) line_eo_s<n, 1>(Dt, jl0 + J0.src, 1, jl0 + J0.dst);
+      if (J1.active) line_eo_s<n, n>(Dt, jl1 + J1.src, n, jl1 + J1.dst);
+    } else {
+      if (J0.active) line_eo_s<n>(Dt, jl0 + J0.src, J0.sst(), jl0 + J0.dst);
+      if (P::rounds > 1 && J1.active) line_eo_s<n>(Dt, jl1 + J1.src, J1.sst(), jl1 + J1.dst);
+    }
   };
   auto div_lines = [&]() {
     if (J0.active) line_eo<n>(Dt, J0.dst, jl0, jl0);
@@ -351,7 +375,7 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         sq[v * nn + l] = q[v];
-        if constexpr (!P::one) sq[P::ST + v * nn + tl] = q[v];
+        if constexpr (!P::single) sq[P::ST + v * nn + tl] = q[v];
       }
     }
   };
