@@ -116,15 +116,19 @@ struct PJob {
   __device__ PJob(int job) {
     using P = PLay<n, CPW>;
     constexpr int nn = n * n;
-    if constexpr (P::one || P::split) {
-      int j;
-      if constexpr (P::one) {
-        dir = job >= P::Z0;
-        j = dir ? job - P::Z0 : job;
-      } else {
-        dir = job >= kWave;
-        j = dir ? job - kWave : job;
-      }
+    if constexpr (P::one) {
+      dir = job >= P::Z0;
+      const int j = dir ? job - P::Z0 : job;
+      active = j < 4 * n;
+      const int jj = active ? j : 0;
+      slot = 0;
+      v = jj / n;
+      line = jj % n;
+      src = dir ? v * nn + line : v * nn + line * n;
+      dst = (dir ? P::GZ : P::GX) + v * nn + line * n;
+    } else if constexpr (P::split) {
+      dir = job >= kWave;
+      const int j = dir ? job - kWave : job;
       slot = j / (4 * n);
       active = slot < CPW;
       const int jj = active ? j % (4 * n) : 0;
