@@ -485,15 +485,16 @@ __global__ __launch_bounds__(kWave * adj_waves<n>()) void k_pred_adj(Phys ph, Ad
   // becomes Lq[b]
   auto slice_vjp = [&](int b, const double* qsrc, const double aFx[4], const double aFz[4], double aSw,
                        const double add[4]) {
+    double q[4] = {0, 0, 0, 0};   // the node's state, kept for the flux adjoint
     if (node)
-      for (int v = 0; v < 4; ++v) sq[v * nn + l] = qsrc[v * nn + l];
+      for (int v = 0; v < 4; ++v) { q[v] = qsrc[v * nn + l]; sq[v * nn + l] = q[v]; }
     wave_sync_a();
     if (job) line_M<n>(Dv, jbase, jstride, sq, sg + dir * sl, ih);     // gradients
     wave_sync_a();
     double aq[4] = {0, 0, 0, 0};
     if (node) {
-      double q[4], gx[4], gz[4], agx[4], agz[4];
-      for (int v = 0; v < 4; ++v) { q[v] = sq[v * nn + l]; gx[v] = sg[v * nn + l]; gz[v] = sg[sl + v * nn + l]; }
+      double gx[4], gz[4], agx[4], agz[4];
+      for (int v = 0; v < 4; ++v) { gx[v] = sg[v * nn + l]; gz[v] = sg[sl + v * nn + l]; }
       flux_source_vjp(ph, q, gx, gz, z, rb, aFx, aFz, aSw, aq, agx, agz);
       for (int v = 0; v < 4; ++v) { sg[v * nn + l] = agx[v]; sg[sl + v * nn + l] = agz[v]; }
     }
