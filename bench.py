@@ -372,7 +372,9 @@ def adjoint_leg(steps=50):
         th = torch.zeros((C, n, n), dtype=torch.float64, device="cuda")
         th[:, :, :] = 0.1
         th.requires_grad_(True)
-        L = theta_rollout(th, m, 2, dt, keep=keep)   # warm-up
+        # warm-up at the timed length, so that the kept iterates' 2.8 GB come
+        # from the allocator's cache in the timed run, as in any repeated use
+        L = theta_rollout(th, m, steps, dt, keep=keep)
         L.backward()
         torch.cuda.synchronize()
         th.grad = None
