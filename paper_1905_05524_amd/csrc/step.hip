@@ -613,14 +613,14 @@ __global__ __launch_bounds__(kWave * WPB, (n <= 7 ? 3 : 1)) void k_predictor(Phy
 // w, w + W, ... (W = n: one wavefront per time node).  Each wavefront runs
 // the slice machinery of k_predictor with one cell per wavefront (the slice
 // in one LDS layout, line jobs, even-odd contractions) on its time nodes one
-// after the other, in its own LDS region of 4 slices.  Within a Picard sweep the n residuals are
-// independent; they meet in a shared LDS area, where the time matrix mixes
-// them: X_b = Q + dt sum_a P[b][a] R_a (with one wavefront per node each
-// residual sits in its wavefront's region, else in an area of its own).  The
-// first sweep evaluates one residual (every node starts from Q^n).  In the
-// final pass every wavefront
-// leaves the weighted sum of its nodes' state, fluxes and sources in its
-// region; the first wavefront sums the W regions in order and runs the
+// after the other, in its own LDS region of 4 slices.  Within a Picard
+// sweep the n residuals are independent; they meet in a shared LDS area,
+// where the time matrix mixes them: X_b = Q + dt sum_a P[b][a] R_a (with one
+// wavefront per node each residual sits in its wavefront's region, else in
+// an area of its own).  The first sweep evaluates one residual (every node
+// starts from Q^n).  In the final pass every wavefront leaves the weighted
+// sum of its nodes' state, fluxes and sources in its region; the first
+// wavefront sums the W regions in order and runs the
 // epilogue of k_predictor (volume term, Q*, face data).  Same arithmetic as
 // k_predictor up to the order of the sums.
 template <int n, int W, bool PW>
