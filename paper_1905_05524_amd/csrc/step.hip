@@ -361,18 +361,30 @@ __device__ __forceinline__ void predictor_wave(Phys ph, StepArgs a, int wave, in
   double* jl1 = wl + (J1.active ? J1.slot : 0) * P::cell;
   // the gradient pass (slice to gradients) and the divergence pass (fluxes,
   // in place)
+  // with one cell per wavefront the job's two offsets are kept packed in one
+  // register through the sweeps (opaque to the compiler, so that it does not
+  // keep the unpacked values instead)
+  int jp0 = J0.src | (J0.dst << 16);
+  if constexpr (P::one) asm volatile("" : "+v"(jp0));
   auto grad_lines = [&]() {
     if constexpr (P::split) {   // x jobs in the first round, z jobs in the second
       if (J0.active) line_eo_s<n, 1>(Dt, jl0 + J0.src, 1, jl0 + J0.dst);
       if (J1.active) line_eo_s<n, n>(Dt, jl1 + J1.src, n, jl1 + J1.dst);
+    } else if constexpr (P::one) {
+      const int s0 = jp0 & 0xffff, d0 = jp0 >> 16;
+      if (J0.active) line_eo_s<n>(Dt, jl0 + s0, d0 - s0 > 4 * nn ? n : 1, jl0 + d0);
     } else {
       if (J0.active) line_eo_s<n>(Dt, jl0 + J0.src, J0.sst(), jl0 + J0.dst);
       if (P::rounds > 1 && J1.active) line_eo_s<n>(Dt, jl1 + J1.src, J1.sst(), jl1 + J1.dst);
     }
   };
   auto div_lines = [&]() {
-    if (J0.active) line_eo<n>(Dt, J0.dst, jl0, jl0);
-    if (P::rounds > 1 && J1.active) line_eo<n>(Dt, J1.dst, jl1, jl1);
+    if constexpr (P::one) {
+      if (J0.active) line_eo<n>(Dt, jp0 >> 16, jl0, jl0);
+    } else {
+      if (J0.active) line_eo<n>(Dt, J0.dst, jl0, jl0);
+      if (P::rounds > 1 && J1.active) line_eo<n>(Dt, J1.dst, jl1, jl1);
+    }
   };
   auto put_slice = [&](const double q[4]) {
     if (node) {
